@@ -1,0 +1,165 @@
+"""Direct (no NUFFT) evaluation of the discrete potential and energy.
+Oracle: test infrastructure only.
+
+Definitions, all in FP64, on the grid x_n = -R_j/2 + n_j h_j, h_j = R_j/N_j,
+n_j = 0..N_j-1, H = prod_j h_j:
+
+  rho^_j = H sum_n rho_n exp(-i k_j . x_n)               trapezoid rule, eq. 3.2
+  u_n    = Re sum_j c_j rho^_j exp(+i k_j . x_n)          quadrature (3.7) of (3.5)
+  E      = (lambda/2) H sum_n rho_n u_n                   energy remark after Alg. 2
+         = (lambda/2) sum_j c_j |rho^_j|^2                (substitute rho^, rho real)
+
+with c_j = (2 pi)^{-d} W_j S(k_j) (symbols.py) and the nodes of quadrature.py.
+These are Algorithm 1's steps 4 and 5 evaluated as plain sums: O(N M) work.
+
+The exponential factorises over axes, exp(-i k.x) = prod_j exp(-i k_j x_j), so
+each sum is taken as a matrix product over the first axis followed by
+elementwise products with the other axes' phase tables.  That is a
+regrouping of the same finite sum, not an approximation.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .quadrature import fourier_nodes
+from .symbols import coefficients
+
+_CHUNK_ELEMS = 1 << 23   # complex elements per intermediate block (128 MB)
+
+
+def _axes(n, box):
+    return [-0.5 * float(R) + np.arange(int(N), dtype=np.float64) * (float(R) / int(N))
+            for N, R in zip(n, box)]
+
+
+def _cell_volume(n, box):
+    return float(np.prod([float(R) / int(N) for N, R in zip(n, box)]))
+
+
+def rho_hat(rho, box, k):
+    """Type-2 sum rho^_j = H sum_n rho_n exp(-i k_j . x_n) at every node (eq. 3.2)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n = rho.shape
+    d = rho.ndim
+    x = _axes(n, box)
+    H = _cell_volume(n, box)
+    k = np.asarray(k, dtype=np.float64)
+    M = k.shape[0]
+    out = np.empty(M, dtype=np.complex128)
+    rest = int(np.prod(n[1:]))
+    B = max(1, _CHUNK_ELEMS // max(rest, 1))
+    flat = rho.reshape(n[0], rest)
+    for s in range(0, M, B):
+        kb = k[s:s + B]
+        P = [np.exp(-1j * np.outer(kb[:, j], x[j])) for j in range(d)]
+        T = P[0] @ flat                                   # (B, N2[*N3])
+        if d == 2:
+            out[s:s + B] = np.einsum("bj,bj->b", T, P[1])
+        else:
+            T = T.reshape(kb.shape[0], n[1], n[2])
+            T2 = np.einsum("bjk,bj->bk", T, P[1])
+            out[s:s + B] = np.einsum("bk,bk->b", T2, P[2])
+    return H * out
+
+
+def sum_to_grid(v, k, n, box):
+    """Type-1 sum f_n = sum_j v_j exp(+i k_j . x_n) on the whole grid (complex)."""
+    v = np.asarray(v, dtype=np.complex128)
+    k = np.asarray(k, dtype=np.float64)
+    d = len(n)
+    x = _axes(n, box)
+    rest = int(np.prod(n[1:]))
+    out = np.zeros((int(n[0]), rest), dtype=np.complex128)
+    M = k.shape[0]
+    B = max(1, _CHUNK_ELEMS // max(rest, 1))
+    for s in range(0, M, B):
+        kb = k[s:s + B]
+        P = [np.exp(1j * np.outer(kb[:, j], x[j])) for j in range(d)]
+        if d == 2:
+            Q = v[s:s + B, None] * P[1]
+        else:
+            Q = (v[s:s + B, None, None] * P[1][:, :, None] * P[2][:, None, :]).reshape(kb.shape[0], rest)
+        out += P[0].T @ Q
+    return out.reshape(tuple(int(t) for t in n))
+
+
+def sum_to_points(v, k, n, box, index):
+    """f_s = sum_j v_j exp(+i k_j . x_{n_s}) at selected grid points.
+
+    index: integer array (S, d) of grid indices.  Per-axis phase tables are
+    gathered at each point's indices, so no exponential is taken per (j, s)."""
+    v = np.asarray(v, dtype=np.complex128)
+    k = np.asarray(k, dtype=np.float64)
+    index = np.asarray(index, dtype=np.int64)
+    d = len(n)
+    x = _axes(n, box)
+    S = index.shape[0]
+    out = np.zeros(S, dtype=np.complex128)
+    M = k.shape[0]
+    B = max(1, _CHUNK_ELEMS // max(S, 1))
+    for s in range(0, M, B):
+        kb = k[s:s + B]
+        E = None
+        for j in range(d):
+            Pj = np.exp(1j * np.outer(kb[:, j], x[j]))   # (B, N_j)
+            g = Pj[:, index[:, j]]
+            E = g if E is None else E * g
+        out += v[s:s + B] @ E
+    return out
+
+
+def energy_fourier(c, rhohat, lam):
+    return 0.5 * lam * float(np.sum(c * (rhohat.real ** 2 + rhohat.imag ** 2)))
+
+
+def energy_physical(rho, u, box, lam):
+    return 0.5 * lam * _cell_volume(rho.shape, box) * float(np.sum(rho * u))
+
+
+def potential(rho, box, kernel, k, W, axis=None):
+    """u = Re sum_j c_j rho^_j exp(i k_j.x_n); returns (u, rho^, c, max|Im|)."""
+    c = coefficients(kernel, k, W, axis)
+    rh = rho_hat(rho, box, k)
+    f = sum_to_grid(c * rh, k, rho.shape, box)
+    return f.real.copy(), rh, c, float(np.max(np.abs(f.imag))) if f.size else 0.0
+
+
+def apply_operator(g, box, kernel, k, W, axis=None):
+    """A g with A_{nl} = H Re sum_j c_j exp(i k_j.(x_n - x_l)); A is symmetric, so this is
+    also the vector-Jacobian product of u with respect to rho."""
+    return potential(np.asarray(g, dtype=np.float64), box, kernel, k, W, axis)[0]
+
+
+def energy_gradient_rho(u, box, lam):
+    """dE/drho_n = lambda H u_n (E = (lambda/2) H rho^T A rho with A symmetric)."""
+    return lam * _cell_volume(u.shape, box) * u
+
+
+def energy_gradient_psi(u, psi, box, lam):
+    """dE/dpsi*_n = lambda H u_n psi_n for rho = |psi|^2."""
+    return lam * _cell_volume(u.shape, box) * u * psi
+
+
+@dataclass
+class Result:
+    u: np.ndarray
+    energy_physical: float
+    energy_fourier: float
+    rhohat: np.ndarray
+    c: np.ndarray
+    k: np.ndarray
+    W: np.ndarray
+    imag_max: float
+
+
+def evaluate(problem, rho):
+    """Full oracle evaluation of a workloads.Problem on density rho (FP64)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    k, W = fourier_nodes(problem)
+    u, rh, c, im = potential(rho, problem.box, problem.kernel, k, W, problem.axis)
+    return Result(u=u,
+                  energy_physical=energy_physical(rho, u, problem.box, problem.lam),
+                  energy_fourier=energy_fourier(c, rh, problem.lam),
+                  rhohat=rh, c=c, k=k, W=W, imag_max=im)
