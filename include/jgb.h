@@ -1,0 +1,174 @@
+/*
+ * jgb.h -- C ABI of the MI355X library for free-space Coulomb and dipole-dipole
+ * convolutions by the Fourier-quadrature + NUFFT method of Jiang, Greengard and
+ * Bao (arXiv:1311.4120).
+ *
+ * What is computed (Section 3, Algorithm 1 and the energy remark after
+ * Algorithm 2).  On the uniform grid x_n = -R_j/2 + n_j h_j, h_j = R_j/N_j,
+ * n_j = 0..N_j-1 (eq. 3.2), with H = prod_j h_j:
+ *
+ *   rho^_j = H sum_n rho_n exp(-i k_j . x_n)                    (eq. 3.2)
+ *   u_n    = Re sum_j c_j rho^_j exp(+i k_j . x_n)               (eq. 3.7)
+ *   E      = (lambda/2) H sum_n rho_n u_n                        (eq. gpe2)
+ *
+ * where k_j and W_j are the Fourier quadrature nodes and weights of eq. 3.7
+ * (Gauss-Legendre in r on [0,K], Gauss-Legendre in theta, trapezoidal in phi)
+ * and c_j = (2 pi)^{-d} W_j |k_j|^{d-1} U^(k_j) with the kernel's transform
+ * U^ from eq. int3dd.  The type-2 and type-1 sums are evaluated by NUFFTs on
+ * the GPU to the requested tolerance; the result matches the direct sums to
+ * eps in relative L2 norm.
+ *
+ * Conventions shared by every call.
+ *   - Arrays are C-order (N_1, N_2[, N_3]): the last axis is contiguous; axis j
+ *     of the array is coordinate x_j.  Element [i_1,i_2,i_3] sits at
+ *     (-R_1/2 + i_1 h_1, ...).
+ *   - rho, u and gradients are device pointers of float64 (JGB_FP64) or
+ *     float32 (JGB_MIXED).  Energies are always one float64 in device memory.
+ *   - The caller owns every array it passes.  A plan owns its node tables,
+ *     bins and workspace: allocated in jgb_plan, freed in jgb_destroy.
+ *   - Compute calls only enqueue work on the plan's stream and return; they
+ *     never synchronise, so they may be captured in a HIP graph.  A launch
+ *     failure returns JGB_ERR_DEVICE; an asynchronous fault surfaces at the
+ *     caller's next synchronisation.
+ *   - A plan is not thread-safe; distinct plans are independent.  Two calls
+ *     on one plan that overlap in time (different streams) race on its
+ *     workspace.
+ *   - Every call returns a jgb_status and never throws.  jgb_last_error()
+ *     gives a message for the last failure on the calling thread.
+ */
+#ifndef JGB_H
+#define JGB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JGB_OK = 0,
+  JGB_ERR_INVALID_ARG = 1,   /* a parameter or pointer violates its contract */
+  JGB_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement   */
+  JGB_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed; nothing leaked */
+  JGB_ERR_DEVICE = 4         /* a HIP runtime call or kernel launch failed     */
+} jgb_status;
+
+/* The interaction kernels of eq. int3dd handled by this library.
+ *   JGB_COULOMB_3D : U = 1/(4 pi |x|),  U^ = 1/|k|^2             (eq. Cou3D)
+ *   JGB_COULOMB_2D : U = 1/(2 pi |x|) in the plane, U^ = 1/|k|    (eq. Cou2D)
+ *   JGB_DIPOLE_3D  : U = (3/4pi)(1 - 3 (x.n)^2/|x|^2)/|x|^3,
+ *                    U^ = -1 + 3 (n.k)^2/|k|^2                    (eqs. dipkernel, dipkernelF) */
+typedef enum { JGB_COULOMB_3D = 0, JGB_COULOMB_2D = 1, JGB_DIPOLE_3D = 2 } jgb_kernel;
+
+/* JGB_FP64: every step in float64.
+ * JGB_MIXED: grids, FFTs and kernel taps in float32; nodes, weights, symbol,
+ *            deconvolution factors and energies in float64; requires eps >= 1e-6. */
+typedef enum { JGB_FP64 = 0, JGB_MIXED = 1 } jgb_precision;
+
+/* Gauss-Legendre rule for the polar angle (3D only).
+ *   JGB_THETA_GL   : GL nodes in theta on [0, pi], weight includes sin(theta)
+ *                    (the literal reading of eq. 3.7).
+ *   JGB_COSTHETA_GL: GL nodes in cos(theta) on [-1, 1] (the same integral). */
+typedef enum { JGB_THETA_GL = 0, JGB_COSTHETA_GL = 1 } jgb_theta_rule;
+
+/* flags */
+#define JGB_FLAG_NONE 0u
+
+typedef struct jgb_plan_s* jgb_plan_t;
+
+typedef struct {
+  uint32_t struct_size;    /* = sizeof(jgb_params); guards against ABI drift */
+  int32_t dim;             /* 2 or 3 */
+  int64_t n[3];            /* N_j: even, 4 <= N_j <= 512, 2 N_j of the form 2^a 3^b 5^c;
+                              n[2] ignored when dim == 2 */
+  double box[3];           /* R_j > 0, full side lengths of B = prod [-R_j/2, R_j/2) */
+  int32_t kernel;          /* jgb_kernel; JGB_COULOMB_2D needs dim == 2, the others dim == 3 */
+  double dipole_axis[3];   /* unit vector n (| |n| - 1 | <= 1e-12); ignored for Coulomb */
+  double lambda;           /* interaction constant of eq. gpe2, finite */
+  double eps;              /* requested relative L2 accuracy of u (and relative accuracy of E)
+                              against the direct sums: [1e-13, 1e-2]; JGB_MIXED needs >= 1e-6 */
+  int32_t precision;       /* jgb_precision */
+  int32_t n_r;             /* radial GL nodes, >= 1 */
+  int32_t n_theta;         /* polar GL nodes (3D), >= 1; ignored when dim == 2 */
+  int32_t n_phi;           /* azimuthal trapezoid nodes: even, >= 2 (k -> -k closure) */
+  int32_t theta_rule;      /* jgb_theta_rule */
+  double kmax;             /* radius K of the Fourier ball; 0 -> pi / max_j h_j; must be
+                              in (0, pi / max_j h_j] otherwise */
+  int32_t device;          /* HIP device ordinal the plan lives on */
+  void* stream;            /* hipStream_t for all work of this plan (NULL = default stream) */
+  uint32_t flags;          /* JGB_FLAG_* (none defined yet; must be 0) */
+} jgb_params;
+
+/* Plan facts, for diagnostics and for sizing caller buffers. */
+typedef struct {
+  uint32_t struct_size;    /* = sizeof(jgb_info) */
+  int32_t dim;
+  int64_t n[3];            /* grid (dim == 2: n[2] = 1) */
+  int64_t nf[3];           /* oversampled FFT grid (2 N_j) */
+  int64_t n_nodes;         /* M = n_r n_theta n_phi (3D) or n_r n_phi (2D) */
+  int64_t n_half;          /* nodes processed on the device: M / 2 (k and -k paired) */
+  int32_t width;           /* spreading kernel width in fine-grid cells per axis */
+  double beta;             /* exponential-of-semicircle kernel shape parameter */
+  double kmax;             /* K actually used */
+  int64_t workspace_bytes; /* device memory owned by the plan */
+} jgb_info;
+
+/* Build a plan: validates the parameters, generates the Fourier nodes and
+ * weights on the device (Algorithm 1, step 3), bin-sorts them, tabulates the
+ * deconvolution factors and allocates the workspace.  Synchronises the plan's
+ * stream before returning.  On success *out owns all plan memory.
+ * Errors: INVALID_ARG (NULL pointers, any rule in jgb_params broken),
+ * UNSUPPORTED (valid but outside this build), OUT_OF_MEMORY, DEVICE. */
+jgb_status jgb_plan(const jgb_params* params, jgb_plan_t* out);
+
+/* u = U*rho on the grid (Algorithm 1, steps 4-5) and, if energy != NULL,
+ * E = (lambda/2) H sum rho u (physical-side trapezoid sum, energy remark).
+ * rho, u: device arrays of prod N_j elements of the plan's dtype;
+ * energy: device float64 or NULL.  rho and u must not overlap.
+ * Enqueue only (asynchronous on the plan's stream). */
+jgb_status jgb_potential(jgb_plan_t plan, const void* rho, void* u, double* energy);
+
+/* E only, via the Fourier-side sum E = (lambda/2) sum_j c_j |rho^_j|^2, which
+ * equals the physical-side sum exactly for real rho (substitute eq. 3.2 into
+ * the energy).  Runs only the type-2 half of the pipeline.
+ * rho: device array; energy: device float64.  Enqueue only. */
+jgb_status jgb_energy(jgb_plan_t plan, const void* rho, double* energy);
+
+/* Vector-Jacobian product of jgb_potential with respect to rho:
+ * grad_rho = A^T grad_u, where u = A rho and A_{nl} = H Re sum_j c_j
+ * exp(i k_j.(x_n - x_l)) is symmetric, so this applies A to grad_u (the type-2
+ * NUFFT is the adjoint of the type-1, end of Section 2).  Device arrays of the
+ * plan's dtype; must not overlap.  Enqueue only. */
+jgb_status jgb_potential_backward(jgb_plan_t plan, const void* grad_u, void* grad_rho);
+
+/* Type-2 stage alone (Algorithm 1, step 4), for diagnostics: rho^_j at the
+ * device's half node set (k_j with phi index l < n_phi/2; the other half is
+ * conj(rho^) at -k_j), in natural node order (radial index slowest, then
+ * theta, then phi).  rhohat: device complex array of n_half elements
+ * (interleaved re, im) of the plan's dtype.  Enqueue only. */
+jgb_status jgb_transform(jgb_plan_t plan, const void* rho, void* rhohat);
+
+/* Fourier nodes of the plan for diagnostics (Algorithm 1, step 3): all M
+ * nodes in natural order.  k: device float64 array (M, dim); w: device float64
+ * array of the quadrature weights W_j (measure dr dtheta dphi with sin(theta),
+ * or dr dphi); c: device float64 array of c_j = (2pi)^{-d} W_j |k_j|^{d-1} U^(k_j).
+ * Any of the three may be NULL.  Enqueue only. */
+jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* c);
+
+/* Copy plan facts into *info (host memory, info->struct_size must be set). */
+jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info);
+
+/* Synchronise the plan's stream, then free everything the plan owns.
+ * NULL is accepted and ignored. */
+jgb_status jgb_destroy(jgb_plan_t plan);
+
+/* Message for the last non-OK status returned on the calling thread ("" if
+ * none).  The pointer stays valid until the next jgb_* call on this thread. */
+const char* jgb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JGB_H */

@@ -1,0 +1,135 @@
+"""Torch-facing wrapper over the C ABI.  PyTorch supplies device memory and
+the stream; every computation is a kernel of libjgb.so."""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+_KERNELS = {"coulomb3d": _lib.COULOMB_3D, "coulomb2d": _lib.COULOMB_2D, "dipole3d": _lib.DIPOLE_3D}
+_RULES = {"theta": _lib.THETA_GL, "costheta": _lib.COSTHETA_GL}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A planned free-space convolution u = U*rho on one uniform grid.
+
+    n, box:    grid points N_j and full side lengths R_j (2 or 3 axes)
+    kernel:    "coulomb3d", "coulomb2d" or "dipole3d" (or the jgb_kernel ints)
+    nodes:     (n_r, n_theta, n_phi) for 3D, (n_r, n_phi) for 2D
+    precision: "fp64" or "mixed"
+    """
+
+    def __init__(self, n: Sequence[int], box: Sequence[float], kernel, nodes: Sequence[int],
+                 eps: float = 1e-10, precision: str = "fp64", lam: float = 1.0,
+                 axis: Sequence[float] = (0.0, 0.0, 1.0), theta_rule="theta", kmax: float = 0.0,
+                 device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None):
+        dim = len(n)
+        kern = _KERNELS.get(kernel, kernel)
+        rule = _RULES.get(theta_rule, theta_rule)
+        dev = torch.cuda.current_device() if device is None else int(device)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        p = _lib.Params()
+        p.struct_size = ctypes.sizeof(_lib.Params)
+        p.dim = dim
+        for i in range(dim):
+            p.n[i] = int(n[i])
+            p.box[i] = float(box[i])
+        p.kernel = int(kern)
+        for i in range(3):
+            p.dipole_axis[i] = float(axis[i]) if i < len(axis) else 0.0
+        p.lam = float(lam)
+        p.eps = float(eps)
+        p.precision = _lib.FP64 if precision == "fp64" else _lib.MIXED
+        if dim == 3:
+            p.n_r, p.n_theta, p.n_phi = (int(v) for v in nodes)
+        else:
+            p.n_r, p.n_phi = int(nodes[0]), int(nodes[-1])
+            p.n_theta = 1
+        p.theta_rule = int(rule)
+        p.kmax = float(kmax)
+        p.device = dev
+        p.stream = ctypes.c_void_p(st.cuda_stream)
+        p.flags = 0
+        self._params = p
+        self.n = tuple(int(v) for v in n)
+        self.dim = dim
+        self.device = torch.device("cuda", dev)
+        self.stream = st
+        self.dtype = torch.float64 if p.precision == _lib.FP64 else torch.float32
+        self.lam = float(lam)
+        self.H = math.prod(float(b) / int(m) for b, m in zip(box, n))
+        h = ctypes.c_void_p()
+        check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+        info = _lib.Info()
+        info.struct_size = ctypes.sizeof(_lib.Info)
+        check(lib.jgb_plan_info(self._h, ctypes.byref(info)))
+        self.info = {f: (list(getattr(info, f)) if f in ("n", "nf") else getattr(info, f))
+                     for f, _ in _lib.Info._fields_ if f != "struct_size"}
+
+    # ------------------------------------------------------------ checks
+    def _check_grid(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != self.dtype \
+                or tuple(t.shape) != self.n or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s tensor of shape %s on %s"
+                             % (name, self.dtype, self.n, self.device))
+
+    # ------------------------------------------------------------ calls
+    def potential(self, rho, out=None, energy=True):
+        """u = U*rho on the grid and E = (lambda/2) H sum rho u (0-d float64 tensor or None)."""
+        self._check_grid(rho, "rho")
+        u = torch.empty_like(rho) if out is None else out
+        E = torch.empty((), dtype=torch.float64, device=self.device) if energy else None
+        check(lib.jgb_potential(self._h, _ptr(rho), _ptr(u), _ptr(E) if energy else None))
+        return u, E
+
+    def energy(self, rho, out=None):
+        self._check_grid(rho, "rho")
+        E = torch.empty((), dtype=torch.float64, device=self.device) if out is None else out
+        check(lib.jgb_energy(self._h, _ptr(rho), _ptr(E)))
+        return E
+
+    def backward(self, grad_u, out=None):
+        """Vector-Jacobian product of potential() with respect to rho."""
+        self._check_grid(grad_u, "grad_u")
+        g = torch.empty_like(grad_u) if out is None else out
+        check(lib.jgb_potential_backward(self._h, _ptr(grad_u), _ptr(g)))
+        return g
+
+    def transform(self, rho):
+        """rho^ at the half node set (phi index < n_phi/2) in natural order."""
+        self._check_grid(rho, "rho")
+        cdt = torch.complex128 if self.dtype == torch.float64 else torch.complex64
+        out = torch.empty(self.info["n_half"], dtype=cdt, device=self.device)
+        check(lib.jgb_transform(self._h, _ptr(rho), _ptr(out)))
+        return out
+
+    def nodes(self):
+        """(k (M, d), W (M,), c (M,)) of the plan's Fourier quadrature, float64."""
+        M = self.info["n_nodes"]
+        k = torch.empty((M, self.dim), dtype=torch.float64, device=self.device)
+        W = torch.empty(M, dtype=torch.float64, device=self.device)
+        c = torch.empty(M, dtype=torch.float64, device=self.device)
+        check(lib.jgb_nodes(self._h, _ptr(k), _ptr(W), _ptr(c)))
+        return k, W, c
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.jgb_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,216 @@
+// extern "C" entry points declared in include/jgb.h.  Each call checks its
+// arguments, makes the plan's device current, enqueues kernels on the plan's
+// stream and converts every failure into a status code and a thread-local
+// message.  Nothing is thrown across the ABI.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.h"
+
+namespace jgb {
+
+Status validate(const jgb_params* p);
+Status build_plan(Plan& pl, const jgb_params* p);
+void free_plan(Plan& pl);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* get_error() { return g_last_error.c_str(); }
+
+}  // namespace jgb
+
+using jgb::Plan;
+
+struct jgb_plan_s {
+  Plan pl;
+};
+
+namespace {
+
+jgb_status report(jgb_status code, const std::string& msg) {
+  if (code != JGB_OK) jgb::set_error(msg);
+  return code;
+}
+
+jgb_status from_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return JGB_OK;
+  return report(JGB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + nb && y < x + na;
+}
+
+size_t grid_bytes(const Plan& pl) {
+  return (size_t)pl.n[0] * pl.n[1] * pl.n[2] * pl.real_bytes;
+}
+
+template <typename T>
+jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy) {
+  hipError_t e;
+  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
+  if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_POTENTIAL, nullptr, pl.stream)) != hipSuccess)
+    return from_hip(e, "interpolation");
+  if ((e = jgb::launch_spread<T>(pl, pl.stream)) != hipSuccess) return from_hip(e, "spreading");
+  if ((e = jgb::launch_fft_inverse<T>(pl, (T*)u, energy ? (const T*)rho : nullptr, pl.stream)) != hipSuccess)
+    return from_hip(e, "inverse FFT");
+  if (energy) {
+    double scale = 0.5 * pl.p.lambda * pl.H;
+    if ((e = jgb::launch_energy_finalize(pl.d_eparts, jgb::fft_inverse_z_blocks(pl), scale, energy, pl.stream)) !=
+        hipSuccess)
+      return from_hip(e, "energy");
+  }
+  return JGB_OK;
+}
+
+template <typename T>
+jgb_status run_energy(Plan& pl, const void* rho, double* energy) {
+  hipError_t e;
+  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
+  if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_ENERGY, nullptr, pl.stream)) != hipSuccess)
+    return from_hip(e, "interpolation");
+  int nb = jgb::interp_blocks(pl, jgb::kInterpNodesPerWave);
+  if ((e = jgb::launch_energy_finalize(pl.d_eparts, nb, 0.5 * pl.p.lambda, energy, pl.stream)) != hipSuccess)
+    return from_hip(e, "energy");
+  return JGB_OK;
+}
+
+template <typename T>
+jgb_status run_transform(Plan& pl, const void* rho, void* out) {
+  hipError_t e;
+  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
+  if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_TRANSFORM, out, pl.stream)) != hipSuccess)
+    return from_hip(e, "interpolation");
+  return JGB_OK;
+}
+
+jgb_status check_plan(jgb_plan_t plan) {
+  if (!plan) return report(JGB_ERR_INVALID_ARG, "plan is NULL");
+  hipError_t e = hipSetDevice(plan->pl.device);
+  if (e != hipSuccess) return from_hip(e, "hipSetDevice");
+  return JGB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+jgb_status jgb_plan(const jgb_params* params, jgb_plan_t* out) {
+  jgb::set_error("");
+  if (!out) return report(JGB_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  jgb::Status v = jgb::validate(params);
+  if (v.code != JGB_OK) return report(v.code, v.msg);
+  jgb_plan_s* h = new (std::nothrow) jgb_plan_s();
+  if (!h) return report(JGB_ERR_OUT_OF_MEMORY, "host allocation failed");
+  jgb::Status s;
+  try {
+    s = jgb::build_plan(h->pl, params);
+  } catch (const std::bad_alloc&) {
+    s = jgb::Status{JGB_ERR_OUT_OF_MEMORY, "host allocation failed"};
+  } catch (...) {
+    s = jgb::Status{JGB_ERR_DEVICE, "unexpected failure while planning"};
+  }
+  if (s.code != JGB_OK) {
+    (void)hipStreamSynchronize(h->pl.stream);
+    jgb::free_plan(h->pl);
+    delete h;
+    return report(s.code, s.msg);
+  }
+  *out = h;
+  return JGB_OK;
+}
+
+jgb_status jgb_potential(jgb_plan_t plan, const void* rho, void* u, double* energy) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!rho || !u) return report(JGB_ERR_INVALID_ARG, "rho and u must not be NULL");
+  size_t nb = grid_bytes(pl);
+  if (overlap(rho, nb, u, nb)) return report(JGB_ERR_INVALID_ARG, "rho and u overlap");
+  return pl.fp64 ? run_potential<double>(pl, rho, u, energy) : run_potential<float>(pl, rho, u, energy);
+}
+
+jgb_status jgb_energy(jgb_plan_t plan, const void* rho, double* energy) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!rho || !energy) return report(JGB_ERR_INVALID_ARG, "rho and energy must not be NULL");
+  return pl.fp64 ? run_energy<double>(pl, rho, energy) : run_energy<float>(pl, rho, energy);
+}
+
+jgb_status jgb_potential_backward(jgb_plan_t plan, const void* grad_u, void* grad_rho) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!grad_u || !grad_rho) return report(JGB_ERR_INVALID_ARG, "grad_u and grad_rho must not be NULL");
+  size_t nb = grid_bytes(pl);
+  if (overlap(grad_u, nb, grad_rho, nb)) return report(JGB_ERR_INVALID_ARG, "grad_u and grad_rho overlap");
+  // A is symmetric: the vector-Jacobian product is the same operator applied to grad_u
+  return pl.fp64 ? run_potential<double>(pl, grad_u, grad_rho, nullptr)
+                 : run_potential<float>(pl, grad_u, grad_rho, nullptr);
+}
+
+jgb_status jgb_transform(jgb_plan_t plan, const void* rho, void* rhohat) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!rho || !rhohat) return report(JGB_ERR_INVALID_ARG, "rho and rhohat must not be NULL");
+  return pl.fp64 ? run_transform<double>(pl, rho, rhohat) : run_transform<float>(pl, rho, rhohat);
+}
+
+jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* cc) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!k && !w && !cc) return JGB_OK;
+  return from_hip(jgb::launch_node_export(pl, k, w, cc, pl.stream), "node export");
+}
+
+jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info) {
+  if (!plan) return report(JGB_ERR_INVALID_ARG, "plan is NULL");
+  if (!info) return report(JGB_ERR_INVALID_ARG, "info is NULL");
+  if (info->struct_size != sizeof(jgb_info)) return report(JGB_ERR_INVALID_ARG, "info.struct_size != sizeof(jgb_info)");
+  const Plan& pl = plan->pl;
+  info->dim = pl.dim;
+  if (pl.dim == 3) {
+    for (int i = 0; i < 3; ++i) {
+      info->n[i] = pl.n[i];
+      info->nf[i] = pl.nf[i];
+    }
+  } else {
+    info->n[0] = pl.n[1];
+    info->n[1] = pl.n[2];
+    info->n[2] = 1;
+    info->nf[0] = pl.nf[1];
+    info->nf[1] = pl.nf[2];
+    info->nf[2] = 1;
+  }
+  info->n_nodes = pl.M;
+  info->n_half = pl.Mh;
+  info->width = pl.width;
+  info->beta = pl.beta;
+  info->kmax = pl.K;
+  info->workspace_bytes = (int64_t)pl.workspace_bytes;
+  return JGB_OK;
+}
+
+jgb_status jgb_destroy(jgb_plan_t plan) {
+  if (!plan) return JGB_OK;
+  (void)hipSetDevice(plan->pl.device);
+  hipError_t e = hipStreamSynchronize(plan->pl.stream);
+  jgb::free_plan(plan->pl);
+  delete plan;
+  if (e != hipSuccess) return from_hip(e, "stream synchronize");
+  return JGB_OK;
+}
+
+const char* jgb_last_error(void) { return jgb::get_error(); }
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal declarations of the jgb library: the plan object, the spreading
+// kernel, and the launchers of every device kernel.
+//
+// Internal geometry.  Every problem is handled as three axes (a0, a1, a2),
+// a2 contiguous in memory.  A 3D problem maps physical axes (x1, x2, x3) to
+// (a0, a1, a2); a 2D problem maps (x1, x2) to (a1, a2) and leaves a0 with one
+// grid point, one fine-grid point and a spreading width of one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "jgb.h"
+
+namespace jgb {
+
+// Largest spreading width supported (taps per axis).
+constexpr int kMaxWidth = 16;
+// Largest FFT line length (oversampled grid points on one axis).
+constexpr int kMaxLine = 1024;
+// Output tile of the type-1 gather kernel: TX x TY lanes, TZ points per lane.
+constexpr int kTileZ = 16;
+
+// ----------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+const char* get_error();
+
+struct Status {
+  jgb_status code = JGB_OK;
+  std::string msg;
+  static Status ok() { return {}; }
+};
+
+// ----------------------------------------------------------------- plan
+
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+struct NodeArrays {
+  // Half node set in bin-sorted order.
+  int* start[3] = {nullptr, nullptr, nullptr};  // first tap per axis, wrapped into [0, nf)
+  void* frac[3] = {nullptr, nullptr, nullptr};  // s - start in fine cells, T
+  double* coef = nullptr;                      // 2 c_j (pair k, -k folded in)
+  int* perm = nullptr;                         // sorted position -> natural half index
+  void* uhat = nullptr;                        // c_j rho^_j, complex T
+  void* wts = nullptr;                         // per node 3 x width kernel values, T
+};
+
+struct WorkItem {
+  int tile;    // linear tile index (t0 * nt1 + t1) * nt2 + t2
+  int vbegin;  // range of the tile's candidate-node list handled by this item
+  int vend;
+  int slot;    // -1: write the tile to the grid; >= 0: write partial slot
+};
+
+struct Plan {
+  jgb_params p{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int dim = 3;
+  bool fp64 = true;
+  size_t real_bytes = 8;
+
+  int n[3] = {1, 1, 1};    // grid points per internal axis
+  int nf[3] = {1, 1, 1};   // oversampled grid per internal axis
+  int w[3] = {1, 1, 1};    // taps per internal axis
+  double h[3] = {1, 1, 1}; // physical spacing per internal axis (1 for the unit axis)
+  double box[3] = {1, 1, 1};
+  double H = 1.0;          // cell volume prod h_j over physical axes
+  double K = 0.0;          // radius of the Fourier ball
+  int width = 0;
+  double beta = 0.0;
+  int64_t M = 0, Mh = 0;
+  int n_r = 0, n_theta = 1, n_phi = 0;
+
+  // 1D quadrature rules on the device (float64)
+  double* d_gl_r = nullptr;   // radial GL nodes s and weights on [-1,1]: 2*n_r
+  double* d_gl_t = nullptr;   // theta GL nodes and weights: 2*n_theta
+
+  NodeArrays nodes;
+
+  // bins == output tiles of the gather
+  int T[3] = {1, 1, 1};      // tile / bin extent per axis
+  int nt[3] = {1, 1, 1};     // tiles per axis
+  int ntiles = 0;
+  int* d_bin_start = nullptr;  // ntiles + 1 offsets into the sorted node list
+  int* d_cand[3] = {nullptr, nullptr, nullptr};     // candidate bins per axis, flattened
+  int* d_cand_off[3] = {nullptr, nullptr, nullptr}; // nt[a] + 1 offsets
+  WorkItem* d_items = nullptr;
+  int nitems = 0;
+  int nslots = 0;
+  int* d_multi = nullptr;      // per multi-chunk tile: tile index, first slot, slot count (3 ints)
+  int nmulti = 0;
+  void* d_partials = nullptr;  // nslots tiles of complex T
+
+  // FFT tables
+  void* d_tw[3] = {nullptr, nullptr, nullptr};      // exp(-2 pi i t / nf) for t < nf, complex T
+  double* d_deconv[3] = {nullptr, nullptr, nullptr};// 1 / phi^(m) for m in [-n/2, n/2)
+
+  // grids
+  void* d_F = nullptr;  // nf0*nf1*nf2 complex T
+  void* d_G = nullptr;  // same size
+  double* d_eparts = nullptr;  // energy partials
+  int neparts = 0;
+
+  size_t workspace_bytes = 0;
+  std::vector<void*> allocations;
+};
+
+// ----------------------------------------------------------------- kernel shape
+
+// Exponential of semicircle, phi(x) = exp(beta (sqrt(1 - (2x/w)^2) - 1)) for
+// |x| <= w/2: the spreading kernel (a substitute for the Gaussian of the
+// Section 2 NUFFT, chosen for its smaller width at equal accuracy).
+template <typename T>
+__host__ __device__ inline T es_kernel(T x, T two_over_w, T beta) {
+  T z = x * two_over_w;
+  T q = T(1) - z * z;
+  if (q <= T(0)) return T(0);
+  return exp(beta * (sqrt(q) - T(1)));
+}
+
+// ----------------------------------------------------------------- launchers
+
+hipError_t launch_gl_roots(int n, double* out, hipStream_t s);
+hipError_t launch_node_keys(const Plan& pl, int* keys, hipStream_t s);
+hipError_t launch_node_setup(const Plan& pl, const int* perm_dev, hipStream_t s);
+hipError_t launch_node_export(const Plan& pl, double* k, double* w, double* c, hipStream_t s);
+
+// mode of the interpolation pass
+enum InterpMode { INTERP_POTENTIAL = 0, INTERP_ENERGY = 1, INTERP_TRANSFORM = 2 };
+
+template <typename T>
+hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s);
+template <typename T>
+hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hipStream_t s);
+template <typename T>
+hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t s);
+template <typename T>
+hipError_t launch_spread(const Plan& pl, hipStream_t s);
+int fft_inverse_z_blocks(const Plan& pl);
+int interp_blocks(const Plan& pl, int nodes_per_wave);
+constexpr int kInterpNodesPerWave = 8;
+hipError_t launch_energy_finalize(const double* parts, int n, double scale, double* out, hipStream_t s);
+
+}  // namespace jgb

@@ -1,0 +1,509 @@
+// Oversampled-grid FFTs of the two NUFFTs (Section 2, eqs. 2.5-2.6 and the
+// deconvolution step; the type-2 transform runs the type-1 steps in reverse).
+//
+// Each 3D FFT is three passes of batched 1D transforms, one per axis.  A pass
+// stages LB lines of length L in LDS, runs a Stockham autosort FFT with radices
+// 2, 3, 4, 5, 8 (twiddles from a float64 table rounded to the working type),
+// and writes the lines back.  Zero padding is never stored: forward passes
+// place the N nonzero inputs of a line at fine indices (m mod L),
+// m in [-N/2, N/2), and zero the rest in LDS; inverse passes write only those N
+// outputs (the crop to the physical grid).
+//
+//   forward (type-2 front, sign -1):
+//     Z: rho (N0 N1 N2 reals) x H/(phi^0 phi^1 phi^2)  -> A1 [N0][N1][nf2]
+//     Y: A1 -> A2 [N0][nf1][nf2]
+//     X: A2 -> F  [nf0][nf1][nf2]
+//   inverse (type-1 back, sign +1):
+//     X: G  -> B2 [N0][nf1][nf2]
+//     Y: B2 -> B1 [N0][N1][nf2]
+//     Z: B1 -> u = Re(.) / (phi^0 phi^1 phi^2), and partial sums of rho u
+#include <cmath>
+
+#include "common.h"
+
+namespace jgb {
+
+namespace {
+
+template <typename T>
+struct C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ inline C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ inline C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ inline C2<T> cmul(C2<T> a, C2<T> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// multiply by i * s (s = +-1)
+template <typename T>
+__device__ inline C2<T> cmul_is(C2<T> a, T s) { return {-s * a.y, s * a.x}; }
+template <typename T>
+__device__ inline C2<T> cscale(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// In-register DFTs of small radix, y_k = sum_n x_n exp(s 2 pi i n k / R).
+template <typename T>
+__device__ inline void dft2(C2<T>* v, T) {
+  C2<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename T>
+__device__ inline void dft4(C2<T>* v, T s) {
+  C2<T> a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+  C2<T> c = cadd(v[1], v[3]), d = csub(v[1], v[3]);
+  C2<T> isd = cmul_is(d, s);
+  v[0] = cadd(a, c);
+  v[2] = csub(a, c);
+  v[1] = cadd(b, isd);
+  v[3] = csub(b, isd);
+}
+
+template <typename T>
+__device__ inline void dft3(C2<T>* v, T s) {
+  const T h = T(0.86602540378443864676);  // sin(2 pi / 3)
+  C2<T> t = cadd(v[1], v[2]);
+  C2<T> m = {v[0].x - T(0.5) * t.x, v[0].y - T(0.5) * t.y};
+  C2<T> d = cmul_is(csub(v[1], v[2]), s * h);
+  v[0] = cadd(v[0], t);
+  v[1] = cadd(m, d);
+  v[2] = csub(m, d);
+}
+
+template <typename T>
+__device__ inline void dft5(C2<T>* v, T s) {
+  const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
+  const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
+  C2<T> a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  C2<T> a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  C2<T> x0 = v[0];
+  C2<T> r1 = {x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
+  C2<T> r2 = {x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
+  C2<T> q1 = {s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y};
+  C2<T> q2 = {s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y};
+  C2<T> iq1 = cmul_is(q1, s), iq2 = cmul_is(q2, s);
+  v[0] = cadd(x0, cadd(a1, a2));
+  v[1] = cadd(r1, iq1);
+  v[4] = csub(r1, iq1);
+  v[2] = cadd(r2, iq2);
+  v[3] = csub(r2, iq2);
+}
+
+template <typename T>
+__device__ inline void dft8(C2<T>* v, T s) {
+  const T r = T(0.70710678118654752440);
+  C2<T> e[4] = {v[0], v[2], v[4], v[6]};
+  C2<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4(e, s);
+  dft4(o, s);
+  // twiddles w^k, w = exp(s 2 pi i / 8)
+  C2<T> o1 = {r * (o[1].x - s * o[1].y), r * (o[1].y + s * o[1].x)};
+  C2<T> o2 = cmul_is(o[2], s);
+  C2<T> o3 = {r * (-o[3].x - s * o[3].y), r * (-o[3].y + s * o[3].x)};
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+template <typename T, int R>
+__device__ inline void dft(C2<T>* v, T s) {
+  if constexpr (R == 2) dft2(v, s);
+  if constexpr (R == 3) dft3(v, s);
+  if constexpr (R == 4) dft4(v, s);
+  if constexpr (R == 5) dft5(v, s);
+  if constexpr (R == 8) dft8(v, s);
+}
+
+enum PassKind { PASS_FWD_Z = 0, PASS_COMPLEX = 1, PASS_INV_Z = 2 };
+
+template <typename T>
+struct PassArgs {
+  int L;            // line length
+  int64_t nlines;
+  int LB;           // lines per block
+  int nin;          // inputs per line (L, or N when the input is zero-padded)
+  int nout;         // outputs per line (L, or N when the output is cropped)
+  int64_t ic;       // lines per outer group; line l = (outer, inner) = (l / ic, l % ic)
+  int64_t in_os, in_is, in_es;
+  int64_t out_os, out_is, out_es;
+  int lines_fastest;  // global access order: 1 -> consecutive threads on consecutive lines
+  T sign;
+  int nrad;
+  int rad[12];
+  const C2<T>* tw;  // exp(-2 pi i t / L), t < L
+  const void* in;
+  void* out;
+  // forward Z: deconvolution and cell volume; inverse Z: deconvolution and energy
+  const double* dec0;
+  const double* dec1;
+  const double* dec2;
+  double scale;
+  int n1, n2;         // physical grid sizes of axes 1 and 2 (Z passes)
+  const T* rho;       // inverse Z: density for the energy partial (nullable)
+  double* eparts;     // inverse Z: per-block partials of sum rho u
+};
+
+// Position on the fine grid of physical index i of a line of N: (i - N/2) mod L.
+__device__ inline int fine_pos(int i, int N, int L) {
+  int m = i - N / 2;
+  return m < 0 ? m + L : m;
+}
+
+template <typename T, int R, int MAXV>
+__device__ inline void stage(C2<T>* lds, int ldl, int L, int LB, int Ns, const C2<T>* tw, T sign) {
+  const int nbf = L / R;           // butterflies per line
+  const int nb = LB * nbf;         // butterflies in the block
+  constexpr int MAXB = (MAXV + R - 1) / R;   // butterflies per thread at most
+  C2<T> v[MAXB][R];
+  int dst[MAXB];
+  const int stride_tw = L / (Ns * R);
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    int b = threadIdx.x + i * blockDim.x;
+    if (b < nb) {
+      int l = b % LB;
+      int j = b / LB;
+      int k = j % Ns;
+      C2<T>* row = lds + l * ldl;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = row[j + r * nbf];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C2<T> w = tw[(r * k * stride_tw) % L];
+          w.y *= -sign;  // table holds exp(-2 pi i t/L); sign +1 needs the conjugate
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+      dft<T, R>(v[i], sign);
+      dst[i] = l * ldl + (j / Ns) * Ns * R + k;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    int b = threadIdx.x + i * blockDim.x;
+    if (b < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[dst[i] + r * Ns] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int KIND, int MAXV>
+__global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int L = a.L;
+  const int ldl = L + 1;
+  const int LB = a.LB;
+  const int64_t line0 = (int64_t)blockIdx.x * LB;
+
+  // zero the padding region of every line when the input is padded
+  if (a.nin < L) {
+    const int N = a.nin;
+    const int nz = L - N;  // fine positions [N - N/2, L - N/2) stay zero
+    for (int idx = threadIdx.x; idx < LB * nz; idx += blockDim.x) {
+      int l = idx / nz, e = idx % nz;
+      lds[l * ldl + (N - N / 2) + e] = C2<T>{T(0), T(0)};
+    }
+  }
+
+  // load
+  const int total_in = LB * a.nin;
+  for (int idx = threadIdx.x; idx < total_in; idx += blockDim.x) {
+    int l, e;
+    if (a.lines_fastest) {
+      l = idx % LB;
+      e = idx / LB;
+    } else {
+      l = idx / a.nin;
+      e = idx % a.nin;
+    }
+    int64_t line = line0 + l;
+    int pos = (a.nin < L) ? fine_pos(e, a.nin, L) : e;
+    C2<T> v = {T(0), T(0)};
+    if (line < a.nlines) {
+      int64_t base = (line / a.ic) * a.in_os + (line % a.ic) * a.in_is + (int64_t)e * a.in_es;
+      if constexpr (KIND == PASS_FWD_Z) {
+        // line = i0 * n1 + i1; element e = i2
+        int64_t i0 = line / a.n1, i1 = line % a.n1;
+        double d = a.scale * a.dec0[i0] * a.dec1[i1] * a.dec2[e];
+        v.x = (T)((double)((const T*)a.in)[base] * d);
+      } else {
+        v = ((const C2<T>*)a.in)[base];
+      }
+    }
+    lds[l * ldl + pos] = v;
+  }
+  __syncthreads();
+
+  // FFT stages
+  int Ns = 1;
+  for (int st = 0; st < a.nrad; ++st) {
+    int R = a.rad[st];
+    switch (R) {
+      case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
+      case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
+      case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
+      case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
+      default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
+    }
+    Ns *= R;
+  }
+
+  // store
+  double eacc = 0.0;
+  const int total_out = LB * a.nout;
+  for (int idx = threadIdx.x; idx < total_out; idx += blockDim.x) {
+    int l, e;
+    if (a.lines_fastest) {
+      l = idx % LB;
+      e = idx / LB;
+    } else {
+      l = idx / a.nout;
+      e = idx % a.nout;
+    }
+    int64_t line = line0 + l;
+    if (line >= a.nlines) continue;
+    int pos = (a.nout < L) ? fine_pos(e, a.nout, L) : e;
+    C2<T> v = lds[l * ldl + pos];
+    int64_t base = (line / a.ic) * a.out_os + (line % a.ic) * a.out_is + (int64_t)e * a.out_es;
+    if constexpr (KIND == PASS_INV_Z) {
+      int64_t i0 = line / a.n1, i1 = line % a.n1;
+      double u = (double)v.x * (a.dec0[i0] * a.dec1[i1] * a.dec2[e]);
+      ((T*)a.out)[base] = (T)u;
+      if (a.rho) eacc += (double)a.rho[base] * u;
+    } else {
+      ((C2<T>*)a.out)[base] = v;
+    }
+  }
+
+  if constexpr (KIND == PASS_INV_Z) {
+    if (a.eparts) {
+      // deterministic block sum: wave shuffle, then waves in order
+      for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
+      __shared__ double wsum[4];
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = eacc;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i];
+        a.eparts[blockIdx.x] = s;
+      }
+    }
+  }
+}
+
+void factor(int L, int* rad, int& nrad) {
+  nrad = 0;
+  int m = L;
+  while (m % 8 == 0) {
+    rad[nrad++] = 8;
+    m /= 8;
+  }
+  while (m % 4 == 0) {
+    rad[nrad++] = 4;
+    m /= 4;
+  }
+  while (m % 2 == 0) {
+    rad[nrad++] = 2;
+    m /= 2;
+  }
+  while (m % 3 == 0) {
+    rad[nrad++] = 3;
+    m /= 3;
+  }
+  while (m % 5 == 0) {
+    rad[nrad++] = 5;
+    m /= 5;
+  }
+}
+
+template <typename T>
+int lines_per_block(int L) {
+  int cap = (sizeof(T) == 8) ? 4096 : 8192;  // complex elements staged per block
+  int lb = cap / L;
+  if (lb > 16) lb = 16;
+  if (lb < 1) lb = 1;
+  return lb;
+}
+
+template <typename T, int KIND>
+hipError_t run_pass(PassArgs<T> a, hipStream_t s) {
+  factor(a.L, a.rad, a.nrad);
+  a.LB = lines_per_block<T>(a.L);
+  unsigned blocks = (unsigned)((a.nlines + a.LB - 1) / a.LB);
+  size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
+  constexpr int MAXV = (sizeof(T) == 8 ? 4096 : 8192) / 256;
+  hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV>), dim3(blocks), dim3(256), smem, s, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+PassArgs<T> base_args(const Plan& pl, int axis, T sign) {
+  PassArgs<T> a{};
+  a.L = pl.nf[axis];
+  a.sign = sign;
+  a.tw = (const C2<T>*)pl.d_tw[axis];
+  a.n1 = pl.n[1];
+  a.n2 = pl.n[2];
+  return a;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
+  const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
+  const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
+  const bool has_x = f0 > 1;
+  void* A1 = has_x ? pl.d_F : pl.d_G;
+  void* A2 = has_x ? pl.d_G : pl.d_F;
+  hipError_t e;
+  {  // Z: rho -> A1 [n0][n1][f2]
+    PassArgs<T> a = base_args<T>(pl, 2, T(-1));
+    a.nlines = n0 * n1;
+    a.nin = (int)n2;
+    a.nout = (int)f2;
+    a.ic = 1;
+    a.in_os = n2;
+    a.in_is = 0;
+    a.in_es = 1;
+    a.out_os = f2;
+    a.out_is = 0;
+    a.out_es = 1;
+    a.lines_fastest = 0;
+    a.in = rho;
+    a.out = A1;
+    a.dec0 = pl.d_deconv[0];
+    a.dec1 = pl.d_deconv[1];
+    a.dec2 = pl.d_deconv[2];
+    a.scale = pl.H;
+    if ((e = run_pass<T, PASS_FWD_Z>(a, s)) != hipSuccess) return e;
+  }
+  {  // Y: A1 -> A2 [n0][f1][f2]
+    PassArgs<T> a = base_args<T>(pl, 1, T(-1));
+    a.nlines = n0 * f2;
+    a.nin = (int)n1;
+    a.nout = (int)f1;
+    a.ic = f2;
+    a.in_os = n1 * f2;
+    a.in_is = 1;
+    a.in_es = f2;
+    a.out_os = f1 * f2;
+    a.out_is = 1;
+    a.out_es = f2;
+    a.lines_fastest = 1;
+    a.in = A1;
+    a.out = A2;
+    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+  }
+  if (has_x) {  // X: A2 -> F [f0][f1][f2]
+    PassArgs<T> a = base_args<T>(pl, 0, T(-1));
+    a.nlines = f1 * f2;
+    a.nin = (int)n0;
+    a.nout = (int)f0;
+    a.ic = f1 * f2;
+    a.in_os = 0;
+    a.in_is = 1;
+    a.in_es = f1 * f2;
+    a.out_os = 0;
+    a.out_is = 1;
+    a.out_es = f1 * f2;
+    a.lines_fastest = 1;
+    a.in = A2;
+    a.out = pl.d_F;
+    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hipStream_t s) {
+  const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
+  const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
+  const bool has_x = f0 > 1;
+  void* B2 = has_x ? pl.d_F : pl.d_G;
+  void* B1 = has_x ? pl.d_G : pl.d_F;
+  hipError_t e;
+  if (has_x) {  // X: G -> B2 [n0][f1][f2]
+    PassArgs<T> a = base_args<T>(pl, 0, T(1));
+    a.nlines = f1 * f2;
+    a.nin = (int)f0;
+    a.nout = (int)n0;
+    a.ic = f1 * f2;
+    a.in_os = 0;
+    a.in_is = 1;
+    a.in_es = f1 * f2;
+    a.out_os = 0;
+    a.out_is = 1;
+    a.out_es = f1 * f2;
+    a.lines_fastest = 1;
+    a.in = pl.d_G;
+    a.out = B2;
+    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+  }
+  {  // Y: B2 -> B1 [n0][n1][f2]
+    PassArgs<T> a = base_args<T>(pl, 1, T(1));
+    a.nlines = n0 * f2;
+    a.nin = (int)f1;
+    a.nout = (int)n1;
+    a.ic = f2;
+    a.in_os = f1 * f2;
+    a.in_is = 1;
+    a.in_es = f2;
+    a.out_os = n1 * f2;
+    a.out_is = 1;
+    a.out_es = f2;
+    a.lines_fastest = 1;
+    a.in = B2;
+    a.out = B1;
+    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+  }
+  {  // Z: B1 -> u [n0][n1][n2], real part, deconvolution, energy partials
+    PassArgs<T> a = base_args<T>(pl, 2, T(1));
+    a.nlines = n0 * n1;
+    a.nin = (int)f2;
+    a.nout = (int)n2;
+    a.ic = 1;
+    a.in_os = f2;
+    a.in_is = 0;
+    a.in_es = 1;
+    a.out_os = n2;
+    a.out_is = 0;
+    a.out_es = 1;
+    a.lines_fastest = 0;
+    a.in = B1;
+    a.out = u;
+    a.dec0 = pl.d_deconv[0];
+    a.dec1 = pl.d_deconv[1];
+    a.dec2 = pl.d_deconv[2];
+    a.rho = rho_for_energy;
+    a.eparts = rho_for_energy ? pl.d_eparts : nullptr;
+    if ((e = run_pass<T, PASS_INV_Z>(a, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int fft_inverse_z_blocks(const Plan& pl) {
+  int lb = pl.fp64 ? lines_per_block<double>(pl.nf[2]) : lines_per_block<float>(pl.nf[2]);
+  int64_t nl = (int64_t)pl.n[0] * pl.n[1];
+  return (int)((nl + lb - 1) / lb);
+}
+
+template hipError_t launch_fft_forward<double>(const Plan&, const double*, hipStream_t);
+template hipError_t launch_fft_forward<float>(const Plan&, const float*, hipStream_t);
+template hipError_t launch_fft_inverse<double>(const Plan&, double*, const double*, hipStream_t);
+template hipError_t launch_fft_inverse<float>(const Plan&, float*, const float*, hipStream_t);
+
+}  // namespace jgb

@@ -1,0 +1,377 @@
+// Plan construction: parameter checks, NUFFT accuracy parameters, device node
+// generation and bin sort, FFT and deconvolution tables, gather work lists and
+// workspace.  Everything here runs once per plan; the compute calls only read
+// what the plan holds.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "common.h"
+
+namespace jgb {
+
+namespace {
+
+constexpr int kChunk = 1024;  // candidate nodes per gather work item at most
+
+bool is_235(int64_t n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+Status fail(jgb_status c, const std::string& m) { return Status{c, m}; }
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on the
+// three-term recurrence (host copy for the deconvolution quadrature).
+void host_gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    if (2 * i + 1 == n) z = 0.0;
+    double p1 = 1, dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0;
+      p1 = z;
+      double d0 = 0.0, d1 = 1.0;
+      for (int k = 1; k < n; ++k) {
+        double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+        double d2 = d0 + (2.0 * k + 1.0) * p1;
+        p0 = p1;
+        p1 = p2;
+        d0 = d1;
+        d1 = d2;
+      }
+      dp = d1;
+      if (2 * i + 1 == n) break;
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    x[n - 1 - i] = -z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Fourier transform of the spreading kernel, phi^(xi) = int phi(x) cos(xi x) dx
+// over |x| <= w/2, by Gauss-Legendre quadrature in float64.
+std::vector<double> kernel_ft(int w, double beta, const std::vector<double>& xi) {
+  std::vector<double> z, om;
+  int nq = std::max(200, 8 * w + 40);
+  host_gauss_legendre(nq, z, om);
+  std::vector<double> out(xi.size(), 0.0);
+  double half = 0.5 * w;
+  for (size_t k = 0; k < xi.size(); ++k) {
+    double s = 0.0;
+    for (int q = 0; q < nq; ++q) {
+      double phi = std::exp(beta * (std::sqrt((1.0 - z[q]) * (1.0 + z[q])) - 1.0));
+      s += om[q] * phi * std::cos(xi[k] * half * z[q]);
+    }
+    out[k] = half * s;
+  }
+  return out;
+}
+
+template <typename Tp>
+Status dev_alloc(Plan& pl, Tp** ptr, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(JGB_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  pl.allocations.push_back(p);
+  pl.workspace_bytes += bytes;
+  *ptr = (Tp*)p;
+  return Status::ok();
+}
+
+Status upload(Plan& pl, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return Status::ok();
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, pl.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl.stream);
+  if (e != hipSuccess) return fail(JGB_ERR_DEVICE, std::string("upload: ") + hipGetErrorString(e));
+  return Status::ok();
+}
+
+#define TRY(x)                       \
+  do {                               \
+    Status st_ = (x);                \
+    if (st_.code != JGB_OK) return st_; \
+  } while (0)
+
+#define TRY_HIP(x, what)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) return fail(JGB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+Status validate(const jgb_params* p) {
+  if (!p) return fail(JGB_ERR_INVALID_ARG, "params is NULL");
+  if (p->struct_size != sizeof(jgb_params)) return fail(JGB_ERR_INVALID_ARG, "params.struct_size != sizeof(jgb_params)");
+  if (p->dim != 2 && p->dim != 3) return fail(JGB_ERR_INVALID_ARG, "dim must be 2 or 3");
+  for (int j = 0; j < p->dim; ++j) {
+    int64_t n = p->n[j];
+    if (n < 8 || n > 512 || n % 2) return fail(JGB_ERR_INVALID_ARG, "n[j] must be even and in [8, 512]");
+    if (!is_235(2 * n)) return fail(JGB_ERR_UNSUPPORTED, "2 n[j] must factor into 2, 3 and 5");
+    if (!(std::isfinite(p->box[j]) && p->box[j] > 0)) return fail(JGB_ERR_INVALID_ARG, "box[j] must be finite and > 0");
+  }
+  if (p->kernel == JGB_COULOMB_2D) {
+    if (p->dim != 2) return fail(JGB_ERR_INVALID_ARG, "JGB_COULOMB_2D needs dim == 2");
+  } else if (p->kernel == JGB_COULOMB_3D || p->kernel == JGB_DIPOLE_3D) {
+    if (p->dim != 3) return fail(JGB_ERR_INVALID_ARG, "3D kernels need dim == 3");
+  } else {
+    return fail(JGB_ERR_INVALID_ARG, "unknown kernel");
+  }
+  if (p->kernel == JGB_DIPOLE_3D) {
+    double nn = 0;
+    for (int i = 0; i < 3; ++i) {
+      if (!std::isfinite(p->dipole_axis[i])) return fail(JGB_ERR_INVALID_ARG, "dipole_axis not finite");
+      nn += p->dipole_axis[i] * p->dipole_axis[i];
+    }
+    if (std::fabs(std::sqrt(nn) - 1.0) > 1e-12) return fail(JGB_ERR_INVALID_ARG, "dipole_axis must be a unit vector");
+  }
+  if (!std::isfinite(p->lambda)) return fail(JGB_ERR_INVALID_ARG, "lambda must be finite");
+  if (!(p->eps >= 1e-13 && p->eps <= 1e-2)) return fail(JGB_ERR_INVALID_ARG, "eps must be in [1e-13, 1e-2]");
+  if (p->precision != JGB_FP64 && p->precision != JGB_MIXED) return fail(JGB_ERR_INVALID_ARG, "unknown precision");
+  if (p->precision == JGB_MIXED && p->eps < 1e-6) return fail(JGB_ERR_INVALID_ARG, "JGB_MIXED needs eps >= 1e-6");
+  if (p->n_r < 1) return fail(JGB_ERR_INVALID_ARG, "n_r must be >= 1");
+  if (p->dim == 3 && p->n_theta < 1) return fail(JGB_ERR_INVALID_ARG, "n_theta must be >= 1");
+  if (p->n_phi < 2 || p->n_phi % 2) return fail(JGB_ERR_INVALID_ARG, "n_phi must be even and >= 2");
+  if (p->theta_rule != JGB_THETA_GL && p->theta_rule != JGB_COSTHETA_GL) return fail(JGB_ERR_INVALID_ARG, "unknown theta_rule");
+  double hmax = 0;
+  for (int j = 0; j < p->dim; ++j) hmax = std::max(hmax, p->box[j] / (double)p->n[j]);
+  double kn = M_PI / hmax;
+  if (!(std::isfinite(p->kmax) && p->kmax >= 0)) return fail(JGB_ERR_INVALID_ARG, "kmax must be finite and >= 0");
+  if (p->kmax > kn * (1 + 1e-12)) return fail(JGB_ERR_INVALID_ARG, "kmax must not exceed pi / max_j h_j");
+  if (p->flags != 0) return fail(JGB_ERR_INVALID_ARG, "flags must be 0");
+  int64_t M = (int64_t)p->n_r * p->n_phi * (p->dim == 3 ? p->n_theta : 1);
+  if (M / 2 > (int64_t)std::numeric_limits<int>::max() / 2) return fail(JGB_ERR_UNSUPPORTED, "too many nodes");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(JGB_ERR_DEVICE, "no HIP device");
+  }
+  if (p->device < 0 || p->device >= ndev) return fail(JGB_ERR_INVALID_ARG, "device ordinal out of range");
+  return Status::ok();
+}
+
+// Spreading width and shape for a requested accuracy at oversampling 2: the
+// kernel's aliasing error falls by about a decade per extra tap.
+void accuracy_parameters(double eps, int& w, double& beta) {
+  w = (int)std::ceil(std::log10(10.0 / eps)) + 1;
+  w = std::max(2, std::min(kMaxWidth, w));
+  beta = 2.30 * w;
+}
+
+Status build_plan(Plan& pl, const jgb_params* p) {
+  pl.p = *p;
+  pl.device = p->device;
+  pl.stream = (hipStream_t)p->stream;
+  pl.dim = p->dim;
+  pl.fp64 = p->precision == JGB_FP64;
+  pl.real_bytes = pl.fp64 ? 8 : 4;
+  TRY_HIP(hipSetDevice(pl.device), "hipSetDevice");
+
+  // internal axes
+  if (pl.dim == 3) {
+    for (int i = 0; i < 3; ++i) {
+      pl.n[i] = (int)p->n[i];
+      pl.box[i] = p->box[i];
+    }
+  } else {
+    pl.n[0] = 1;
+    pl.box[0] = 1.0;
+    pl.n[1] = (int)p->n[0];
+    pl.n[2] = (int)p->n[1];
+    pl.box[1] = p->box[0];
+    pl.box[2] = p->box[1];
+  }
+  double hmax = 0;
+  pl.H = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    if (pl.n[i] == 1) {
+      pl.nf[i] = 1;
+      pl.h[i] = 1.0;
+      continue;
+    }
+    pl.nf[i] = 2 * pl.n[i];
+    pl.h[i] = pl.box[i] / pl.n[i];
+    pl.H *= pl.h[i];
+    hmax = std::max(hmax, pl.h[i]);
+  }
+  pl.K = (p->kmax > 0) ? p->kmax : M_PI / hmax;
+  accuracy_parameters(p->eps, pl.width, pl.beta);
+  for (int i = 0; i < 3; ++i) pl.w[i] = (pl.n[i] == 1) ? 1 : pl.width;
+  pl.n_r = p->n_r;
+  pl.n_theta = (pl.dim == 3) ? p->n_theta : 1;
+  pl.n_phi = p->n_phi;
+  pl.M = (int64_t)pl.n_r * pl.n_theta * pl.n_phi;
+  pl.Mh = pl.M / 2;
+
+  // tiles (== bins)
+  pl.T[2] = kTileZ;
+  if (pl.dim == 3) {
+    pl.T[0] = 8;
+    pl.T[1] = 8;
+  } else {
+    pl.T[0] = 1;
+    pl.T[1] = 64;
+  }
+  pl.ntiles = 1;
+  for (int i = 0; i < 3; ++i) {
+    pl.nt[i] = (pl.nf[i] + pl.T[i] - 1) / pl.T[i];
+    pl.ntiles *= pl.nt[i];
+  }
+
+  // 1D rules on the device
+  TRY(dev_alloc(pl, &pl.d_gl_r, 2 * sizeof(double) * pl.n_r));
+  TRY(dev_alloc(pl, &pl.d_gl_t, 2 * sizeof(double) * pl.n_theta));
+  TRY_HIP(launch_gl_roots(pl.n_r, pl.d_gl_r, pl.stream), "gl roots");
+  TRY_HIP(launch_gl_roots(pl.n_theta, pl.d_gl_t, pl.stream), "gl roots");
+
+  // bin keys of the half node set, stable counting sort on the host
+  const int64_t Mh = pl.Mh;
+  int* d_keys = nullptr;
+  TRY(dev_alloc(pl, &d_keys, sizeof(int) * Mh));
+  TRY_HIP(launch_node_keys(pl, d_keys, pl.stream), "node keys");
+  std::vector<int> keys(Mh);
+  TRY_HIP(hipMemcpyAsync(keys.data(), d_keys, sizeof(int) * Mh, hipMemcpyDeviceToHost, pl.stream), "keys copy");
+  TRY_HIP(hipStreamSynchronize(pl.stream), "keys sync");
+  std::vector<int> bin_start(pl.ntiles + 1, 0);
+  for (int64_t h = 0; h < Mh; ++h) bin_start[keys[h] + 1]++;
+  for (int b = 0; b < pl.ntiles; ++b) bin_start[b + 1] += bin_start[b];
+  std::vector<int> perm(Mh);
+  {
+    std::vector<int> fill(bin_start.begin(), bin_start.end() - 1);
+    for (int64_t h = 0; h < Mh; ++h) perm[fill[keys[h]]++] = (int)h;
+  }
+  TRY(dev_alloc(pl, &pl.nodes.perm, sizeof(int) * Mh));
+  TRY(upload(pl, pl.nodes.perm, perm.data(), sizeof(int) * Mh));
+  for (int i = 0; i < 3; ++i) {
+    TRY(dev_alloc(pl, &pl.nodes.start[i], sizeof(int) * Mh));
+    TRY(dev_alloc(pl, &pl.nodes.frac[i], pl.real_bytes * Mh));
+  }
+  TRY(dev_alloc(pl, &pl.nodes.coef, sizeof(double) * Mh));
+  TRY(dev_alloc(pl, &pl.nodes.uhat, 2 * pl.real_bytes * Mh));
+  TRY(dev_alloc(pl, &pl.nodes.wts, 48 * pl.real_bytes * Mh));
+  TRY_HIP(launch_node_setup(pl, pl.nodes.perm, pl.stream), "node setup");
+  TRY(dev_alloc(pl, &pl.d_bin_start, sizeof(int) * (pl.ntiles + 1)));
+  TRY(upload(pl, pl.d_bin_start, bin_start.data(), sizeof(int) * (pl.ntiles + 1)));
+
+  // candidate bins per axis: bins holding a first tap whose footprint reaches the tile
+  std::vector<int> cand[3], coff[3];
+  for (int a = 0; a < 3; ++a) {
+    const int nf = pl.nf[a], T = pl.T[a], nt = pl.nt[a], w = pl.w[a];
+    coff[a].push_back(0);
+    for (int t = 0; t < nt; ++t) {
+      for (int b = 0; b < nt; ++b) {
+        bool hit = false;
+        for (int x0 = b * T; x0 < std::min((b + 1) * T, nf) && !hit; ++x0)
+          for (int i = t * T; i < std::min((t + 1) * T, nf) && !hit; ++i)
+            if ((((i - x0) % nf) + nf) % nf < w) hit = true;
+        if (hit) cand[a].push_back(b);
+      }
+      coff[a].push_back((int)cand[a].size());
+    }
+    TRY(dev_alloc(pl, &pl.d_cand[a], sizeof(int) * cand[a].size()));
+    TRY(dev_alloc(pl, &pl.d_cand_off[a], sizeof(int) * coff[a].size()));
+    TRY(upload(pl, pl.d_cand[a], cand[a].data(), sizeof(int) * cand[a].size()));
+    TRY(upload(pl, pl.d_cand_off[a], coff[a].data(), sizeof(int) * coff[a].size()));
+  }
+
+  // gather work items: one per tile, more for tiles with long candidate lists
+  std::vector<WorkItem> items;
+  std::vector<int> multi;
+  int nslots = 0;
+  for (int t0 = 0; t0 < pl.nt[0]; ++t0)
+    for (int t1 = 0; t1 < pl.nt[1]; ++t1)
+      for (int t2 = 0; t2 < pl.nt[2]; ++t2) {
+        int64_t L = 0;
+        for (int c0 = coff[0][t0]; c0 < coff[0][t0 + 1]; ++c0)
+          for (int c1 = coff[1][t1]; c1 < coff[1][t1 + 1]; ++c1)
+            for (int c2 = coff[2][t2]; c2 < coff[2][t2 + 1]; ++c2) {
+              int bin = (cand[0][c0] * pl.nt[1] + cand[1][c1]) * pl.nt[2] + cand[2][c2];
+              L += bin_start[bin + 1] - bin_start[bin];
+            }
+        int tile = (t0 * pl.nt[1] + t1) * pl.nt[2] + t2;
+        if (L <= kChunk) {
+          items.push_back(WorkItem{tile, 0, (int)L, -1});
+        } else {
+          int k = (int)((L + kChunk - 1) / kChunk);
+          multi.push_back(tile);
+          multi.push_back(nslots);
+          multi.push_back(k);
+          for (int c = 0; c < k; ++c) {
+            int vb = c * kChunk;
+            int ve = (int)std::min<int64_t>(L, (int64_t)(c + 1) * kChunk);
+            items.push_back(WorkItem{tile, vb, ve, nslots + c});
+          }
+          nslots += k;
+        }
+      }
+  // longest items first so the split tiles do not form the tail
+  std::stable_sort(items.begin(), items.end(),
+                   [](const WorkItem& x, const WorkItem& y) { return (x.vend - x.vbegin) > (y.vend - y.vbegin); });
+  pl.nitems = (int)items.size();
+  pl.nslots = nslots;
+  pl.nmulti = (int)multi.size() / 3;
+  TRY(dev_alloc(pl, &pl.d_items, sizeof(WorkItem) * items.size()));
+  TRY(upload(pl, pl.d_items, items.data(), sizeof(WorkItem) * items.size()));
+  TRY(dev_alloc(pl, &pl.d_multi, sizeof(int) * multi.size()));
+  TRY(upload(pl, pl.d_multi, multi.data(), sizeof(int) * multi.size()));
+  TRY(dev_alloc(pl, &pl.d_partials, (size_t)nslots * 64 * kTileZ * 2 * pl.real_bytes));
+
+  // FFT twiddles and deconvolution factors per axis
+  for (int a = 0; a < 3; ++a) {
+    const int L = pl.nf[a];
+    std::vector<double> twd(2 * L);
+    for (int t = 0; t < L; ++t) {
+      twd[2 * t] = std::cos(2.0 * M_PI * t / L);
+      twd[2 * t + 1] = -std::sin(2.0 * M_PI * t / L);
+    }
+    if (pl.fp64) {
+      TRY(dev_alloc(pl, &pl.d_tw[a], sizeof(double) * 2 * L));
+      TRY(upload(pl, pl.d_tw[a], twd.data(), sizeof(double) * 2 * L));
+    } else {
+      std::vector<float> twf(twd.begin(), twd.end());
+      TRY(dev_alloc(pl, &pl.d_tw[a], sizeof(float) * 2 * L));
+      TRY(upload(pl, pl.d_tw[a], twf.data(), sizeof(float) * 2 * L));
+    }
+    const int N = pl.n[a];
+    std::vector<double> dec(N, 1.0);
+    if (N > 1) {
+      std::vector<double> xi(N);
+      for (int i = 0; i < N; ++i) xi[i] = 2.0 * M_PI * (i - N / 2) / (double)L;
+      std::vector<double> ph = kernel_ft(pl.w[a], pl.beta, xi);
+      for (int i = 0; i < N; ++i) dec[i] = 1.0 / ph[i];
+    }
+    TRY(dev_alloc(pl, &pl.d_deconv[a], sizeof(double) * N));
+    TRY(upload(pl, pl.d_deconv[a], dec.data(), sizeof(double) * N));
+  }
+
+  // grids and energy partials
+  size_t ngrid = (size_t)pl.nf[0] * pl.nf[1] * pl.nf[2];
+  TRY(dev_alloc(pl, &pl.d_F, ngrid * 2 * pl.real_bytes));
+  TRY(dev_alloc(pl, &pl.d_G, ngrid * 2 * pl.real_bytes));
+  pl.neparts = std::max(fft_inverse_z_blocks(pl), interp_blocks(pl, kInterpNodesPerWave));
+  pl.neparts = std::max(pl.neparts, 1);
+  TRY(dev_alloc(pl, &pl.d_eparts, sizeof(double) * pl.neparts));
+  TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");
+  TRY_HIP(hipGetLastError(), "plan kernels");
+  return Status::ok();
+}
+
+void free_plan(Plan& pl) {
+  for (void* p : pl.allocations) (void)hipFree(p);
+  pl.allocations.clear();
+}
+
+}  // namespace jgb
