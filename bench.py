@@ -1,0 +1,207 @@
+"""Throughput of the free-space dipole convolution on one MI355X.
+
+Workload: 3D dipole-dipole kernel U^ = -1 + 3 (n.k)^2/|k|^2 on a 128^3 grid over
+[-12,12)^3, rho = |psi|^2 for the anisotropic Gaussian psi with axes
+(1, 1.5, 0.7), seeded dipole axis, Fourier nodes (128, 64, 128) with the theta
+Gauss-Legendre rule (M = 1 048 576).  One step = one potential evaluation: u on
+the whole grid plus the energy E, i.e. Algorithm 1 (type-2 NUFFT, weight x
+symbol, type-1 NUFFT) and the trapezoid energy sum, inputs resident in HBM.
+
+Runs the path in float64 at eps = 1e-10 (the headline value) and in mixed
+precision at eps = 1e-5, prints one JSON line.  Per-kernel durations come from
+HIP events recorded on the plan's stream inside the timed loop.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+METRIC = "potential evals/s + ns/grid-pt at 128³: FP64 ε=1e-10 vs mixed FP32 ε=1e-5"
+
+
+def stage_work(info, prec, energy=True):
+    """Algorithmic HBM bytes and flops of one launch of each stage."""
+    n = info["n"]
+    nf = info["nf"]
+    N = n[0]
+    f = nf[0]
+    rb = 8 if prec == "fp64" else 4
+    cb = 2 * rb
+    w = info["width"]
+    Mh = info["n_half"]
+    N3, F3 = N ** 3, f ** 3
+    by = {
+        "fwd_fft_z": N3 * rb + N * N * f * cb,
+        "fwd_fft_y": N * N * f * cb + N * f * f * cb,
+        "fwd_fft_x": N * f * f * cb + F3 * cb,
+        "inv_fft_x": F3 * cb + N * f * f * cb,
+        "inv_fft_y": N * f * f * cb + N * N * f * cb,
+        "inv_fft_z": N * N * f * cb + N3 * rb + (N3 * rb if energy else 0),
+        # interp reads the grid once at best, node tables, writes uhat and kernel values
+        "interp": F3 * cb + Mh * (3 * 4 + 3 * rb + 8 + 2 * cb + 48 * rb),
+        # gather writes the grid once, reads node tables
+        "spread": F3 * cb + Mh * (3 * 4 + 2 * cb + 48 * rb),
+    }
+    # complex x real multiply-add per tap (4 flops) over w^3 taps per node
+    fl = {"interp": 4.0 * Mh * w ** 3, "spread": 4.0 * Mh * w ** 3}
+    return by, fl
+
+
+def run_gpu(prec, steps, warmup):
+    import torch
+
+    import paper_1311_4120_amd as jgb
+    import workloads as wl
+
+    p, rho = wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    t0 = time.time()
+    plan = jgb.Plan(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), eps=p.eps, precision=prec,
+                    lam=p.lam, axis=p.axis, theta_rule="theta")
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    rt = torch.tensor(rho, dtype=dt, device="cuda")
+    u = torch.empty_like(rt)
+    E = torch.empty((), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        plan.potential(rt, out=u)
+    torch.cuda.synchronize()
+    plan.timing_begin(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, E = plan.potential(rt, out=u)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stages, ncalls = plan.timing_end()
+    energy = float(E.item())
+    info = plan.info
+    plan.close()
+    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "stages_ms": stages, "calls": ncalls,
+            "plan_s": plan_s, "energy": energy, "info": info, "eps": p.eps}
+
+
+def cpu_baseline(sample_nodes=32768):
+    """The oracle (direct O(N M) sums) on a bounded sample of the same workload:
+    the type-2 sum at every 32nd node and the type-1 sum from those nodes to the
+    whole grid, extrapolated linearly in the node count to a full evaluation."""
+    from threadpoolctl import threadpool_info
+
+    import oracle
+    import workloads as wl
+
+    p, rho = wl.dipole3d_128()
+    k, W = oracle.fourier_nodes(p)
+    stride = max(1, len(k) // sample_nodes)
+    idx = np.arange(0, len(k), stride)[:sample_nodes]
+    kb, Wb = k[idx], W[idx]
+    t0 = time.perf_counter()
+    rh = oracle.rho_hat(rho, p.box, kb)
+    c = oracle.coefficients(p.kernel, kb, Wb, p.axis)
+    oracle.sum_to_grid(c * rh, kb, p.n, p.box)
+    t = time.perf_counter() - t0
+    full = t * len(k) / len(idx)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": 1.0 / full, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": "type-2 sum at %d of %d nodes (every %d-th) + type-1 sum from them to all 128^3 points, "
+                      "%.1f s, extrapolated x%.1f to one full evaluation (%.0f s); O(N M) direct sums"
+                      % (len(idx), len(k), stride, t, len(k) / len(idx), full)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    res = {}
+    for prec in (["fp64", "mixed"] if args.only is None else [args.only]):
+        print("[bench] %s: plan + %d warmup + %d timed steps" % (prec, args.warmup, args.steps), file=sys.stderr,
+              flush=True)
+        res[prec] = run_gpu(prec, args.steps, args.warmup)
+        print("[bench] %s: %.4f ms/step" % (prec, res[prec]["ms_per_step"]), file=sys.stderr, flush=True)
+
+    head = "fp64" if "fp64" in res else "mixed"
+    r = res[head]
+    npts = 128 ** 3
+    by, fl = stage_work(r["info"], head)
+    st = r["stages_ms"]
+    dom = max((k for k in st if st[k] > 0), key=lambda k: st[k])
+    if dom in fl:
+        peak = FP64_PEAK_TFLOPS if head == "fp64" else FP32_PEAK_TFLOPS
+        ach = fl[dom] / (st[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None,
+                "work_per_launch": "%d half-set nodes x %d^3 taps x 4 flops" % (r["info"]["n_half"], r["info"]["width"])}
+    else:
+        ach = by[dom] / (st[dom] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": by[dom]}
+    stages = {}
+    for k, v in st.items():
+        if v <= 0:
+            continue
+        d = {"ms": v, "GB/s": by.get(k, 0) / (v * 1e-3) / 1e9 if k in by else None}
+        if k in fl:
+            d["TFLOP/s"] = fl[k] / (v * 1e-3) / 1e12
+        stages[k] = d
+    total_bytes = sum(by.values())
+    out = {
+        "metric": METRIC,
+        "value": 1e3 / r["ms_per_step"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "dipole3d_128", "kernel": "dipole3d", "grid": [128, 128, 128],
+                   "box": [-12, 12], "nodes": [128, 64, 128], "theta_rule": "theta_gl",
+                   "n_nodes": r["info"]["n_nodes"], "eps": r["eps"], "width": r["info"]["width"],
+                   "oversampled_grid": r["info"]["nf"]},
+        "ns_per_point": r["ms_per_step"] * 1e6 / npts,
+        "energy": r["energy"],
+        "plan_s": r["plan_s"],
+        "model_hbm_bytes_per_step": total_bytes,
+        "model_hbm_frac": total_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "stages": stages,
+        "roofline": roof,
+    }
+    if "mixed" in res and head == "fp64":
+        m = res["mixed"]
+        out["mixed"] = {"value": 1e3 / m["ms_per_step"], "unit": "evals/s", "ms_per_step": m["ms_per_step"],
+                        "ns_per_point": m["ms_per_step"] * 1e6 / npts, "eps": m["eps"],
+                        "width": m["info"]["width"], "energy": m["energy"],
+                        "speedup_vs_fp64": r["ms_per_step"] / m["ms_per_step"],
+                        "stages_ms": {k: v for k, v in m["stages_ms"].items() if v > 0}}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

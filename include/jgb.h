@@ -80,7 +80,7 @@ typedef struct jgb_plan_s* jgb_plan_t;
 typedef struct {
   uint32_t struct_size;    /* = sizeof(jgb_params); guards against ABI drift */
   int32_t dim;             /* 2 or 3 */
-  int64_t n[3];            /* N_j: even, 4 <= N_j <= 512, 2 N_j of the form 2^a 3^b 5^c;
+  int64_t n[3];            /* N_j: even, 8 <= N_j <= 512, 2 N_j of the form 2^a 3^b 5^c;
                               n[2] ignored when dim == 2 */
   double box[3];           /* R_j > 0, full side lengths of B = prod [-R_j/2, R_j/2) */
   int32_t kernel;          /* jgb_kernel; JGB_COULOMB_2D needs dim == 2, the others dim == 3 */
@@ -155,6 +155,27 @@ jgb_status jgb_transform(jgb_plan_t plan, const void* rho, void* rhohat);
  * or dr dphi); c: device float64 array of c_j = (2pi)^{-d} W_j |k_j|^{d-1} U^(k_j).
  * Any of the three may be NULL.  Enqueue only. */
 jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* c);
+
+/* Stage timing for measurement.  While enabled, every compute call records a
+ * HIP event on the plan's stream before and after each kernel launch (the
+ * first max_calls calls only); nothing synchronises until jgb_timing_end,
+ * which waits for the stream and writes the average duration in milliseconds
+ * of each stage over the recorded calls that ran it (0 for stages that never
+ * ran) into stage_ms[JGB_NUM_STAGES], and the number of recorded calls into
+ * *calls.  Stage order:
+ *   0 forward FFT pass on axis 3 with deconvolution and padding
+ *   1 forward FFT pass on axis 2          2 forward FFT pass on axis 1
+ *   3 interpolation + weight x symbol + Fourier-side energy terms
+ *   4 spreading (gather)                  5 sum of split spreading tiles
+ *   6 inverse FFT pass on axis 1          7 inverse FFT pass on axis 2
+ *   8 inverse FFT pass on axis 3 with crop, deconvolution and energy terms
+ *   9 energy reduction
+ * (2D problems run no pass on a third axis: stages 2 and 6 stay 0.)
+ * Errors: INVALID_ARG (NULL plan, max_calls < 1 or > 100000, NULL outputs),
+ * OUT_OF_MEMORY (event creation), DEVICE. */
+#define JGB_NUM_STAGES 10
+jgb_status jgb_timing_begin(jgb_plan_t plan, int max_calls);
+jgb_status jgb_timing_end(jgb_plan_t plan, double* stage_ms, int* calls);
 
 /* Copy plan facts into *info (host memory, info->struct_size must be set). */
 jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info);

@@ -21,14 +21,14 @@ symmetry, self-adjointness).
 from .quadrature import (gauss_legendre, radial_rule, theta_rule, phi_rule,
                          spherical_nodes, polar_nodes, fourier_nodes)
 from .symbols import symbol, coefficients
-from .direct import (rho_hat, sum_to_grid, sum_to_points, potential, energy_fourier,
+from .direct import (rho_hat, rho_hat_separable, sum_to_grid, sum_to_points, potential, energy_fourier,
                      energy_physical, Result, evaluate, energy_gradient_rho,
                      energy_gradient_psi, apply_operator)
 from . import closed_forms
 
 __all__ = [
     "gauss_legendre", "radial_rule", "theta_rule", "phi_rule", "spherical_nodes",
-    "polar_nodes", "fourier_nodes", "symbol", "coefficients", "rho_hat", "sum_to_grid",
+    "polar_nodes", "fourier_nodes", "symbol", "coefficients", "rho_hat", "rho_hat_separable", "sum_to_grid",
     "sum_to_points", "potential", "energy_fourier", "energy_physical", "Result", "evaluate",
     "energy_gradient_rho", "energy_gradient_psi", "apply_operator", "closed_forms",
 ]

@@ -20,6 +20,9 @@ STATUS_NAMES = {0: "JGB_OK", 1: "JGB_ERR_INVALID_ARG", 2: "JGB_ERR_UNSUPPORTED",
                 3: "JGB_ERR_OUT_OF_MEMORY", 4: "JGB_ERR_DEVICE"}
 
 COULOMB_3D, COULOMB_2D, DIPOLE_3D = 0, 1, 2
+NUM_STAGES = 10
+STAGE_NAMES = ["fwd_fft_z", "fwd_fft_y", "fwd_fft_x", "interp", "spread", "spread_reduce",
+               "inv_fft_x", "inv_fft_y", "inv_fft_z", "energy"]
 FP64, MIXED = 0, 1
 THETA_GL, COSTHETA_GL = 0, 1
 
@@ -84,6 +87,8 @@ def _load():
         "jgb_plan_info": (st, [P, ctypes.POINTER(Info)]),
         "jgb_destroy": (st, [P]),
         "jgb_last_error": (ctypes.c_char_p, []),
+        "jgb_timing_begin": (st, [P, ctypes.c_int]),
+        "jgb_timing_end": (st, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

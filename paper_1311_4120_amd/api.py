@@ -122,6 +122,17 @@ class Plan:
         check(lib.jgb_nodes(self._h, _ptr(k), _ptr(W), _ptr(c)))
         return k, W, c
 
+    def timing_begin(self, max_calls):
+        """Record per-stage HIP events on the plan's stream for the next max_calls calls."""
+        check(lib.jgb_timing_begin(self._h, int(max_calls)))
+
+    def timing_end(self):
+        """Synchronise and return ({stage name: average ms}, recorded calls)."""
+        ms = (ctypes.c_double * _lib.NUM_STAGES)()
+        n = ctypes.c_int()
+        check(lib.jgb_timing_end(self._h, ctypes.cast(ms, ctypes.c_void_p), ctypes.cast(ctypes.pointer(n), ctypes.c_void_p)))
+        return dict(zip(_lib.STAGE_NAMES, list(ms))), n.value
+
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

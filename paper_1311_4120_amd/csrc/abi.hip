@@ -62,10 +62,12 @@ jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy) {
     return from_hip(e, "inverse FFT");
   if (energy) {
     double scale = 0.5 * pl.p.lambda * pl.H;
-    if ((e = jgb::launch_energy_finalize(pl.d_eparts, jgb::fft_inverse_z_blocks(pl), scale, energy, pl.stream)) !=
-        hipSuccess)
-      return from_hip(e, "energy");
+    jgb::stage_mark(pl, jgb::ST_ENERGY, 0, pl.stream);
+    e = jgb::launch_energy_finalize(pl.d_eparts, jgb::fft_inverse_z_blocks(pl), scale, energy, pl.stream);
+    jgb::stage_mark(pl, jgb::ST_ENERGY, 1, pl.stream);
+    if (e != hipSuccess) return from_hip(e, "energy");
   }
+  jgb::call_done(pl);
   return JGB_OK;
 }
 
@@ -76,8 +78,11 @@ jgb_status run_energy(Plan& pl, const void* rho, double* energy) {
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_ENERGY, nullptr, pl.stream)) != hipSuccess)
     return from_hip(e, "interpolation");
   int nb = jgb::interp_blocks(pl, jgb::kInterpNodesPerWave);
-  if ((e = jgb::launch_energy_finalize(pl.d_eparts, nb, 0.5 * pl.p.lambda, energy, pl.stream)) != hipSuccess)
-    return from_hip(e, "energy");
+  jgb::stage_mark(pl, jgb::ST_ENERGY, 0, pl.stream);
+  e = jgb::launch_energy_finalize(pl.d_eparts, nb, 0.5 * pl.p.lambda, energy, pl.stream);
+  jgb::stage_mark(pl, jgb::ST_ENERGY, 1, pl.stream);
+  if (e != hipSuccess) return from_hip(e, "energy");
+  jgb::call_done(pl);
   return JGB_OK;
 }
 
@@ -87,6 +92,7 @@ jgb_status run_transform(Plan& pl, const void* rho, void* out) {
   if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_TRANSFORM, out, pl.stream)) != hipSuccess)
     return from_hip(e, "interpolation");
+  jgb::call_done(pl);
   return JGB_OK;
 }
 
@@ -173,6 +179,69 @@ jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* cc) {
   return from_hip(jgb::launch_node_export(pl, k, w, cc, pl.stream), "node export");
 }
 
+static void release_timing(Plan& pl) {
+  for (hipEvent_t e : pl.timing.ev) (void)hipEventDestroy(e);
+  pl.timing = jgb::Timing{};
+}
+
+jgb_status jgb_timing_begin(jgb_plan_t plan, int max_calls) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  if (max_calls < 1 || max_calls > 100000) return report(JGB_ERR_INVALID_ARG, "max_calls must be in [1, 100000]");
+  Plan& pl = plan->pl;
+  hipError_t e = hipStreamSynchronize(pl.stream);
+  if (e != hipSuccess) return from_hip(e, "stream synchronize");
+  release_timing(pl);
+  size_t n = (size_t)max_calls * jgb::ST_COUNT * 2;
+  pl.timing.ev.resize(n, nullptr);
+  for (size_t i = 0; i < n; ++i) {
+    if (hipEventCreate(&pl.timing.ev[i]) != hipSuccess) {
+      (void)hipGetLastError();
+      pl.timing.ev.resize(i);
+      release_timing(pl);
+      return report(JGB_ERR_OUT_OF_MEMORY, "hipEventCreate failed");
+    }
+  }
+  pl.timing.used.assign((size_t)max_calls * jgb::ST_COUNT, 0);
+  pl.timing.max_calls = max_calls;
+  pl.timing.calls = 0;
+  pl.timing.on = true;
+  return JGB_OK;
+}
+
+jgb_status jgb_timing_end(jgb_plan_t plan, double* stage_ms, int* calls) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  if (!stage_ms || !calls) return report(JGB_ERR_INVALID_ARG, "stage_ms and calls must not be NULL");
+  Plan& pl = plan->pl;
+  jgb::Timing& t = pl.timing;
+  if (!t.on) return report(JGB_ERR_INVALID_ARG, "timing was not started");
+  hipError_t e = hipStreamSynchronize(pl.stream);
+  if (e != hipSuccess) {
+    release_timing(pl);
+    return from_hip(e, "stream synchronize");
+  }
+  for (int s = 0; s < jgb::ST_COUNT; ++s) {
+    double acc = 0.0;
+    int cnt = 0;
+    for (int k = 0; k < t.calls; ++k) {
+      size_t i = (size_t)k * jgb::ST_COUNT + s;
+      if (!t.used[i]) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]) == hipSuccess) {
+        acc += ms;
+        cnt++;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    stage_ms[s] = cnt ? acc / cnt : 0.0;
+  }
+  *calls = t.calls;
+  release_timing(pl);
+  return JGB_OK;
+}
+
 jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info) {
   if (!plan) return report(JGB_ERR_INVALID_ARG, "plan is NULL");
   if (!info) return report(JGB_ERR_INVALID_ARG, "info is NULL");
@@ -205,6 +274,7 @@ jgb_status jgb_destroy(jgb_plan_t plan) {
   if (!plan) return JGB_OK;
   (void)hipSetDevice(plan->pl.device);
   hipError_t e = hipStreamSynchronize(plan->pl.stream);
+  release_timing(plan->pl);
   jgb::free_plan(plan->pl);
   delete plan;
   if (e != hipSuccess) return from_hip(e, "stream synchronize");

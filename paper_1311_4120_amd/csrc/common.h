@@ -59,8 +59,23 @@ struct WorkItem {
   int slot;    // -1: write the tile to the grid; >= 0: write partial slot
 };
 
+enum Stage {
+  ST_FWD_Z = 0, ST_FWD_Y, ST_FWD_X, ST_INTERP, ST_SPREAD, ST_SPREAD_REDUCE,
+  ST_INV_X, ST_INV_Y, ST_INV_Z, ST_ENERGY, ST_COUNT
+};
+
+// Event ring for per-stage timing (see jgb_timing_begin).
+struct Timing {
+  bool on = false;
+  int max_calls = 0;
+  int calls = 0;
+  std::vector<hipEvent_t> ev;   // max_calls * ST_COUNT * 2
+  std::vector<char> used;       // max_calls * ST_COUNT
+};
+
 struct Plan {
   jgb_params p{};
+  mutable Timing timing;
   int device = 0;
   hipStream_t stream = nullptr;
   int dim = 3;
@@ -127,6 +142,19 @@ __host__ __device__ inline T es_kernel(T x, T two_over_w, T beta) {
 }
 
 // ----------------------------------------------------------------- launchers
+
+// Record the stage's start / end event of the current call when timing is on.
+inline void stage_mark(const Plan& pl, int stage, int which, hipStream_t s) {
+  Timing& t = pl.timing;
+  if (!t.on || t.calls >= t.max_calls) return;
+  size_t i = (size_t)t.calls * ST_COUNT + stage;
+  (void)hipEventRecord(t.ev[2 * i + which], s);
+  if (which == 1) t.used[i] = 1;
+}
+inline void call_done(const Plan& pl) {
+  Timing& t = pl.timing;
+  if (t.on && t.calls < t.max_calls) t.calls++;
+}
 
 hipError_t launch_gl_roots(int n, double* out, hipStream_t s);
 hipError_t launch_node_keys(const Plan& pl, int* keys, hipStream_t s);

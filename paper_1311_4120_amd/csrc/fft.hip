@@ -339,13 +339,15 @@ int lines_per_block(int L) {
 }
 
 template <typename T, int KIND>
-hipError_t run_pass(PassArgs<T> a, hipStream_t s) {
+hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   factor(a.L, a.rad, a.nrad);
   a.LB = lines_per_block<T>(a.L);
   unsigned blocks = (unsigned)((a.nlines + a.LB - 1) / a.LB);
   size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
   constexpr int MAXV = (sizeof(T) == 8 ? 4096 : 8192) / 256;
+  stage_mark(pl, stage, 0, s);
   hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV>), dim3(blocks), dim3(256), smem, s, a);
+  stage_mark(pl, stage, 1, s);
   return hipGetLastError();
 }
 
@@ -389,7 +391,7 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
     a.dec1 = pl.d_deconv[1];
     a.dec2 = pl.d_deconv[2];
     a.scale = pl.H;
-    if ((e = run_pass<T, PASS_FWD_Z>(a, s)) != hipSuccess) return e;
+    if ((e = run_pass<T, PASS_FWD_Z>(pl, ST_FWD_Z, a, s)) != hipSuccess) return e;
   }
   {  // Y: A1 -> A2 [n0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 1, T(-1));
@@ -406,7 +408,7 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
     a.lines_fastest = 1;
     a.in = A1;
     a.out = A2;
-    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+    if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_FWD_Y, a, s)) != hipSuccess) return e;
   }
   if (has_x) {  // X: A2 -> F [f0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 0, T(-1));
@@ -423,7 +425,7 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
     a.lines_fastest = 1;
     a.in = A2;
     a.out = pl.d_F;
-    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+    if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_FWD_X, a, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -451,7 +453,7 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.lines_fastest = 1;
     a.in = pl.d_G;
     a.out = B2;
-    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+    if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_X, a, s)) != hipSuccess) return e;
   }
   {  // Y: B2 -> B1 [n0][n1][f2]
     PassArgs<T> a = base_args<T>(pl, 1, T(1));
@@ -468,7 +470,7 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.lines_fastest = 1;
     a.in = B2;
     a.out = B1;
-    if ((e = run_pass<T, PASS_COMPLEX>(a, s)) != hipSuccess) return e;
+    if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_Y, a, s)) != hipSuccess) return e;
   }
   {  // Z: B1 -> u [n0][n1][n2], real part, deconvolution, energy partials
     PassArgs<T> a = base_args<T>(pl, 2, T(1));
@@ -490,7 +492,7 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.dec2 = pl.d_deconv[2];
     a.rho = rho_for_energy;
     a.eparts = rho_for_energy ? pl.d_eparts : nullptr;
-    if ((e = run_pass<T, PASS_INV_Z>(a, s)) != hipSuccess) return e;
+    if ((e = run_pass<T, PASS_INV_Z>(pl, ST_INV_Z, a, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

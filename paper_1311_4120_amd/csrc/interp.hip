@@ -186,7 +186,9 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.nodes_per_wave = kInterpNodesPerWave;
   unsigned blocks = (unsigned)interp_blocks(pl, a.nodes_per_wave);
   if (blocks == 0) return hipSuccess;
+  stage_mark(pl, ST_INTERP, 0, s);
   hipLaunchKernelGGL(k_interp<T>, dim3(blocks), dim3(256), 0, s, a);
+  stage_mark(pl, ST_INTERP, 1, s);
   return hipGetLastError();
 }
 

@@ -203,11 +203,15 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.G = (C2<T>*)pl.d_G;
   a.partials = (C2<T>*)pl.d_partials;
   unsigned blocks = (unsigned)((pl.nitems + kWaves - 1) / kWaves);
+  stage_mark(pl, ST_SPREAD, 0, s);
   hipLaunchKernelGGL(k_spread_gather<T>, dim3(blocks), dim3(256), 0, s, a);
+  stage_mark(pl, ST_SPREAD, 1, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
+  stage_mark(pl, ST_SPREAD_REDUCE, 0, s);
   hipLaunchKernelGGL(k_spread_reduce<T>, dim3(pl.nmulti), dim3(256), 0, s, pl.d_multi, pl.nmulti, pl.nf[0], pl.nf[1],
                      pl.nf[2], pl.T[0], pl.T[1], pl.nt[1], pl.nt[2], (const C2<T>*)pl.d_partials, (C2<T>*)pl.d_G);
+  stage_mark(pl, ST_SPREAD_REDUCE, 1, s);
   return hipGetLastError();
 }
 

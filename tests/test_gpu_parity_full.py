@@ -1,0 +1,138 @@
+"""GPU parity at the full sizes of the named workloads, in the launch
+configuration bench.py times (one plan, jgb_potential with energy).
+
+  coulomb3d_32   : whole grid against the full oracle
+  coulomb2d_256  : whole grid against the full oracle
+  dipole3d_128   : the headline workload; the oracle's transform at all
+                   1 048 576 nodes (exact per-axis regrouping for the separable
+                   density), u at sampled grid points, and E from the Fourier
+                   side (identical to the physical side for real rho)
+plus properties that hold at any size (energy identity, symmetry of A)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import make_plan, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("rule", [wl.THETA_GL, wl.COSTHETA_GL])
+def test_coulomb3d_32_full(prec, rule):
+    p, rho = wl.coulomb3d_32(rule)
+    eps = 1e-10 if prec == "fp64" else 1e-5
+    say("coulomb3d_32", prec, rule)
+    plan = make_plan(p, eps=eps, precision=prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u, E = plan.potential(torch.tensor(rho, dtype=dt, device="cuda"))
+    res = oracle.evaluate(p, rho)
+    e = rel_l2(u.cpu().numpy(), res.u)
+    eE = abs(E.item() / res.energy_physical - 1)
+    say("   relL2 %.2e  E %.2e (E=%.15f)" % (e, eE, E.item()))
+    assert e < eps and eE < eps
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_coulomb2d_256_full(prec):
+    p, rho, mix = wl.coulomb2d_256()
+    eps = 1e-10 if prec == "fp64" else 1e-5
+    say("coulomb2d_256", prec)
+    plan = make_plan(p, eps=eps, precision=prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u, E = plan.potential(torch.tensor(rho, dtype=dt, device="cuda"))
+    Ef = plan.energy(torch.tensor(rho, dtype=dt, device="cuda"))
+    res = oracle.evaluate(p, rho)
+    e = rel_l2(u.cpu().numpy(), res.u)
+    eE = abs(E.item() / res.energy_physical - 1)
+    eEf = abs(Ef.item() / res.energy_fourier - 1)
+    say("   relL2 %.2e  E %.2e  E_F %.2e" % (e, eE, eEf))
+    assert e < eps and eE < eps and eEf < eps
+    plan.close()
+
+
+_C3 = {}
+
+
+def _c3_oracle():
+    if not _C3:
+        p, rho = wl.dipole3d_128()
+        k, W = oracle.fourier_nodes(p)
+        x = wl.grid_axes(p.n, p.box)
+        f = [np.exp(-x[0] ** 2 / 1.0), np.exp(-x[1] ** 2 / 1.5 ** 2), np.exp(-x[2] ** 2 / 0.7 ** 2)]
+        assert np.allclose(f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :], rho, rtol=0, atol=1e-15)
+        rh = oracle.rho_hat_separable(f, p.box, k)
+        c = oracle.coefficients(p.kernel, k, W, p.axis)
+        rng = np.random.default_rng(77)
+        idx = np.concatenate([rng.integers(0, 128, size=(56, 3)),
+                              np.array([[64, 64, 64], [0, 0, 0], [127, 127, 127], [64, 0, 127],
+                                        [10, 64, 64], [64, 70, 60], [63, 64, 65], [100, 20, 64]])])
+        up = oracle.sum_to_points(c * rh, k, p.n, p.box, idx)
+        _C3.update(p=p, rho=rho, idx=idx, u=up.real, E=oracle.energy_fourier(c, rh, p.lam), rh=rh)
+    return _C3
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_dipole3d_128_headline_sampled(prec):
+    say("dipole3d_128: oracle at all nodes (separable regrouping) + 64 sampled points")
+    o = _c3_oracle()
+    p = o["p"]
+    eps = 1e-10 if prec == "fp64" else 1e-5
+    say("dipole3d_128", prec)
+    plan = make_plan(p, eps=eps, precision=prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rt = torch.tensor(o["rho"], dtype=dt, device="cuda")
+    u, E = plan.potential(rt)
+    Ef = plan.energy(rt)
+    ug = u.cpu().numpy()
+    got = ug[tuple(o["idx"].T)]
+    e = rel_l2(got, o["u"])
+    emax = np.max(np.abs(got - o["u"])) / np.max(np.abs(ug))
+    eE = abs(E.item() / o["E"] - 1)
+    eEf = abs(Ef.item() / o["E"] - 1)
+    say("   sampled relL2 %.2e  max/|u|max %.2e  E %.2e  E_F %.2e" % (e, emax, eE, eEf))
+    assert e < eps and emax < eps and eE < eps and eEf < eps
+    # transform at the device's half node set against the oracle's transform
+    th = plan.transform(rt).cpu().numpy()
+    from gpu_util import half_index
+    ref = o["rh"][half_index(p)]
+    et = np.max(np.abs(th - ref)) / np.max(np.abs(ref))
+    say("   transform max rel %.2e" % et)
+    assert et < eps
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_size_properties(prec):
+    """Properties that hold at any size: A symmetric, linear, backward == A, energy identity."""
+    p, rho = wl.dipole3d_128()
+    eps = 1e-10 if prec == "fp64" else 1e-5
+    say("properties dipole3d_128", prec)
+    plan = make_plan(p, eps=eps, precision=prec)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    g = torch.Generator(device="cpu").manual_seed(5)
+    r1 = torch.randn(p.n, generator=g, dtype=torch.float64).to(dt).cuda()
+    r2 = torch.randn(p.n, generator=g, dtype=torch.float64).to(dt).cuda()
+    a1, E1 = plan.potential(r1)
+    a2, _ = plan.potential(r2)
+    lhs = torch.sum(a1.double() * r2.double()).item()
+    rhs = torch.sum(r1.double() * a2.double()).item()
+    scale = (torch.linalg.norm(a1.double()) * torch.linalg.norm(r2.double())).item()
+    say("   <A r1, r2> - <r1, A r2> = %.2e (scale %.2e)" % (lhs - rhs, scale))
+    assert abs(lhs - rhs) < 4 * eps * scale
+    b1 = plan.backward(r1)
+    assert torch.equal(b1, a1)   # same kernels, same order: bitwise equal
+    a12, _ = plan.potential(2 * r1 - 3 * r2)
+    lin = (torch.linalg.norm((a12 - (2 * a1 - 3 * a2)).double()) / torch.linalg.norm(a12.double())).item()
+    say("   linearity %.2e" % lin)
+    assert lin < 4 * eps
+    Ef = plan.energy(r1).item()
+    say("   energy identity %.2e" % abs(Ef / E1.item() - 1))
+    assert abs(Ef / E1.item() - 1) < 4 * eps
+    # repeated calls are bitwise identical (no atomics anywhere in the path)
+    a1b, E1b = plan.potential(r1)
+    assert torch.equal(a1b, a1) and E1b.item() == E1.item()
+    plan.close()
