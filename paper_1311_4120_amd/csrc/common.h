@@ -44,7 +44,7 @@ struct cplx {
 
 struct NodeArrays {
   // Half node set in bin-sorted order.
-  int* start[3] = {nullptr, nullptr, nullptr};  // first tap per axis, wrapped into [0, nf)
+  int4* hdr = nullptr;                         // first tap per axis (x, y, z), wrapped into [0, nf); w unused
   void* frac[3] = {nullptr, nullptr, nullptr};  // s - start in fine cells, T
   double* coef = nullptr;                      // 2 c_j (pair k, -k folded in)
   int* perm = nullptr;                         // sorted position -> natural half index

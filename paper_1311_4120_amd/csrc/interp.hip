@@ -32,9 +32,7 @@ struct InterpArgs {
   int w0, w1, w2;
   T beta0, beta1, beta2;
   T tw0, tw1, tw2;  // 2 / w per axis
-  const int* st0;
-  const int* st1;
-  const int* st2;
+  const int4* hdr;
   const T* f0;
   const T* f1;
   const T* f2;
@@ -69,7 +67,8 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T> a) {
   for (int nn = 0; nn < a.nodes_per_wave; ++nn) {
     const int64_t j = first + nn;
     if (j >= a.Mh) break;
-    const int x0 = a.st0[j], y0 = a.st1[j], z0 = a.st2[j];
+    const int4 h = a.hdr[j];
+    const int x0 = h.x, y0 = h.y, z0 = h.z;
 
     // kernel values: lane 16*axis + tap
     T wv = T(0);
@@ -169,9 +168,7 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.tw0 = (T)(2.0 / pl.w[0]);
   a.tw1 = (T)(2.0 / pl.w[1]);
   a.tw2 = (T)(2.0 / pl.w[2]);
-  a.st0 = pl.nodes.start[0];
-  a.st1 = pl.nodes.start[1];
-  a.st2 = pl.nodes.start[2];
+  a.hdr = pl.nodes.hdr;
   a.f0 = (const T*)pl.nodes.frac[0];
   a.f1 = (const T*)pl.nodes.frac[1];
   a.f2 = (const T*)pl.nodes.frac[2];

@@ -199,8 +199,8 @@ __global__ void k_node_keys(NodeParams q, int64_t Mh, int* keys) {
 }
 
 template <typename T>
-__global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int* st0, int* st1, int* st2,
-                             T* f0, T* f1, T* f2, double* coef) {
+__global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int4* hdr, T* f0, T* f1, T* f2,
+                             double* coef) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= Mh) return;
   int64_t h = perm[p];
@@ -209,9 +209,7 @@ __global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int* st0
   half_node(q, h, k, W);
   fine_position(q, k, s);
   footprint(q, s, st, frac);
-  st0[p] = st[0];
-  st1[p] = st[1];
-  st2[p] = st[2];
+  hdr[p] = make_int4(st[0], st[1], st[2], 0);
   f0[p] = (T)frac[0];
   f1[p] = (T)frac[1];
   f2[p] = (T)frac[2];
@@ -265,11 +263,11 @@ hipError_t launch_node_setup(const Plan& pl, const int* perm, hipStream_t s) {
   const NodeArrays& a = pl.nodes;
   if (pl.fp64) {
     hipLaunchKernelGGL(k_node_setup<double>, dim3(grid_for(pl.Mh, 256)), dim3(256), 0, s, q, pl.Mh, perm,
-                       a.start[0], a.start[1], a.start[2], (double*)a.frac[0], (double*)a.frac[1],
+                       a.hdr, (double*)a.frac[0], (double*)a.frac[1],
                        (double*)a.frac[2], a.coef);
   } else {
     hipLaunchKernelGGL(k_node_setup<float>, dim3(grid_for(pl.Mh, 256)), dim3(256), 0, s, q, pl.Mh, perm,
-                       a.start[0], a.start[1], a.start[2], (float*)a.frac[0], (float*)a.frac[1],
+                       a.hdr, (float*)a.frac[0], (float*)a.frac[1],
                        (float*)a.frac[2], a.coef);
   }
   return hipGetLastError();

@@ -255,10 +255,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   }
   TRY(dev_alloc(pl, &pl.nodes.perm, sizeof(int) * Mh));
   TRY(upload(pl, pl.nodes.perm, perm.data(), sizeof(int) * Mh));
-  for (int i = 0; i < 3; ++i) {
-    TRY(dev_alloc(pl, &pl.nodes.start[i], sizeof(int) * Mh));
-    TRY(dev_alloc(pl, &pl.nodes.frac[i], pl.real_bytes * Mh));
-  }
+  TRY(dev_alloc(pl, &pl.nodes.hdr, sizeof(int4) * Mh));
+  for (int i = 0; i < 3; ++i) TRY(dev_alloc(pl, &pl.nodes.frac[i], pl.real_bytes * Mh));
   TRY(dev_alloc(pl, &pl.nodes.coef, sizeof(double) * Mh));
   TRY(dev_alloc(pl, &pl.nodes.uhat, 2 * pl.real_bytes * Mh));
   TRY(dev_alloc(pl, &pl.nodes.wts, 48 * pl.real_bytes * Mh));

@@ -41,9 +41,7 @@ struct SpreadArgs {
   const int* coff2;
   const WorkItem* items;
   int nitems;
-  const int* st0;
-  const int* st1;
-  const int* st2;
+  const int4* hdr;
   const C2<T>* uhat;
   const T* wts;
   C2<T>* G;
@@ -51,6 +49,40 @@ struct SpreadArgs {
 };
 
 constexpr int kWaves = 4;
+
+// Add the node's z taps to the tile column.  Tap t lands on tile z index O + t;
+// O is the node's first tap relative to the tile, a compile-time constant per
+// instantiation, so accumulators and weights are addressed statically.
+// Weights past the kernel width are stored as zeros.
+template <typename T, int O>
+__device__ __forceinline__ void add_column(T (&ar)[kTileZ], T (&ai)[kTileZ], const T (&wz)[kMaxWidth], T pr, T pi) {
+#pragma unroll
+  for (int t = 0; t < kMaxWidth; ++t) {
+    const int z = O + t;
+    if (z >= 0 && z < kTileZ) {
+      ar[z] += wz[t] * pr;
+      ai[z] += wz[t] * pi;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void add_column_dispatch(int o, T (&ar)[kTileZ], T (&ai)[kTileZ], const T (&wz)[kMaxWidth],
+                                                    T pr, T pi) {
+  switch (o) {
+#define JGB_CASE(O) \
+  case O:           \
+    add_column<T, O>(ar, ai, wz, pr, pi); \
+    break;
+    JGB_CASE(-15) JGB_CASE(-14) JGB_CASE(-13) JGB_CASE(-12) JGB_CASE(-11) JGB_CASE(-10) JGB_CASE(-9)
+    JGB_CASE(-8) JGB_CASE(-7) JGB_CASE(-6) JGB_CASE(-5) JGB_CASE(-4) JGB_CASE(-3) JGB_CASE(-2) JGB_CASE(-1)
+    JGB_CASE(0) JGB_CASE(1) JGB_CASE(2) JGB_CASE(3) JGB_CASE(4) JGB_CASE(5) JGB_CASE(6) JGB_CASE(7)
+    JGB_CASE(8) JGB_CASE(9) JGB_CASE(10) JGB_CASE(11) JGB_CASE(12) JGB_CASE(13) JGB_CASE(14) JGB_CASE(15)
+#undef JGB_CASE
+    default:
+      break;
+  }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
@@ -65,8 +97,7 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int t0 = tile / (a.nt2 * a.nt1);
   const int o0 = t0 * a.T0, o1 = t1 * a.T1, o2 = t2 * kTileZ;
   const int lx = lane / a.T1, ly = lane % a.T1;
-  const int g0 = o0 + lx, g1 = o1 + ly;
-  const bool lane_ok = (g0 < a.nf0) && (g1 < a.nf1);
+  const bool lane_ok = (o0 + lx < a.nf0) && (o1 + ly < a.nf1);
 
   T ar[kTileZ], ai[kTileZ];
 #pragma unroll
@@ -86,34 +117,37 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
         const int bin = (b0 * a.nt1 + b1) * a.nt2 + b2;
         const int s = a.bin_start[bin], e = a.bin_start[bin + 1];
         const int cnt = e - s;
-        int lo = v > vbegin ? v : vbegin;
-        int hi = (v + cnt) < vend ? (v + cnt) : vend;
+        const int lo = v > vbegin ? v : vbegin;
+        const int hi = (v + cnt) < vend ? (v + cnt) : vend;
         for (int vv = lo; vv < hi; ++vv) {
           const int j = s + (vv - v);
-          const int x0 = a.st0[j], y0 = a.st1[j], z0 = a.st2[j];
-          // uniform z range of the footprint inside this tile
-          int dz0 = o2 - z0;
-          if (dz0 < 0) dz0 += a.nf2;
-          int dx = g0 - x0;
+          const int4 h = a.hdr[j];
+          // first tap of the footprint relative to the tile origin, modulo the grid
+          int ex = h.x - o0;
+          if (ex < 0) ex += a.nf0;
+          int ey = h.y - o1;
+          if (ey < 0) ey += a.nf1;
+          int ez = h.z - o2;
+          if (ez < 0) ez += a.nf2;
+          const bool zin = ez < kTileZ;               // footprint starts inside the tile
+          const bool zwrap = a.nf2 - ez < a.w2;       // footprint starts before it and reaches in
+          if (!((ex < a.T0 || a.nf0 - ex < a.w0) && (ey < a.T1 || a.nf1 - ey < a.w1) && (zin || zwrap))) continue;
+          const T* wj = a.wts + (int64_t)j * 48;
+          int dx = lx - ex;
           if (dx < 0) dx += a.nf0;
-          int dy = g1 - y0;
+          int dy = ly - ey;
           if (dy < 0) dy += a.nf1;
           const bool in = lane_ok && dx < a.w0 && dy < a.w1;
-          const T* wj = a.wts + (int64_t)j * 48;
-          T wxy = in ? wj[dx < a.w0 ? dx : 0] * wj[16 + (dy < a.w1 ? dy : 0)] : T(0);
-          if (!__any(in)) continue;
+          const T wx = wj[in ? dx : 0];
+          const T wy = wj[16 + (in ? dy : 0)];
+          const T p = in ? wx * wy : T(0);
           const C2<T> u = a.uhat[j];
-          const T pr = wxy * u.x, pi = wxy * u.y;
+          const T pr = p * u.x, pi = p * u.y;
+          T wz[kMaxWidth];
 #pragma unroll
-          for (int z = 0; z < kTileZ; ++z) {
-            int dz = dz0 + z;
-            if (dz >= a.nf2) dz -= a.nf2;
-            if (dz < a.w2) {
-              const T wz = wj[32 + dz];
-              ar[z] += wz * pr;
-              ai[z] += wz * pi;
-            }
-          }
+          for (int t = 0; t < kMaxWidth; ++t) wz[t] = wj[32 + t];
+          if (zin) add_column_dispatch<T>(ez, ar, ai, wz, pr, pi);
+          if (zwrap) add_column_dispatch<T>(ez - a.nf2, ar, ai, wz, pr, pi);
         }
         v += cnt;
       }
@@ -121,6 +155,7 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   }
 
   if (!lane_ok) return;
+  const int g0 = o0 + lx, g1 = o1 + ly;
   if (item.slot < 0) {
     C2<T>* dst = a.G + ((int64_t)g0 * a.nf1 + g1) * a.nf2 + o2;
 #pragma unroll
@@ -195,9 +230,7 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.coff2 = pl.d_cand_off[2];
   a.items = pl.d_items;
   a.nitems = pl.nitems;
-  a.st0 = pl.nodes.start[0];
-  a.st1 = pl.nodes.start[1];
-  a.st2 = pl.nodes.start[2];
+  a.hdr = pl.nodes.hdr;
   a.uhat = (const C2<T>*)pl.nodes.uhat;
   a.wts = (const T*)pl.nodes.wts;
   a.G = (C2<T>*)pl.d_G;
