@@ -54,7 +54,7 @@ struct NodeArrays {
 
 struct WorkItem {
   int tile;    // linear tile index (t0 * nt1 + t1) * nt2 + t2
-  int vbegin;  // range of the tile's candidate-node list handled by this item
+  int vbegin;  // range of the node list d_list handled by this item
   int vend;
   int slot;    // -1: write the tile to the grid; >= 0: write partial slot
 };
@@ -105,8 +105,8 @@ struct Plan {
   int nt[3] = {1, 1, 1};     // tiles per axis
   int ntiles = 0;
   int* d_bin_start = nullptr;  // ntiles + 1 offsets into the sorted node list
-  int* d_cand[3] = {nullptr, nullptr, nullptr};     // candidate bins per axis, flattened
-  int* d_cand_off[3] = {nullptr, nullptr, nullptr}; // nt[a] + 1 offsets
+  int* d_list = nullptr;       // per tile, the nodes whose footprint touches it (concatenated)
+  int64_t nlist = 0;
   WorkItem* d_items = nullptr;
   int nitems = 0;
   int nslots = 0;

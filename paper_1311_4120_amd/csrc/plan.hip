@@ -13,7 +13,7 @@ namespace jgb {
 
 namespace {
 
-constexpr int kChunk = 1024;  // candidate nodes per gather work item at most
+constexpr int kChunk = 4096;  // listed nodes per gather work item (one block of 4 wavefronts) at most
 
 bool is_235(int64_t n) {
   if (n < 1) return false;
@@ -264,57 +264,72 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   TRY(dev_alloc(pl, &pl.d_bin_start, sizeof(int) * (pl.ntiles + 1)));
   TRY(upload(pl, pl.d_bin_start, bin_start.data(), sizeof(int) * (pl.ntiles + 1)));
 
-  // candidate bins per axis: bins holding a first tap whose footprint reaches the tile
-  std::vector<int> cand[3], coff[3];
-  for (int a = 0; a < 3; ++a) {
-    const int nf = pl.nf[a], T = pl.T[a], nt = pl.nt[a], w = pl.w[a];
-    coff[a].push_back(0);
-    for (int t = 0; t < nt; ++t) {
-      for (int b = 0; b < nt; ++b) {
-        bool hit = false;
-        for (int x0 = b * T; x0 < std::min((b + 1) * T, nf) && !hit; ++x0)
-          for (int i = t * T; i < std::min((t + 1) * T, nf) && !hit; ++i)
-            if ((((i - x0) % nf) + nf) % nf < w) hit = true;
-        if (hit) cand[a].push_back(b);
-      }
-      coff[a].push_back((int)cand[a].size());
+  // exact per-tile node lists: node j (bin-sorted order) is listed under every
+  // output tile its w^3 footprint touches, so the gather never visits a node
+  // that misses its tile
+  std::vector<int4> hdr(Mh);
+  TRY_HIP(hipMemcpyAsync(hdr.data(), pl.nodes.hdr, sizeof(int4) * Mh, hipMemcpyDeviceToHost, pl.stream), "hdr copy");
+  TRY_HIP(hipStreamSynchronize(pl.stream), "hdr sync");
+  auto touched = [&](int a, int x0, int* out) {
+    const int nf = pl.nf[a], T = pl.T[a], w = pl.w[a];
+    int n = 0;
+    for (int t = 0; t < w; ++t) {
+      int tile = ((x0 + t) % nf) / T;
+      bool seen = false;
+      for (int i = 0; i < n; ++i) seen |= (out[i] == tile);
+      if (!seen) out[n++] = tile;
     }
-    TRY(dev_alloc(pl, &pl.d_cand[a], sizeof(int) * cand[a].size()));
-    TRY(dev_alloc(pl, &pl.d_cand_off[a], sizeof(int) * coff[a].size()));
-    TRY(upload(pl, pl.d_cand[a], cand[a].data(), sizeof(int) * cand[a].size()));
-    TRY(upload(pl, pl.d_cand_off[a], coff[a].data(), sizeof(int) * coff[a].size()));
+    return n;
+  };
+  std::vector<int64_t> tcount(pl.ntiles + 1, 0);
+  {
+    int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
+    for (int64_t j = 0; j < Mh; ++j) {
+      int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
+      for (int a0 = 0; a0 < nx; ++a0)
+        for (int a1 = 0; a1 < ny; ++a1)
+          for (int a2 = 0; a2 < nz; ++a2) tcount[(tx[a0] * pl.nt[1] + ty[a1]) * pl.nt[2] + tz[a2] + 1]++;
+    }
   }
+  for (int t = 0; t < pl.ntiles; ++t) tcount[t + 1] += tcount[t];
+  const int64_t nlist = tcount[pl.ntiles];
+  if (nlist > (int64_t)std::numeric_limits<int>::max()) return fail(JGB_ERR_UNSUPPORTED, "gather lists too long");
+  std::vector<int> list(std::max<int64_t>(nlist, 1));
+  {
+    std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
+    int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
+    for (int64_t j = 0; j < Mh; ++j) {
+      int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
+      for (int a0 = 0; a0 < nx; ++a0)
+        for (int a1 = 0; a1 < ny; ++a1)
+          for (int a2 = 0; a2 < nz; ++a2) list[fill[(tx[a0] * pl.nt[1] + ty[a1]) * pl.nt[2] + tz[a2]]++] = (int)j;
+    }
+  }
+  TRY(dev_alloc(pl, &pl.d_list, sizeof(int) * list.size()));
+  TRY(upload(pl, pl.d_list, list.data(), sizeof(int) * list.size()));
+  pl.nlist = nlist;
 
-  // gather work items: one per tile, more for tiles with long candidate lists
+  // gather work items: one block per tile, more for tiles with long lists
   std::vector<WorkItem> items;
   std::vector<int> multi;
   int nslots = 0;
-  for (int t0 = 0; t0 < pl.nt[0]; ++t0)
-    for (int t1 = 0; t1 < pl.nt[1]; ++t1)
-      for (int t2 = 0; t2 < pl.nt[2]; ++t2) {
-        int64_t L = 0;
-        for (int c0 = coff[0][t0]; c0 < coff[0][t0 + 1]; ++c0)
-          for (int c1 = coff[1][t1]; c1 < coff[1][t1 + 1]; ++c1)
-            for (int c2 = coff[2][t2]; c2 < coff[2][t2 + 1]; ++c2) {
-              int bin = (cand[0][c0] * pl.nt[1] + cand[1][c1]) * pl.nt[2] + cand[2][c2];
-              L += bin_start[bin + 1] - bin_start[bin];
-            }
-        int tile = (t0 * pl.nt[1] + t1) * pl.nt[2] + t2;
-        if (L <= kChunk) {
-          items.push_back(WorkItem{tile, 0, (int)L, -1});
-        } else {
-          int k = (int)((L + kChunk - 1) / kChunk);
-          multi.push_back(tile);
-          multi.push_back(nslots);
-          multi.push_back(k);
-          for (int c = 0; c < k; ++c) {
-            int vb = c * kChunk;
-            int ve = (int)std::min<int64_t>(L, (int64_t)(c + 1) * kChunk);
-            items.push_back(WorkItem{tile, vb, ve, nslots + c});
-          }
-          nslots += k;
-        }
+  for (int tile = 0; tile < pl.ntiles; ++tile) {
+    const int64_t b = tcount[tile], e = tcount[tile + 1], L = e - b;
+    if (L <= kChunk) {
+      items.push_back(WorkItem{tile, (int)b, (int)e, -1});
+    } else {
+      int k = (int)((L + kChunk - 1) / kChunk);
+      multi.push_back(tile);
+      multi.push_back(nslots);
+      multi.push_back(k);
+      for (int c = 0; c < k; ++c) {
+        int64_t vb = b + (int64_t)c * kChunk;
+        int64_t ve = std::min<int64_t>(e, vb + kChunk);
+        items.push_back(WorkItem{tile, (int)vb, (int)ve, nslots + c});
       }
+      nslots += k;
+    }
+  }
   // longest items first so the split tiles do not form the tail
   std::stable_sort(items.begin(), items.end(),
                    [](const WorkItem& x, const WorkItem& y) { return (x.vend - x.vbegin) > (y.vend - y.vbegin); });

@@ -32,13 +32,7 @@ struct SpreadArgs {
   int w0, w1, w2;
   int T0, T1;
   int nt1, nt2;
-  const int* bin_start;
-  const int* cand0;
-  const int* cand1;
-  const int* cand2;
-  const int* coff0;
-  const int* coff1;
-  const int* coff2;
+  const int* list;
   const WorkItem* items;
   int nitems;
   const int4* hdr;
@@ -84,13 +78,16 @@ __device__ __forceinline__ void add_column_dispatch(int o, T (&ar)[kTileZ], T (&
   }
 }
 
+// One block per work item (a tile and a range of its node list).  The four
+// wavefronts each take a contiguous quarter of the range and accumulate the
+// whole 8 x 8 x kTileZ tile in registers; the partial tiles are then summed
+// in LDS in a fixed order and written once.
 template <typename T>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
+  __shared__ C2<T> red[2][64 * kTileZ];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int it = blockIdx.x * kWaves + wave;
-  if (it >= a.nitems) return;
-  const WorkItem item = a.items[it];
+  const WorkItem item = a.items[blockIdx.x];
   const int tile = item.tile;
   const int t2 = tile % a.nt2;
   const int t1 = (tile / a.nt2) % a.nt1;
@@ -106,54 +103,79 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     ai[z] = T(0);
   }
 
-  int v = 0;
-  const int vbegin = item.vbegin, vend = item.vend;
-  for (int c0 = a.coff0[t0]; c0 < a.coff0[t0 + 1] && v < vend; ++c0) {
-    const int b0 = a.cand0[c0];
-    for (int c1 = a.coff1[t1]; c1 < a.coff1[t1 + 1] && v < vend; ++c1) {
-      const int b1 = a.cand1[c1];
-      for (int c2 = a.coff2[t2]; c2 < a.coff2[t2 + 1] && v < vend; ++c2) {
-        const int b2 = a.cand2[c2];
-        const int bin = (b0 * a.nt1 + b1) * a.nt2 + b2;
-        const int s = a.bin_start[bin], e = a.bin_start[bin + 1];
-        const int cnt = e - s;
-        const int lo = v > vbegin ? v : vbegin;
-        const int hi = (v + cnt) < vend ? (v + cnt) : vend;
-        for (int vv = lo; vv < hi; ++vv) {
-          const int j = s + (vv - v);
-          const int4 h = a.hdr[j];
-          // first tap of the footprint relative to the tile origin, modulo the grid
-          int ex = h.x - o0;
-          if (ex < 0) ex += a.nf0;
-          int ey = h.y - o1;
-          if (ey < 0) ey += a.nf1;
-          int ez = h.z - o2;
-          if (ez < 0) ez += a.nf2;
-          const bool zin = ez < kTileZ;               // footprint starts inside the tile
-          const bool zwrap = a.nf2 - ez < a.w2;       // footprint starts before it and reaches in
-          if (!((ex < a.T0 || a.nf0 - ex < a.w0) && (ey < a.T1 || a.nf1 - ey < a.w1) && (zin || zwrap))) continue;
-          const T* wj = a.wts + (int64_t)j * 48;
-          int dx = lx - ex;
-          if (dx < 0) dx += a.nf0;
-          int dy = ly - ey;
-          if (dy < 0) dy += a.nf1;
-          const bool in = lane_ok && dx < a.w0 && dy < a.w1;
-          const T wx = wj[in ? dx : 0];
-          const T wy = wj[16 + (in ? dy : 0)];
-          const T p = in ? wx * wy : T(0);
-          const C2<T> u = a.uhat[j];
-          const T pr = p * u.x, pi = p * u.y;
-          T wz[kMaxWidth];
+  const int n = item.vend - item.vbegin;
+  const int q = (n + kWaves - 1) / kWaves;
+  const int kb = item.vbegin + wave * q;
+  const int ke = (kb + q < item.vend) ? kb + q : item.vend;
+
+  // x and y kernel values of the next node: lanes 0..15 hold phi_x, 16..31 phi_y
+  int jn = 0;
+  T wxyn = T(0);
+  if (kb < ke) {
+    jn = a.list[kb];
+    wxyn = a.wts[(int64_t)jn * 48 + (lane & 31)];
+  }
+  for (int k = kb; k < ke; ++k) {
+    const int j = jn;
+    const T wxy = wxyn;
+    const int4 h = a.hdr[j];
+    const C2<T> u = a.uhat[j];
+    const T* wj = a.wts + (int64_t)j * 48;
+    T wz[kMaxWidth];
 #pragma unroll
-          for (int t = 0; t < kMaxWidth; ++t) wz[t] = wj[32 + t];
-          if (zin) add_column_dispatch<T>(ez, ar, ai, wz, pr, pi);
-          if (zwrap) add_column_dispatch<T>(ez - a.nf2, ar, ai, wz, pr, pi);
-        }
-        v += cnt;
-      }
+    for (int t = 0; t < kMaxWidth; ++t) wz[t] = wj[32 + t];
+    if (k + 1 < ke) {
+      jn = a.list[k + 1];
+      wxyn = a.wts[(int64_t)jn * 48 + (lane & 31)];
     }
+    // first tap of the footprint relative to the tile origin, modulo the grid
+    int ex = h.x - o0;
+    if (ex < 0) ex += a.nf0;
+    int ey = h.y - o1;
+    if (ey < 0) ey += a.nf1;
+    int ez = h.z - o2;
+    if (ez < 0) ez += a.nf2;
+    int dx = lx - ex;
+    if (dx < 0) dx += a.nf0;
+    int dy = ly - ey;
+    if (dy < 0) dy += a.nf1;
+    const bool in = lane_ok && dx < a.w0 && dy < a.w1;
+    const T wx = __shfl(wxy, dx & 15, 64);
+    const T wy = __shfl(wxy, 16 + (dy & 15), 64);
+    const T p = in ? wx * wy : T(0);
+    const T pr = p * u.x, pi = p * u.y;
+    if (ez < kTileZ) add_column_dispatch<T>(ez, ar, ai, wz, pr, pi);   // footprint starts inside the tile
+    if (a.nf2 - ez < a.w2) add_column_dispatch<T>(ez - a.nf2, ar, ai, wz, pr, pi);  // starts before it
   }
 
+  // fixed-order sum of the four partial tiles: (w0 + w2) + (w1 + w3)
+  const int base = lane * kTileZ;
+  if (wave >= 2) {
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) red[wave - 2][base + z] = C2<T>{ar[z], ai[z]};
+  }
+  __syncthreads();
+  if (wave < 2) {
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) {
+      C2<T> o = red[wave][base + z];
+      ar[z] += o.x;
+      ai[z] += o.y;
+    }
+  }
+  __syncthreads();
+  if (wave == 1) {
+#pragma unroll
+    for (int z = 0; z < kTileZ; ++z) red[0][base + z] = C2<T>{ar[z], ai[z]};
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int z = 0; z < kTileZ; ++z) {
+    C2<T> o = red[0][base + z];
+    ar[z] += o.x;
+    ai[z] += o.y;
+  }
   if (!lane_ok) return;
   const int g0 = o0 + lx, g1 = o1 + ly;
   if (item.slot < 0) {
@@ -221,13 +243,7 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.T1 = pl.T[1];
   a.nt1 = pl.nt[1];
   a.nt2 = pl.nt[2];
-  a.bin_start = pl.d_bin_start;
-  a.cand0 = pl.d_cand[0];
-  a.cand1 = pl.d_cand[1];
-  a.cand2 = pl.d_cand[2];
-  a.coff0 = pl.d_cand_off[0];
-  a.coff1 = pl.d_cand_off[1];
-  a.coff2 = pl.d_cand_off[2];
+  a.list = pl.d_list;
   a.items = pl.d_items;
   a.nitems = pl.nitems;
   a.hdr = pl.nodes.hdr;
@@ -235,7 +251,8 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.wts = (const T*)pl.nodes.wts;
   a.G = (C2<T>*)pl.d_G;
   a.partials = (C2<T>*)pl.d_partials;
-  unsigned blocks = (unsigned)((pl.nitems + kWaves - 1) / kWaves);
+  unsigned blocks = (unsigned)pl.nitems;
+  if (blocks == 0) return hipErrorInvalidConfiguration;
   stage_mark(pl, ST_SPREAD, 0, s);
   hipLaunchKernelGGL(k_spread_gather<T>, dim3(blocks), dim3(256), 0, s, a);
   stage_mark(pl, ST_SPREAD, 1, s);
