@@ -77,7 +77,7 @@ jgb_status run_energy(Plan& pl, const void* rho, double* energy) {
   if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_ENERGY, nullptr, pl.stream)) != hipSuccess)
     return from_hip(e, "interpolation");
-  int nb = jgb::interp_blocks(pl, jgb::kInterpNodesPerWave);
+  int nb = jgb::interp_blocks(pl);
   jgb::stage_mark(pl, jgb::ST_ENERGY, 0, pl.stream);
   e = jgb::launch_energy_finalize(pl.d_eparts, nb, 0.5 * pl.p.lambda, energy, pl.stream);
   jgb::stage_mark(pl, jgb::ST_ENERGY, 1, pl.stream);

@@ -23,6 +23,12 @@ constexpr int kMaxWidth = 16;
 constexpr int kMaxLine = 1024;
 // Output tile of the type-1 gather kernel: TX x TY lanes, TZ points per lane.
 constexpr int kTileZ = 16;
+// Per-node kernel values written by the interpolation for the spreading:
+// [0,16) phi along a0, [16,32) along a1, [32,48) zeros, [48,64) along a2,
+// [64,80) zeros.  Entries past the width are zero, and the zero pads let the
+// gather read any 16-tap window of the a2 values at a uniform offset.
+constexpr int kRec = 80;
+constexpr int kRecZ = 48;
 
 // ----------------------------------------------------------------- errors
 
@@ -49,7 +55,7 @@ struct NodeArrays {
   double* coef = nullptr;                      // 2 c_j (pair k, -k folded in)
   int* perm = nullptr;                         // sorted position -> natural half index
   void* uhat = nullptr;                        // c_j rho^_j, complex T
-  void* wts = nullptr;                         // per node 3 x width kernel values, T
+  void* wts = nullptr;                         // per node kRec kernel values, T (layout below)
 };
 
 struct WorkItem {
@@ -100,12 +106,26 @@ struct Plan {
 
   NodeArrays nodes;
 
-  // bins == output tiles of the gather
+  // bins == output tiles of the gather; each bin splits into nsub sub-bins of
+  // extent S, the unit whose oversampled-grid neighbourhood the interpolation
+  // stages in LDS
   int T[3] = {1, 1, 1};      // tile / bin extent per axis
+  int S[3] = {1, 1, 1};      // sub-bin extent per axis (divides T)
+  int E[3] = {1, 1, 1};      // staged interpolation region per axis (E[2] padded)
+  int nsub = 1;
+  struct InterpItem {
+    int sub;    // key of the sub-bin: bin * nsub + sub-bin index
+    int begin;  // range of bin-sorted nodes
+    int end;
+  };
+  InterpItem* d_iitems = nullptr;
+  int niitems = 0;
+  size_t interp_lds = 0;     // bytes of the staged grid region
   int nt[3] = {1, 1, 1};     // tiles per axis
   int ntiles = 0;
   int* d_bin_start = nullptr;  // ntiles + 1 offsets into the sorted node list
-  int* d_list = nullptr;       // per tile, the nodes whose footprint touches it (concatenated)
+  int2* d_list = nullptr;      // per tile, the nodes whose footprint touches it (concatenated):
+                               // (node, first tap relative to the tile per axis, 10 bits each)
   int64_t nlist = 0;
   WorkItem* d_items = nullptr;
   int nitems = 0;
@@ -173,8 +193,7 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
 template <typename T>
 hipError_t launch_spread(const Plan& pl, hipStream_t s);
 int fft_inverse_z_blocks(const Plan& pl);
-int interp_blocks(const Plan& pl, int nodes_per_wave);
-constexpr int kInterpNodesPerWave = 8;
+int interp_blocks(const Plan& pl);
 hipError_t launch_energy_finalize(const double* parts, int n, double scale, double* out, hipStream_t s);
 
 }  // namespace jgb

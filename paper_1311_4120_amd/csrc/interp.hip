@@ -8,12 +8,13 @@
 // (indices periodic on the fine grid; F already carries H and the
 // deconvolution, so this is the trapezoid transform of eq. 3.2 at k_j).
 //
-// One wavefront per node.  Lanes 0..47 first evaluate the 3 x w kernel values
-// (lane 16a + i holds phi for axis a, tap i).  Lanes then own (b, c) tap pairs
-// of the two inner axes and loop over the outer axis, so a wavefront reads
-// w contiguous runs of w complex values per row; the per-lane partial sums
-// are reduced across the wavefront.  Nodes are bin-sorted, so consecutive
-// nodes of a block touch overlapping footprints in cache.
+// One block per sub-bin (or a slice of a crowded one): the block stages the
+// grid region every footprint of the sub-bin can touch -- the sub-bin plus
+// w - 1 cells on the high side of each axis -- in LDS with coalesced loads,
+// then each wavefront interpolates one node at a time from LDS.  Lanes 0..47
+// first evaluate the 3 x w kernel values (lane 16a + i holds phi for axis a,
+// tap i); lanes then own (b, c) tap pairs of the two inner axes and loop over
+// the outer one, and the per-lane sums are reduced across the wavefront.
 #include "common.h"
 
 namespace jgb {
@@ -27,11 +28,14 @@ struct C2 {
 
 template <typename T>
 struct InterpArgs {
-  int64_t Mh;
   int nf0, nf1, nf2;
   int w0, w1, w2;
-  T beta0, beta1, beta2;
+  int T0, T1, T2, S0, S1, S2;
+  int nt1, nt2, nsub;
+  int E0, E1, E2;   // staged region extents; E2 is padded (see the plan)
+  T beta;
   T tw0, tw1, tw2;  // 2 / w per axis
+  const Plan::InterpItem* items;
   const int4* hdr;
   const T* f0;
   const T* f1;
@@ -44,72 +48,120 @@ struct InterpArgs {
   T* wts;
   C2<T>* out;
   double* eparts;
-  int nodes_per_wave;
 };
 
-constexpr int kWavesPerBlock = 4;
+constexpr int kInterpThreads = 1024;
+constexpr int kInterpWaves = kInterpThreads / 64;
 
-template <typename T>
-__device__ inline T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// value of lane src, uniform across the wavefront
+__device__ __forceinline__ double lane_value(double v, int src) {
+  int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
+// DPP move with row mask RM; lanes without a source (or outside RM) read 0
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RM, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RM, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, 0xf, false));
+}
+
+// Sum over the 64 lanes: inclusive scans within rows of 16 (row_shr 1, 2, 4, 8),
+// then row 0 and 2 totals into rows 1 and 3 (row_bcast:15), then the first
+// half's total into rows 2 and 3 (row_bcast:31); lane 63 ends with the sum.
 template <typename T>
-__global__ void __launch_bounds__(256) k_interp(InterpArgs<T> a) {
+__device__ __forceinline__ T wave_total(T v) {
+  v += dpp<0x111, 0xf>(v);
+  v += dpp<0x112, 0xf>(v);
+  v += dpp<0x114, 0xf>(v);
+  v += dpp<0x118, 0xf>(v);
+  v += dpp<0x142, 0xa>(v);
+  v += dpp<0x143, 0xc>(v);
+  return lane_value(v, 63);
+}
+
+template <typename T, int W>
+__global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* tile = reinterpret_cast<C2<T>*>(smem_raw);
+  __shared__ T wbuf[kInterpWaves][64];
+  __shared__ double ws[kInterpWaves];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t first = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * a.nodes_per_wave;
-  const int npairs = a.w1 * a.w2;
+  const Plan::InterpItem item = a.items[blockIdx.x];
+
+  // origin of the sub-bin on the fine grid
+  const int bin = item.sub / a.nsub, sub = item.sub % a.nsub;
+  const int m1 = a.T1 / a.S1, m2 = a.T2 / a.S2;
+  const int s2 = sub % m2, s1 = (sub / m2) % m1, s0 = sub / (m2 * m1);
+  const int b2 = bin % a.nt2, b1 = (bin / a.nt2) % a.nt1, b0 = bin / (a.nt2 * a.nt1);
+  const int ox = b0 * a.T0 + s0 * a.S0, oy = b1 * a.T1 + s1 * a.S1, oz = b2 * a.T2 + s2 * a.S2;
+
+  // stage the neighbourhood (periodic on the fine grid; the padding columns of
+  // the last axis are loaded too and never read)
+  const int nreg = a.E0 * a.E1 * a.E2;
+  for (int idx = threadIdx.x; idx < nreg; idx += kInterpThreads) {
+    int i2 = idx % a.E2, i1 = (idx / a.E2) % a.E1, i0 = idx / (a.E2 * a.E1);
+    // the region may be wider than the grid on small grids: reduce modulo nf
+    const int g0 = (ox + i0) % a.nf0, g1 = (oy + i1) % a.nf1, g2 = (oz + i2) % a.nf2;
+    tile[idx] = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
+  }
+  __syncthreads();
+
+  constexpr int NP = W * W;             // (b, c) tap pairs of the two inner axes
+  constexpr int NQ = (NP + 63) / 64;    // pairs per lane
+  const int plane = a.E1 * a.E2;
+  const T* wrow = wbuf[wave];
   double eacc = 0.0;
-
-  for (int nn = 0; nn < a.nodes_per_wave; ++nn) {
-    const int64_t j = first + nn;
-    if (j >= a.Mh) break;
+  for (int j = item.begin + wave; j < item.end; j += kInterpWaves) {
     const int4 h = a.hdr[j];
-    const int x0 = h.x, y0 = h.y, z0 = h.z;
+    const int lx0 = h.x - ox, ly0 = h.y - oy, lz0 = h.z - oz;  // in [0, S)
 
-    // kernel values: lane 16*axis + tap
-    T wv = T(0);
+    // kernel values: lane 16*axis + tap, one evaluation per lane
+    T wv;
     {
-      int ax = lane >> 4, t = lane & 15;
-      if (ax == 0 && t < a.w0) wv = (a.w0 == 1) ? T(1) : es_kernel<T>(T(t) - a.f0[j], a.tw0, a.beta0);
-      if (ax == 1 && t < a.w1) wv = (a.w1 == 1) ? T(1) : es_kernel<T>(T(t) - a.f1[j], a.tw1, a.beta1);
-      if (ax == 2 && t < a.w2) wv = (a.w2 == 1) ? T(1) : es_kernel<T>(T(t) - a.f2[j], a.tw2, a.beta2);
+      const int ax = lane >> 4, t = lane & 15;
+      const T f = ax == 0 ? a.f0[j] : (ax == 1 ? a.f1[j] : a.f2[j]);
+      const T tw = ax == 0 ? a.tw0 : (ax == 1 ? a.tw1 : a.tw2);
+      const int wa_ = ax == 0 ? a.w0 : (ax == 1 ? a.w1 : a.w2);
+      wv = es_kernel<T>(T(t) - f, tw, a.beta);
+      if (wa_ == 1) wv = T(1);
+      if (ax > 2 || t >= wa_) wv = T(0);
     }
-    if (a.mode == INTERP_POTENTIAL && lane < 48) a.wts[j * 48 + lane] = wv;
+    if (a.mode == INTERP_POTENTIAL && lane < 48) a.wts[(int64_t)j * kRec + (lane < 32 ? lane : lane + 16)] = wv;
+    wbuf[wave][lane] = wv;
+    __builtin_amdgcn_wave_barrier();
 
-    // this lane's (b, c) pairs
-    C2<T> acc[4];
-    int off[4];
-    T wyz[4];
+    C2<T> acc[NQ];
+    int off[NQ];
+    T wyz[NQ];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int p = lane + 64 * q;
+    for (int q = 0; q < NQ; ++q) {
+      const int p = lane + 64 * q;
+      const bool ok = p < NP;
+      const int bb = ok ? p / W : 0, cc = ok ? p % W : 0;
+      wyz[q] = ok ? wrow[16 + bb] * wrow[32 + cc] : T(0);
+      off[q] = (lx0 * a.E1 + ly0 + bb) * a.E2 + lz0 + cc;
       acc[q] = C2<T>{T(0), T(0)};
-      int b = p / a.w2, c = p % a.w2;
-      bool ok = p < npairs;
-      int bb = ok ? b : 0, cc = ok ? c : 0;
-      T wy = __shfl(wv, 16 + bb, 64);
-      T wz = __shfl(wv, 32 + cc, 64);
-      wyz[q] = ok ? wy * wz : T(0);
-      int gy = y0 + bb;
-      if (gy >= a.nf1) gy -= a.nf1;
-      int gz = z0 + cc;
-      if (gz >= a.nf2) gz -= a.nf2;
-      off[q] = gy * a.nf2 + gz;
     }
-    const int nq = (npairs + 63) >> 6;
-    for (int ia = 0; ia < a.w0; ++ia) {
-      T wa = __shfl(wv, ia, 64);
-      int gx = x0 + ia;
-      if (gx >= a.nf0) gx -= a.nf0;
-      const C2<T>* row = a.F + (int64_t)gx * a.nf1 * a.nf2;
+    // the outer axis: W taps in 3D, one in 2D
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < nq) {
-          C2<T> v = row[off[q]];
+    for (int ia = 0; ia < W; ++ia) {
+      if (ia < a.w0) {
+        const T wa = lane_value(wv, ia);
+        const C2<T>* row = tile + ia * plane;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const C2<T> v = row[off[q]];
           acc[q].x += wa * v.x;
           acc[q].y += wa * v.y;
         }
@@ -117,12 +169,12 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T> a) {
     }
     T sr = T(0), si = T(0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       sr += wyz[q] * acc[q].x;
       si += wyz[q] * acc[q].y;
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
+    sr = wave_total(sr);
+    si = wave_total(si);
     if (lane == 0) {
       if (a.mode == INTERP_TRANSFORM) {
         a.out[a.perm[j]] = C2<T>{sr, si};
@@ -133,41 +185,58 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T> a) {
         if (a.mode == INTERP_POTENTIAL) a.uhat[j] = C2<T>{(T)(c * re), (T)(c * im)};
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
 
   if (a.mode != INTERP_TRANSFORM && a.eparts) {
-    __shared__ double ws[kWavesPerBlock];
     if (lane == 0) ws[wave] = eacc;
     __syncthreads();
     if (threadIdx.x == 0) {
       double s = 0.0;
-      for (int i = 0; i < kWavesPerBlock; ++i) s += ws[i];
+      for (int i = 0; i < kInterpWaves; ++i) s += ws[i];
       a.eparts[blockIdx.x] = s;
     }
   }
 }
 
+template <typename T, int W>
+hipError_t launch_w(const InterpArgs<T>& a, unsigned blocks, size_t smem, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_interp<T, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_interp<T, W>), dim3(blocks), dim3(kInterpThreads), smem, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-int interp_blocks(const Plan& pl, int nodes_per_wave) {
-  int64_t per_block = (int64_t)kWavesPerBlock * nodes_per_wave;
-  return (int)((pl.Mh + per_block - 1) / per_block);
-}
+int interp_blocks(const Plan& pl) { return pl.niitems; }
 
 template <typename T>
 hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t s) {
   InterpArgs<T> a{};
-  a.Mh = pl.Mh;
   a.nf0 = pl.nf[0];
   a.nf1 = pl.nf[1];
   a.nf2 = pl.nf[2];
   a.w0 = pl.w[0];
   a.w1 = pl.w[1];
   a.w2 = pl.w[2];
-  a.beta0 = a.beta1 = a.beta2 = (T)pl.beta;
+  a.T0 = pl.T[0];
+  a.T1 = pl.T[1];
+  a.T2 = pl.T[2];
+  a.S0 = pl.S[0];
+  a.S1 = pl.S[1];
+  a.S2 = pl.S[2];
+  a.nt1 = pl.nt[1];
+  a.nt2 = pl.nt[2];
+  a.nsub = pl.nsub;
+  a.E0 = pl.E[0];
+  a.E1 = pl.E[1];
+  a.E2 = pl.E[2];
+  a.beta = (T)pl.beta;
   a.tw0 = (T)(2.0 / pl.w[0]);
   a.tw1 = (T)(2.0 / pl.w[1]);
   a.tw2 = (T)(2.0 / pl.w[2]);
+  a.items = pl.d_iitems;
   a.hdr = pl.nodes.hdr;
   a.f0 = (const T*)pl.nodes.frac[0];
   a.f1 = (const T*)pl.nodes.frac[1];
@@ -180,13 +249,24 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.wts = (T*)pl.nodes.wts;
   a.out = (C2<T>*)out;
   a.eparts = pl.d_eparts;
-  a.nodes_per_wave = kInterpNodesPerWave;
-  unsigned blocks = (unsigned)interp_blocks(pl, a.nodes_per_wave);
+  unsigned blocks = (unsigned)pl.niitems;
   if (blocks == 0) return hipSuccess;
+  const size_t smem = pl.interp_lds;
+  hipError_t e;
   stage_mark(pl, ST_INTERP, 0, s);
-  hipLaunchKernelGGL(k_interp<T>, dim3(blocks), dim3(256), 0, s, a);
+  switch (pl.width) {
+#define JGB_W(W) \
+  case W:        \
+    e = launch_w<T, W>(a, blocks, smem, s); \
+    break;
+    JGB_W(2) JGB_W(3) JGB_W(4) JGB_W(5) JGB_W(6) JGB_W(7) JGB_W(8) JGB_W(9) JGB_W(10) JGB_W(11) JGB_W(12)
+    JGB_W(13) JGB_W(14) JGB_W(15) JGB_W(16)
+#undef JGB_W
+    default:
+      e = hipErrorInvalidValue;
+  }
   stage_mark(pl, ST_INTERP, 1, s);
-  return hipGetLastError();
+  return e;
 }
 
 template hipError_t launch_interp<double>(const Plan&, InterpMode, void*, hipStream_t);

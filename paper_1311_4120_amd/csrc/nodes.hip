@@ -28,7 +28,7 @@ struct NodeParams {
   double K;
   double axis[3];
   double box[3];  // physical side lengths per internal axis (unit axis: 0)
-  int nf[3], w[3], T[3], nt[3];
+  int nf[3], w[3], T[3], nt[3], S[3];
   const double* gl_r;
   const double* gl_t;
 };
@@ -49,6 +49,7 @@ NodeParams make_params(const Plan& pl) {
     q.w[i] = pl.w[i];
     q.T[i] = pl.T[i];
     q.nt[i] = pl.nt[i];
+    q.S[i] = pl.S[i];
   }
   q.gl_r = pl.d_gl_r;
   q.gl_t = pl.d_gl_t;
@@ -195,7 +196,11 @@ __global__ void k_node_keys(NodeParams q, int64_t Mh, int* keys) {
   fine_position(q, k, s);
   footprint(q, s, st, frac);
   int b0 = st[0] / q.T[0], b1 = st[1] / q.T[1], b2 = st[2] / q.T[2];
-  keys[h] = (b0 * q.nt[1] + b1) * q.nt[2] + b2;
+  int bin = (b0 * q.nt[1] + b1) * q.nt[2] + b2;
+  int s0 = (st[0] % q.T[0]) / q.S[0], s1 = (st[1] % q.T[1]) / q.S[1], s2 = (st[2] % q.T[2]) / q.S[2];
+  int m1 = q.T[1] / q.S[1], m2 = q.T[2] / q.S[2];
+  int nsub = (q.T[0] / q.S[0]) * m1 * m2;
+  keys[h] = bin * nsub + (s0 * m1 + s1) * m2 + s2;
 }
 
 template <typename T>

@@ -13,6 +13,8 @@ namespace jgb {
 
 namespace {
 
+constexpr int kInterpChunk = 512;     // nodes per interpolation block at most
+constexpr size_t kInterpLdsMax = 120 * 1024;
 constexpr int kChunk = 4096;  // listed nodes per gather work item (one block of 4 wavefronts) at most
 
 bool is_235(int64_t n) {
@@ -230,6 +232,31 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     pl.nt[i] = (pl.nf[i] + pl.T[i] - 1) / pl.T[i];
     pl.ntiles *= pl.nt[i];
   }
+  // sub-bins: halve the largest extent until the staged neighbourhood fits
+  for (int i = 0; i < 3; ++i) pl.S[i] = pl.T[i];
+  // the last extent is padded so that (E2 - w2) is a multiple of the number of
+  // complex elements per 128-byte LDS row: consecutive lanes of the
+  // interpolation then hit distinct banks
+  auto set_extents = [&]() {
+    for (int i = 0; i < 3; ++i) pl.E[i] = pl.S[i] + pl.w[i] - 1;
+    const int per_row = pl.fp64 ? 8 : 16;
+    pl.E[2] = pl.w[2] + per_row * ((pl.S[2] - 1 + per_row - 1) / per_row);
+    if (pl.E[2] < pl.S[2] + pl.w[2] - 1) pl.E[2] = pl.S[2] + pl.w[2] - 1;
+  };
+  auto region_bytes = [&]() {
+    set_extents();
+    return (size_t)pl.E[0] * pl.E[1] * pl.E[2] * 2 * pl.real_bytes;
+  };
+  while (region_bytes() > kInterpLdsMax) {
+    int a = 2;
+    if (pl.S[0] > pl.S[a]) a = 0;
+    if (pl.S[1] > pl.S[a]) a = 1;
+    if (pl.S[a] == 1) break;
+    pl.S[a] /= 2;
+  }
+  pl.interp_lds = region_bytes();
+  if (pl.interp_lds > kInterpLdsMax) return fail(JGB_ERR_UNSUPPORTED, "interpolation neighbourhood exceeds LDS");
+  pl.nsub = (pl.T[0] / pl.S[0]) * (pl.T[1] / pl.S[1]) * (pl.T[2] / pl.S[2]);
 
   // 1D rules on the device
   TRY(dev_alloc(pl, &pl.d_gl_r, 2 * sizeof(double) * pl.n_r));
@@ -245,13 +272,30 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   std::vector<int> keys(Mh);
   TRY_HIP(hipMemcpyAsync(keys.data(), d_keys, sizeof(int) * Mh, hipMemcpyDeviceToHost, pl.stream), "keys copy");
   TRY_HIP(hipStreamSynchronize(pl.stream), "keys sync");
-  std::vector<int> bin_start(pl.ntiles + 1, 0);
-  for (int64_t h = 0; h < Mh; ++h) bin_start[keys[h] + 1]++;
-  for (int b = 0; b < pl.ntiles; ++b) bin_start[b + 1] += bin_start[b];
+  const int nkeys = pl.ntiles * pl.nsub;
+  std::vector<int> sub_start(nkeys + 1, 0);
+  for (int64_t h = 0; h < Mh; ++h) sub_start[keys[h] + 1]++;
+  for (int b = 0; b < nkeys; ++b) sub_start[b + 1] += sub_start[b];
   std::vector<int> perm(Mh);
   {
-    std::vector<int> fill(bin_start.begin(), bin_start.end() - 1);
+    std::vector<int> fill(sub_start.begin(), sub_start.end() - 1);
     for (int64_t h = 0; h < Mh; ++h) perm[fill[keys[h]]++] = (int)h;
+  }
+  std::vector<int> bin_start(pl.ntiles + 1, 0);
+  for (int b = 0; b <= pl.ntiles; ++b) bin_start[b] = sub_start[(size_t)b * pl.nsub];
+  // interpolation work items: nonempty sub-bins, long ones split
+  {
+    std::vector<Plan::InterpItem> iit;
+    for (int k = 0; k < nkeys; ++k) {
+      for (int b = sub_start[k]; b < sub_start[k + 1]; b += kInterpChunk)
+        iit.push_back(Plan::InterpItem{k, b, std::min(sub_start[k + 1], b + kInterpChunk)});
+    }
+    std::stable_sort(iit.begin(), iit.end(), [](const Plan::InterpItem& x, const Plan::InterpItem& y) {
+      return (x.end - x.begin) > (y.end - y.begin);
+    });
+    pl.niitems = (int)iit.size();
+    TRY(dev_alloc(pl, &pl.d_iitems, sizeof(Plan::InterpItem) * iit.size()));
+    TRY(upload(pl, pl.d_iitems, iit.data(), sizeof(Plan::InterpItem) * iit.size()));
   }
   TRY(dev_alloc(pl, &pl.nodes.perm, sizeof(int) * Mh));
   TRY(upload(pl, pl.nodes.perm, perm.data(), sizeof(int) * Mh));
@@ -259,7 +303,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   for (int i = 0; i < 3; ++i) TRY(dev_alloc(pl, &pl.nodes.frac[i], pl.real_bytes * Mh));
   TRY(dev_alloc(pl, &pl.nodes.coef, sizeof(double) * Mh));
   TRY(dev_alloc(pl, &pl.nodes.uhat, 2 * pl.real_bytes * Mh));
-  TRY(dev_alloc(pl, &pl.nodes.wts, 48 * pl.real_bytes * Mh));
+  TRY(dev_alloc(pl, &pl.nodes.wts, kRec * pl.real_bytes * Mh));
+  TRY_HIP(hipMemsetAsync(pl.nodes.wts, 0, kRec * pl.real_bytes * Mh, pl.stream), "clear kernel values");
   TRY_HIP(launch_node_setup(pl, pl.nodes.perm, pl.stream), "node setup");
   TRY(dev_alloc(pl, &pl.d_bin_start, sizeof(int) * (pl.ntiles + 1)));
   TRY(upload(pl, pl.d_bin_start, bin_start.data(), sizeof(int) * (pl.ntiles + 1)));
@@ -294,7 +339,9 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   for (int t = 0; t < pl.ntiles; ++t) tcount[t + 1] += tcount[t];
   const int64_t nlist = tcount[pl.ntiles];
   if (nlist > (int64_t)std::numeric_limits<int>::max()) return fail(JGB_ERR_UNSUPPORTED, "gather lists too long");
-  std::vector<int> list(std::max<int64_t>(nlist, 1));
+  // entry: node index and its first tap relative to the tile origin on each
+  // axis, modulo the grid (10 bits each; nf <= 1024)
+  std::vector<int2> list(nlist + 1, make_int2(0, 0));  // one spare entry
   {
     std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
     int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
@@ -302,11 +349,17 @@ Status build_plan(Plan& pl, const jgb_params* p) {
       int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
       for (int a0 = 0; a0 < nx; ++a0)
         for (int a1 = 0; a1 < ny; ++a1)
-          for (int a2 = 0; a2 < nz; ++a2) list[fill[(tx[a0] * pl.nt[1] + ty[a1]) * pl.nt[2] + tz[a2]]++] = (int)j;
+          for (int a2 = 0; a2 < nz; ++a2) {
+            const int tile = (tx[a0] * pl.nt[1] + ty[a1]) * pl.nt[2] + tz[a2];
+            const int ex = ((hdr[j].x - tx[a0] * pl.T[0]) % pl.nf[0] + pl.nf[0]) % pl.nf[0];
+            const int ey = ((hdr[j].y - ty[a1] * pl.T[1]) % pl.nf[1] + pl.nf[1]) % pl.nf[1];
+            const int ez = ((hdr[j].z - tz[a2] * pl.T[2]) % pl.nf[2] + pl.nf[2]) % pl.nf[2];
+            list[fill[tile]++] = make_int2((int)j, ex | (ey << 10) | (ez << 20));
+          }
     }
   }
-  TRY(dev_alloc(pl, &pl.d_list, sizeof(int) * list.size()));
-  TRY(upload(pl, pl.d_list, list.data(), sizeof(int) * list.size()));
+  TRY(dev_alloc(pl, &pl.d_list, sizeof(int2) * list.size()));
+  TRY(upload(pl, pl.d_list, list.data(), sizeof(int2) * list.size()));
   pl.nlist = nlist;
 
   // gather work items: one block per tile, more for tiles with long lists
@@ -374,7 +427,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   size_t ngrid = (size_t)pl.nf[0] * pl.nf[1] * pl.nf[2];
   TRY(dev_alloc(pl, &pl.d_F, ngrid * 2 * pl.real_bytes));
   TRY(dev_alloc(pl, &pl.d_G, ngrid * 2 * pl.real_bytes));
-  pl.neparts = std::max(fft_inverse_z_blocks(pl), interp_blocks(pl, kInterpNodesPerWave));
+  pl.neparts = std::max(fft_inverse_z_blocks(pl), interp_blocks(pl));
   pl.neparts = std::max(pl.neparts, 1);
   TRY(dev_alloc(pl, &pl.d_eparts, sizeof(double) * pl.neparts));
   TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");

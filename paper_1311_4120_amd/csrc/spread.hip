@@ -32,10 +32,9 @@ struct SpreadArgs {
   int w0, w1, w2;
   int T0, T1;
   int nt1, nt2;
-  const int* list;
+  const int2* list;
   const WorkItem* items;
   int nitems;
-  const int4* hdr;
   const C2<T>* uhat;
   const T* wts;
   C2<T>* G;
@@ -44,37 +43,19 @@ struct SpreadArgs {
 
 constexpr int kWaves = 4;
 
-// Add the node's z taps to the tile column.  Tap t lands on tile z index O + t;
-// O is the node's first tap relative to the tile, a compile-time constant per
-// instantiation, so accumulators and weights are addressed statically.
-// Weights past the kernel width are stored as zeros.
-template <typename T, int O>
-__device__ __forceinline__ void add_column(T (&ar)[kTileZ], T (&ai)[kTileZ], const T (&wz)[kMaxWidth], T pr, T pi) {
-#pragma unroll
-  for (int t = 0; t < kMaxWidth; ++t) {
-    const int z = O + t;
-    if (z >= 0 && z < kTileZ) {
-      ar[z] += wz[t] * pr;
-      ai[z] += wz[t] * pi;
-    }
-  }
-}
-
+// Add one node's contribution to the wavefront's tile column.  o is the
+// node's first a2 tap relative to the tile origin (uniform); the 16 kernel
+// values that land on tile z = 0..15 are the window rec[kRecZ - o + z] of the
+// zero-padded record, read with one uniform load, so the update is the same
+// 32 multiply-adds for every node with no branch on o.
 template <typename T>
-__device__ __forceinline__ void add_column_dispatch(int o, T (&ar)[kTileZ], T (&ai)[kTileZ], const T (&wz)[kMaxWidth],
-                                                    T pr, T pi) {
-  switch (o) {
-#define JGB_CASE(O) \
-  case O:           \
-    add_column<T, O>(ar, ai, wz, pr, pi); \
-    break;
-    JGB_CASE(-15) JGB_CASE(-14) JGB_CASE(-13) JGB_CASE(-12) JGB_CASE(-11) JGB_CASE(-10) JGB_CASE(-9)
-    JGB_CASE(-8) JGB_CASE(-7) JGB_CASE(-6) JGB_CASE(-5) JGB_CASE(-4) JGB_CASE(-3) JGB_CASE(-2) JGB_CASE(-1)
-    JGB_CASE(0) JGB_CASE(1) JGB_CASE(2) JGB_CASE(3) JGB_CASE(4) JGB_CASE(5) JGB_CASE(6) JGB_CASE(7)
-    JGB_CASE(8) JGB_CASE(9) JGB_CASE(10) JGB_CASE(11) JGB_CASE(12) JGB_CASE(13) JGB_CASE(14) JGB_CASE(15)
-#undef JGB_CASE
-    default:
-      break;
+__device__ __forceinline__ void add_window(T (&ar)[kTileZ], T (&ai)[kTileZ], const T* rec, int o, T pr, T pi) {
+  const T* wz = rec + (kRecZ - o);
+#pragma unroll
+  for (int z = 0; z < kTileZ; ++z) {
+    const T v = wz[z];
+    ar[z] += v * pr;
+    ai[z] += v * pi;
   }
 }
 
@@ -82,7 +63,11 @@ __device__ __forceinline__ void add_column_dispatch(int o, T (&ar)[kTileZ], T (&
 // wavefronts each take a contiguous quarter of the range and accumulate the
 // whole 8 x 8 x kTileZ tile in registers; the partial tiles are then summed
 // in LDS in a fixed order and written once.
-template <typename T>
+//
+// Nodes are taken B at a time: the scalar loads of a batch (node values and
+// z windows) are issued together and the next batch's list entries ride along,
+// so one round trip to the scalar cache serves B nodes.
+template <typename T, int B>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   __shared__ C2<T> red[2][64 * kTileZ];
   const int lane = threadIdx.x & 63;
@@ -107,45 +92,50 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int q = (n + kWaves - 1) / kWaves;
   const int kb = item.vbegin + wave * q;
   const int ke = (kb + q < item.vend) ? kb + q : item.vend;
+  const int last = ke - 1;
 
-  // x and y kernel values of the next node: lanes 0..15 hold phi_x, 16..31 phi_y
-  int jn = 0;
-  T wxyn = T(0);
+  int2 ent[B];
   if (kb < ke) {
-    jn = a.list[kb];
-    wxyn = a.wts[(int64_t)jn * 48 + (lane & 31)];
-  }
-  for (int k = kb; k < ke; ++k) {
-    const int j = jn;
-    const T wxy = wxyn;
-    const int4 h = a.hdr[j];
-    const C2<T> u = a.uhat[j];
-    const T* wj = a.wts + (int64_t)j * 48;
-    T wz[kMaxWidth];
 #pragma unroll
-    for (int t = 0; t < kMaxWidth; ++t) wz[t] = wj[32 + t];
-    if (k + 1 < ke) {
-      jn = a.list[k + 1];
-      wxyn = a.wts[(int64_t)jn * 48 + (lane & 31)];
+    for (int b = 0; b < B; ++b) ent[b] = a.list[kb + b <= last ? kb + b : last];
+  }
+  for (int k = kb; k < ke; k += B) {
+    int2 cur[B];
+    C2<T> u[B];
+    T wxy[B];
+    const T* rec[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      cur[b] = ent[b];
+      rec[b] = a.wts + (int64_t)cur[b].x * kRec;
+      u[b] = a.uhat[cur[b].x];
+      wxy[b] = rec[b][lane & 31];
     }
-    // first tap of the footprint relative to the tile origin, modulo the grid
-    int ex = h.x - o0;
-    if (ex < 0) ex += a.nf0;
-    int ey = h.y - o1;
-    if (ey < 0) ey += a.nf1;
-    int ez = h.z - o2;
-    if (ez < 0) ez += a.nf2;
-    int dx = lx - ex;
-    if (dx < 0) dx += a.nf0;
-    int dy = ly - ey;
-    if (dy < 0) dy += a.nf1;
-    const bool in = lane_ok && dx < a.w0 && dy < a.w1;
-    const T wx = __shfl(wxy, dx & 15, 64);
-    const T wy = __shfl(wxy, 16 + (dy & 15), 64);
-    const T p = in ? wx * wy : T(0);
-    const T pr = p * u.x, pi = p * u.y;
-    if (ez < kTileZ) add_column_dispatch<T>(ez, ar, ai, wz, pr, pi);   // footprint starts inside the tile
-    if (a.nf2 - ez < a.w2) add_column_dispatch<T>(ez - a.nf2, ar, ai, wz, pr, pi);  // starts before it
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const int kn = k + B + b;
+      ent[b] = a.list[kn <= last ? kn : last];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (k + b > last) break;
+      const int ex = cur[b].y & 1023, ey = (cur[b].y >> 10) & 1023, ez = (cur[b].y >> 20) & 1023;
+      int dx = lx - ex;
+      if (dx < 0) dx += a.nf0;
+      int dy = ly - ey;
+      if (dy < 0) dy += a.nf1;
+      const bool in = lane_ok && dx < a.w0 && dy < a.w1;
+      const T wx = __shfl(wxy[b], dx & 15, 64);
+      const T wy = __shfl(wxy[b], 16 + (dy & 15), 64);
+      const T p = in ? wx * wy : T(0);
+      const T pr = p * u[b].x, pi = p * u[b].y;
+      // the footprint starts inside the tile (o = ez) or before it and wraps in
+      // (o = ez - nf2 > -w2); on grids narrower than kTileZ + w2 both can hold
+      const bool zin = ez < kTileZ;
+      const bool zwrap = a.nf2 - ez < a.w2;
+      add_window(ar, ai, rec[b], zin ? ez : ez - a.nf2, pr, pi);
+      if (zin && zwrap) add_window(ar, ai, rec[b], ez - a.nf2, pr, pi);
+    }
   }
 
   // fixed-order sum of the four partial tiles: (w0 + w2) + (w1 + w3)
@@ -246,7 +236,6 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.list = pl.d_list;
   a.items = pl.d_items;
   a.nitems = pl.nitems;
-  a.hdr = pl.nodes.hdr;
   a.uhat = (const C2<T>*)pl.nodes.uhat;
   a.wts = (const T*)pl.nodes.wts;
   a.G = (C2<T>*)pl.d_G;
@@ -254,7 +243,8 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   unsigned blocks = (unsigned)pl.nitems;
   if (blocks == 0) return hipErrorInvalidConfiguration;
   stage_mark(pl, ST_SPREAD, 0, s);
-  hipLaunchKernelGGL(k_spread_gather<T>, dim3(blocks), dim3(256), 0, s, a);
+  constexpr int kBatch = sizeof(T) == 8 ? 2 : 4;
+  hipLaunchKernelGGL((k_spread_gather<T, kBatch>), dim3(blocks), dim3(256), 0, s, a);
   stage_mark(pl, ST_SPREAD, 1, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
