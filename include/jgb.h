@@ -142,6 +142,24 @@ jgb_status jgb_energy(jgb_plan_t plan, const void* rho, double* energy);
  * plan's dtype; must not overlap.  Enqueue only. */
 jgb_status jgb_potential_backward(jgb_plan_t plan, const void* grad_u, void* grad_rho);
 
+/* Density of a wave function, rho = |psi|^2 (the introduction, after eq.
+ * gpe2).  psi: device complex array (interleaved re, im) of prod N_j elements
+ * of the plan's real dtype; rho: device real array.  Must not overlap.
+ * Enqueue only. */
+jgb_status jgb_density(jgb_plan_t plan, const void* psi, void* rho);
+
+/* Gradient of the interaction energy E(|psi|^2) = (lambda/2) H sum |psi|^2 u
+ * (eq. gpe2) with respect to conj(psi): since u = A rho with A symmetric,
+ * dE/drho = lambda H u and dE/dpsi* = lambda H u psi.  Writes
+ *   grad = factor * g * lambda * H * u * psi,
+ * where g = *gscale (a device float64, e.g. the upstream gradient of a
+ * scalar loss; NULL means 1) and factor is a host constant (2 gives PyTorch's
+ * convention for complex inputs, grad = dL/dRe + i dL/dIm = 2 dL/dpsi*).
+ * psi, grad: device complex arrays; u: device real array from jgb_potential
+ * of rho = |psi|^2.  grad must not overlap u.  Enqueue only. */
+jgb_status jgb_psi_gradient(jgb_plan_t plan, const void* psi, const void* u, const double* gscale, double factor,
+                            void* grad);
+
 /* Type-2 stage alone (Algorithm 1, step 4), for diagnostics: rho^_j at the
  * device's half node set (k_j with phi index l < n_phi/2; the other half is
  * conj(rho^) at -k_j), in natural node order (radial index slowest, then

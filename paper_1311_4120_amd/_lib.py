@@ -84,6 +84,8 @@ def _load():
         "jgb_potential_backward": (st, [P, P, P]),
         "jgb_transform": (st, [P, P, P]),
         "jgb_nodes": (st, [P, P, P, P]),
+        "jgb_density": (st, [P, P, P]),
+        "jgb_psi_gradient": (st, [P, P, P, P, ctypes.c_double, P]),
         "jgb_plan_info": (st, [P, ctypes.POINTER(Info)]),
         "jgb_destroy": (st, [P]),
         "jgb_last_error": (ctypes.c_char_p, []),

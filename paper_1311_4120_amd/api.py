@@ -105,6 +105,32 @@ class Plan:
         check(lib.jgb_potential_backward(self._h, _ptr(grad_u), _ptr(g)))
         return g
 
+    def _check_psi(self, psi):
+        cdt = torch.complex128 if self.dtype == torch.float64 else torch.complex64
+        if not isinstance(psi, torch.Tensor) or psi.device != self.device or psi.dtype != cdt \
+                or tuple(psi.shape) != self.n or not psi.is_contiguous():
+            raise ValueError("psi must be a contiguous %s tensor of shape %s on %s" % (cdt, self.n, self.device))
+
+    def density(self, psi, out=None):
+        """rho = |psi|^2 (kernel on the plan's stream)."""
+        self._check_psi(psi)
+        rho = torch.empty(self.n, dtype=self.dtype, device=self.device) if out is None else out
+        check(lib.jgb_density(self._h, _ptr(psi), _ptr(rho)))
+        return rho
+
+    def psi_gradient(self, psi, u, gscale=None, factor=2.0, out=None):
+        """factor * gscale * lambda * H * u * psi: with factor 2 the PyTorch gradient of E(|psi|^2)."""
+        self._check_psi(psi)
+        self._check_grid(u, "u")
+        grad = torch.empty_like(psi) if out is None else out
+        g = None
+        if gscale is not None:
+            if gscale.dtype != torch.float64 or gscale.device != self.device or gscale.numel() != 1:
+                raise ValueError("gscale must be a float64 scalar tensor on %s" % self.device)
+            g = _ptr(gscale)
+        check(lib.jgb_psi_gradient(self._h, _ptr(psi), _ptr(u), g, float(factor), _ptr(grad)))
+        return grad
+
     def transform(self, rho):
         """rho^ at the half node set (phi index < n_phi/2) in natural order."""
         self._check_grid(rho, "rho")
@@ -144,3 +170,28 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class InteractionEnergy(torch.autograd.Function):
+    """E(psi) = (lambda/2) H sum |psi|^2 (U * |psi|^2) with the plan's kernel; the
+    backward returns PyTorch's complex gradient 2 g dE/dpsi* = 2 g lambda H u psi.
+    Every step (|psi|^2, the convolution, the energy sum, the gradient) is a
+    kernel of the library."""
+
+    @staticmethod
+    def forward(ctx, psi, plan):
+        rho = plan.density(psi)
+        u, E = plan.potential(rho)
+        ctx.save_for_backward(psi, u)
+        ctx.plan = plan
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        psi, u = ctx.saved_tensors
+        g = gE.detach().to(torch.float64).contiguous()
+        return ctx.plan.psi_gradient(psi, u, gscale=g, factor=2.0), None
+
+
+# the dipolar energy of the dipole kernel is the same function with a dipole plan
+DipolarEnergy = InteractionEnergy

@@ -2,6 +2,7 @@
 // arguments, makes the plan's device current, enqueues kernels on the plan's
 // stream and converts every failure into a status code and a thread-local
 // message.  Nothing is thrown across the ABI.
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -169,6 +170,32 @@ jgb_status jgb_transform(jgb_plan_t plan, const void* rho, void* rhohat) {
   Plan& pl = plan->pl;
   if (!rho || !rhohat) return report(JGB_ERR_INVALID_ARG, "rho and rhohat must not be NULL");
   return pl.fp64 ? run_transform<double>(pl, rho, rhohat) : run_transform<float>(pl, rho, rhohat);
+}
+
+jgb_status jgb_density(jgb_plan_t plan, const void* psi, void* rho) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!psi || !rho) return report(JGB_ERR_INVALID_ARG, "psi and rho must not be NULL");
+  size_t nb = grid_bytes(pl);
+  if (overlap(psi, 2 * nb, rho, nb)) return report(JGB_ERR_INVALID_ARG, "psi and rho overlap");
+  hipError_t e = pl.fp64 ? jgb::launch_density<double>(pl, psi, rho, pl.stream)
+                         : jgb::launch_density<float>(pl, psi, rho, pl.stream);
+  return from_hip(e, "density");
+}
+
+jgb_status jgb_psi_gradient(jgb_plan_t plan, const void* psi, const void* u, const double* gscale, double factor,
+                            void* grad) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!psi || !u || !grad) return report(JGB_ERR_INVALID_ARG, "psi, u and grad must not be NULL");
+  if (!std::isfinite(factor)) return report(JGB_ERR_INVALID_ARG, "factor must be finite");
+  size_t nb = grid_bytes(pl);
+  if (overlap(grad, 2 * nb, u, nb)) return report(JGB_ERR_INVALID_ARG, "grad and u overlap");
+  hipError_t e = pl.fp64 ? jgb::launch_psi_gradient<double>(pl, psi, u, gscale, factor, grad, pl.stream)
+                         : jgb::launch_psi_gradient<float>(pl, psi, u, gscale, factor, grad, pl.stream);
+  return from_hip(e, "psi gradient");
 }
 
 jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* cc) {

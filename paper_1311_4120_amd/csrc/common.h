@@ -192,6 +192,11 @@ template <typename T>
 hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t s);
 template <typename T>
 hipError_t launch_spread(const Plan& pl, hipStream_t s);
+template <typename T>
+hipError_t launch_density(const Plan& pl, const void* psi, void* rho, hipStream_t s);
+template <typename T>
+hipError_t launch_psi_gradient(const Plan& pl, const void* psi, const void* u, const double* gscale, double factor,
+                               void* grad, hipStream_t s);
 int fft_inverse_z_blocks(const Plan& pl);
 int interp_blocks(const Plan& pl);
 hipError_t launch_energy_finalize(const double* parts, int n, double scale, double* out, hipStream_t s);

@@ -1,0 +1,141 @@
+"""Differentiable interaction energy E(|psi|^2) through torch.autograd
+(InteractionEnergy / DipolarEnergy), every step a library kernel.
+
+Checks: the gradient against the oracle's 2 lambda H u psi (u from the direct
+sums); torch.autograd.gradcheck; central finite differences in complex128 on
+the FP64 path along random directions and at single entries; the
+complex64 (mixed) gradient against the FP64 one; and the 256^3 wave-packet
+workload (forward + backward at full size, finite differences along random
+directions)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import make_plan, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _small_problem(eps=1e-12, precision=wl.FP64):
+    rng = np.random.default_rng(31)
+    axis = tuple(wl.unit_vector(rng))
+    return wl.Problem("grad_small", 3, (20, 16, 24), (10.0, 8.0, 12.0), wl.DIPOLE_3D, 16, 12, 20,
+                      theta_rule=wl.COSTHETA_GL, axis=axis, eps=eps, precision=precision, lam=1.7)
+
+
+def _psi(p, seed=32):
+    rng = np.random.default_rng(seed)
+    pk = wl.random_wave_packets(rng, p=3, lo=-1.5, hi=1.5)
+    pk.widths[:] = rng.uniform(0.9, 1.3, size=len(pk.widths))
+    return pk.evaluate(p.n, p.box)
+
+
+def _energy(plan, psi_t):
+    import paper_1311_4120_amd as jgb
+    return jgb.DipolarEnergy.apply(psi_t, plan)
+
+
+def test_gradient_matches_oracle():
+    p = _small_problem()
+    say("autograd vs oracle")
+    plan = make_plan(p)
+    psi = _psi(p)
+    pt = torch.tensor(psi, dtype=torch.complex128, device="cuda", requires_grad=True)
+    E = _energy(plan, pt)
+    E.backward()
+    g = pt.grad.cpu().numpy()
+    res = oracle.evaluate(p, np.abs(psi) ** 2)
+    gref = 2 * oracle.energy_gradient_psi(res.u, psi, p.box, p.lam)
+    e = rel_l2(g, gref)
+    eE = abs(E.item() - res.energy_physical) / (0.5 * np.sum(np.abs(res.c) * np.abs(res.rhohat) ** 2))
+    say("   grad relL2 %.2e, E err %.2e" % (e, eE))
+    assert e < 1e-10 and eE < 1e-10
+    plan.close()
+
+
+def test_gradcheck():
+    p = wl.Problem("gc", 3, (8, 8, 8), (6.0, 6.0, 6.0), wl.DIPOLE_3D, 8, 6, 8, axis=(0.6, 0.0, 0.8),
+                   eps=1e-12)
+    say("gradcheck 8^3")
+    plan = make_plan(p)
+    psi = torch.tensor(_psi(p, 33), dtype=torch.complex128, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x: _energy(plan, x), (psi,), eps=1e-6, atol=1e-7, rtol=1e-5)
+    plan.close()
+
+
+def test_finite_differences_complex128():
+    p = _small_problem()
+    say("finite differences")
+    plan = make_plan(p)
+    psi = torch.tensor(_psi(p, 34), dtype=torch.complex128, device="cuda", requires_grad=True)
+    E = _energy(plan, psi)
+    E.backward()
+    g = psi.grad.detach()
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    d = 1e-4
+    with torch.no_grad():
+        for _ in range(4):
+            v = torch.randn(p.n, dtype=torch.complex128, generator=gen).cuda()
+            v /= torch.linalg.norm(v)
+            fd = (_energy(plan, psi + d * v) - _energy(plan, psi - d * v)).item() / (2 * d)
+            an = torch.sum(torch.conj(g) * v).real.item()
+            say("   direction: fd %.12e  analytic %.12e" % (fd, an))
+            assert abs(fd - an) < 1e-7 * max(1e-3, abs(an)) + 1e-12
+        idx = [(0, 0, 0), (10, 8, 12), (5, 3, 17), (19, 15, 23)]
+        for ix in idx:
+            for unit in (1.0, 1j):
+                e = torch.zeros(p.n, dtype=torch.complex128, device="cuda")
+                e[ix] = unit
+                fd = (_energy(plan, psi + d * e) - _energy(plan, psi - d * e)).item() / (2 * d)
+                an = (g[ix].real if unit == 1.0 else g[ix].imag).item()
+                # central differences of E ~ 0.1 carry ~1e-16 E / (2 d) ~ 1e-12 of rounding noise
+                assert abs(fd - an) < 1e-6 * abs(an) + 2e-11, (ix, unit, fd, an)
+    plan.close()
+
+
+def test_mixed_gradient_against_fp64():
+    p = _small_problem()
+    say("mixed vs fp64 gradient")
+    psi = _psi(p, 35)
+    p64 = make_plan(p)
+    pm = make_plan(p, eps=1e-5, precision="mixed")
+    a = torch.tensor(psi, dtype=torch.complex128, device="cuda", requires_grad=True)
+    b = torch.tensor(psi, dtype=torch.complex64, device="cuda", requires_grad=True)
+    _energy(p64, a).backward()
+    _energy(pm, b).backward()
+    e = rel_l2(b.grad.cpu().numpy().astype(np.complex128), a.grad.cpu().numpy())
+    say("   relL2 %.2e" % e)
+    assert e < 1e-5
+    p64.close()
+    pm.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_dipole_grad_256(prec):
+    """256^3 wave packets, nodes (256,128,256): forward + backward at full size and
+    finite differences (complex128 on the FP64 path) along random directions."""
+    p, packets = wl.dipole_grad_256()
+    say("dipole_grad_256", prec)
+    eps = 1e-5 if prec == "mixed" else 1e-12
+    plan = make_plan(p, eps=eps, precision=prec)
+    cdt = torch.complex64 if prec == "mixed" else torch.complex128
+    psi = torch.tensor(packets.evaluate(p.n, p.box), dtype=cdt, device="cuda", requires_grad=True)
+    E = _energy(plan, psi)
+    E.backward()
+    g = psi.grad.detach()
+    assert torch.isfinite(g).all() and np.isfinite(E.item())
+    say("   E = %.12e" % E.item())
+    if prec == "fp64":
+        gen = torch.Generator(device="cpu").manual_seed(8)
+        d = 1e-4
+        with torch.no_grad():
+            for _ in range(3):
+                v = torch.randn(p.n, dtype=torch.complex128, generator=gen).cuda()
+                v /= torch.linalg.norm(v)
+                fd = (_energy(plan, psi + d * v) - _energy(plan, psi - d * v)).item() / (2 * d)
+                an = torch.sum(torch.conj(g) * v).real.item()
+                say("   direction: fd %.12e  analytic %.12e" % (fd, an))
+                assert abs(fd - an) < 1e-6 * max(1e-4, abs(an)) + 1e-11
+    plan.close()
