@@ -93,6 +93,40 @@ def run_gpu(prec, steps, warmup):
             "plan_s": plan_s, "energy": energy, "info": info, "eps": p.eps}
 
 
+def run_batched(steps, warmup):
+    """64 seeded Gaussian-mixture densities, N in {64, 96, 128, 160}, mixed
+    precision, evaluated by one HIP graph launch per step."""
+    import torch
+
+    import paper_1311_4120_amd as jgb
+    import workloads as wl
+
+    members = wl.batched_coulomb()
+    kws = [dict(n=p.n, box=p.box, kernel="coulomb3d", nodes=(p.n_r, p.n_theta, p.n_phi), eps=p.eps,
+                precision="mixed") for p, _ in members]
+    t0 = time.time()
+    b = jgb.Batch(kws, nstreams=4)
+    rhos = [torch.tensor(mix.evaluate(p.n, p.box), dtype=torch.float32, device="cuda") for p, mix in members]
+    b.bind(rhos)
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    for _ in range(warmup):
+        b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    npts = sum(p.npoints for p, _ in members)
+    nodes = sum(p.nnodes for p, _ in members)
+    b.close()
+    return {"workload": "batched_coulomb", "members": len(members), "grid_points": npts, "nodes": nodes,
+            "ms_per_launch": 1e3 * wall / steps, "evals_per_s": len(members) * steps / wall,
+            "grid_points_per_s": npts * steps / wall, "launches": steps, "plan_and_capture_s": plan_s,
+            "precision": "mixed", "eps": 1e-5, "graph": "one hipGraph launch per step over 4 branches"}
+
+
 def cpu_baseline(sample_nodes=32768):
     """The oracle (direct O(N M) sums) on a bounded sample of the same workload:
     the type-2 sum at every 32nd node and the type-1 sum from those nodes to the
@@ -127,6 +161,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
@@ -197,6 +232,9 @@ def main():
                         "width": m["info"]["width"], "energy": m["energy"],
                         "speedup_vs_fp64": r["ms_per_step"] / m["ms_per_step"],
                         "stages_ms": {k: v for k, v in m["stages_ms"].items() if v > 0}}
+    if not args.no_batched and args.only is None:
+        print("[bench] batched_coulomb: 64 densities, one graph launch per step", file=sys.stderr, flush=True)
+        out["batched"] = run_batched(max(3, args.steps // 10), 2)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

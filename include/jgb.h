@@ -195,6 +195,43 @@ jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* c);
 jgb_status jgb_timing_begin(jgb_plan_t plan, int max_calls);
 jgb_status jgb_timing_end(jgb_plan_t plan, double* stage_ms, int* calls);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent densities evaluated together, as in the repeated
+ * evaluations of a time-splitting or ground-state solver (Section 1: u is
+ * needed on the grid many times for different rho).  A batch owns one plan
+ * per member; binding device buffers captures every member's full pipeline
+ * (forward FFT, interpolation, spreading, inverse FFT, energy) into one HIP
+ * graph whose independent members run on up to nstreams concurrent branches
+ * (longest members first, each to the least loaded branch).  Each evaluation
+ * of the whole batch is then one graph launch. */
+typedef struct jgb_batch_s* jgb_batch_t;
+
+/* Create the member plans (as jgb_plan each; all params must name
+ * params[0].device and params[0].stream) and nstreams streams of the batch's
+ * own at default priority (the graph is captured on them, so params[0].stream
+ * may be the NULL stream).  count in [1, 65536], nstreams in [1, 8].
+ * Errors as jgb_plan (the message names the failing member). */
+jgb_status jgb_batch_create(const jgb_params* params, int count, int nstreams, jgb_batch_t* out);
+
+/* Bind member i to the device arrays rho[i] -> u[i] (its grid and dtype) and,
+ * if energies != NULL, its energy to energies[i] (device float64 array of
+ * count).  The host arrays rho and u are read during the call only.
+ * Synchronises the batch stream, then captures and instantiates the graph
+ * (replacing a previous one).  Member plans must not have timing enabled. */
+jgb_status jgb_batch_bind(jgb_batch_t batch, const void* const* rho, void* const* u, double* energies);
+
+/* Evaluate every member: the graph runs on a stream owned by the batch,
+ * ordered after the work already enqueued on params[0].stream, and later work
+ * on params[0].stream is ordered after it.  Enqueue only.  INVALID_ARG if
+ * nothing is bound. */
+jgb_status jgb_batch_run(jgb_batch_t batch);
+
+/* Member plan i (owned by the batch: do not destroy it). */
+jgb_status jgb_batch_plan(jgb_batch_t batch, int i, jgb_plan_t* plan);
+
+/* Synchronise, then free the graph, streams, events and member plans. */
+jgb_status jgb_batch_destroy(jgb_batch_t batch);
+
 /* Copy plan facts into *info (host memory, info->struct_size must be set). */
 jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info);
 

@@ -90,6 +90,11 @@ def _load():
         "jgb_destroy": (st, [P]),
         "jgb_last_error": (ctypes.c_char_p, []),
         "jgb_timing_begin": (st, [P, ctypes.c_int]),
+        "jgb_batch_create": (st, [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)]),
+        "jgb_batch_bind": (st, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
+        "jgb_batch_run": (st, [P]),
+        "jgb_batch_plan": (st, [P, ctypes.c_int, ctypes.POINTER(P)]),
+        "jgb_batch_destroy": (st, [P]),
         "jgb_timing_end": (st, [P, P, P]),
     }
     for name, (res, args) in sig.items():

@@ -19,6 +19,37 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream):
+    dim = len(n)
+    kern = _KERNELS.get(kernel, kernel)
+    rule = _RULES.get(theta_rule, theta_rule)
+    dev = torch.cuda.current_device() if device is None else int(device)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    p = _lib.Params()
+    p.struct_size = ctypes.sizeof(_lib.Params)
+    p.dim = dim
+    for i in range(dim):
+        p.n[i] = int(n[i])
+        p.box[i] = float(box[i])
+    p.kernel = int(kern)
+    for i in range(3):
+        p.dipole_axis[i] = float(axis[i]) if i < len(axis) else 0.0
+    p.lam = float(lam)
+    p.eps = float(eps)
+    p.precision = _lib.FP64 if precision == "fp64" else _lib.MIXED
+    if dim == 3:
+        p.n_r, p.n_theta, p.n_phi = (int(v) for v in nodes)
+    else:
+        p.n_r, p.n_phi = int(nodes[0]), int(nodes[-1])
+        p.n_theta = 1
+    p.theta_rule = int(rule)
+    p.kmax = float(kmax)
+    p.device = dev
+    p.stream = ctypes.c_void_p(st.cuda_stream)
+    p.flags = 0
+    return p, dev, st
+
+
 class Plan:
     """A planned free-space convolution u = U*rho on one uniform grid.
 
@@ -32,49 +63,39 @@ class Plan:
                  eps: float = 1e-10, precision: str = "fp64", lam: float = 1.0,
                  axis: Sequence[float] = (0.0, 0.0, 1.0), theta_rule="theta", kmax: float = 0.0,
                  device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None):
-        dim = len(n)
-        kern = _KERNELS.get(kernel, kernel)
-        rule = _RULES.get(theta_rule, theta_rule)
-        dev = torch.cuda.current_device() if device is None else int(device)
-        st = stream if stream is not None else torch.cuda.current_stream(dev)
-        p = _lib.Params()
-        p.struct_size = ctypes.sizeof(_lib.Params)
-        p.dim = dim
-        for i in range(dim):
-            p.n[i] = int(n[i])
-            p.box[i] = float(box[i])
-        p.kernel = int(kern)
-        for i in range(3):
-            p.dipole_axis[i] = float(axis[i]) if i < len(axis) else 0.0
-        p.lam = float(lam)
-        p.eps = float(eps)
-        p.precision = _lib.FP64 if precision == "fp64" else _lib.MIXED
-        if dim == 3:
-            p.n_r, p.n_theta, p.n_phi = (int(v) for v in nodes)
-        else:
-            p.n_r, p.n_phi = int(nodes[0]), int(nodes[-1])
-            p.n_theta = 1
-        p.theta_rule = int(rule)
-        p.kmax = float(kmax)
-        p.device = dev
-        p.stream = ctypes.c_void_p(st.cuda_stream)
-        p.flags = 0
+        p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream)
+        self._init_from(p, dev, st, box)
+        h = ctypes.c_void_p()
+        check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))
+        self._set_handle(h, owned=True)
+
+    @classmethod
+    def _member(cls, p, dev, st, box, handle):
+        self = cls.__new__(cls)
+        self._init_from(p, dev, st, box)
+        self._set_handle(handle, owned=False)
+        return self
+
+    def _init_from(self, p, dev, st, box):
         self._params = p
-        self.n = tuple(int(v) for v in n)
+        dim = p.dim
+        self.n = tuple(int(p.n[i]) for i in range(dim))
         self.dim = dim
         self.device = torch.device("cuda", dev)
         self.stream = st
         self.dtype = torch.float64 if p.precision == _lib.FP64 else torch.float32
-        self.lam = float(lam)
-        self.H = math.prod(float(b) / int(m) for b, m in zip(box, n))
-        h = ctypes.c_void_p()
-        check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))
+        self.lam = float(p.lam)
+        self.H = math.prod(float(b) / int(m) for b, m in zip(box, self.n))
+
+    def _set_handle(self, h, owned):
         self._h = h
+        self._owned = owned
         info = _lib.Info()
         info.struct_size = ctypes.sizeof(_lib.Info)
         check(lib.jgb_plan_info(self._h, ctypes.byref(info)))
         self.info = {f: (list(getattr(info, f)) if f in ("n", "nf") else getattr(info, f))
                      for f, _ in _lib.Info._fields_ if f != "struct_size"}
+
 
     # ------------------------------------------------------------ checks
     def _check_grid(self, t, name):
@@ -161,9 +182,9 @@ class Plan:
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and getattr(self, "_owned", True):
             lib.jgb_destroy(h)
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -195,3 +216,66 @@ class InteractionEnergy(torch.autograd.Function):
 
 # the dipolar energy of the dipole kernel is the same function with a dipole plan
 DipolarEnergy = InteractionEnergy
+
+
+class Batch:
+    """Independent densities evaluated by one HIP graph launch.
+
+    members: list of dicts of Plan keyword arguments (n, box, kernel, nodes, eps,
+    precision, lam, axis, theta_rule, kmax).  bind() takes the density tensors
+    and allocates the outputs; run() evaluates every member."""
+
+    def __init__(self, members, nstreams=4, device=None, stream=None):
+        dev = torch.cuda.current_device() if device is None else int(device)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        arr = (_lib.Params * len(members))()
+        boxes = []
+        for i, m in enumerate(members):
+            kw = dict(eps=1e-10, precision="fp64", lam=1.0, axis=(0.0, 0.0, 1.0), theta_rule="theta", kmax=0.0)
+            kw.update(m)
+            p, _, _ = _make_params(kw["n"], kw["box"], kw["kernel"], kw["nodes"], kw["eps"], kw["precision"],
+                                   kw["lam"], kw["axis"], kw["theta_rule"], kw["kmax"], dev, st)
+            arr[i] = p
+            boxes.append(kw["box"])
+        h = ctypes.c_void_p()
+        check(lib.jgb_batch_create(arr, len(members), int(nstreams), ctypes.byref(h)))
+        self._h = h
+        self.device = torch.device("cuda", dev)
+        self.plans = []
+        for i in range(len(members)):
+            ph = ctypes.c_void_p()
+            check(lib.jgb_batch_plan(self._h, i, ctypes.byref(ph)))
+            self.plans.append(Plan._member(arr[i], dev, st, boxes[i], ph))
+        self.rho = self.u = self.energies = None
+
+    def bind(self, rhos):
+        """Capture the batch for these density tensors; returns (u list, energies tensor)."""
+        if len(rhos) != len(self.plans):
+            raise ValueError("one density per member")
+        for r, p in zip(rhos, self.plans):
+            p._check_grid(r, "rho")
+        self.rho = list(rhos)
+        self.u = [torch.empty_like(r) for r in rhos]
+        self.energies = torch.empty(len(rhos), dtype=torch.float64, device=self.device)
+        rp = (ctypes.c_void_p * len(rhos))(*[r.data_ptr() for r in self.rho])
+        up = (ctypes.c_void_p * len(rhos))(*[u.data_ptr() for u in self.u])
+        check(lib.jgb_batch_bind(self._h, rp, up, ctypes.c_void_p(self.energies.data_ptr())))
+        return self.u, self.energies
+
+    def run(self):
+        check(lib.jgb_batch_run(self._h))
+        return self.u, self.energies
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            for p in self.plans:
+                p._h = ctypes.c_void_p()
+            lib.jgb_batch_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

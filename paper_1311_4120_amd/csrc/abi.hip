@@ -3,8 +3,10 @@
 // stream and converts every failure into a status code and a thread-local
 // message.  Nothing is thrown across the ABI.
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 #include <string>
 
 #include "common.h"
@@ -30,6 +32,18 @@ struct jgb_plan_s {
   Plan pl;
 };
 
+struct jgb_batch_s {
+  std::vector<jgb_plan_s*> plans;
+  hipStream_t stream = nullptr;           // the caller's stream (params[0].stream), may be the NULL stream
+  std::vector<hipStream_t> branches;      // streams owned by the batch; the graph is captured on branch 0
+  std::vector<hipEvent_t> events;         // fork + one join event per extra branch
+  hipEvent_t ev_in = nullptr;             // caller stream -> batch, batch -> caller ordering
+  hipEvent_t ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
 namespace {
 
 jgb_status report(jgb_status code, const std::string& msg) {
@@ -53,19 +67,19 @@ size_t grid_bytes(const Plan& pl) {
 }
 
 template <typename T>
-jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy) {
+jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st) {
   hipError_t e;
-  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
-  if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_POTENTIAL, nullptr, pl.stream)) != hipSuccess)
+  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, st)) != hipSuccess) return from_hip(e, "forward FFT");
+  if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_POTENTIAL, nullptr, st)) != hipSuccess)
     return from_hip(e, "interpolation");
-  if ((e = jgb::launch_spread<T>(pl, pl.stream)) != hipSuccess) return from_hip(e, "spreading");
-  if ((e = jgb::launch_fft_inverse<T>(pl, (T*)u, energy ? (const T*)rho : nullptr, pl.stream)) != hipSuccess)
+  if ((e = jgb::launch_spread<T>(pl, st)) != hipSuccess) return from_hip(e, "spreading");
+  if ((e = jgb::launch_fft_inverse<T>(pl, (T*)u, energy ? (const T*)rho : nullptr, st)) != hipSuccess)
     return from_hip(e, "inverse FFT");
   if (energy) {
     double scale = 0.5 * pl.p.lambda * pl.H;
-    jgb::stage_mark(pl, jgb::ST_ENERGY, 0, pl.stream);
-    e = jgb::launch_energy_finalize(pl.d_eparts, jgb::fft_inverse_z_blocks(pl), scale, energy, pl.stream);
-    jgb::stage_mark(pl, jgb::ST_ENERGY, 1, pl.stream);
+    jgb::stage_mark(pl, jgb::ST_ENERGY, 0, st);
+    e = jgb::launch_energy_finalize(pl.d_eparts, jgb::fft_inverse_z_blocks(pl), scale, energy, st);
+    jgb::stage_mark(pl, jgb::ST_ENERGY, 1, st);
     if (e != hipSuccess) return from_hip(e, "energy");
   }
   jgb::call_done(pl);
@@ -141,7 +155,8 @@ jgb_status jgb_potential(jgb_plan_t plan, const void* rho, void* u, double* ener
   if (!rho || !u) return report(JGB_ERR_INVALID_ARG, "rho and u must not be NULL");
   size_t nb = grid_bytes(pl);
   if (overlap(rho, nb, u, nb)) return report(JGB_ERR_INVALID_ARG, "rho and u overlap");
-  return pl.fp64 ? run_potential<double>(pl, rho, u, energy) : run_potential<float>(pl, rho, u, energy);
+  return pl.fp64 ? run_potential<double>(pl, rho, u, energy, pl.stream)
+                 : run_potential<float>(pl, rho, u, energy, pl.stream);
 }
 
 jgb_status jgb_energy(jgb_plan_t plan, const void* rho, double* energy) {
@@ -160,8 +175,8 @@ jgb_status jgb_potential_backward(jgb_plan_t plan, const void* grad_u, void* gra
   size_t nb = grid_bytes(pl);
   if (overlap(grad_u, nb, grad_rho, nb)) return report(JGB_ERR_INVALID_ARG, "grad_u and grad_rho overlap");
   // A is symmetric: the vector-Jacobian product is the same operator applied to grad_u
-  return pl.fp64 ? run_potential<double>(pl, grad_u, grad_rho, nullptr)
-                 : run_potential<float>(pl, grad_u, grad_rho, nullptr);
+  return pl.fp64 ? run_potential<double>(pl, grad_u, grad_rho, nullptr, pl.stream)
+                 : run_potential<float>(pl, grad_u, grad_rho, nullptr, pl.stream);
 }
 
 jgb_status jgb_transform(jgb_plan_t plan, const void* rho, void* rhohat) {
@@ -204,6 +219,172 @@ jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* cc) {
   Plan& pl = plan->pl;
   if (!k && !w && !cc) return JGB_OK;
   return from_hip(jgb::launch_node_export(pl, k, w, cc, pl.stream), "node export");
+}
+
+static void release_graph(jgb_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+static void release_batch(jgb_batch_s* b) {
+  (void)hipSetDevice(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  for (hipStream_t s : b->branches) (void)hipStreamSynchronize(s);
+  release_graph(b);
+  for (hipStream_t s : b->branches) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  for (jgb_plan_s* p : b->plans) (void)jgb_destroy(p);
+  delete b;
+}
+
+jgb_status jgb_batch_create(const jgb_params* params, int count, int nstreams, jgb_batch_t* out) {
+  jgb::set_error("");
+  if (!out) return report(JGB_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!params) return report(JGB_ERR_INVALID_ARG, "params is NULL");
+  if (count < 1 || count > 65536) return report(JGB_ERR_INVALID_ARG, "count must be in [1, 65536]");
+  if (nstreams < 1 || nstreams > 8) return report(JGB_ERR_INVALID_ARG, "nstreams must be in [1, 8]");
+  for (int i = 1; i < count; ++i)
+    if (params[i].device != params[0].device || params[i].stream != params[0].stream)
+      return report(JGB_ERR_INVALID_ARG, "all members of a batch share params[0]'s device and stream");
+  jgb_batch_s* b = new (std::nothrow) jgb_batch_s();
+  if (!b) return report(JGB_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->device = params[0].device;
+  b->stream = (hipStream_t)params[0].stream;
+  for (int i = 0; i < count; ++i) {
+    jgb_plan_t p = nullptr;
+    jgb_status st = jgb_plan(&params[i], &p);
+    if (st != JGB_OK) {
+      std::string msg = "member " + std::to_string(i) + ": " + jgb::get_error();
+      release_batch(b);
+      return report(st, msg);
+    }
+    b->plans.push_back(p);
+  }
+  (void)hipSetDevice(b->device);
+  for (int k = 0; k < nstreams; ++k) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      release_batch(b);
+      return report(JGB_ERR_DEVICE, "stream creation failed");
+    }
+    b->branches.push_back(s);
+  }
+  for (int k = 0; k < nstreams + 2; ++k) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      release_batch(b);
+      return report(JGB_ERR_DEVICE, "event creation failed");
+    }
+    b->events.push_back(e);
+  }
+  b->ev_in = b->events.back();
+  b->events.pop_back();
+  b->ev_out = b->events.back();
+  b->events.pop_back();
+  *out = b;
+  return JGB_OK;
+}
+
+jgb_status jgb_batch_bind(jgb_batch_t b, const void* const* rho, void* const* u, double* energies) {
+  if (!b) return report(JGB_ERR_INVALID_ARG, "batch is NULL");
+  if (!rho || !u) return report(JGB_ERR_INVALID_ARG, "rho and u must not be NULL");
+  const int count = (int)b->plans.size();
+  for (int i = 0; i < count; ++i) {
+    if (!rho[i] || !u[i]) return report(JGB_ERR_INVALID_ARG, "rho[i] and u[i] must not be NULL");
+    size_t nb = grid_bytes(b->plans[i]->pl);
+    if (overlap(rho[i], nb, u[i], nb)) return report(JGB_ERR_INVALID_ARG, "rho[i] and u[i] overlap");
+    if (b->plans[i]->pl.timing.on) return report(JGB_ERR_INVALID_ARG, "a member plan has timing enabled");
+  }
+  hipError_t e = hipSetDevice(b->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  for (size_t k = 0; k < b->branches.size() && e == hipSuccess; ++k) e = hipStreamSynchronize(b->branches[k]);
+  if (e != hipSuccess) return from_hip(e, "batch bind");
+  release_graph(b);
+  // longest-processing-time assignment of members to branches by grid volume
+  const int nbr = (int)b->branches.size();
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto work = [&](int i) {
+    const Plan& pl = b->plans[i]->pl;
+    return (double)pl.nf[0] * pl.nf[1] * pl.nf[2] + 8.0 * (double)pl.Mh * pl.width;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
+  std::vector<double> load(nbr, 0.0);
+  std::vector<std::vector<int>> members(nbr);
+  for (int i : order) {
+    int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[k] += work(i);
+    members[k].push_back(i);
+  }
+  hipStream_t origin = b->branches[0];
+  e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return from_hip(e, "begin capture");
+  jgb_status st = JGB_OK;
+  hipError_t ce = hipEventRecord(b->events[0], origin);
+  for (int k = 1; k < nbr && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branches[k], b->events[0], 0);
+  for (int k = 0; k < nbr && ce == hipSuccess && st == JGB_OK; ++k) {
+    for (int i : members[k]) {
+      Plan& pl = b->plans[i]->pl;
+      double* E = energies ? energies + i : nullptr;
+      st = pl.fp64 ? run_potential<double>(pl, rho[i], u[i], E, b->branches[k])
+                   : run_potential<float>(pl, rho[i], u[i], E, b->branches[k]);
+      if (st != JGB_OK) break;
+    }
+  }
+  for (int k = 1; k < nbr && ce == hipSuccess && st == JGB_OK; ++k) {
+    ce = hipEventRecord(b->events[k], b->branches[k]);
+    if (ce == hipSuccess) ce = hipStreamWaitEvent(origin, b->events[k], 0);
+  }
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(origin, &g);
+  if (st != JGB_OK || ce != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (st != JGB_OK) return st;
+    return from_hip(ce != hipSuccess ? ce : ee, "capture");
+  }
+  b->graph = g;
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    release_graph(b);
+    return from_hip(e, "graph instantiate");
+  }
+  return JGB_OK;
+}
+
+jgb_status jgb_batch_run(jgb_batch_t b) {
+  if (!b) return report(JGB_ERR_INVALID_ARG, "batch is NULL");
+  if (!b->exec) return report(JGB_ERR_INVALID_ARG, "batch has no bound buffers (call jgb_batch_bind)");
+  // order after the caller's earlier work, launch on the batch's own stream,
+  // and order the caller's later work after the graph
+  hipStream_t origin = b->branches[0];
+  hipError_t e = hipSetDevice(b->device);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_in, b->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(origin, b->ev_in, 0);
+  if (e == hipSuccess) e = hipGraphLaunch(b->exec, origin);
+  if (e == hipSuccess) e = hipEventRecord(b->ev_out, origin);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out, 0);
+  return from_hip(e, "graph launch");
+}
+
+jgb_status jgb_batch_plan(jgb_batch_t b, int i, jgb_plan_t* plan) {
+  if (!b || !plan) return report(JGB_ERR_INVALID_ARG, "batch and plan must not be NULL");
+  if (i < 0 || i >= (int)b->plans.size()) return report(JGB_ERR_INVALID_ARG, "member index out of range");
+  *plan = b->plans[i];
+  return JGB_OK;
+}
+
+jgb_status jgb_batch_destroy(jgb_batch_t b) {
+  if (!b) return JGB_OK;
+  release_batch(b);
+  return JGB_OK;
 }
 
 static void release_timing(Plan& pl) {

@@ -199,6 +199,7 @@ hipError_t launch_psi_gradient(const Plan& pl, const void* psi, const void* u, c
                                void* grad, hipStream_t s);
 int fft_inverse_z_blocks(const Plan& pl);
 int interp_blocks(const Plan& pl);
+hipError_t interp_prepare(const Plan& pl);
 hipError_t launch_energy_finalize(const double* parts, int n, double scale, double* out, hipStream_t s);
 
 }  // namespace jgb

@@ -201,15 +201,33 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
 
 template <typename T, int W>
 hipError_t launch_w(const InterpArgs<T>& a, unsigned blocks, size_t smem, hipStream_t s) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_interp<T, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_interp<T, W>), dim3(blocks), dim3(kInterpThreads), smem, s, a);
   return hipGetLastError();
+}
+
+template <typename T, int W>
+hipError_t allow_lds(size_t smem) {
+  return hipFuncSetAttribute((const void*)k_interp<T, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
 }
 
 }  // namespace
 
 int interp_blocks(const Plan& pl) { return pl.niitems; }
+
+// Let the plan's interpolation kernel use its staged-region size of LDS
+// (called once at plan time, outside any stream capture).
+hipError_t interp_prepare(const Plan& pl) {
+  switch (pl.width) {
+#define JGB_W(W) \
+  case W:        \
+    return pl.fp64 ? allow_lds<double, W>(pl.interp_lds) : allow_lds<float, W>(pl.interp_lds);
+    JGB_W(2) JGB_W(3) JGB_W(4) JGB_W(5) JGB_W(6) JGB_W(7) JGB_W(8) JGB_W(9) JGB_W(10) JGB_W(11) JGB_W(12)
+    JGB_W(13) JGB_W(14) JGB_W(15) JGB_W(16)
+#undef JGB_W
+    default:
+      return hipErrorInvalidValue;
+  }
+}
 
 template <typename T>
 hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t s) {

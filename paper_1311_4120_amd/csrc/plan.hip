@@ -430,6 +430,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   pl.neparts = std::max(fft_inverse_z_blocks(pl), interp_blocks(pl));
   pl.neparts = std::max(pl.neparts, 1);
   TRY(dev_alloc(pl, &pl.d_eparts, sizeof(double) * pl.neparts));
+  TRY_HIP(interp_prepare(pl), "interpolation LDS limit");
   TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");
   TRY_HIP(hipGetLastError(), "plan kernels");
   return Status::ok();
