@@ -69,7 +69,7 @@ def run_gpu(prec, steps, warmup):
     dt = torch.float64 if prec == "fp64" else torch.float32
     t0 = time.time()
     plan = jgb.Plan(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), eps=p.eps, precision=prec,
-                    lam=p.lam, axis=p.axis, theta_rule="theta")
+                    lam=p.lam, axis=p.axis, theta_rule="theta", autotune=True)
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     rt = torch.tensor(rho, dtype=dt, device="cuda")
@@ -90,7 +90,8 @@ def run_gpu(prec, steps, warmup):
     info = plan.info
     plan.close()
     return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "stages_ms": stages, "calls": ncalls,
-            "plan_s": plan_s, "energy": energy, "info": info, "eps": p.eps}
+            "plan_s": plan_s, "energy": energy, "info": info, "eps": p.eps,
+            "tuned": {"interp_chunk": info["interp_chunk"], "spread_chunk": info["spread_chunk"]}}
 
 
 def run_batched(steps, warmup):
@@ -103,7 +104,9 @@ def run_batched(steps, warmup):
 
     members = wl.batched_coulomb()
     kws = [dict(n=p.n, box=p.box, kernel="coulomb3d", nodes=(p.n_r, p.n_theta, p.n_phi), eps=p.eps,
-                precision="mixed") for p, _ in members]
+                precision="mixed", autotune=True) for p, _ in members]
+    # members of one grid size share a tuning: cache it for the run
+    os.environ.setdefault("JGB_AUTOTUNE_CACHE", os.path.join("/tmp", "jgb_autotune_bench_%d.json" % os.getpid()))
     t0 = time.time()
     b = jgb.Batch(kws, nstreams=4)
     rhos = [torch.tensor(mix.evaluate(p.n, p.box), dtype=torch.float32, device="cuda") for p, mix in members]
@@ -220,6 +223,7 @@ def main():
         "ns_per_point": r["ms_per_step"] * 1e6 / npts,
         "energy": r["energy"],
         "plan_s": r["plan_s"],
+        "autotuned": r["tuned"],
         "model_hbm_bytes_per_step": total_bytes,
         "model_hbm_frac": total_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "stages": stages,

@@ -74,6 +74,12 @@ typedef enum { JGB_THETA_GL = 0, JGB_COSTHETA_GL = 1 } jgb_theta_rule;
 
 /* flags */
 #define JGB_FLAG_NONE 0u
+/* Time the candidate work-item sizes of the interpolation and spreading
+ * kernels on the device at plan time and keep the fastest.  When the
+ * environment variable JGB_AUTOTUNE_CACHE names a file, results are read from
+ * and written to it (a JSON object keyed by grid, node counts, cutoff, width
+ * and precision), so later plans of the same shape skip the timing. */
+#define JGB_FLAG_AUTOTUNE 1u
 
 typedef struct jgb_plan_s* jgb_plan_t;
 
@@ -97,7 +103,7 @@ typedef struct {
                               in (0, pi / max_j h_j] otherwise */
   int32_t device;          /* HIP device ordinal the plan lives on */
   void* stream;            /* hipStream_t for all work of this plan (NULL = default stream) */
-  uint32_t flags;          /* JGB_FLAG_* (none defined yet; must be 0) */
+  uint32_t flags;          /* JGB_FLAG_* (any other bit -> INVALID_ARG) */
 } jgb_params;
 
 /* Plan facts, for diagnostics and for sizing caller buffers. */
@@ -112,6 +118,8 @@ typedef struct {
   double beta;             /* exponential-of-semicircle kernel shape parameter */
   double kmax;             /* K actually used */
   int64_t workspace_bytes; /* device memory owned by the plan */
+  int32_t interp_chunk;    /* nodes per interpolation block at most */
+  int32_t spread_chunk;    /* list entries per spreading block at most */
 } jgb_info;
 
 /* Build a plan: validates the parameters, generates the Fourier nodes and

@@ -24,6 +24,7 @@ NUM_STAGES = 10
 STAGE_NAMES = ["fwd_fft_z", "fwd_fft_y", "fwd_fft_x", "interp", "spread", "spread_reduce",
                "inv_fft_x", "inv_fft_y", "inv_fft_z", "energy"]
 FP64, MIXED = 0, 1
+FLAG_AUTOTUNE = 1
 THETA_GL, COSTHETA_GL = 0, 1
 
 
@@ -61,6 +62,8 @@ class Info(ctypes.Structure):
         ("beta", ctypes.c_double),
         ("kmax", ctypes.c_double),
         ("workspace_bytes", ctypes.c_int64),
+        ("interp_chunk", ctypes.c_int32),
+        ("spread_chunk", ctypes.c_int32),
     ]
 
 

@@ -19,7 +19,8 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream):
+def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
+                 autotune=False):
     dim = len(n)
     kern = _KERNELS.get(kernel, kernel)
     rule = _RULES.get(theta_rule, theta_rule)
@@ -46,7 +47,7 @@ def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, k
     p.kmax = float(kmax)
     p.device = dev
     p.stream = ctypes.c_void_p(st.cuda_stream)
-    p.flags = 0
+    p.flags = _lib.FLAG_AUTOTUNE if autotune else 0
     return p, dev, st
 
 
@@ -62,8 +63,9 @@ class Plan:
     def __init__(self, n: Sequence[int], box: Sequence[float], kernel, nodes: Sequence[int],
                  eps: float = 1e-10, precision: str = "fp64", lam: float = 1.0,
                  axis: Sequence[float] = (0.0, 0.0, 1.0), theta_rule="theta", kmax: float = 0.0,
-                 device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None):
-        p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream)
+                 device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, autotune: bool = False):
+        p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
+                                  autotune)
         self._init_from(p, dev, st, box)
         h = ctypes.c_void_p()
         check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))
@@ -231,10 +233,11 @@ class Batch:
         arr = (_lib.Params * len(members))()
         boxes = []
         for i, m in enumerate(members):
-            kw = dict(eps=1e-10, precision="fp64", lam=1.0, axis=(0.0, 0.0, 1.0), theta_rule="theta", kmax=0.0)
+            kw = dict(eps=1e-10, precision="fp64", lam=1.0, axis=(0.0, 0.0, 1.0), theta_rule="theta", kmax=0.0,
+                      autotune=False)
             kw.update(m)
             p, _, _ = _make_params(kw["n"], kw["box"], kw["kernel"], kw["nodes"], kw["eps"], kw["precision"],
-                                   kw["lam"], kw["axis"], kw["theta_rule"], kw["kmax"], dev, st)
+                                   kw["lam"], kw["axis"], kw["theta_rule"], kw["kmax"], dev, st, kw["autotune"])
             arr[i] = p
             boxes.append(kw["box"])
         h = ctypes.c_void_p()

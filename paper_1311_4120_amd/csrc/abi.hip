@@ -475,6 +475,8 @@ jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info) {
   info->beta = pl.beta;
   info->kmax = pl.K;
   info->workspace_bytes = (int64_t)pl.workspace_bytes;
+  info->interp_chunk = pl.interp_chunk;
+  info->spread_chunk = pl.spread_chunk;
   return JGB_OK;
 }
 

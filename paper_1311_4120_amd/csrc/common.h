@@ -120,6 +120,12 @@ struct Plan {
   };
   InterpItem* d_iitems = nullptr;
   int niitems = 0;
+  int iitems_cap = 0;
+  int interp_chunk = 512;      // nodes per interpolation block at most (tunable)
+  int spread_chunk = 4096;     // list entries per gather block at most (tunable)
+  int items_cap = 0, multi_cap = 0, slots_cap = 0;
+  std::vector<int> h_sub_start;      // host copy: sorted-node offsets per sub-bin key
+  std::vector<int64_t> h_tcount;     // host copy: list offsets per tile
   size_t interp_lds = 0;     // bytes of the staged grid region
   int nt[3] = {1, 1, 1};     // tiles per axis
   int ntiles = 0;

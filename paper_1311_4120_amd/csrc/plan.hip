@@ -5,7 +5,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <limits>
+#include <string>
 
 #include "common.h"
 
@@ -13,9 +16,10 @@ namespace jgb {
 
 namespace {
 
-constexpr int kInterpChunk = 512;     // nodes per interpolation block at most
+// candidate work-item sizes; the first of each is the smallest and sizes the buffers
+constexpr int kInterpChunks[] = {256, 512, 1024, 2048};
+constexpr int kSpreadChunks[] = {1024, 2048, 4096, 8192};
 constexpr size_t kInterpLdsMax = 120 * 1024;
-constexpr int kChunk = 4096;  // listed nodes per gather work item (one block of 4 wavefronts) at most
 
 bool is_235(int64_t n) {
   if (n < 1) return false;
@@ -113,6 +117,200 @@ Status upload(Plan& pl, void* dst, const void* src, size_t bytes) {
     if (e_ != hipSuccess) return fail(JGB_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+
+// Interpolation work items: nonempty sub-bins, split into runs of at most chunk nodes.
+std::vector<Plan::InterpItem> interp_items(const Plan& pl, int chunk) {
+  std::vector<Plan::InterpItem> iit;
+  const std::vector<int>& ss = pl.h_sub_start;
+  for (size_t k = 0; k + 1 < ss.size(); ++k)
+    for (int b = ss[k]; b < ss[k + 1]; b += chunk) iit.push_back(Plan::InterpItem{(int)k, b, std::min(ss[k + 1], b + chunk)});
+  std::stable_sort(iit.begin(), iit.end(), [](const Plan::InterpItem& x, const Plan::InterpItem& y) {
+    return (x.end - x.begin) > (y.end - y.begin);
+  });
+  return iit;
+}
+
+// Gather work items: one block per tile, tiles with longer lists split into
+// chunks whose partial tiles are summed afterwards.
+void spread_items(const Plan& pl, int chunk, std::vector<WorkItem>& items, std::vector<int>& multi, int& nslots) {
+  items.clear();
+  multi.clear();
+  nslots = 0;
+  const std::vector<int64_t>& tc = pl.h_tcount;
+  for (int tile = 0; tile < pl.ntiles; ++tile) {
+    const int64_t b = tc[tile], e = tc[tile + 1], L = e - b;
+    if (L <= chunk) {
+      items.push_back(WorkItem{tile, (int)b, (int)e, -1});
+    } else {
+      int k = (int)((L + chunk - 1) / chunk);
+      multi.push_back(tile);
+      multi.push_back(nslots);
+      multi.push_back(k);
+      for (int c = 0; c < k; ++c) {
+        int64_t vb = b + (int64_t)c * chunk;
+        int64_t ve = std::min<int64_t>(e, vb + chunk);
+        items.push_back(WorkItem{tile, (int)vb, (int)ve, nslots + c});
+      }
+      nslots += k;
+    }
+  }
+  // longest items first so the split tiles do not form the tail
+  std::stable_sort(items.begin(), items.end(),
+                   [](const WorkItem& x, const WorkItem& y) { return (x.vend - x.vbegin) > (y.vend - y.vbegin); });
+}
+
+Status apply_interp_chunk(Plan& pl, int chunk) {
+  std::vector<Plan::InterpItem> iit = interp_items(pl, chunk);
+  if ((int)iit.size() > pl.iitems_cap) return fail(JGB_ERR_DEVICE, "interpolation items exceed capacity");
+  TRY(upload(pl, pl.d_iitems, iit.data(), sizeof(Plan::InterpItem) * iit.size()));
+  pl.niitems = (int)iit.size();
+  pl.interp_chunk = chunk;
+  return Status::ok();
+}
+
+Status apply_spread_chunk(Plan& pl, int chunk) {
+  std::vector<WorkItem> items;
+  std::vector<int> multi;
+  int nslots = 0;
+  spread_items(pl, chunk, items, multi, nslots);
+  if ((int)items.size() > pl.items_cap || (int)multi.size() > pl.multi_cap || nslots > pl.slots_cap)
+    return fail(JGB_ERR_DEVICE, "gather items exceed capacity");
+  TRY(upload(pl, pl.d_items, items.data(), sizeof(WorkItem) * items.size()));
+  TRY(upload(pl, pl.d_multi, multi.data(), sizeof(int) * multi.size()));
+  pl.nitems = (int)items.size();
+  pl.nslots = nslots;
+  pl.nmulti = (int)multi.size() / 3;
+  pl.spread_chunk = chunk;
+  return Status::ok();
+}
+
+// ------------------------------------------------------------ autotuning
+//
+// The work-item sizes of the two tap kernels trade load balance against
+// per-item overhead, and the best values depend on the node distribution
+// (grid, node counts, cutoff), the width and the precision.  With
+// JGB_FLAG_AUTOTUNE the plan times every candidate on the device and keeps
+// the fastest; results are cached in the JSON file named by the environment
+// variable JGB_AUTOTUNE_CACHE (an object mapping a key string to
+// {"interp_chunk": i, "spread_chunk": s}).
+
+std::string tune_key(const Plan& pl) {
+  char buf[256];
+  double kh = pl.K * std::max(pl.h[0] * (pl.n[0] > 1), std::max(pl.h[1], pl.h[2])) / M_PI;
+  snprintf(buf, sizeof(buf), "gfx950 d%d n%dx%dx%d nodes%dx%dx%d rule%d kh%.6f w%d %s", pl.dim, pl.n[0], pl.n[1],
+           pl.n[2], pl.n_r, pl.n_theta, pl.n_phi, pl.p.theta_rule, kh, pl.width, pl.fp64 ? "fp64" : "mixed");
+  return buf;
+}
+
+bool cache_lookup(const std::string& path, const std::string& key, int& ic, int& sc) {
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return false;
+  std::string text;
+  char chunk[4096];
+  size_t got;
+  while ((got = fread(chunk, 1, sizeof(chunk), f)) > 0) text.append(chunk, got);
+  fclose(f);
+  size_t at = text.find("\"" + key + "\"");
+  if (at == std::string::npos) return false;
+  size_t i1 = text.find("\"interp_chunk\":", at), i2 = text.find("\"spread_chunk\":", at);
+  if (i1 == std::string::npos || i2 == std::string::npos) return false;
+  if (sscanf(text.c_str() + i1, "\"interp_chunk\": %d", &ic) != 1) return false;
+  if (sscanf(text.c_str() + i2, "\"spread_chunk\": %d", &sc) != 1) return false;
+  bool ok_i = false, ok_s = false;
+  for (int c : kInterpChunks) ok_i |= (c == ic);
+  for (int c : kSpreadChunks) ok_s |= (c == sc);
+  return ok_i && ok_s;
+}
+
+void cache_store(const std::string& path, const std::string& key, int ic, int sc, double ms_i, double ms_s) {
+  std::string text;
+  if (FILE* f = fopen(path.c_str(), "r")) {
+    char chunk[4096];
+    size_t got;
+    while ((got = fread(chunk, 1, sizeof(chunk), f)) > 0) text.append(chunk, got);
+    fclose(f);
+  }
+  size_t close = text.rfind('}');
+  char entry[512];
+  snprintf(entry, sizeof(entry), "\"%s\": {\"interp_chunk\": %d, \"spread_chunk\": %d, \"interp_ms\": %.4f, \"spread_ms\": %.4f}",
+           key.c_str(), ic, sc, ms_i, ms_s);
+  std::string out;
+  if (close == std::string::npos || text.find('{') == std::string::npos) {
+    out = std::string("{\n  ") + entry + "\n}\n";
+  } else {
+    std::string head = text.substr(0, close);
+    while (!head.empty() && (head.back() == '\n' || head.back() == ' ')) head.pop_back();
+    bool empty = head.find_last_not_of("{ \n") == std::string::npos;
+    out = head + (empty ? "\n  " : ",\n  ") + entry + "\n}\n";
+  }
+  if (FILE* f = fopen(path.c_str(), "w")) {
+    fwrite(out.data(), 1, out.size(), f);
+    fclose(f);
+  }
+}
+
+template <typename T>
+Status time_stage(Plan& pl, bool interp, double& best_ms) {
+  hipEvent_t e0, e1;
+  TRY_HIP(hipEventCreate(&e0), "event");
+  TRY_HIP(hipEventCreate(&e1), "event");
+  best_ms = 1e30;
+  hipError_t err = hipSuccess;
+  for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+    err = hipEventRecord(e0, pl.stream);
+    if (err == hipSuccess)
+      err = interp ? launch_interp<T>(pl, INTERP_POTENTIAL, nullptr, pl.stream) : launch_spread<T>(pl, pl.stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, pl.stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (rep > 0 && err == hipSuccess) best_ms = std::min(best_ms, (double)ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  TRY_HIP(err, "autotune timing");
+  return Status::ok();
+}
+
+Status autotune(Plan& pl) {
+  const char* path = getenv("JGB_AUTOTUNE_CACHE");
+  const std::string key = tune_key(pl);
+  int ic = 0, sc = 0;
+  if (path && cache_lookup(path, key, ic, sc)) {
+    TRY(apply_interp_chunk(pl, ic));
+    TRY(apply_spread_chunk(pl, sc));
+    return Status::ok();
+  }
+  // ordinary values on the grid: time on an all-zero oversampled grid
+  size_t ngrid = (size_t)pl.nf[0] * pl.nf[1] * pl.nf[2];
+  TRY_HIP(hipMemsetAsync(pl.d_F, 0, ngrid * 2 * pl.real_bytes, pl.stream), "autotune clear");
+  double best_i = 1e30, best_s = 1e30;
+  for (int c : kInterpChunks) {
+    TRY(apply_interp_chunk(pl, c));
+    double ms;
+    TRY(pl.fp64 ? time_stage<double>(pl, true, ms) : time_stage<float>(pl, true, ms));
+    if (ms < best_i) {
+      best_i = ms;
+      ic = c;
+    }
+  }
+  TRY(apply_interp_chunk(pl, ic));
+  double ms0;
+  TRY(pl.fp64 ? time_stage<double>(pl, true, ms0) : time_stage<float>(pl, true, ms0));  // node values for spreading
+  for (int c : kSpreadChunks) {
+    TRY(apply_spread_chunk(pl, c));
+    double ms;
+    TRY(pl.fp64 ? time_stage<double>(pl, false, ms) : time_stage<float>(pl, false, ms));
+    if (ms < best_s) {
+      best_s = ms;
+      sc = c;
+    }
+  }
+  TRY(apply_spread_chunk(pl, sc));
+  if (path) cache_store(path, key, ic, sc, best_i, best_s);
+  return Status::ok();
+}
+
 }  // namespace
 
 Status validate(const jgb_params* p) {
@@ -153,7 +351,7 @@ Status validate(const jgb_params* p) {
   double kn = M_PI / hmax;
   if (!(std::isfinite(p->kmax) && p->kmax >= 0)) return fail(JGB_ERR_INVALID_ARG, "kmax must be finite and >= 0");
   if (p->kmax > kn * (1 + 1e-12)) return fail(JGB_ERR_INVALID_ARG, "kmax must not exceed pi / max_j h_j");
-  if (p->flags != 0) return fail(JGB_ERR_INVALID_ARG, "flags must be 0");
+  if (p->flags & ~JGB_FLAG_AUTOTUNE) return fail(JGB_ERR_INVALID_ARG, "unknown flags");
   int64_t M = (int64_t)p->n_r * p->n_phi * (p->dim == 3 ? p->n_theta : 1);
   if (M / 2 > (int64_t)std::numeric_limits<int>::max() / 2) return fail(JGB_ERR_UNSUPPORTED, "too many nodes");
   int ndev = 0;
@@ -283,19 +481,11 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   }
   std::vector<int> bin_start(pl.ntiles + 1, 0);
   for (int b = 0; b <= pl.ntiles; ++b) bin_start[b] = sub_start[(size_t)b * pl.nsub];
-  // interpolation work items: nonempty sub-bins, long ones split
+  pl.h_sub_start = sub_start;
   {
-    std::vector<Plan::InterpItem> iit;
-    for (int k = 0; k < nkeys; ++k) {
-      for (int b = sub_start[k]; b < sub_start[k + 1]; b += kInterpChunk)
-        iit.push_back(Plan::InterpItem{k, b, std::min(sub_start[k + 1], b + kInterpChunk)});
-    }
-    std::stable_sort(iit.begin(), iit.end(), [](const Plan::InterpItem& x, const Plan::InterpItem& y) {
-      return (x.end - x.begin) > (y.end - y.begin);
-    });
-    pl.niitems = (int)iit.size();
-    TRY(dev_alloc(pl, &pl.d_iitems, sizeof(Plan::InterpItem) * iit.size()));
-    TRY(upload(pl, pl.d_iitems, iit.data(), sizeof(Plan::InterpItem) * iit.size()));
+    pl.iitems_cap = (int)interp_items(pl, kInterpChunks[0]).size();
+    TRY(dev_alloc(pl, &pl.d_iitems, sizeof(Plan::InterpItem) * std::max(pl.iitems_cap, 1)));
+    TRY(apply_interp_chunk(pl, pl.interp_chunk));
   }
   TRY(dev_alloc(pl, &pl.nodes.perm, sizeof(int) * Mh));
   TRY(upload(pl, pl.nodes.perm, perm.data(), sizeof(int) * Mh));
@@ -362,38 +552,20 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   TRY(upload(pl, pl.d_list, list.data(), sizeof(int2) * list.size()));
   pl.nlist = nlist;
 
-  // gather work items: one block per tile, more for tiles with long lists
-  std::vector<WorkItem> items;
-  std::vector<int> multi;
-  int nslots = 0;
-  for (int tile = 0; tile < pl.ntiles; ++tile) {
-    const int64_t b = tcount[tile], e = tcount[tile + 1], L = e - b;
-    if (L <= kChunk) {
-      items.push_back(WorkItem{tile, (int)b, (int)e, -1});
-    } else {
-      int k = (int)((L + kChunk - 1) / kChunk);
-      multi.push_back(tile);
-      multi.push_back(nslots);
-      multi.push_back(k);
-      for (int c = 0; c < k; ++c) {
-        int64_t vb = b + (int64_t)c * kChunk;
-        int64_t ve = std::min<int64_t>(e, vb + kChunk);
-        items.push_back(WorkItem{tile, (int)vb, (int)ve, nslots + c});
-      }
-      nslots += k;
-    }
+  pl.h_tcount = tcount;
+  {
+    std::vector<WorkItem> items;
+    std::vector<int> multi;
+    int nslots = 0;
+    spread_items(pl, kSpreadChunks[0], items, multi, nslots);
+    pl.items_cap = (int)items.size();
+    pl.multi_cap = (int)multi.size();
+    pl.slots_cap = nslots;
+    TRY(dev_alloc(pl, &pl.d_items, sizeof(WorkItem) * std::max(pl.items_cap, 1)));
+    TRY(dev_alloc(pl, &pl.d_multi, sizeof(int) * std::max(pl.multi_cap, 1)));
+    TRY(dev_alloc(pl, &pl.d_partials, (size_t)std::max(pl.slots_cap, 1) * 64 * kTileZ * 2 * pl.real_bytes));
+    TRY(apply_spread_chunk(pl, pl.spread_chunk));
   }
-  // longest items first so the split tiles do not form the tail
-  std::stable_sort(items.begin(), items.end(),
-                   [](const WorkItem& x, const WorkItem& y) { return (x.vend - x.vbegin) > (y.vend - y.vbegin); });
-  pl.nitems = (int)items.size();
-  pl.nslots = nslots;
-  pl.nmulti = (int)multi.size() / 3;
-  TRY(dev_alloc(pl, &pl.d_items, sizeof(WorkItem) * items.size()));
-  TRY(upload(pl, pl.d_items, items.data(), sizeof(WorkItem) * items.size()));
-  TRY(dev_alloc(pl, &pl.d_multi, sizeof(int) * multi.size()));
-  TRY(upload(pl, pl.d_multi, multi.data(), sizeof(int) * multi.size()));
-  TRY(dev_alloc(pl, &pl.d_partials, (size_t)nslots * 64 * kTileZ * 2 * pl.real_bytes));
 
   // FFT twiddles and deconvolution factors per axis
   for (int a = 0; a < 3; ++a) {
@@ -427,10 +599,11 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   size_t ngrid = (size_t)pl.nf[0] * pl.nf[1] * pl.nf[2];
   TRY(dev_alloc(pl, &pl.d_F, ngrid * 2 * pl.real_bytes));
   TRY(dev_alloc(pl, &pl.d_G, ngrid * 2 * pl.real_bytes));
-  pl.neparts = std::max(fft_inverse_z_blocks(pl), interp_blocks(pl));
+  pl.neparts = std::max(fft_inverse_z_blocks(pl), pl.iitems_cap);
   pl.neparts = std::max(pl.neparts, 1);
   TRY(dev_alloc(pl, &pl.d_eparts, sizeof(double) * pl.neparts));
   TRY_HIP(interp_prepare(pl), "interpolation LDS limit");
+  if (p->flags & JGB_FLAG_AUTOTUNE) TRY(autotune(pl));
   TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");
   TRY_HIP(hipGetLastError(), "plan kernels");
   return Status::ok();

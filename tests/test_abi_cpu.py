@@ -106,7 +106,7 @@ BAD = [
     ("odd n_phi", dict(n_phi=7), 1),
     ("theta rule", dict(theta_rule=5), 1),
     ("kmax too large", dict(kmax=100.0), 1),
-    ("flags", dict(flags=1), 1),
+    ("flags", dict(flags=6), 1),
 ]
 
 

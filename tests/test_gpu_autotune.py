@@ -1,0 +1,42 @@
+"""Autotuned work-item sizes: the plan times the candidates on the device,
+keeps the fastest, writes the JSON cache, and a second plan of the same shape
+reads it back; results agree with a plan at the default sizes."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import make_plan, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_and_cache(prec, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("JGB_AUTOTUNE_CACHE", str(cache))
+    p, rho = wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED)
+    say("autotune", prec)
+    tuned = make_plan(p, autotune=True)
+    ic, sc = tuned.info["interp_chunk"], tuned.info["spread_chunk"]
+    say("   chose interp %d spread %d" % (ic, sc))
+    assert ic in (256, 512, 1024, 2048) and sc in (1024, 2048, 4096, 8192)
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    entry = next(iter(data.values()))
+    assert entry["interp_chunk"] == ic and entry["spread_chunk"] == sc
+    again = make_plan(p, autotune=True)
+    assert (again.info["interp_chunk"], again.info["spread_chunk"]) == (ic, sc)
+    plain = make_plan(p)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rt = torch.tensor(rho, dtype=dt, device="cuda")
+    ua, Ea = tuned.potential(rt)
+    ub, Eb = plain.potential(rt)
+    e = rel_l2(ua.cpu().numpy(), ub.cpu().numpy())
+    say("   tuned vs default relL2 %.2e" % e)
+    assert e < (1e-13 if prec == "fp64" else 1e-6)
+    for pl in (tuned, again, plain):
+        pl.close()
