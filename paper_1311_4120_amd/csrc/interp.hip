@@ -12,9 +12,10 @@
 // grid region every footprint of the sub-bin can touch -- the sub-bin plus
 // w - 1 cells on the high side of each axis -- in LDS with coalesced loads,
 // then each wavefront interpolates one node at a time from LDS.  Lanes 0..47
-// first evaluate the 3 x w kernel values (lane 16a + i holds phi for axis a,
-// tap i); lanes then own (b, c) tap pairs of the two inner axes and loop over
-// the outer one, and the per-lane sums are reduced across the wavefront.
+// first read the node's 3 x w tabulated kernel values (lane 16a + i holds phi
+// for axis a, tap i); lanes then own (b, c) tap pairs of the two inner axes
+// and loop over the outer one, and the per-lane sums are reduced across the
+// wavefront.
 #include "common.h"
 
 namespace jgb {
@@ -33,19 +34,14 @@ struct InterpArgs {
   int T0, T1, T2, S0, S1, S2;
   int nt1, nt2, nsub;
   int E0, E1, E2;   // staged region extents; E2 is padded (see the plan)
-  T beta;
-  T tw0, tw1, tw2;  // 2 / w per axis
   const Plan::InterpItem* items;
   const int4* hdr;
-  const T* f0;
-  const T* f1;
-  const T* f2;
   const double* coef;
   const int* perm;
   const C2<T>* F;
   int mode;
   C2<T>* uhat;
-  T* wts;
+  const T* wts;
   C2<T>* out;
   double* eparts;
 };
@@ -126,18 +122,8 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     const int4 h = a.hdr[j];
     const int lx0 = h.x - ox, ly0 = h.y - oy, lz0 = h.z - oz;  // in [0, S)
 
-    // kernel values: lane 16*axis + tap, one evaluation per lane
-    T wv;
-    {
-      const int ax = lane >> 4, t = lane & 15;
-      const T f = ax == 0 ? a.f0[j] : (ax == 1 ? a.f1[j] : a.f2[j]);
-      const T tw = ax == 0 ? a.tw0 : (ax == 1 ? a.tw1 : a.tw2);
-      const int wa_ = ax == 0 ? a.w0 : (ax == 1 ? a.w1 : a.w2);
-      wv = es_kernel<T>(T(t) - f, tw, a.beta);
-      if (wa_ == 1) wv = T(1);
-      if (ax > 2 || t >= wa_) wv = T(0);
-    }
-    if (a.mode == INTERP_POTENTIAL && lane < 48) a.wts[(int64_t)j * kRec + (lane < 32 ? lane : lane + 16)] = wv;
+    // kernel values from the node's record: lane 16 * axis + tap
+    const T wv = lane < 48 ? a.wts[(int64_t)j * kRec + (lane < 32 ? lane : lane + 16)] : T(0);
     wbuf[wave][lane] = wv;
     __builtin_amdgcn_wave_barrier();
 
@@ -250,21 +236,14 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.E0 = pl.E[0];
   a.E1 = pl.E[1];
   a.E2 = pl.E[2];
-  a.beta = (T)pl.beta;
-  a.tw0 = (T)(2.0 / pl.w[0]);
-  a.tw1 = (T)(2.0 / pl.w[1]);
-  a.tw2 = (T)(2.0 / pl.w[2]);
   a.items = pl.d_iitems;
   a.hdr = pl.nodes.hdr;
-  a.f0 = (const T*)pl.nodes.frac[0];
-  a.f1 = (const T*)pl.nodes.frac[1];
-  a.f2 = (const T*)pl.nodes.frac[2];
   a.coef = pl.nodes.coef;
   a.perm = pl.nodes.perm;
   a.F = (const C2<T>*)pl.d_F;
   a.mode = mode;
   a.uhat = (C2<T>*)pl.nodes.uhat;
-  a.wts = (T*)pl.nodes.wts;
+  a.wts = (const T*)pl.nodes.wts;
   a.out = (C2<T>*)out;
   a.eparts = pl.d_eparts;
   unsigned blocks = (unsigned)pl.niitems;

@@ -25,7 +25,7 @@ namespace {
 
 struct NodeParams {
   int dim, n_r, n_theta, n_phi, rule, kernel;
-  double K;
+  double K, beta;
   double axis[3];
   double box[3];  // physical side lengths per internal axis (unit axis: 0)
   int nf[3], w[3], T[3], nt[3], S[3];
@@ -42,6 +42,7 @@ NodeParams make_params(const Plan& pl) {
   q.rule = pl.p.theta_rule;
   q.kernel = pl.p.kernel;
   q.K = pl.K;
+  q.beta = pl.beta;
   for (int i = 0; i < 3; ++i) q.axis[i] = pl.p.dipole_axis[i];
   for (int i = 0; i < 3; ++i) {
     q.box[i] = (pl.n[i] == 1) ? 0.0 : pl.box[i];
@@ -203,9 +204,15 @@ __global__ void k_node_keys(NodeParams q, int64_t Mh, int* keys) {
   keys[h] = bin * nsub + (s0 * m1 + s1) * m2 + s2;
 }
 
+// Per node: footprint start, fractional offsets, coefficient 2 c_j, and the
+// kernel values of the footprint on each axis.  The kernel values depend on
+// the node alone, so they are tabulated once here and read by both NUFFT
+// directions on every evaluation: record layout (kRec values of T) is
+// [0,16) axis 0 taps, [16,32) axis 1 taps, [48,64) axis 2 taps, zeros elsewhere
+// (the zeros let a window over the axis-2 taps start up to 16 taps early or late).
 template <typename T>
 __global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int4* hdr, T* f0, T* f1, T* f2,
-                             double* coef) {
+                             double* coef, T* wts) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= Mh) return;
   int64_t h = perm[p];
@@ -221,6 +228,13 @@ __global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int4* hd
   double twopi_d = (q.dim == 3) ? 8.0 * M_PI * M_PI * M_PI : 4.0 * M_PI * M_PI;
   // factor 2: the node stands for itself and for -k (conjugate transform, same c)
   coef[p] = 2.0 * W * symbol(q, k) / twopi_d;
+  T* rec = wts + p * kRec;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int w = q.w[ax];
+    const T f = (T)frac[ax], tw = (T)(2.0 / w), beta = (T)q.beta;
+    T* out = rec + (ax == 2 ? 48 : 16 * ax);
+    for (int t = 0; t < 16; ++t) out[t] = (t >= w) ? T(0) : (w == 1 ? T(1) : es_kernel<T>(T(t) - f, tw, beta));
+  }
 }
 
 __global__ void k_node_export(NodeParams q, int64_t M, double* kout, double* wout, double* cout) {
@@ -269,11 +283,11 @@ hipError_t launch_node_setup(const Plan& pl, const int* perm, hipStream_t s) {
   if (pl.fp64) {
     hipLaunchKernelGGL(k_node_setup<double>, dim3(grid_for(pl.Mh, 256)), dim3(256), 0, s, q, pl.Mh, perm,
                        a.hdr, (double*)a.frac[0], (double*)a.frac[1],
-                       (double*)a.frac[2], a.coef);
+                       (double*)a.frac[2], a.coef, (double*)a.wts);
   } else {
     hipLaunchKernelGGL(k_node_setup<float>, dim3(grid_for(pl.Mh, 256)), dim3(256), 0, s, q, pl.Mh, perm,
                        a.hdr, (float*)a.frac[0], (float*)a.frac[1],
-                       (float*)a.frac[2], a.coef);
+                       (float*)a.frac[2], a.coef, (float*)a.wts);
   }
   return hipGetLastError();
 }

@@ -4,13 +4,12 @@
 //
 //   G[g] = sum_j uhat_j phi(g0 - s0_j) phi(g1 - s1_j) phi(g2 - s2_j)   (periodic)
 //
-// Each wavefront owns one output tile of T0 x T1 lanes by kTileZ points along
-// the contiguous axis, holds the tile's accumulators in registers and walks
-// the nodes of the bins that can reach the tile (nodes are bin-sorted by the
-// first tap of their footprint, bins coincide with tiles).  Every test on a
-// node is uniform across the wavefront, so nodes that miss the tile, and
-// z-taps outside the footprint, cost scalar work only.  No atomics: every
-// grid point is written once, which makes the result deterministic.
+// A block owns one output tile of T0 x T1 x kTileZ points (kTileZ along the
+// contiguous axis) and walks the tile's exact node list: every node whose
+// footprint touches the tile, with its first tap relative to the tile origin.
+// The tile update for a group of nodes is a rank-4 matrix product run on the
+// matrix cores (below).  No atomics: every grid point is written once, in a
+// fixed summation order, which makes the result deterministic.
 //
 // Tiles whose candidate list is longer than the chunk cap (the bins near
 // k = 0, where every radial shell crowds into a few cells) are split into
@@ -30,7 +29,7 @@ template <typename T>
 struct SpreadArgs {
   int nf0, nf1, nf2;
   int w0, w1, w2;
-  int T0, T1;
+  int T0, T1, lgT1;  // tile extents on axes 0 and 1 (T0 T1 = 64, T1 a power of two)
   int nt1, nt2;
   const int2* list;
   const WorkItem* items;
@@ -43,33 +42,46 @@ struct SpreadArgs {
 
 constexpr int kWaves = 4;
 
-// Add one node's contribution to the wavefront's tile column.  o is the
-// node's first a2 tap relative to the tile origin (uniform); the 16 kernel
-// values that land on tile z = 0..15 are the window rec[kRecZ - o + z] of the
-// zero-padded record, read with one uniform load, so the update is the same
-// 32 multiply-adds for every node with no branch on o.
+// Matrix-core form of the gather.  For one tile and four nodes at a time,
+//
+//   G[m, z] += sum_k P[m, k] Q[k, z],   P[m, k] = phi_x(x_m - s_k) phi_y(y_m - s_k),
+//                                        Q[k, z] = phi_z(z - s_k) uhat_k,
+//
+// with m the 64 (a0, a1) points of the tile in four row blocks of 16 and z
+// the 16 points along a2: eight 16x16x4 products per four nodes (real and
+// imaginary parts of each row block).  Lane 16k + i supplies P[16b + i, k]
+// and Q[k, i], so every operand comes from an ordinary per-lane load; no
+// value has to be broadcast across the wavefront.
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 template <typename T>
-__device__ __forceinline__ void add_window(T (&ar)[kTileZ], T (&ai)[kTileZ], const T* rec, int o, T pr, T pi) {
-  const T* wz = rec + (kRecZ - o);
-#pragma unroll
-  for (int z = 0; z < kTileZ; ++z) {
-    const T v = wz[z];
-    ar[z] += v * pr;
-    ai[z] += v * pi;
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4v acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-}
+  // row of the 16x16 result held in register r of lane l (column l % 16)
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * r + (l >> 4); }
+};
+template <>
+struct Mfma<float> {
+  typedef f4v acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
 
 // One block per work item (a tile and a range of its node list).  The four
-// wavefronts each take a contiguous quarter of the range and accumulate the
-// whole 8 x 8 x kTileZ tile in registers; the partial tiles are then summed
-// in LDS in a fixed order and written once.
-//
-// Nodes are taken B at a time: the scalar loads of a batch (node values and
-// z windows) are issued together and the next batch's list entries ride along,
-// so one round trip to the scalar cache serves B nodes.
-template <typename T, int B>
+// wavefronts each take a contiguous quarter of the range; their partial tiles
+// are summed in LDS in a fixed order and written once.
+template <typename T>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
-  __shared__ C2<T> red[2][64 * kTileZ];
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T red[2][2 * 64 * kTileZ];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const WorkItem item = a.items[blockIdx.x];
@@ -78,106 +90,109 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int t1 = (tile / a.nt2) % a.nt1;
   const int t0 = tile / (a.nt2 * a.nt1);
   const int o0 = t0 * a.T0, o1 = t1 * a.T1, o2 = t2 * kTileZ;
-  const int lx = lane / a.T1, ly = lane % a.T1;
-  const bool lane_ok = (o0 + lx < a.nf0) && (o1 + ly < a.nf1);
+  const int li = lane & 15, lk = lane >> 4;
 
-  T ar[kTileZ], ai[kTileZ];
+  acc_t acc[4][2];
+  // lane's (a0, a1) point in row block b and whether it lies on the grid
+  int xb[4], yb[4];
+  bool onb[4];
 #pragma unroll
-  for (int z = 0; z < kTileZ; ++z) {
-    ar[z] = T(0);
-    ai[z] = T(0);
+  for (int b = 0; b < 4; ++b) {
+    acc[b][0] = acc_t{T(0), T(0), T(0), T(0)};
+    acc[b][1] = acc_t{T(0), T(0), T(0), T(0)};
+    const int m = 16 * b + li;
+    xb[b] = m >> a.lgT1;
+    yb[b] = m & (a.T1 - 1);
+    onb[b] = (o0 + xb[b] < a.nf0) && (o1 + yb[b] < a.nf1);
   }
 
   const int n = item.vend - item.vbegin;
   const int q = (n + kWaves - 1) / kWaves;
   const int kb = item.vbegin + wave * q;
   const int ke = (kb + q < item.vend) ? kb + q : item.vend;
-  const int last = ke - 1;
 
-  int2 ent[B];
-  if (kb < ke) {
+  // list entries are fetched one group ahead; ke - 1 >= kb is a valid index
+  // whenever the loop runs, and vbegin <= list length always is (the list
+  // carries a spare entry past its end)
+  int2 ent_next = a.list[(kb + lk < ke) ? kb + lk : (kb < ke ? ke - 1 : item.vbegin)];
+  for (int g = kb; g < ke; g += 4) {
+    const bool valid = g + lk < ke;
+    const int2 ent = ent_next;
+    ent_next = a.list[(g + 4 + lk < ke) ? g + 4 + lk : ke - 1];
+    const int j = ent.x;
+    const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
+    const T* rec = a.wts + (int64_t)j * kRec;
+    const C2<T> u = a.uhat[j];
+    // phi_z at tile z = li: the footprint starts inside the tile (offset ez) or
+    // before it (offset ez - nf2); on grids narrower than kTileZ + w2 both
+    const bool zin = ez < kTileZ;
+    const bool zwrap = a.nf2 - ez < a.w2;
+    T wz = rec[kRecZ - (zin ? ez : ez - a.nf2) + li];
+    if (zin && zwrap) wz += rec[kRecZ - (ez - a.nf2) + li];
+    const T qr = valid ? wz * u.x : T(0);
+    const T qi = valid ? wz * u.y : T(0);
 #pragma unroll
-    for (int b = 0; b < B; ++b) ent[b] = a.list[kb + b <= last ? kb + b : last];
-  }
-  for (int k = kb; k < ke; k += B) {
-    int2 cur[B];
-    C2<T> u[B];
-    T wxy[B];
-    const T* rec[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      cur[b] = ent[b];
-      rec[b] = a.wts + (int64_t)cur[b].x * kRec;
-      u[b] = a.uhat[cur[b].x];
-      wxy[b] = rec[b][lane & 31];
-    }
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const int kn = k + B + b;
-      ent[b] = a.list[kn <= last ? kn : last];
-    }
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      if (k + b > last) break;
-      const int ex = cur[b].y & 1023, ey = (cur[b].y >> 10) & 1023, ez = (cur[b].y >> 20) & 1023;
-      int dx = lx - ex;
+    for (int b = 0; b < 4; ++b) {
+      int dx = xb[b] - ex;
       if (dx < 0) dx += a.nf0;
-      int dy = ly - ey;
+      int dy = yb[b] - ey;
       if (dy < 0) dy += a.nf1;
-      const bool in = lane_ok && dx < a.w0 && dy < a.w1;
-      const T wx = __shfl(wxy[b], dx & 15, 64);
-      const T wy = __shfl(wxy[b], 16 + (dy & 15), 64);
-      const T p = in ? wx * wy : T(0);
-      const T pr = p * u[b].x, pi = p * u[b].y;
-      // the footprint starts inside the tile (o = ez) or before it and wraps in
-      // (o = ez - nf2 > -w2); on grids narrower than kTileZ + w2 both can hold
-      const bool zin = ez < kTileZ;
-      const bool zwrap = a.nf2 - ez < a.w2;
-      add_window(ar, ai, rec[b], zin ? ez : ez - a.nf2, pr, pi);
-      if (zin && zwrap) add_window(ar, ai, rec[b], ez - a.nf2, pr, pi);
+      const bool in = onb[b] && dx < a.w0 && dy < a.w1;
+      const T pv = in ? rec[in ? dx : 0] * rec[16 + (in ? dy : 0)] : T(0);
+      acc[b][0] = Mfma<T>::mma(pv, qr, acc[b][0]);
+      acc[b][1] = Mfma<T>::mma(pv, qi, acc[b][1]);
     }
   }
 
   // fixed-order sum of the four partial tiles: (w0 + w2) + (w1 + w3)
-  const int base = lane * kTileZ;
+  const int base = lane;  // element (b, part, r) at base + 64 * (8 b + 4 part + r)
   if (wave >= 2) {
 #pragma unroll
-    for (int z = 0; z < kTileZ; ++z) red[wave - 2][base + z] = C2<T>{ar[z], ai[z]};
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        red[wave - 2][base + 64 * (b * 8 + r)] = acc[b][0][r];
+        red[wave - 2][base + 64 * (b * 8 + 4 + r)] = acc[b][1][r];
+      }
   }
   __syncthreads();
   if (wave < 2) {
 #pragma unroll
-    for (int z = 0; z < kTileZ; ++z) {
-      C2<T> o = red[wave][base + z];
-      ar[z] += o.x;
-      ai[z] += o.y;
-    }
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc[b][0][r] += red[wave][base + 64 * (b * 8 + r)];
+        acc[b][1][r] += red[wave][base + 64 * (b * 8 + 4 + r)];
+      }
   }
   __syncthreads();
   if (wave == 1) {
 #pragma unroll
-    for (int z = 0; z < kTileZ; ++z) red[0][base + z] = C2<T>{ar[z], ai[z]};
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        red[0][base + 64 * (b * 8 + r)] = acc[b][0][r];
+        red[0][base + 64 * (b * 8 + 4 + r)] = acc[b][1][r];
+      }
   }
   __syncthreads();
   if (wave != 0) return;
+  const int z = lane & 15;
 #pragma unroll
-  for (int z = 0; z < kTileZ; ++z) {
-    C2<T> o = red[0][base + z];
-    ar[z] += o.x;
-    ai[z] += o.y;
-  }
-  if (!lane_ok) return;
-  const int g0 = o0 + lx, g1 = o1 + ly;
-  if (item.slot < 0) {
-    C2<T>* dst = a.G + ((int64_t)g0 * a.nf1 + g1) * a.nf2 + o2;
+  for (int b = 0; b < 4; ++b)
 #pragma unroll
-    for (int z = 0; z < kTileZ; ++z)
-      if (o2 + z < a.nf2) dst[z] = C2<T>{ar[z], ai[z]};
-  } else {
-    C2<T>* dst = a.partials + ((int64_t)item.slot * 64 + lane) * kTileZ;
-#pragma unroll
-    for (int z = 0; z < kTileZ; ++z) dst[z] = C2<T>{ar[z], ai[z]};
-  }
+    for (int r = 0; r < 4; ++r) {
+      const T vr = acc[b][0][r] + red[0][base + 64 * (b * 8 + r)];
+      const T vi = acc[b][1][r] + red[0][base + 64 * (b * 8 + 4 + r)];
+      const int m = 16 * b + Mfma<T>::row(lane, r);
+      const int x = m >> a.lgT1, y = m & (a.T1 - 1);
+      if (item.slot < 0) {
+        if (o0 + x < a.nf0 && o1 + y < a.nf1 && o2 + z < a.nf2)
+          a.G[((int64_t)(o0 + x) * a.nf1 + (o1 + y)) * a.nf2 + o2 + z] = C2<T>{vr, vi};
+      } else {
+        a.partials[((int64_t)item.slot * 64 + m) * kTileZ + z] = C2<T>{vr, vi};
+      }
+    }
 }
 
 // Sum the partial tiles of each split tile in slot order and store the tile.
@@ -231,6 +246,9 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.w2 = pl.w[2];
   a.T0 = pl.T[0];
   a.T1 = pl.T[1];
+  a.lgT1 = 0;
+  while ((1 << a.lgT1) < pl.T[1]) ++a.lgT1;
+  if ((1 << a.lgT1) != pl.T[1] || pl.T[0] * pl.T[1] != 64) return hipErrorInvalidValue;
   a.nt1 = pl.nt[1];
   a.nt2 = pl.nt[2];
   a.list = pl.d_list;
@@ -243,8 +261,7 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   unsigned blocks = (unsigned)pl.nitems;
   if (blocks == 0) return hipErrorInvalidConfiguration;
   stage_mark(pl, ST_SPREAD, 0, s);
-  constexpr int kBatch = sizeof(T) == 8 ? 2 : 4;
-  hipLaunchKernelGGL((k_spread_gather<T, kBatch>), dim3(blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_spread_gather<T>), dim3(blocks), dim3(256), 0, s, a);
   stage_mark(pl, ST_SPREAD, 1, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
