@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "fastdiv.h"
 #include "jgb.h"
 
 namespace jgb {

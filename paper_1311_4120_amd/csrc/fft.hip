@@ -137,6 +137,9 @@ struct PassArgs {
   T sign;
   int nrad;
   int rad[12];
+  int tws[12];      // twiddle stride of each radix stage, L / (Ns R)
+  FastDiv dNs[12];  // Ns of each radix stage (product of the earlier radices)
+  FastDiv dLB, dnin, dnout, dic, dn1;
   const C2<T>* tw;  // exp(-2 pi i t / L), t < L
   const void* in;
   void* out;
@@ -157,33 +160,35 @@ __device__ inline int fine_pos(int i, int N, int L) {
 }
 
 template <typename T, int R, int MAXV>
-__device__ inline void stage(C2<T>* lds, int ldl, int L, int LB, int Ns, const C2<T>* tw, T sign) {
+__device__ inline void stage(C2<T>* lds, int ldl, int L, int LB, int Ns, const FastDiv& dLB, const FastDiv& dNs,
+                             int stride_tw, const C2<T>* tw, T sign) {
   const int nbf = L / R;           // butterflies per line
   const int nb = LB * nbf;         // butterflies in the block
   constexpr int MAXB = (MAXV + R - 1) / R;   // butterflies per thread at most
   C2<T> v[MAXB][R];
   int dst[MAXB];
-  const int stride_tw = L / (Ns * R);
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     int b = threadIdx.x + i * blockDim.x;
     if (b < nb) {
-      int l = b % LB;
-      int j = b / LB;
-      int k = j % Ns;
+      const int j = (int)dLB.div(b);
+      const int l = b - j * LB;
+      const int jq = (int)dNs.div(j);
+      const int k = j - jq * Ns;
       C2<T>* row = lds + l * ldl;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = row[j + r * nbf];
       if (Ns > 1) {
+        // r k stride_tw < R Ns L / (Ns R) = L: no reduction needed
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C2<T> w = tw[(r * k * stride_tw) % L];
+          C2<T> w = tw[r * k * stride_tw];
           w.y *= -sign;  // table holds exp(-2 pi i t/L); sign +1 needs the conjugate
           v[i][r] = cmul(v[i][r], w);
         }
       }
       dft<T, R>(v[i], sign);
-      dst[i] = l * ldl + (j / Ns) * Ns * R + k;
+      dst[i] = l * ldl + jq * Ns * R + k;
     }
   }
   __syncthreads();
@@ -205,14 +210,14 @@ __global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
   const int L = a.L;
   const int ldl = L + 1;
   const int LB = a.LB;
-  const int64_t line0 = (int64_t)blockIdx.x * LB;
+  const int line0 = blockIdx.x * LB;
 
   // zero the padding region of every line when the input is padded
   if (a.nin < L) {
     const int N = a.nin;
     const int nz = L - N;  // fine positions [N - N/2, L - N/2) stay zero
     for (int idx = threadIdx.x; idx < LB * nz; idx += blockDim.x) {
-      int l = idx / nz, e = idx % nz;
+      const int e = (int)a.dLB.div(idx), l = idx - e * LB;
       lds[l * ldl + (N - N / 2) + e] = C2<T>{T(0), T(0)};
     }
   }
@@ -222,20 +227,21 @@ __global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
   for (int idx = threadIdx.x; idx < total_in; idx += blockDim.x) {
     int l, e;
     if (a.lines_fastest) {
-      l = idx % LB;
-      e = idx / LB;
+      e = (int)a.dLB.div(idx);
+      l = idx - e * LB;
     } else {
-      l = idx / a.nin;
-      e = idx % a.nin;
+      l = (int)a.dnin.div(idx);
+      e = idx - l * a.nin;
     }
-    int64_t line = line0 + l;
+    const int line = line0 + l;
     int pos = (a.nin < L) ? fine_pos(e, a.nin, L) : e;
     C2<T> v = {T(0), T(0)};
     if (line < a.nlines) {
-      int64_t base = (line / a.ic) * a.in_os + (line % a.ic) * a.in_is + (int64_t)e * a.in_es;
+      const int lo = (int)a.dic.div(line);
+      const int64_t base = (int64_t)lo * a.in_os + (int64_t)(line - lo * (int)a.ic) * a.in_is + (int64_t)e * a.in_es;
       if constexpr (KIND == PASS_FWD_Z) {
         // line = i0 * n1 + i1; element e = i2
-        int64_t i0 = line / a.n1, i1 = line % a.n1;
+        const int i0 = (int)a.dn1.div(line), i1 = line - i0 * a.n1;
         double d = a.scale * a.dec0[i0] * a.dec1[i1] * a.dec2[e];
         v.x = (T)((double)((const T*)a.in)[base] * d);
       } else {
@@ -249,13 +255,15 @@ __global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
   // FFT stages
   int Ns = 1;
   for (int st = 0; st < a.nrad; ++st) {
-    int R = a.rad[st];
+    const int R = a.rad[st];
+    const FastDiv& dNs = a.dNs[st];
+    const int tws = a.tws[st];
     switch (R) {
-      case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
-      case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
-      case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
-      case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
-      default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.tw, a.sign); break;
+      case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
     }
     Ns *= R;
   }
@@ -266,19 +274,20 @@ __global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
   for (int idx = threadIdx.x; idx < total_out; idx += blockDim.x) {
     int l, e;
     if (a.lines_fastest) {
-      l = idx % LB;
-      e = idx / LB;
+      e = (int)a.dLB.div(idx);
+      l = idx - e * LB;
     } else {
-      l = idx / a.nout;
-      e = idx % a.nout;
+      l = (int)a.dnout.div(idx);
+      e = idx - l * a.nout;
     }
-    int64_t line = line0 + l;
+    const int line = line0 + l;
     if (line >= a.nlines) continue;
     int pos = (a.nout < L) ? fine_pos(e, a.nout, L) : e;
     C2<T> v = lds[l * ldl + pos];
-    int64_t base = (line / a.ic) * a.out_os + (line % a.ic) * a.out_is + (int64_t)e * a.out_es;
+    const int lo = (int)a.dic.div(line);
+    const int64_t base = (int64_t)lo * a.out_os + (int64_t)(line - lo * (int)a.ic) * a.out_is + (int64_t)e * a.out_es;
     if constexpr (KIND == PASS_INV_Z) {
-      int64_t i0 = line / a.n1, i1 = line % a.n1;
+      const int i0 = (int)a.dn1.div(line), i1 = line - i0 * a.n1;
       double u = (double)v.x * (a.dec0[i0] * a.dec1[i1] * a.dec2[e]);
       ((T*)a.out)[base] = (T)u;
       if (a.rho) eacc += (double)a.rho[base] * u;
@@ -342,6 +351,20 @@ template <typename T, int KIND>
 hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   factor(a.L, a.rad, a.nrad);
   a.LB = lines_per_block<T>(a.L);
+  {
+    int Ns = 1;
+    for (int st = 0; st < a.nrad; ++st) {
+      a.dNs[st] = FastDiv((uint32_t)Ns);
+      a.tws[st] = a.L / (Ns * a.rad[st]);
+      Ns *= a.rad[st];
+    }
+  }
+  if (a.nlines >= (1 << 30) || (int64_t)a.LB * a.L >= (1 << 30)) return hipErrorInvalidValue;
+  a.dLB = FastDiv((uint32_t)a.LB);
+  a.dnin = FastDiv((uint32_t)a.nin);
+  a.dnout = FastDiv((uint32_t)a.nout);
+  a.dic = FastDiv((uint32_t)a.ic);
+  a.dn1 = FastDiv((uint32_t)(a.n1 > 0 ? a.n1 : 1));
   unsigned blocks = (unsigned)((a.nlines + a.LB - 1) / a.LB);
   size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
   constexpr int MAXV = (sizeof(T) == 8 ? 4096 : 8192) / 256;

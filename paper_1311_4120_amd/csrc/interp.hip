@@ -104,12 +104,32 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
 
   // stage the neighbourhood (periodic on the fine grid; the padding columns of
   // the last axis are loaded too and never read)
-  const int nreg = a.E0 * a.E1 * a.E2;
-  for (int idx = threadIdx.x; idx < nreg; idx += kInterpThreads) {
-    int i2 = idx % a.E2, i1 = (idx / a.E2) % a.E1, i0 = idx / (a.E2 * a.E1);
-    // the region may be wider than the grid on small grids: reduce modulo nf
-    const int g0 = (ox + i0) % a.nf0, g1 = (oy + i1) % a.nf1, g2 = (oz + i2) % a.nf2;
-    tile[idx] = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
+  // thread t copies element i2 = t mod E2 of rows t / E2, t / E2 + rpp, ...
+  // (rpp rows per pass); the row's (i0, i1) advances by increments, so no
+  // element costs a division
+  {
+    const int rpp = kInterpThreads / a.E2;
+    const int r0 = threadIdx.x / a.E2;
+    if (r0 < rpp) {
+      const int i2 = threadIdx.x - r0 * a.E2;
+      const int g2 = (oz + i2) % a.nf2;
+      const int d0 = rpp / a.E1, d1 = rpp - d0 * a.E1;
+      int i0 = r0 / a.E1, i1 = r0 - (r0 / a.E1) * a.E1;
+      const int nrow = a.E0 * a.E1;
+      for (int r = r0; r < nrow; r += rpp) {
+        // the region may be wider than the grid on small grids: wrap as often as needed
+        int g0 = ox + i0, g1 = oy + i1;
+        while (g0 >= a.nf0) g0 -= a.nf0;
+        while (g1 >= a.nf1) g1 -= a.nf1;
+        tile[r * a.E2 + i2] = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
+        i0 += d0;
+        i1 += d1;
+        if (i1 >= a.E1) {
+          i1 -= a.E1;
+          ++i0;
+        }
+      }
+    }
   }
   __syncthreads();
 
