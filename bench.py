@@ -32,7 +32,13 @@ METRIC = "potential evals/s + ns/grid-pt at 128Â³: FP64 Îµ=1e-10 vs mixed FP32 Î
 
 
 def stage_work(info, prec, energy=True):
-    """Algorithmic HBM bytes and flops of one launch of each stage."""
+    """Algorithmic HBM bytes and flops of one launch of each stage.
+
+    FFT passes: input + output of the pass.  Tap kernels: one pass over the
+    oversampled grid (interpolation reads F, spreading writes G) and 5 flops
+    per tap (complex x real multiply-add + the weight product) over the w^3
+    taps of every node the launch processes (the half set; the other half is
+    its mirror image)."""
     n = info["n"]
     nf = info["nf"]
     N = n[0]
@@ -49,14 +55,31 @@ def stage_work(info, prec, energy=True):
         "inv_fft_x": F3 * cb + N * f * f * cb,
         "inv_fft_y": N * f * f * cb + N * N * f * cb,
         "inv_fft_z": N * N * f * cb + N3 * rb + (N3 * rb if energy else 0),
-        # interp reads the grid once at best, node tables, writes uhat and kernel values
-        "interp": F3 * cb + Mh * (3 * 4 + 3 * rb + 8 + 2 * cb + 48 * rb),
-        # gather writes the grid once, reads node tables
-        "spread": F3 * cb + Mh * (3 * 4 + 2 * cb + 48 * rb),
+        "interp": F3 * cb,
+        "spread": F3 * cb,
     }
-    # complex x real multiply-add per tap (4 flops) over w^3 taps per node
-    fl = {"interp": 4.0 * Mh * w ** 3, "spread": 4.0 * Mh * w ** 3}
+    fl = {"interp": 5.0 * Mh * w ** 3, "spread": 5.0 * Mh * w ** 3}
     return by, fl
+
+
+def roofline(stage, ms, by, fl, prec):
+    """The stage's roofline: whichever bound (HBM bytes, or flops at the
+    compute peak of its unit) takes longer, and the achieved fraction of it."""
+    t = ms * 1e-3
+    t_mem = by[stage] / (HBM_PEAK_GBS * 1e9)
+    peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+    t_cmp = fl[stage] / (peak * 1e12) if stage in fl else 0.0
+    if t_cmp > t_mem:
+        ach = fl[stage] / t / 1e12
+        return {"kernel": stage, "bound": "mfma" if stage == "spread" else "alu", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None, "flops_per_launch": fl[stage],
+                "bytes_per_launch": by[stage]}
+    ach = by[stage] / t / 1e9
+    out = {"kernel": stage, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": by[stage]}
+    if stage in fl:
+        out["flops_per_launch"] = fl[stage]
+    return out
 
 
 def run_gpu(prec, steps, warmup):
@@ -184,16 +207,7 @@ def main():
     by, fl = stage_work(r["info"], head)
     st = r["stages_ms"]
     dom = max((k for k in st if st[k] > 0), key=lambda k: st[k])
-    if dom in fl:
-        peak = FP64_PEAK_TFLOPS if head == "fp64" else FP32_PEAK_TFLOPS
-        ach = fl[dom] / (st[dom] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None,
-                "work_per_launch": "%d half-set nodes x %d^3 taps x 4 flops" % (r["info"]["n_half"], r["info"]["width"])}
-    else:
-        ach = by[dom] / (st[dom] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": by[dom]}
+    roof = roofline(dom, st[dom], by, fl, head)
     stages = {}
     for k, v in st.items():
         if v <= 0:
