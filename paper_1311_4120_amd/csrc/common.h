@@ -24,12 +24,11 @@ constexpr int kMaxWidth = 16;
 constexpr int kMaxLine = 1024;
 // Output tile of the type-1 gather kernel: TX x TY lanes, TZ points per lane.
 constexpr int kTileZ = 16;
-// Per-node kernel values written by the interpolation for the spreading:
-// [0,16) phi along a0, [16,32) along a1, [32,48) zeros, [48,64) along a2,
-// [64,80) zeros.  Entries past the width are zero, and the zero pads let the
-// gather read any 16-tap window of the a2 values at a uniform offset.
-constexpr int kRec = 80;
-constexpr int kRecZ = 48;
+// Per-node kernel values, tabulated at plan time: w values per internal axis,
+// axis a at [a w, a w + w) of the node's record (a unit axis has the single
+// value 1 at tap 0 and zeros after it); records are rec_stride values apart,
+// 3 w rounded up to a multiple of 4.
+inline int record_stride(int width) { return (3 * width + 3) / 4 * 4; }
 
 // ----------------------------------------------------------------- errors
 
@@ -56,7 +55,7 @@ struct NodeArrays {
   double* coef = nullptr;                      // 2 c_j (pair k, -k folded in)
   int* perm = nullptr;                         // sorted position -> natural half index
   void* uhat = nullptr;                        // c_j rho^_j, complex T
-  void* wts = nullptr;                         // per node kRec kernel values, T (layout below)
+  void* wts = nullptr;                         // per node record_stride(width) kernel values, T
 };
 
 struct WorkItem {

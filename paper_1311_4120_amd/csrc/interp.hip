@@ -42,6 +42,7 @@ struct InterpArgs {
   int mode;
   C2<T>* uhat;
   const T* wts;
+  int rstride;      // values per node record (axis a's taps at [a W, a W + W))
   C2<T>* out;
   double* eparts;
 };
@@ -143,7 +144,8 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     const int lx0 = h.x - ox, ly0 = h.y - oy, lz0 = h.z - oz;  // in [0, S)
 
     // kernel values from the node's record: lane 16 * axis + tap
-    const T wv = lane < 48 ? a.wts[(int64_t)j * kRec + (lane < 32 ? lane : lane + 16)] : T(0);
+    const int ax = lane >> 4, tap = lane & 15;
+    const T wv = (ax < 3 && tap < W) ? a.wts[(int64_t)j * a.rstride + ax * W + (tap < W ? tap : 0)] : T(0);
     wbuf[wave][lane] = wv;
     __builtin_amdgcn_wave_barrier();
 
@@ -264,6 +266,7 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.mode = mode;
   a.uhat = (C2<T>*)pl.nodes.uhat;
   a.wts = (const T*)pl.nodes.wts;
+  a.rstride = record_stride(pl.width);
   a.out = (C2<T>*)out;
   a.eparts = pl.d_eparts;
   unsigned blocks = (unsigned)pl.niitems;

@@ -24,7 +24,7 @@ namespace jgb {
 namespace {
 
 struct NodeParams {
-  int dim, n_r, n_theta, n_phi, rule, kernel;
+  int dim, n_r, n_theta, n_phi, rule, kernel, width, rstride;
   double K, beta;
   double axis[3];
   double box[3];  // physical side lengths per internal axis (unit axis: 0)
@@ -41,6 +41,8 @@ NodeParams make_params(const Plan& pl) {
   q.n_phi = pl.n_phi;
   q.rule = pl.p.theta_rule;
   q.kernel = pl.p.kernel;
+  q.width = pl.width;
+  q.rstride = record_stride(pl.width);
   q.K = pl.K;
   q.beta = pl.beta;
   for (int i = 0; i < 3; ++i) q.axis[i] = pl.p.dipole_axis[i];
@@ -207,9 +209,8 @@ __global__ void k_node_keys(NodeParams q, int64_t Mh, int* keys) {
 // Per node: footprint start, fractional offsets, coefficient 2 c_j, and the
 // kernel values of the footprint on each axis.  The kernel values depend on
 // the node alone, so they are tabulated once here and read by both NUFFT
-// directions on every evaluation: record layout (kRec values of T) is
-// [0,16) axis 0 taps, [16,32) axis 1 taps, [48,64) axis 2 taps, zeros elsewhere
-// (the zeros let a window over the axis-2 taps start up to 16 taps early or late).
+// directions on every evaluation: axis a's w taps at [a w, a w + w) of the
+// node's record (a unit axis: 1 at tap 0, zeros after it).
 template <typename T>
 __global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int4* hdr, T* f0, T* f1, T* f2,
                              double* coef, T* wts) {
@@ -228,12 +229,12 @@ __global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int4* hd
   double twopi_d = (q.dim == 3) ? 8.0 * M_PI * M_PI * M_PI : 4.0 * M_PI * M_PI;
   // factor 2: the node stands for itself and for -k (conjugate transform, same c)
   coef[p] = 2.0 * W * symbol(q, k) / twopi_d;
-  T* rec = wts + p * kRec;
+  T* rec = wts + p * q.rstride;
   for (int ax = 0; ax < 3; ++ax) {
     const int w = q.w[ax];
     const T f = (T)frac[ax], tw = (T)(2.0 / w), beta = (T)q.beta;
-    T* out = rec + (ax == 2 ? 48 : 16 * ax);
-    for (int t = 0; t < 16; ++t) out[t] = (t >= w) ? T(0) : (w == 1 ? T(1) : es_kernel<T>(T(t) - f, tw, beta));
+    T* out = rec + ax * q.width;
+    for (int t = 0; t < q.width; ++t) out[t] = (t >= w) ? T(0) : (w == 1 ? T(1) : es_kernel<T>(T(t) - f, tw, beta));
   }
 }
 

@@ -501,8 +501,9 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   for (int i = 0; i < 3; ++i) TRY(dev_alloc(pl, &pl.nodes.frac[i], pl.real_bytes * Mh));
   TRY(dev_alloc(pl, &pl.nodes.coef, sizeof(double) * Mh));
   TRY(dev_alloc(pl, &pl.nodes.uhat, 2 * pl.real_bytes * Mh));
-  TRY(dev_alloc(pl, &pl.nodes.wts, kRec * pl.real_bytes * Mh));
-  TRY_HIP(hipMemsetAsync(pl.nodes.wts, 0, kRec * pl.real_bytes * Mh, pl.stream), "clear kernel values");
+  TRY(dev_alloc(pl, &pl.nodes.wts, (size_t)record_stride(pl.width) * pl.real_bytes * Mh));
+  TRY_HIP(hipMemsetAsync(pl.nodes.wts, 0, (size_t)record_stride(pl.width) * pl.real_bytes * Mh, pl.stream),
+          "clear kernel values");
   TRY_HIP(launch_node_setup(pl, pl.nodes.perm, pl.stream), "node setup");
   TRY(dev_alloc(pl, &pl.d_bin_start, sizeof(int) * (pl.ntiles + 1)));
   TRY(upload(pl, pl.d_bin_start, bin_start.data(), sizeof(int) * (pl.ntiles + 1)));

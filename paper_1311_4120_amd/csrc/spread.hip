@@ -29,8 +29,8 @@ template <typename T>
 struct SpreadArgs {
   int nf0, nf1, nf2;
   int w0, w1, w2;
-  int T0, T1, lgT1;  // tile extents on axes 0 and 1 (T0 T1 = 64, T1 a power of two)
   int nt1, nt2;
+  int width, rstride;  // taps per axis in a node record, values per record
   const int2* list;
   const WorkItem* items;
   int nitems;
@@ -75,12 +75,32 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
 
+// Raw operands of one group of four list entries, loaded one group ahead of
+// their use so that the loads overlap the previous group's products.  NX and
+// NY are the distinct axis-0 and axis-1 kernel values a lane needs over its
+// four row blocks (the tile shape makes one of them 1).
+template <typename T, int NX, int NY>
+struct GroupLoads {
+  T z0, z1;        // axis-2 values of the one or two windows onto the tile
+  bool vz0, vz1;
+  T u_re, u_im;    // weighted node value
+  T px[NX], py[NY];
+  bool valid;      // lane's list entry exists
+  int dx[NX], dy[NY];
+};
+
 // One block per work item (a tile and a range of its node list).  The four
 // wavefronts each take a contiguous quarter of the range; their partial tiles
-// are summed in LDS in a fixed order and written once.
-template <typename T>
+// are summed in LDS in a fixed order and written once.  T1 is the tile extent
+// on axis 1 (8 for 8 x 8 x 16 tiles, 64 for the 1 x 64 x 16 tiles of 2D
+// problems); lane li of row block b holds the point m = 16 b + li, at
+// (m / T1, m mod T1).
+template <typename T, int T1>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int T0 = 64 / T1;
+  constexpr int NX = (T1 == 8) ? 4 : 1;   // distinct x over the row blocks
+  constexpr int NY = (T1 == 8) ? 1 : 4;   // distinct y over the row blocks
   __shared__ T red[2][2 * 64 * kTileZ];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -89,21 +109,30 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int t2 = tile % a.nt2;
   const int t1 = (tile / a.nt2) % a.nt1;
   const int t0 = tile / (a.nt2 * a.nt1);
-  const int o0 = t0 * a.T0, o1 = t1 * a.T1, o2 = t2 * kTileZ;
+  const int o0 = t0 * T0, o1 = t1 * T1, o2 = t2 * kTileZ;
   const int li = lane & 15, lk = lane >> 4;
+  const int W = a.width;
+
+  // the lane's x values (per row block when NX = 4) and y values (per row
+  // block when NY = 4), and whether they lie on the grid
+  int xs[NX], ys[NY];
+  bool xon[NX], yon[NY];
+#pragma unroll
+  for (int b = 0; b < NX; ++b) {
+    xs[b] = (16 * b + li) / T1;
+    xon[b] = o0 + xs[b] < a.nf0;
+  }
+#pragma unroll
+  for (int b = 0; b < NY; ++b) {
+    ys[b] = (16 * b + li) % T1;
+    yon[b] = o1 + ys[b] < a.nf1;
+  }
 
   acc_t acc[4][2];
-  // lane's (a0, a1) point in row block b and whether it lies on the grid
-  int xb[4], yb[4];
-  bool onb[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     acc[b][0] = acc_t{T(0), T(0), T(0), T(0)};
     acc[b][1] = acc_t{T(0), T(0), T(0), T(0)};
-    const int m = 16 * b + li;
-    xb[b] = m >> a.lgT1;
-    yb[b] = m & (a.T1 - 1);
-    onb[b] = (o0 + xb[b] < a.nf0) && (o1 + yb[b] < a.nf1);
   }
 
   const int n = item.vend - item.vbegin;
@@ -111,36 +140,66 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int kb = item.vbegin + wave * q;
   const int ke = (kb + q < item.vend) ? kb + q : item.vend;
 
-  // list entries are fetched one group ahead; ke - 1 >= kb is a valid index
-  // whenever the loop runs, and vbegin <= list length always is (the list
-  // carries a spare entry past its end)
-  int2 ent_next = a.list[(kb + lk < ke) ? kb + lk : (kb < ke ? ke - 1 : item.vbegin)];
-  for (int g = kb; g < ke; g += 4) {
-    const bool valid = g + lk < ke;
-    const int2 ent = ent_next;
-    ent_next = a.list[(g + 4 + lk < ke) ? g + 4 + lk : ke - 1];
+  // Issue the loads of the group whose entries start at g.  Lanes past the end
+  // read entry ke - 1 (>= kb, a valid index whenever the wave has work), so
+  // every address is a real node's; their results are masked by `valid`.
+  auto fetch = [&](int g) {
+    GroupLoads<T, NX, NY> r;
+    const int idx = g + lk;
+    r.valid = idx < ke;
+    const int2 ent = a.list[r.valid ? idx : ke - 1];
     const int j = ent.x;
     const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
-    const T* rec = a.wts + (int64_t)j * kRec;
+    const T* rec = a.wts + (int64_t)j * a.rstride;
     const C2<T> u = a.uhat[j];
-    // phi_z at tile z = li: the footprint starts inside the tile (offset ez) or
-    // before it (offset ez - nf2); on grids narrower than kTileZ + w2 both
+    r.u_re = u.x;
+    r.u_im = u.y;
+    // axis 2: tap li - o of the footprint lands on tile z = li, for the start
+    // o = ez inside the tile or o = ez - nf2 before it; on grids narrower than
+    // kTileZ + w both windows can hold
     const bool zin = ez < kTileZ;
     const bool zwrap = a.nf2 - ez < a.w2;
-    T wz = rec[kRecZ - (zin ? ez : ez - a.nf2) + li];
-    if (zin && zwrap) wz += rec[kRecZ - (ez - a.nf2) + li];
-    const T qr = valid ? wz * u.x : T(0);
-    const T qi = valid ? wz * u.y : T(0);
+    const int d0 = li - (zin ? ez : ez - a.nf2);
+    const int d1 = li - (ez - a.nf2);
+    r.vz0 = d0 >= 0 && d0 < a.w2;
+    r.vz1 = zin && zwrap && d1 < a.w2;
+    r.z0 = rec[2 * W + (r.vz0 ? d0 : 0)];
+    r.z1 = rec[2 * W + (r.vz1 ? d1 : 0)];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int dx = xb[b] - ex;
+    for (int b = 0; b < NX; ++b) {
+      int dx = xs[b] - ex;
       if (dx < 0) dx += a.nf0;
-      int dy = yb[b] - ey;
+      r.dx[b] = (xon[b] && dx < a.w0) ? dx : -1;
+      r.px[b] = rec[r.dx[b] >= 0 ? dx : 0];
+    }
+#pragma unroll
+    for (int b = 0; b < NY; ++b) {
+      int dy = ys[b] - ey;
       if (dy < 0) dy += a.nf1;
-      const bool in = onb[b] && dx < a.w0 && dy < a.w1;
-      const T pv = in ? rec[in ? dx : 0] * rec[16 + (in ? dy : 0)] : T(0);
-      acc[b][0] = Mfma<T>::mma(pv, qr, acc[b][0]);
-      acc[b][1] = Mfma<T>::mma(pv, qi, acc[b][1]);
+      r.dy[b] = (yon[b] && dy < a.w1) ? dy : -1;
+      r.py[b] = rec[W + (r.dy[b] >= 0 ? dy : 0)];
+    }
+    return r;
+  };
+
+  if (kb < ke) {
+    GroupLoads<T, NX, NY> cur = fetch(kb);
+    for (int g = kb; g < ke; g += 4) {
+      // next group's loads go out before this group's products (past the end
+      // they re-read the last entry and are discarded)
+      const GroupLoads<T, NX, NY> nxt = fetch(g + 4 < ke ? g + 4 : g);
+      const T wz = (cur.vz0 ? cur.z0 : T(0)) + (cur.vz1 ? cur.z1 : T(0));
+      const T qr = cur.valid ? wz * cur.u_re : T(0);
+      const T qi = cur.valid ? wz * cur.u_im : T(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int bx = NX == 4 ? b : 0, by = NY == 4 ? b : 0;
+        const bool in = cur.dx[bx] >= 0 && cur.dy[by] >= 0;
+        const T pv = in ? cur.px[bx] * cur.py[by] : T(0);
+        acc[b][0] = Mfma<T>::mma(pv, qr, acc[b][0]);
+        acc[b][1] = Mfma<T>::mma(pv, qi, acc[b][1]);
+      }
+      cur = nxt;
     }
   }
 
@@ -185,7 +244,7 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
       const T vr = acc[b][0][r] + red[0][base + 64 * (b * 8 + r)];
       const T vi = acc[b][1][r] + red[0][base + 64 * (b * 8 + 4 + r)];
       const int m = 16 * b + Mfma<T>::row(lane, r);
-      const int x = m >> a.lgT1, y = m & (a.T1 - 1);
+      const int x = m / T1, y = m % T1;
       if (item.slot < 0) {
         if (o0 + x < a.nf0 && o1 + y < a.nf1 && o2 + z < a.nf2)
           a.G[((int64_t)(o0 + x) * a.nf1 + (o1 + y)) * a.nf2 + o2 + z] = C2<T>{vr, vi};
@@ -244,12 +303,9 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.w0 = pl.w[0];
   a.w1 = pl.w[1];
   a.w2 = pl.w[2];
-  a.T0 = pl.T[0];
-  a.T1 = pl.T[1];
-  a.lgT1 = 0;
-  while ((1 << a.lgT1) < pl.T[1]) ++a.lgT1;
-  if ((1 << a.lgT1) != pl.T[1] || pl.T[0] * pl.T[1] != 64) return hipErrorInvalidValue;
   a.nt1 = pl.nt[1];
+  a.width = pl.width;
+  a.rstride = record_stride(pl.width);
   a.nt2 = pl.nt[2];
   a.list = pl.d_list;
   a.items = pl.d_items;
@@ -261,7 +317,12 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   unsigned blocks = (unsigned)pl.nitems;
   if (blocks == 0) return hipErrorInvalidConfiguration;
   stage_mark(pl, ST_SPREAD, 0, s);
-  hipLaunchKernelGGL((k_spread_gather<T>), dim3(blocks), dim3(256), 0, s, a);
+  if (pl.T[0] == 8 && pl.T[1] == 8)
+    hipLaunchKernelGGL((k_spread_gather<T, 8>), dim3(blocks), dim3(256), 0, s, a);
+  else if (pl.T[0] == 1 && pl.T[1] == 64)
+    hipLaunchKernelGGL((k_spread_gather<T, 64>), dim3(blocks), dim3(256), 0, s, a);
+  else
+    return hipErrorInvalidValue;
   stage_mark(pl, ST_SPREAD, 1, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
