@@ -203,52 +203,99 @@ __device__ inline void stage(C2<T>* lds, int ldl, int L, int LB, int Ns, const F
   __syncthreads();
 }
 
-template <typename T, int KIND, int MAXV>
-__global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
+// One block transforms LB lines.  Global traffic is issued in bulk: every
+// thread computes clamped (always valid) addresses for all of its up to MAXV
+// elements and issues the loads back to back, and only then writes LDS, so
+// that the loads are in flight together; the store phase reads LDS into
+// registers first and then stores.  The pass kind fixes the access order:
+// the complex passes run along a strided axis with consecutive threads on
+// consecutive lines, the Z passes along the contiguous axis.
+template <typename T, int KIND, int MAXV, int NT>
+__global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
+  constexpr bool LINES_FASTEST = (KIND == PASS_COMPLEX);
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
   const int L = a.L;
   const int ldl = L + 1;
   const int LB = a.LB;
   const int line0 = blockIdx.x * LB;
+  // Z passes: deconvolution factors of the block's lines and of the elements,
+  // staged after the lines
+  double* fline = reinterpret_cast<double*>(smem_raw + (size_t)LB * ldl * sizeof(C2<T>));
+  double* felem = fline + LB;
+
+  if constexpr (KIND != PASS_COMPLEX) {
+    const int ne = (KIND == PASS_FWD_Z) ? a.nin : a.nout;
+    for (int t = threadIdx.x; t < LB + ne; t += NT) {
+      if (t < LB) {
+        int line = line0 + t;
+        if (line >= a.nlines) line = 0;
+        const int i0 = (int)a.dn1.div(line), i1 = line - i0 * a.n1;
+        fline[t] = (KIND == PASS_FWD_Z ? a.scale : 1.0) * a.dec0[i0] * a.dec1[i1];
+      } else {
+        felem[t - LB] = a.dec2[t - LB];
+      }
+    }
+  }
 
   // zero the padding region of every line when the input is padded
   if (a.nin < L) {
     const int N = a.nin;
     const int nz = L - N;  // fine positions [N - N/2, L - N/2) stay zero
-    for (int idx = threadIdx.x; idx < LB * nz; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < LB * nz; idx += NT) {
       const int e = (int)a.dLB.div(idx), l = idx - e * LB;
       lds[l * ldl + (N - N / 2) + e] = C2<T>{T(0), T(0)};
     }
   }
+  if constexpr (KIND != PASS_COMPLEX) __syncthreads();  // factors staged
 
   // load
-  const int total_in = LB * a.nin;
-  for (int idx = threadIdx.x; idx < total_in; idx += blockDim.x) {
-    int l, e;
-    if (a.lines_fastest) {
-      e = (int)a.dLB.div(idx);
-      l = idx - e * LB;
-    } else {
-      l = (int)a.dnin.div(idx);
-      e = idx - l * a.nin;
-    }
-    const int line = line0 + l;
-    int pos = (a.nin < L) ? fine_pos(e, a.nin, L) : e;
-    C2<T> v = {T(0), T(0)};
-    if (line < a.nlines) {
-      const int lo = (int)a.dic.div(line);
-      const int64_t base = (int64_t)lo * a.in_os + (int64_t)(line - lo * (int)a.ic) * a.in_is + (int64_t)e * a.in_es;
-      if constexpr (KIND == PASS_FWD_Z) {
-        // line = i0 * n1 + i1; element e = i2
-        const int i0 = (int)a.dn1.div(line), i1 = line - i0 * a.n1;
-        double d = a.scale * a.dec0[i0] * a.dec1[i1] * a.dec2[e];
-        v.x = (T)((double)((const T*)a.in)[base] * d);
+  {
+    const int total_in = LB * a.nin;
+    C2<T> buf[MAXV];
+    int dst[MAXV];
+    int le[MAXV];  // Z pass: line (high bits) and element (low 16 bits)
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx0 = threadIdx.x + i * NT;
+      const bool ok = idx0 < total_in;
+      const int idx = ok ? idx0 : 0;
+      int l, e;
+      if constexpr (LINES_FASTEST) {
+        e = (int)a.dLB.div(idx);
+        l = idx - e * LB;
       } else {
-        v = ((const C2<T>*)a.in)[base];
+        l = (int)a.dnin.div(idx);
+        e = idx - l * a.nin;
+      }
+      const int line = line0 + l;
+      const bool lok = ok && line < a.nlines;
+      const int ln = lok ? line : 0;
+      const int lo = (int)a.dic.div(ln);
+      const int64_t base = (int64_t)lo * a.in_os + (int64_t)(ln - lo * (int)a.ic) * a.in_is + (int64_t)e * a.in_es;
+      if constexpr (KIND == PASS_FWD_Z) {
+        const T r = ((const T*)a.in)[base];
+        buf[i] = C2<T>{lok ? r : T(0), T(0)};
+      } else {
+        const C2<T> v = ((const C2<T>*)a.in)[base];
+        buf[i] = lok ? v : C2<T>{T(0), T(0)};
+      }
+      const int pos = (a.nin < L) ? fine_pos(e, a.nin, L) : e;
+      dst[i] = ok ? l * ldl + pos : -1;
+      le[i] = (l << 16) | e;
+    }
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      if (dst[i] >= 0) {
+        C2<T> v = buf[i];
+        if constexpr (KIND == PASS_FWD_Z) {
+          // deconvolution and cell volume, applied in float64
+          const double d = fline[le[i] >> 16] * felem[le[i] & 0xffff];
+          v.x = (T)((double)v.x * d);
+        }
+        lds[dst[i]] = v;
       }
     }
-    lds[l * ldl + pos] = v;
   }
   __syncthreads();
 
@@ -268,31 +315,62 @@ __global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
     Ns *= R;
   }
 
-  // store
+  // store: LDS reads first, then the global stores
   double eacc = 0.0;
-  const int total_out = LB * a.nout;
-  for (int idx = threadIdx.x; idx < total_out; idx += blockDim.x) {
-    int l, e;
-    if (a.lines_fastest) {
-      e = (int)a.dLB.div(idx);
-      l = idx - e * LB;
-    } else {
-      l = (int)a.dnout.div(idx);
-      e = idx - l * a.nout;
+  {
+    const int total_out = LB * a.nout;
+    C2<T> buf[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx0 = threadIdx.x + i * NT;
+      const int idx = idx0 < total_out ? idx0 : 0;
+      int l, e;
+      if constexpr (LINES_FASTEST) {
+        e = (int)a.dLB.div(idx);
+        l = idx - e * LB;
+      } else {
+        l = (int)a.dnout.div(idx);
+        e = idx - l * a.nout;
+      }
+      const int pos = (a.nout < L) ? fine_pos(e, a.nout, L) : e;
+      buf[i] = lds[l * ldl + pos];
     }
-    const int line = line0 + l;
-    if (line >= a.nlines) continue;
-    int pos = (a.nout < L) ? fine_pos(e, a.nout, L) : e;
-    C2<T> v = lds[l * ldl + pos];
-    const int lo = (int)a.dic.div(line);
-    const int64_t base = (int64_t)lo * a.out_os + (int64_t)(line - lo * (int)a.ic) * a.out_is + (int64_t)e * a.out_es;
+    T rho_v[KIND == PASS_INV_Z ? MAXV : 1];
     if constexpr (KIND == PASS_INV_Z) {
-      const int i0 = (int)a.dn1.div(line), i1 = line - i0 * a.n1;
-      double u = (double)v.x * (a.dec0[i0] * a.dec1[i1] * a.dec2[e]);
-      ((T*)a.out)[base] = (T)u;
-      if (a.rho) eacc += (double)a.rho[base] * u;
-    } else {
-      ((C2<T>*)a.out)[base] = v;
+      // density values for the energy partials, loaded together
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i) {
+        const int idx0 = threadIdx.x + i * NT;
+        const int idx = idx0 < total_out ? idx0 : 0;
+        const int l = (int)a.dnout.div(idx), e = idx - l * a.nout;
+        int line = line0 + l;
+        if (line >= a.nlines) line = 0;
+        rho_v[i] = a.rho ? a.rho[(int64_t)line * a.out_os + e] : T(0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = threadIdx.x + i * NT;
+      if (idx >= total_out) continue;
+      int l, e;
+      if constexpr (LINES_FASTEST) {
+        e = (int)a.dLB.div(idx);
+        l = idx - e * LB;
+      } else {
+        l = (int)a.dnout.div(idx);
+        e = idx - l * a.nout;
+      }
+      const int line = line0 + l;
+      if (line >= a.nlines) continue;
+      const int lo = (int)a.dic.div(line);
+      const int64_t base = (int64_t)lo * a.out_os + (int64_t)(line - lo * (int)a.ic) * a.out_is + (int64_t)e * a.out_es;
+      if constexpr (KIND == PASS_INV_Z) {
+        const double u = (double)buf[i].x * (fline[l] * felem[e]);
+        ((T*)a.out)[base] = (T)u;
+        eacc += (double)rho_v[i] * u;
+      } else {
+        ((C2<T>*)a.out)[base] = buf[i];
+      }
     }
   }
 
@@ -300,7 +378,7 @@ __global__ void __launch_bounds__(256) k_fft_pass(PassArgs<T> a) {
     if (a.eparts) {
       // deterministic block sum: wave shuffle, then waves in order
       for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
-      __shared__ double wsum[4];
+      __shared__ double wsum[NT / 64];
       __syncthreads();
       if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = eacc;
       __syncthreads();
@@ -338,11 +416,18 @@ void factor(int L, int* rad, int& nrad) {
   }
 }
 
+// Block shape: 256 threads (fp64) or 512 (fp32), at most 16 complex elements
+// per thread, so 4096 or 8192 elements (64 KB) staged per block; up to 16 or
+// 32 lines, which makes every strided-pass row of a block 256 contiguous bytes.
+template <typename T>
+constexpr int pass_threads() { return sizeof(T) == 8 ? 256 : 512; }
+
 template <typename T>
 int lines_per_block(int L) {
-  int cap = (sizeof(T) == 8) ? 4096 : 8192;  // complex elements staged per block
+  const int cap = 16 * pass_threads<T>();  // complex elements staged per block
+  const int maxlb = sizeof(T) == 8 ? 16 : 32;
   int lb = cap / L;
-  if (lb > 16) lb = 16;
+  if (lb > maxlb) lb = maxlb;
   if (lb < 1) lb = 1;
   return lb;
 }
@@ -367,9 +452,11 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   a.dn1 = FastDiv((uint32_t)(a.n1 > 0 ? a.n1 : 1));
   unsigned blocks = (unsigned)((a.nlines + a.LB - 1) / a.LB);
   size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
-  constexpr int MAXV = (sizeof(T) == 8 ? 4096 : 8192) / 256;
+  if (KIND != PASS_COMPLEX) smem += sizeof(double) * (a.LB + a.L);  // deconvolution factors
+  constexpr int NT = pass_threads<T>();
+  constexpr int MAXV = 16;
   stage_mark(pl, stage, 0, s);
-  hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV>), dim3(blocks), dim3(256), smem, s, a);
+  hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
   stage_mark(pl, stage, 1, s);
   return hipGetLastError();
 }
