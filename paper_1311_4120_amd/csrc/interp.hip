@@ -30,6 +30,7 @@ struct C2 {
 template <typename T>
 struct InterpArgs {
   int nf0, nf1, nf2;
+  FastDiv dnf0, dnf1, dnf2;
   int w0, w1, w2;
   int T0, T1, T2, S0, S1, S2;
   int nt1, nt2, nsub;
@@ -104,25 +105,32 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   const int ox = b0 * a.T0 + s0 * a.S0, oy = b1 * a.T1 + s1 * a.S1, oz = b2 * a.T2 + s2 * a.S2;
 
   // stage the neighbourhood (periodic on the fine grid; the padding columns of
-  // the last axis are loaded too and never read)
-  // thread t copies element i2 = t mod E2 of rows t / E2, t / E2 + rpp, ...
-  // (rpp rows per pass); the row's (i0, i1) advances by increments, so no
-  // element costs a division
+  // the last axis are loaded too and never read).  Thread t copies element
+  // i2 = t mod E2 of rows t / E2, t / E2 + rpp, ... (rpp rows per pass); the
+  // row's (i0, i1) advances by increments, and the loads go out in batches of
+  // kStageBatch before their LDS writes so that they are in flight together.
   {
+    constexpr int kStageBatch = 8;
     const int rpp = kInterpThreads / a.E2;
     const int r0 = threadIdx.x / a.E2;
-    if (r0 < rpp) {
-      const int i2 = threadIdx.x - r0 * a.E2;
-      const int g2 = (oz + i2) % a.nf2;
-      const int d0 = rpp / a.E1, d1 = rpp - d0 * a.E1;
-      int i0 = r0 / a.E1, i1 = r0 - (r0 / a.E1) * a.E1;
-      const int nrow = a.E0 * a.E1;
-      for (int r = r0; r < nrow; r += rpp) {
-        // the region may be wider than the grid on small grids: wrap as often as needed
-        int g0 = ox + i0, g1 = oy + i1;
-        while (g0 >= a.nf0) g0 -= a.nf0;
-        while (g1 >= a.nf1) g1 -= a.nf1;
-        tile[r * a.E2 + i2] = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
+    const bool act = r0 < rpp;
+    const int i2 = act ? threadIdx.x - r0 * a.E2 : 0;
+    const int g2 = (int)a.dnf2.mod((uint32_t)(oz + i2));
+    const int d0 = rpp / a.E1, d1 = rpp - d0 * a.E1;
+    int i0 = r0 / a.E1, i1 = r0 - (r0 / a.E1) * a.E1;
+    const int nrow = a.E0 * a.E1;
+    for (int rb = r0; act && rb < nrow; rb += kStageBatch * rpp) {
+      C2<T> v[kStageBatch];
+      int dst[kStageBatch];
+#pragma unroll
+      for (int k = 0; k < kStageBatch; ++k) {
+        const int r = rb + k * rpp;
+        const bool ok = r < nrow;
+        // the region may be wider than the grid on small grids: reduce modulo nf
+        const int g0 = ok ? (int)a.dnf0.mod((uint32_t)(ox + i0)) : 0;
+        const int g1 = ok ? (int)a.dnf1.mod((uint32_t)(oy + i1)) : 0;
+        v[k] = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
+        dst[k] = ok ? r * a.E2 + i2 : -1;
         i0 += d0;
         i1 += d1;
         if (i1 >= a.E1) {
@@ -130,6 +138,9 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
           ++i0;
         }
       }
+#pragma unroll
+      for (int k = 0; k < kStageBatch; ++k)
+        if (dst[k] >= 0) tile[dst[k]] = v[k];
     }
   }
   __syncthreads();
@@ -139,13 +150,40 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   const int plane = a.E1 * a.E2;
   const T* wrow = wbuf[wave];
   double eacc = 0.0;
-  for (int j = item.begin + wave; j < item.end; j += kInterpWaves) {
-    const int4 h = a.hdr[j];
+  // node data are fetched one node ahead: the record (lane 16 axis + tap), the
+  // footprint start and the coefficient of node j + kInterpWaves go out before
+  // node j's taps are read from LDS
+  const int ax = lane >> 4, tap = lane & 15;
+  const bool wlane = ax < 3 && tap < W;
+  const int woff = wlane ? ax * W + tap : 0;  // inside the node's record for every lane
+  auto fetch_w = [&](int jj) { return a.wts[(int64_t)jj * a.rstride + woff]; };
+  // a per-lane (vector) load of a value every lane needs, so that it is
+  // counted with the other global loads and not with the LDS traffic
+  auto vec_index = [](int jj) {
+    asm volatile("" : "+v"(jj));
+    return jj;
+  };
+  int4 h_next{};
+  T wv_next = T(0);
+  double c_next = 0.0;
+  int j = item.begin + wave;
+  if (j < item.end) {
+    const int jv = vec_index(j);
+    h_next = a.hdr[jv];
+    wv_next = fetch_w(jv);
+    if (a.mode != INTERP_TRANSFORM) c_next = a.coef[jv];
+  }
+  for (; j < item.end; j += kInterpWaves) {
+    const int4 h = h_next;
+    const T wv = wlane ? wv_next : T(0);
+    const double c = c_next;
+    if (j + kInterpWaves < item.end) {
+      const int jv = vec_index(j + kInterpWaves);
+      h_next = a.hdr[jv];
+      wv_next = fetch_w(jv);
+      if (a.mode != INTERP_TRANSFORM) c_next = a.coef[jv];
+    }
     const int lx0 = h.x - ox, ly0 = h.y - oy, lz0 = h.z - oz;  // in [0, S)
-
-    // kernel values from the node's record: lane 16 * axis + tap
-    const int ax = lane >> 4, tap = lane & 15;
-    const T wv = (ax < 3 && tap < W) ? a.wts[(int64_t)j * a.rstride + ax * W + (tap < W ? tap : 0)] : T(0);
     wbuf[wave][lane] = wv;
     __builtin_amdgcn_wave_barrier();
 
@@ -187,7 +225,6 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
       if (a.mode == INTERP_TRANSFORM) {
         a.out[a.perm[j]] = C2<T>{sr, si};
       } else {
-        double c = a.coef[j];
         double re = (double)sr, im = (double)si;
         eacc += c * (re * re + im * im);
         if (a.mode == INTERP_POTENTIAL) a.uhat[j] = C2<T>{(T)(c * re), (T)(c * im)};
@@ -243,6 +280,9 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.nf0 = pl.nf[0];
   a.nf1 = pl.nf[1];
   a.nf2 = pl.nf[2];
+  a.dnf0 = FastDiv((uint32_t)pl.nf[0]);
+  a.dnf1 = FastDiv((uint32_t)pl.nf[1]);
+  a.dnf2 = FastDiv((uint32_t)pl.nf[2]);
   a.w0 = pl.w[0];
   a.w1 = pl.w[1];
   a.w2 = pl.w[2];
