@@ -23,7 +23,7 @@ namespace jgb {
 namespace {
 
 template <typename T>
-struct C2 {
+struct alignas(2 * sizeof(T)) C2 {  // one 16-byte (fp64) or 8-byte (fp32) LDS access
   T x, y;
 };
 
@@ -87,7 +87,8 @@ __device__ __forceinline__ T wave_total(T v) {
   return lane_value(v, 63);
 }
 
-template <typename T, int W>
+// D3: three spreading axes; a 2D problem has one tap on axis 0.
+template <typename T, int W, bool D3>
 __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* tile = reinterpret_cast<C2<T>*>(smem_raw);
@@ -199,18 +200,18 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
       off[q] = (lx0 * a.E1 + ly0 + bb) * a.E2 + lz0 + cc;
       acc[q] = C2<T>{T(0), T(0)};
     }
-    // the outer axis: W taps in 3D, one in 2D
+    // the outer axis: W taps in 3D, one in 2D (a compile-time count, so that
+    // the reads of all taps are one straight-line block the compiler can
+    // keep in flight together)
 #pragma unroll
-    for (int ia = 0; ia < W; ++ia) {
-      if (ia < a.w0) {
-        const T wa = lane_value(wv, ia);
-        const C2<T>* row = tile + ia * plane;
+    for (int ia = 0; ia < (D3 ? W : 1); ++ia) {
+      const T wa = lane_value(wv, ia);
+      const C2<T>* row = tile + ia * plane;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const C2<T> v = row[off[q]];
-          acc[q].x += wa * v.x;
-          acc[q].y += wa * v.y;
-        }
+      for (int q = 0; q < NQ; ++q) {
+        const C2<T> v = row[off[q]];
+        acc[q].x += wa * v.x;
+        acc[q].y += wa * v.y;
       }
     }
     T sr = T(0), si = T(0);
@@ -245,14 +246,21 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
 }
 
 template <typename T, int W>
-hipError_t launch_w(const InterpArgs<T>& a, unsigned blocks, size_t smem, hipStream_t s) {
-  hipLaunchKernelGGL((k_interp<T, W>), dim3(blocks), dim3(kInterpThreads), smem, s, a);
+hipError_t launch_w(const InterpArgs<T>& a, bool d3, unsigned blocks, size_t smem, hipStream_t s) {
+  if (d3)
+    hipLaunchKernelGGL((k_interp<T, W, true>), dim3(blocks), dim3(kInterpThreads), smem, s, a);
+  else
+    hipLaunchKernelGGL((k_interp<T, W, false>), dim3(blocks), dim3(kInterpThreads), smem, s, a);
   return hipGetLastError();
 }
 
 template <typename T, int W>
 hipError_t allow_lds(size_t smem) {
-  return hipFuncSetAttribute((const void*)k_interp<T, W>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  hipError_t e = hipFuncSetAttribute((const void*)k_interp<T, W, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)smem);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_interp<T, W, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)smem);
 }
 
 }  // namespace
@@ -317,7 +325,7 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   switch (pl.width) {
 #define JGB_W(W) \
   case W:        \
-    e = launch_w<T, W>(a, blocks, smem, s); \
+    e = launch_w<T, W>(a, pl.dim == 3, blocks, smem, s); \
     break;
     JGB_W(2) JGB_W(3) JGB_W(4) JGB_W(5) JGB_W(6) JGB_W(7) JGB_W(8) JGB_W(9) JGB_W(10) JGB_W(11) JGB_W(12)
     JGB_W(13) JGB_W(14) JGB_W(15) JGB_W(16)

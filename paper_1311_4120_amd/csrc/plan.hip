@@ -19,7 +19,7 @@ namespace {
 // candidate work-item sizes; the first of each is the smallest and sizes the buffers
 constexpr int kInterpChunks[] = {256, 512, 1024, 2048};
 constexpr int kSpreadChunks[] = {1024, 2048, 4096, 8192};
-constexpr size_t kInterpLdsMax = 120 * 1024;
+constexpr size_t kInterpLdsMax = 144 * 1024;  // of 160 KB per CU, beside the kernel's static LDS
 
 bool is_235(int64_t n) {
   if (n < 1) return false;
@@ -437,30 +437,42 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     pl.nt[i] = (pl.nf[i] + pl.T[i] - 1) / pl.T[i];
     pl.ntiles *= pl.nt[i];
   }
-  // sub-bins: halve the largest extent until the staged neighbourhood fits
-  for (int i = 0; i < 3; ++i) pl.S[i] = pl.T[i];
-  // the last extent is padded so that (E2 - w2) is a multiple of the number of
-  // complex elements per 128-byte LDS row: consecutive lanes of the
-  // interpolation then hit distinct banks
-  auto set_extents = [&]() {
-    for (int i = 0; i < 3; ++i) pl.E[i] = pl.S[i] + pl.w[i] - 1;
-    const int per_row = pl.fp64 ? 8 : 16;
-    pl.E[2] = pl.w[2] + per_row * ((pl.S[2] - 1 + per_row - 1) / per_row);
-    if (pl.E[2] < pl.S[2] + pl.w[2] - 1) pl.E[2] = pl.S[2] + pl.w[2] - 1;
-  };
-  auto region_bytes = [&]() {
-    set_extents();
-    return (size_t)pl.E[0] * pl.E[1] * pl.E[2] * 2 * pl.real_bytes;
-  };
-  while (region_bytes() > kInterpLdsMax) {
-    int a = 2;
-    if (pl.S[0] > pl.S[a]) a = 0;
-    if (pl.S[1] > pl.S[a]) a = 1;
-    if (pl.S[a] == 1) break;
-    pl.S[a] /= 2;
+  // sub-bins: the power-of-two sub-tile whose staged neighbourhood fits the LDS
+  // budget with the fewest staged cells per sub-bin cell.  The last extent is
+  // padded so that (E2 - w2) is a multiple of 16: the interpolation's tap reads
+  // (lane -> tap pair (b, c), address b E2 + c) then fall in distinct banks
+  // within every group of 16 lanes, which the LDS (64 banks of 4 bytes) serves
+  // together for 16-byte reads.
+  {
+    const int per_row = 16;
+    auto extents = [&](const int S[3], int E[3]) {
+      for (int i = 0; i < 3; ++i) E[i] = S[i] + pl.w[i] - 1;
+      E[2] = pl.w[2] + per_row * ((S[2] - 1 + per_row - 1) / per_row);
+      if (E[2] < S[2] + pl.w[2] - 1) E[2] = S[2] + pl.w[2] - 1;
+      return (size_t)E[0] * E[1] * E[2] * 2 * pl.real_bytes;
+    };
+    double best = 0.0;
+    bool found = false;
+    for (int s0 = pl.T[0]; s0 >= 1; s0 /= 2)
+      for (int s1 = pl.T[1]; s1 >= 1; s1 /= 2)
+        for (int s2 = pl.T[2]; s2 >= 1; s2 /= 2) {
+          const int S[3] = {s0, s1, s2};
+          int E[3];
+          const size_t bytes = extents(S, E);
+          if (bytes > kInterpLdsMax) continue;
+          const double amp = (double)E[0] * E[1] * E[2] / ((double)s0 * s1 * s2);
+          if (!found || amp < best * (1.0 - 1e-12)) {
+            found = true;
+            best = amp;
+            for (int i = 0; i < 3; ++i) {
+              pl.S[i] = S[i];
+              pl.E[i] = E[i];
+            }
+            pl.interp_lds = bytes;
+          }
+        }
+    if (!found) return fail(JGB_ERR_UNSUPPORTED, "interpolation neighbourhood exceeds LDS");
   }
-  pl.interp_lds = region_bytes();
-  if (pl.interp_lds > kInterpLdsMax) return fail(JGB_ERR_UNSUPPORTED, "interpolation neighbourhood exceeds LDS");
   pl.nsub = (pl.T[0] / pl.S[0]) * (pl.T[1] / pl.S[1]) * (pl.T[2] / pl.S[2]);
 
   // 1D rules on the device
