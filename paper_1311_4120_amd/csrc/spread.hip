@@ -21,7 +21,7 @@ namespace jgb {
 namespace {
 
 template <typename T>
-struct C2 {
+struct alignas(2 * sizeof(T)) C2 {  // one 16-byte (fp64) or 8-byte (fp32) access
   T x, y;
 };
 
