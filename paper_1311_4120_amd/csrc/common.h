@@ -26,9 +26,10 @@ constexpr int kMaxLine = 1024;
 constexpr int kTileZ = 16;
 // Per-node kernel values, tabulated at plan time: w values per internal axis,
 // axis a at [a w, a w + w) of the node's record (a unit axis has the single
-// value 1 at tap 0 and zeros after it); records are rec_stride values apart,
-// 3 w rounded up to a multiple of 4.
-inline int record_stride(int width) { return (3 * width + 3) / 4 * 4; }
+// value 1 at tap 0 and zeros after it), then a zero at 3 w that a load may
+// point at instead of masking its result; records are rec_stride values apart,
+// 3 w + 1 rounded up to a multiple of 4.
+inline int record_stride(int width) { return (3 * width + 1 + 3) / 4 * 4; }
 
 // ----------------------------------------------------------------- errors
 

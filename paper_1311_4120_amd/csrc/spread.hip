@@ -75,18 +75,24 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
 
-// Raw operands of one group of four list entries, loaded one group ahead of
-// their use so that the loads overlap the previous group's products.  NX and
-// NY are the distinct axis-0 and axis-1 kernel values a lane needs over its
-// four row blocks (the tile shape makes one of them 1).
+// Load a V at a 32-bit byte offset from a base shared by the wavefront (the
+// node tables are far below 4 GB): one address add per load.
+template <typename V>
+__device__ __forceinline__ V load_at(const void* base, uint32_t byte_off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// Operands of one group of four list entries, loaded one group ahead of their
+// use so that the loads overlap the previous group's products.  NX and NY are
+// the distinct axis-0 and axis-1 kernel values a lane needs over its four row
+// blocks (the tile shape makes one of them 1).  A tap outside the footprint,
+// or a lane past the end of the list, reads the zero that ends its node's
+// record, so nothing is masked after the loads.
 template <typename T, int NX, int NY>
 struct GroupLoads {
-  T z0, z1;        // axis-2 values of the one or two windows onto the tile
-  bool vz0, vz1;
-  T u_re, u_im;    // weighted node value
+  T z;             // axis-2 value at the lane's tile z
+  C2<T> u;         // weighted node value
   T px[NX], py[NY];
-  bool valid;      // lane's list entry exists
-  int dx[NX], dy[NY];
 };
 
 // One block per work item (a tile and a range of its node list).  The four
@@ -112,20 +118,21 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int o0 = t0 * T0, o1 = t1 * T1, o2 = t2 * kTileZ;
   const int li = lane & 15, lk = lane >> 4;
   const int W = a.width;
+  const uint32_t rbytes = (uint32_t)(a.rstride * sizeof(T));   // bytes per record
+  const uint32_t zslot = (uint32_t)(3 * W * sizeof(T));         // byte offset of the zero
 
   // the lane's x values (per row block when NX = 4) and y values (per row
-  // block when NY = 4), and whether they lie on the grid
+  // block when NY = 4); points off the grid never take a value
   int xs[NX], ys[NY];
-  bool xon[NX], yon[NY];
 #pragma unroll
   for (int b = 0; b < NX; ++b) {
     xs[b] = (16 * b + li) / T1;
-    xon[b] = o0 + xs[b] < a.nf0;
+    if (o0 + xs[b] >= a.nf0) xs[b] = -(1 << 20);
   }
 #pragma unroll
   for (int b = 0; b < NY; ++b) {
     ys[b] = (16 * b + li) % T1;
-    yon[b] = o1 + ys[b] < a.nf1;
+    if (o1 + ys[b] >= a.nf1) ys[b] = -(1 << 20);
   }
 
   acc_t acc[4][2];
@@ -141,43 +148,35 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int ke = (kb + q < item.vend) ? kb + q : item.vend;
 
   // Issue the loads of the group whose entries start at g.  Lanes past the end
-  // read entry ke - 1 (>= kb, a valid index whenever the wave has work), so
-  // every address is a real node's; their results are masked by `valid`.
+  // read entry ke - 1 (>= kb, a valid index whenever the wave has work) and
+  // point every value load at the record's zero.
   auto fetch = [&](int g) {
     GroupLoads<T, NX, NY> r;
     const int idx = g + lk;
-    r.valid = idx < ke;
-    const int2 ent = a.list[r.valid ? idx : ke - 1];
-    const int j = ent.x;
+    const bool valid = idx < ke;
+    const int2 ent = load_at<int2>(a.list, (uint32_t)(valid ? idx : ke - 1) * 8u);
+    const uint32_t j = (uint32_t)ent.x;
     const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
-    const T* rec = a.wts + (int64_t)j * a.rstride;
-    const C2<T> u = a.uhat[j];
-    r.u_re = u.x;
-    r.u_im = u.y;
-    // axis 2: tap li - o of the footprint lands on tile z = li, for the start
-    // o = ez inside the tile or o = ez - nf2 before it; on grids narrower than
-    // kTileZ + w both windows can hold
-    const bool zin = ez < kTileZ;
-    const bool zwrap = a.nf2 - ez < a.w2;
-    const int d0 = li - (zin ? ez : ez - a.nf2);
-    const int d1 = li - (ez - a.nf2);
-    r.vz0 = d0 >= 0 && d0 < a.w2;
-    r.vz1 = zin && zwrap && d1 < a.w2;
-    r.z0 = rec[2 * W + (r.vz0 ? d0 : 0)];
-    r.z1 = rec[2 * W + (r.vz1 ? d1 : 0)];
+    const uint32_t rec = j * rbytes;
+    r.u = load_at<C2<T>>(a.uhat, j * (uint32_t)sizeof(C2<T>));
+    // tap d = (p - start) mod nf of a point p covers it iff d < w (w <= nf)
+    int dz = li - ez;
+    if (dz < 0) dz += a.nf2;
+    const bool inz = valid && dz < a.w2;
+    r.z = load_at<T>(a.wts, rec + (inz ? (uint32_t)((2 * W + dz) * sizeof(T)) : zslot));
 #pragma unroll
     for (int b = 0; b < NX; ++b) {
       int dx = xs[b] - ex;
       if (dx < 0) dx += a.nf0;
-      r.dx[b] = (xon[b] && dx < a.w0) ? dx : -1;
-      r.px[b] = rec[r.dx[b] >= 0 ? dx : 0];
+      const bool in = valid && (uint32_t)dx < (uint32_t)a.w0;
+      r.px[b] = load_at<T>(a.wts, rec + (in ? (uint32_t)(dx * sizeof(T)) : zslot));
     }
 #pragma unroll
     for (int b = 0; b < NY; ++b) {
       int dy = ys[b] - ey;
       if (dy < 0) dy += a.nf1;
-      r.dy[b] = (yon[b] && dy < a.w1) ? dy : -1;
-      r.py[b] = rec[W + (r.dy[b] >= 0 ? dy : 0)];
+      const bool in = valid && (uint32_t)dy < (uint32_t)a.w1;
+      r.py[b] = load_at<T>(a.wts, rec + (in ? (uint32_t)((W + dy) * sizeof(T)) : zslot));
     }
     return r;
   };
@@ -186,16 +185,13 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     GroupLoads<T, NX, NY> cur = fetch(kb);
     for (int g = kb; g < ke; g += 4) {
       // next group's loads go out before this group's products (past the end
-      // they re-read the last entry and are discarded)
+      // they re-read the last group and are discarded)
       const GroupLoads<T, NX, NY> nxt = fetch(g + 4 < ke ? g + 4 : g);
-      const T wz = (cur.vz0 ? cur.z0 : T(0)) + (cur.vz1 ? cur.z1 : T(0));
-      const T qr = cur.valid ? wz * cur.u_re : T(0);
-      const T qi = cur.valid ? wz * cur.u_im : T(0);
+      const T qr = cur.z * cur.u.x;
+      const T qi = cur.z * cur.u.y;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int bx = NX == 4 ? b : 0, by = NY == 4 ? b : 0;
-        const bool in = cur.dx[bx] >= 0 && cur.dy[by] >= 0;
-        const T pv = in ? cur.px[bx] * cur.py[by] : T(0);
+        const T pv = cur.px[NX == 4 ? b : 0] * cur.py[NY == 4 ? b : 0];
         acc[b][0] = Mfma<T>::mma(pv, qr, acc[b][0]);
         acc[b][1] = Mfma<T>::mma(pv, qi, acc[b][1]);
       }
