@@ -416,15 +416,17 @@ void factor(int L, int* rad, int& nrad) {
   }
 }
 
-// Block shape: 256 threads (fp64) or 512 (fp32), at most 16 complex elements
-// per thread, so 4096 or 8192 elements (64 KB) staged per block; up to 16 or
-// 32 lines, which makes every strided-pass row of a block 256 contiguous bytes.
+// Block shape: 512 threads with at most 8 (fp64) or 16 (fp32) complex elements
+// each, so 4096 or 8192 elements (64 KB) staged per block; up to 16 or 32
+// lines, which makes every strided-pass row of a block 256 contiguous bytes.
 template <typename T>
-constexpr int pass_threads() { return sizeof(T) == 8 ? 256 : 512; }
+constexpr int pass_threads() { return 512; }
+template <typename T>
+constexpr int pass_elems() { return sizeof(T) == 8 ? 8 : 16; }
 
 template <typename T>
 int lines_per_block(int L) {
-  const int cap = 16 * pass_threads<T>();  // complex elements staged per block
+  const int cap = pass_elems<T>() * pass_threads<T>();  // complex elements staged per block
   const int maxlb = sizeof(T) == 8 ? 16 : 32;
   int lb = cap / L;
   if (lb > maxlb) lb = maxlb;
@@ -454,7 +456,7 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
   if (KIND != PASS_COMPLEX) smem += sizeof(double) * (a.LB + a.L);  // deconvolution factors
   constexpr int NT = pass_threads<T>();
-  constexpr int MAXV = 16;
+  constexpr int MAXV = pass_elems<T>();
   stage_mark(pl, stage, 0, s);
   hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
   stage_mark(pl, stage, 1, s);

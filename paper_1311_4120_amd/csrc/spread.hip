@@ -181,21 +181,36 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     return r;
   };
 
-  if (kb < ke) {
-    GroupLoads<T, NX, NY> cur = fetch(kb);
-    for (int g = kb; g < ke; g += 4) {
-      // next group's loads go out before this group's products (past the end
-      // they re-read the last group and are discarded)
-      const GroupLoads<T, NX, NY> nxt = fetch(g + 4 < ke ? g + 4 : g);
-      const T qr = cur.z * cur.u.x;
-      const T qi = cur.z * cur.u.y;
+  // Loads run one group ahead of the products in fp64 and two in fp32 (where
+  // the registers allow it without costing occupancy); past the end the
+  // fetches re-read the last group and are discarded.
+  auto mma_group = [&](const GroupLoads<T, NX, NY>& c) {
+    const T qr = c.z * c.u.x;
+    const T qi = c.z * c.u.y;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const T pv = cur.px[NX == 4 ? b : 0] * cur.py[NY == 4 ? b : 0];
-        acc[b][0] = Mfma<T>::mma(pv, qr, acc[b][0]);
-        acc[b][1] = Mfma<T>::mma(pv, qi, acc[b][1]);
+    for (int b = 0; b < 4; ++b) {
+      const T pv = c.px[NX == 4 ? b : 0] * c.py[NY == 4 ? b : 0];
+      acc[b][0] = Mfma<T>::mma(pv, qr, acc[b][0]);
+      acc[b][1] = Mfma<T>::mma(pv, qi, acc[b][1]);
+    }
+  };
+  if (kb < ke) {
+    auto clampg = [&](int g) { return g < ke ? g : kb + ((ke - 1 - kb) & ~3); };
+    GroupLoads<T, NX, NY> cur = fetch(kb);
+    if constexpr (sizeof(T) == 4) {
+      GroupLoads<T, NX, NY> nx1 = fetch(clampg(kb + 4));
+      for (int g = kb; g < ke; g += 4) {
+        const GroupLoads<T, NX, NY> nx2 = fetch(clampg(g + 8));
+        mma_group(cur);
+        cur = nx1;
+        nx1 = nx2;
       }
-      cur = nxt;
+    } else {
+      for (int g = kb; g < ke; g += 4) {
+        const GroupLoads<T, NX, NY> nx1 = fetch(clampg(g + 4));
+        mma_group(cur);
+        cur = nx1;
+      }
     }
   }
 
