@@ -270,24 +270,27 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_spread_reduce(const int* multi, int nmulti, int nf0, int nf1, int nf2,
                                                        int T0, int T1, int nt1, int nt2, const C2<T>* partials,
                                                        C2<T>* G) {
-  const int m = blockIdx.x;
+  // four blocks per split tile, one tile point per thread; the slots are
+  // summed in slot order, their loads issued several at a time
+  const int m = blockIdx.x >> 2;
   if (m >= nmulti) return;
+  const int idx = (blockIdx.x & 3) * 256 + threadIdx.x;  // < 64 kTileZ
   const int tile = multi[3 * m], first = multi[3 * m + 1], count = multi[3 * m + 2];
   const int t2 = tile % nt2;
   const int t1 = (tile / nt2) % nt1;
   const int t0 = tile / (nt2 * nt1);
-  for (int idx = threadIdx.x; idx < 64 * kTileZ; idx += blockDim.x) {
-    const int lane = idx / kTileZ, z = idx % kTileZ;
-    const int g0 = t0 * T0 + lane / T1, g1 = t1 * T1 + lane % T1, g2 = t2 * kTileZ + z;
-    if (g0 >= nf0 || g1 >= nf1 || g2 >= nf2) continue;
-    T sr = T(0), si = T(0);
-    for (int c = 0; c < count; ++c) {
-      C2<T> p = partials[((int64_t)(first + c) * 64 + lane) * kTileZ + z];
-      sr += p.x;
-      si += p.y;
-    }
-    G[((int64_t)g0 * nf1 + g1) * nf2 + g2] = C2<T>{sr, si};
+  const int lane = idx / kTileZ, z = idx % kTileZ;
+  const int g0 = t0 * T0 + lane / T1, g1 = t1 * T1 + lane % T1, g2 = t2 * kTileZ + z;
+  if (g0 >= nf0 || g1 >= nf1 || g2 >= nf2) return;
+  const C2<T>* p = partials + (int64_t)first * 64 * kTileZ + idx;
+  T sr = T(0), si = T(0);
+#pragma unroll 8
+  for (int c = 0; c < count; ++c) {
+    const C2<T> v = p[(int64_t)c * 64 * kTileZ];
+    sr += v.x;
+    si += v.y;
   }
+  G[((int64_t)g0 * nf1 + g1) * nf2 + g2] = C2<T>{sr, si};
 }
 
 __global__ void k_energy_finalize(const double* parts, int n, double scale, double* out) {
@@ -338,7 +341,8 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
   stage_mark(pl, ST_SPREAD_REDUCE, 0, s);
-  hipLaunchKernelGGL(k_spread_reduce<T>, dim3(pl.nmulti), dim3(256), 0, s, pl.d_multi, pl.nmulti, pl.nf[0], pl.nf[1],
+  static_assert(64 * kTileZ == 4 * 256, "four 256-thread blocks per tile");
+  hipLaunchKernelGGL(k_spread_reduce<T>, dim3(4 * pl.nmulti), dim3(256), 0, s, pl.d_multi, pl.nmulti, pl.nf[0], pl.nf[1],
                      pl.nf[2], pl.T[0], pl.T[1], pl.nt[1], pl.nt[2], (const C2<T>*)pl.d_partials, (C2<T>*)pl.d_G);
   stage_mark(pl, ST_SPREAD_REDUCE, 1, s);
   return hipGetLastError();
