@@ -62,6 +62,57 @@ def stage_work(info, prec, energy=True):
     return by, fl
 
 
+# Kernel sources whose measured HBM traffic a stage's roofline may quote: the
+# summary in profiles/ is used only while these files are unchanged.
+STAGE_SOURCES = {
+    "interp": ["paper_1311_4120_amd/csrc/interp.hip"],
+    "spread": ["paper_1311_4120_amd/csrc/spread.hip"],
+}
+TRAFFIC_SOURCES_COMMON = ["paper_1311_4120_amd/csrc/plan.hip", "paper_1311_4120_amd/csrc/common.h",
+                          "paper_1311_4120_amd/csrc/nodes.hip"]
+
+
+def sources_sha1(stage):
+    import hashlib
+    h = hashlib.sha1()
+    for rel in STAGE_SOURCES.get(stage, []) + TRAFFIC_SOURCES_COMMON:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage, prec):
+    """HBM bytes per launch of the stage's kernel from the committed PMC
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or
+    None when there is none or the kernel sources changed since."""
+    if stage not in STAGE_SOURCES:
+        return None
+    path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md" % (stage, prec))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            for key in ("traffic_bytes_per_launch:", "sources_sha1:"):
+                if line.strip().startswith(key):
+                    vals[key] = line.split(":", 1)[1].strip()
+    if vals.get("sources_sha1:") != sources_sha1(stage) or "traffic_bytes_per_launch:" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch:"])
+
+
+def copy_calibration(mib=256, reps=5):
+    """A plain device copy of a known size, for scaling the PMC byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "reps": reps}))
+
+
 def roofline(stage, ms, by, fl, prec):
     """The stage's roofline: whichever bound (HBM bytes, or flops at the
     compute peak of its unit) takes longer, and the achieved fraction of it."""
@@ -188,7 +239,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -208,6 +264,7 @@ def main():
     st = r["stages_ms"]
     dom = max((k for k in st if st[k] > 0), key=lambda k: st[k])
     roof = roofline(dom, st[dom], by, fl, head)
+    roof["traffic"] = measured_traffic(dom, head)
     stages = {}
     for k, v in st.items():
         if v <= 0:
