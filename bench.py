@@ -133,17 +133,18 @@ def roofline(stage, ms, by, fl, prec):
     return out
 
 
-def run_gpu(prec, steps, warmup):
+def run_gpu(prec, steps, warmup, nodes="pattern"):
     import torch
 
     import paper_1311_4120_amd as jgb
     import workloads as wl
 
-    p, rho = wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED)
+    p, rho = wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED, nodes=nodes)
     dt = torch.float64 if prec == "fp64" else torch.float32
     t0 = time.time()
     plan = jgb.Plan(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), eps=p.eps, precision=prec,
-                    lam=p.lam, axis=p.axis, theta_rule="theta", autotune=True)
+                    lam=p.lam, axis=p.axis, theta_rule="theta" if p.theta_rule == wl.THETA_GL else "costheta",
+                    autotune=True)
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     rt = torch.tensor(rho, dtype=dt, device="cuda")
@@ -202,6 +203,79 @@ def run_batched(steps, warmup):
             "ms_per_launch": 1e3 * wall / steps, "evals_per_s": len(members) * steps / wall,
             "grid_points_per_s": npts * steps / wall, "launches": steps, "plan_and_capture_s": plan_s,
             "precision": "mixed", "eps": 1e-5, "graph": "one hipGraph launch per step over 4 branches"}
+
+
+def run_resolved(steps, warmup):
+    """The accuracy-matched node sets of the 128^3 dipole workload: (256,128,256)
+    cos(theta) nodes in float64, (192,96,192) in mixed precision."""
+    out = {"workload": "dipole3d_128, accuracy-matched nodes"}
+    for prec, nodes in (("fp64", [256, 128, 256]), ("mixed", [192, 96, 192])):
+        r = run_gpu(prec, steps, warmup, nodes="resolved")
+        out[prec] = {"nodes": nodes, "n_nodes": r["info"]["n_nodes"], "eps": r["eps"], "ms_per_step": r["ms_per_step"],
+                     "evals_per_s": 1e3 / r["ms_per_step"], "ns_per_point": r["ms_per_step"] * 1e6 / 128 ** 3,
+                     "stages_ms": {k: v for k, v in r["stages_ms"].items() if v > 0}}
+    return out
+
+
+def run_grad256(steps, warmup):
+    """Differentiable dipolar energy on 256^3 (psi = 6 wave packets, complex64,
+    mixed precision, nodes (256,128,256)): one step = E(|psi|^2) forward and
+    dE/dpsi* backward through the autograd function."""
+    import torch
+
+    import paper_1311_4120_amd as jgb
+    import workloads as wl
+
+    p, packets = wl.dipole_grad_256()
+    plan = jgb.Plan(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), eps=p.eps, precision="mixed",
+                    lam=p.lam, axis=p.axis, theta_rule="costheta", autotune=True)
+    psi = torch.tensor(packets.evaluate(p.n, p.box), dtype=torch.complex64, device="cuda", requires_grad=True)
+
+    def step():
+        psi.grad = None
+        E = jgb.DipolarEnergy.apply(psi, plan)
+        E.backward()
+        return E
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        E = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.close()
+    return {"workload": "dipole_grad_256", "grid": [256, 256, 256], "nodes": [256, 128, 256], "precision": "mixed",
+            "eps": p.eps, "ms_per_step": 1e3 * wall / steps, "steps_per_s": steps / wall,
+            "step": "E(|psi|^2) forward + dE/dpsi* backward", "energy": float(E.item())}
+
+
+def fft_comparison(res):
+    """The six pruned passes of one evaluation against rocFFT (torch.fft on ROCm)
+    doing the unpruned forward and inverse 3D transforms of the same 256^3
+    oversampled grid."""
+    import torch
+
+    out = {}
+    passes = ["fwd_fft_z", "fwd_fft_y", "fwd_fft_x", "inv_fft_x", "inv_fft_y", "inv_fft_z"]
+    for prec, dt in (("fp64", torch.complex128), ("mixed", torch.complex64)):
+        if prec not in res:
+            continue
+        x = torch.randn((256, 256, 256), dtype=dt, device="cuda")
+        for _ in range(3):
+            y = torch.fft.ifftn(torch.fft.fftn(x))
+        torch.cuda.synchronize()
+        n = 20
+        t0 = time.perf_counter()
+        for _ in range(n):
+            y = torch.fft.ifftn(torch.fft.fftn(x))
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / n
+        del x, y
+        ours = sum(res[prec]["stages_ms"].get(k, 0.0) for k in passes)
+        out[prec] = {"rocfft_fwd_plus_inv_ms": ms, "pruned_passes_ms": ours, "speedup": ms / ours if ours else None}
+    return out
 
 
 def cpu_baseline(sample_nodes=32768):
@@ -310,6 +384,12 @@ def main():
     if not args.no_batched and args.only is None:
         print("[bench] batched_coulomb: 64 densities, one graph launch per step", file=sys.stderr, flush=True)
         out["batched"] = run_batched(max(3, args.steps // 10), 2)
+        print("[bench] dipole3d_128 with accuracy-matched node sets", file=sys.stderr, flush=True)
+        out["resolved"] = run_resolved(max(3, args.steps // 5), 2)
+        print("[bench] dipole_grad_256: forward + backward", file=sys.stderr, flush=True)
+        out["grad_256"] = run_grad256(max(3, args.steps // 10), 2)
+        print("[bench] FFT passes against rocFFT", file=sys.stderr, flush=True)
+        out["fft_vs_rocfft"] = fft_comparison(res)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle on a bounded sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

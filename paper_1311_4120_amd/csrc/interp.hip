@@ -97,6 +97,10 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Plan::InterpItem item = a.items[blockIdx.x];
+  if (item.sub < 0) {  // idle slot of the dispatch order
+    if (a.mode != INTERP_TRANSFORM && a.eparts && threadIdx.x == 0) a.eparts[blockIdx.x] = 0.0;
+    return;
+  }
 
   // origin of the sub-bin on the fine grid
   const int bin = item.sub / a.nsub, sub = item.sub % a.nsub;

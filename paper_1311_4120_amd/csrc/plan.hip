@@ -118,14 +118,44 @@ Status upload(Plan& pl, void* dst, const void* src, size_t bytes) {
   } while (0)
 
 
-// Dispatch order of work items: longest first (estimated cost), so that the
-// long items -- tiles and sub-bins near k = 0, whose costs run to a thousand
-// times the median -- start early and do not form the tail.  (Giving each XCD
-// a contiguous run of neighbouring items, for L2 reuse, measured slower: the
-// balance matters more here.)
-template <typename Item, typename Weight>
-void longest_first(std::vector<Item>& items, Weight weight) {
-  std::stable_sort(items.begin(), items.end(), [&](const Item& x, const Item& y) { return weight(x) > weight(y); });
+// Dispatch order of work items.  Items are grouped into cost classes a factor
+// 1.5 apart and the classes go largest first, so that the long items (tiles
+// and sub-bins near k = 0, up to a thousand times the median) start early and
+// do not form the tail.  Within a class the items keep their spatial order
+// and are cut into eight contiguous runs, one per XCD (the hardware hands
+// block p to XCD p mod 8, each XCD with its own L2), so that neighbouring
+// items -- which read the same node records and grid halos -- share an L2.
+// Each class is padded to a multiple of eight with idle items.
+#ifndef JGB_ORDER
+#define JGB_ORDER 1
+#endif
+template <typename Item, typename Cost>
+std::vector<Item> dispatch_order(const std::vector<Item>& items, Cost cost, const Item& idle) {
+  constexpr int kXcd = 8;
+  if (JGB_ORDER == 0) {
+    std::vector<Item> o = items;
+    std::stable_sort(o.begin(), o.end(), [&](const Item& x, const Item& y) { return cost(x) > cost(y); });
+    return o;
+  }
+  auto cls = [&](const Item& it) { return (int)std::floor(std::log(1.0 + cost(it)) / std::log(1.5)); };
+  std::vector<Item> o = items;
+  std::stable_sort(o.begin(), o.end(), [&](const Item& x, const Item& y) { return cls(x) > cls(y); });
+  std::vector<Item> out;
+  size_t b = 0;
+  while (b < o.size()) {
+    size_t e = b;
+    while (e < o.size() && cls(o[e]) == cls(o[b])) ++e;
+    const size_t m = e - b, q = (m + kXcd - 1) / kXcd;
+    const size_t p0 = out.size();
+    out.resize(p0 + kXcd * q, idle);
+    for (int x = 0; x < kXcd; ++x)
+      for (size_t i = 0; i < q; ++i) {
+        const size_t src = b + x * q + i;
+        if (src < e) out[p0 + kXcd * i + x] = o[src];
+      }
+    b = e;
+  }
+  return out;
 }
 
 // Interpolation work items: nonempty sub-bins, split into runs of at most
@@ -135,8 +165,8 @@ std::vector<Plan::InterpItem> interp_items(const Plan& pl, int chunk) {
   const std::vector<int>& ss = pl.h_sub_start;
   for (size_t k = 0; k + 1 < ss.size(); ++k)
     for (int b = ss[k]; b < ss[k + 1]; b += chunk) iit.push_back(Plan::InterpItem{(int)k, b, std::min(ss[k + 1], b + chunk)});
-  longest_first(iit, [](const Plan::InterpItem& it) { return it.end - it.begin; });
-  return iit;
+  return dispatch_order(iit, [](const Plan::InterpItem& it) { return (double)(it.end - it.begin); },
+                        Plan::InterpItem{-1, 0, 0});
 }
 
 // Gather work items: one block per tile, tiles with longer lists split into
@@ -163,7 +193,8 @@ void spread_items(const Plan& pl, int chunk, std::vector<WorkItem>& items, std::
       nslots += k;
     }
   }
-  longest_first(items, [](const WorkItem& it) { return it.vend - it.vbegin; });
+  items = dispatch_order(items, [](const WorkItem& it) { return (double)(it.vend - it.vbegin); },
+                         WorkItem{-1, 0, 0, -1});
 }
 
 Status apply_interp_chunk(Plan& pl, int chunk) {

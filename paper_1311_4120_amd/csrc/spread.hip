@@ -111,6 +111,7 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const WorkItem item = a.items[blockIdx.x];
+  if (item.tile < 0) return;  // idle slot of the dispatch order
   const int tile = item.tile;
   const int t2 = tile % a.nt2;
   const int t1 = (tile / a.nt2) % a.nt1;

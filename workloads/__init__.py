@@ -183,14 +183,17 @@ def dipole3d_128(precision=FP64, seed=3, nodes="pattern"):
     """128^3 grid over [-12,12)^3, rho = |psi|^2 for psi with axes (1,1.5,0.7).
 
     nodes="pattern": (128,64,128) with the theta Gauss-Legendre rule, identical work in
-    both precisions; nodes="resolved": (256,128,256) cos(theta) rule."""
+    both precisions; nodes="resolved": the accuracy-matched cos(theta)-rule sets,
+    (256,128,256) in float64 (eps 1e-10) and (192,96,192) in mixed precision (eps 1e-5)."""
     rng = np.random.default_rng(seed)
     axis = tuple(unit_vector(rng, 3))
     eps = 1e-10 if precision == FP64 else 1e-5
     if nodes == "pattern":
         nr, nt, nph, rule = 128, 64, 128, THETA_GL
-    else:
+    elif precision == FP64:
         nr, nt, nph, rule = 256, 128, 256, COSTHETA_GL
+    else:
+        nr, nt, nph, rule = 192, 96, 192, COSTHETA_GL
     p = Problem("dipole3d_128", 3, (128, 128, 128), (24.0, 24.0, 24.0), DIPOLE_3D, nr, nt, nph,
                 theta_rule=rule, axis=axis, eps=eps, precision=precision)
     # psi = exp(-sum x_i^2 / (2 a_i^2)) -> rho = |psi|^2 = exp(-sum x_i^2 / a_i^2)
