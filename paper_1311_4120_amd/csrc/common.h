@@ -147,7 +147,8 @@ struct Plan {
 
   // grids
   void* d_F = nullptr;  // nf0*nf1*nf2 complex T
-  void* d_G = nullptr;  // same size
+  void* d_G = nullptr;  // same size; written only by the spreading (tiles no node touches stay zero)
+  void* d_W = nullptr;  // FFT pass intermediate, n0*nf1*nf2 complex T
   double* d_eparts = nullptr;  // energy partials
   int neparts = 0;
 

@@ -481,8 +481,9 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
   const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
   const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
   const bool has_x = f0 > 1;
-  void* A1 = has_x ? pl.d_F : pl.d_G;
-  void* A2 = has_x ? pl.d_G : pl.d_F;
+  // G belongs to the spreading: the intermediates use F and W
+  void* A1 = has_x ? pl.d_F : pl.d_W;
+  void* A2 = has_x ? pl.d_W : pl.d_F;
   hipError_t e;
   {  // Z: rho -> A1 [n0][n1][f2]
     PassArgs<T> a = base_args<T>(pl, 2, T(-1));
@@ -547,8 +548,8 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
   const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
   const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
   const bool has_x = f0 > 1;
-  void* B2 = has_x ? pl.d_F : pl.d_G;
-  void* B1 = has_x ? pl.d_G : pl.d_F;
+  void* B2 = has_x ? pl.d_F : pl.d_G;  // (2D: the input grid itself)
+  void* B1 = pl.d_W;
   hipError_t e;
   if (has_x) {  // X: G -> B2 [n0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 0, T(1));

@@ -178,6 +178,7 @@ void spread_items(const Plan& pl, int chunk, std::vector<WorkItem>& items, std::
   const std::vector<int64_t>& tc = pl.h_tcount;
   for (int tile = 0; tile < pl.ntiles; ++tile) {
     const int64_t b = tc[tile], e = tc[tile + 1], L = e - b;
+    if (L == 0) continue;  // stays zero (cleared at plan time)
     if (L <= chunk) {
       items.push_back(WorkItem{tile, (int)b, (int)e, -1});
     } else {
@@ -654,6 +655,10 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   size_t ngrid = (size_t)pl.nf[0] * pl.nf[1] * pl.nf[2];
   TRY(dev_alloc(pl, &pl.d_F, ngrid * 2 * pl.real_bytes));
   TRY(dev_alloc(pl, &pl.d_G, ngrid * 2 * pl.real_bytes));
+  TRY(dev_alloc(pl, &pl.d_W, (size_t)pl.n[0] * pl.nf[1] * pl.nf[2] * 2 * pl.real_bytes));
+  // only the spreading writes G, and only tiles some node touches: the others
+  // are cleared here once
+  TRY_HIP(hipMemsetAsync(pl.d_G, 0, ngrid * 2 * pl.real_bytes, pl.stream), "clear spreading grid");
   pl.neparts = std::max(fft_inverse_z_blocks(pl), pl.iitems_cap);
   pl.neparts = std::max(pl.neparts, 1);
   TRY(dev_alloc(pl, &pl.d_eparts, sizeof(double) * pl.neparts));

@@ -143,9 +143,12 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     acc[b][1] = acc_t{T(0), T(0), T(0), T(0)};
   }
 
+  // short lists use fewer wavefronts (less to sum at the end); the count
+  // depends on the list length alone, so the summation order is fixed
   const int n = item.vend - item.vbegin;
-  const int q = (n + kWaves - 1) / kWaves;
-  const int kb = item.vbegin + wave * q;
+  const int nw = (n <= 32) ? 1 : (n <= 128 ? 2 : kWaves);
+  const int q = (n + nw - 1) / nw;
+  const int kb = wave < nw ? item.vbegin + wave * q : item.vend;
   const int ke = (kb + q < item.vend) ? kb + q : item.vend;
 
   // Issue the loads of the group whose entries start at g.  Lanes past the end
@@ -215,9 +218,10 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     }
   }
 
-  // fixed-order sum of the four partial tiles: (w0 + w2) + (w1 + w3)
+  // fixed-order sum of the active wavefronts' partial tiles: w0 alone,
+  // w0 + w1, or (w0 + w2) + (w1 + w3)
   const int base = lane;  // element (b, part, r) at base + 64 * (8 b + 4 part + r)
-  if (wave >= 2) {
+  if (wave >= 2 && nw == kWaves) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -227,7 +231,7 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
       }
   }
   __syncthreads();
-  if (wave < 2) {
+  if (wave < 2 && nw == kWaves) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -237,7 +241,7 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
       }
   }
   __syncthreads();
-  if (wave == 1) {
+  if (wave == 1 && nw >= 2) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -247,14 +251,23 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
       }
   }
   __syncthreads();
+  if (wave == 0 && nw >= 2) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc[b][0][r] += red[0][base + 64 * (b * 8 + r)];
+        acc[b][1][r] += red[0][base + 64 * (b * 8 + 4 + r)];
+      }
+  }
   if (wave != 0) return;
   const int z = lane & 15;
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const T vr = acc[b][0][r] + red[0][base + 64 * (b * 8 + r)];
-      const T vi = acc[b][1][r] + red[0][base + 64 * (b * 8 + 4 + r)];
+      const T vr = acc[b][0][r];
+      const T vi = acc[b][1][r];
       const int m = 16 * b + Mfma<T>::row(lane, r);
       const int x = m / T1, y = m % T1;
       if (item.slot < 0) {
@@ -330,7 +343,7 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.G = (C2<T>*)pl.d_G;
   a.partials = (C2<T>*)pl.d_partials;
   unsigned blocks = (unsigned)pl.nitems;
-  if (blocks == 0) return hipErrorInvalidConfiguration;
+  if (blocks == 0) return hipSuccess;  // no node touches the grid: G stays zero
   stage_mark(pl, ST_SPREAD, 0, s);
   if (pl.T[0] == 8 && pl.T[1] == 8)
     hipLaunchKernelGGL((k_spread_gather<T, 8>), dim3(blocks), dim3(256), 0, s, a);
