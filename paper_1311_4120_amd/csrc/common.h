@@ -113,6 +113,7 @@ struct Plan {
   int T[3] = {1, 1, 1};      // tile / bin extent per axis
   int S[3] = {1, 1, 1};      // sub-bin extent per axis (divides T)
   int E[3] = {1, 1, 1};      // staged interpolation region per axis (E[2] padded)
+  int pstride = 1;           // LDS elements per axis-0 plane of the staged region (>= E1 E2)
   int nsub = 1;
   struct InterpItem {
     int sub;    // key of the sub-bin: bin * nsub + sub-bin index

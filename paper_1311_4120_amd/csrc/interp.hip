@@ -34,7 +34,8 @@ struct InterpArgs {
   int w0, w1, w2;
   int T0, T1, T2, S0, S1, S2;
   int nt1, nt2, nsub;
-  int E0, E1, E2;   // staged region extents; E2 is padded (see the plan)
+  int E0, E1, E2;   // staged region extents; E2 = W + 16 (padded, see the plan)
+  int pstride;      // LDS elements per axis-0 plane of the region
   const Plan::InterpItem* items;
   const int4* hdr;
   const double* coef;
@@ -90,6 +91,7 @@ __device__ __forceinline__ T wave_total(T v) {
 // D3: three spreading axes; a 2D problem has one tap on axis 0.
 template <typename T, int W, bool D3>
 __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
+  constexpr int E2 = W + 16;  // staged row length (the plan guarantees a.E2 == E2)
   extern __shared__ unsigned char smem_raw[];
   C2<T>* tile = reinterpret_cast<C2<T>*>(smem_raw);
   __shared__ T wbuf[kInterpWaves][64];
@@ -116,16 +118,16 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   // kStageBatch before their LDS writes so that they are in flight together.
   {
     constexpr int kStageBatch = 8;
-    const int rpp = kInterpThreads / a.E2;
-    const int r0 = threadIdx.x / a.E2;
+    const int rpp = kInterpThreads / E2;
+    const int r0 = threadIdx.x / E2;
     const bool act = r0 < rpp;
-    const int i2 = act ? threadIdx.x - r0 * a.E2 : 0;
+    const int i2 = act ? threadIdx.x - r0 * E2 : 0;
     const int g2 = (int)a.dnf2.mod((uint32_t)(oz + i2));
     const int d0 = rpp / a.E1, d1 = rpp - d0 * a.E1;
     int i0 = r0 / a.E1, i1 = r0 - (r0 / a.E1) * a.E1;
     const int nrow = a.E0 * a.E1;
     for (int rb = r0; act && rb < nrow; rb += kStageBatch * rpp) {
-      C2<T> v[kStageBatch];
+      T vr[kStageBatch], vi[kStageBatch];
       int dst[kStageBatch];
 #pragma unroll
       for (int k = 0; k < kStageBatch; ++k) {
@@ -134,8 +136,10 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
         // the region may be wider than the grid on small grids: reduce modulo nf
         const int g0 = ok ? (int)a.dnf0.mod((uint32_t)(ox + i0)) : 0;
         const int g1 = ok ? (int)a.dnf1.mod((uint32_t)(oy + i1)) : 0;
-        v[k] = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
-        dst[k] = ok ? r * a.E2 + i2 : -1;
+        const C2<T> v = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
+        vr[k] = v.x;
+        vi[k] = v.y;
+        dst[k] = ok ? i0 * a.pstride + i1 * E2 + i2 : -1;
         i0 += d0;
         i1 += d1;
         if (i1 >= a.E1) {
@@ -145,14 +149,13 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
       }
 #pragma unroll
       for (int k = 0; k < kStageBatch; ++k)
-        if (dst[k] >= 0) tile[dst[k]] = v[k];
+        if (dst[k] >= 0) tile[dst[k]] = C2<T>{vr[k], vi[k]};
     }
   }
   __syncthreads();
 
-  constexpr int NP = W * W;             // (b, c) tap pairs of the two inner axes
+  constexpr int NP = W * W;             // tap pairs of the two axes the lanes own
   constexpr int NQ = (NP + 63) / 64;    // pairs per lane
-  const int plane = a.E1 * a.E2;
   const T* wrow = wbuf[wave];
   double eacc = 0.0;
   // node data are fetched one node ahead: the record (lane 16 axis + tap), the
@@ -192,6 +195,9 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     wbuf[wave][lane] = wv;
     __builtin_amdgcn_wave_barrier();
 
+    // 3D: lane owns tap pair (a, c) of axes 0 and 2 and walks the W taps of
+    // axis 1, E2 elements apart (a constant: immediate LDS offsets).  2D: lane
+    // owns (b, c) of axes 1 and 2; axis 0 has the single tap 0.
     C2<T> acc[NQ];
     int off[NQ];
     T wyz[NQ];
@@ -199,23 +205,24 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     for (int q = 0; q < NQ; ++q) {
       const int p = lane + 64 * q;
       const bool ok = p < NP;
-      const int bb = ok ? p / W : 0, cc = ok ? p % W : 0;
-      wyz[q] = ok ? wrow[16 + bb] * wrow[32 + cc] : T(0);
-      off[q] = (lx0 * a.E1 + ly0 + bb) * a.E2 + lz0 + cc;
+      const int pa = ok ? p / W : 0, pc = ok ? p % W : 0;
+      if constexpr (D3) {
+        wyz[q] = ok ? wrow[pa] * wrow[32 + pc] : T(0);
+        off[q] = (lx0 + pa) * a.pstride + ly0 * E2 + lz0 + pc;
+      } else {
+        wyz[q] = ok ? wrow[16 + pa] * wrow[32 + pc] : T(0);
+        off[q] = (ly0 + pa) * E2 + lz0 + pc;
+      }
       acc[q] = C2<T>{T(0), T(0)};
     }
-    // the outer axis: W taps in 3D, one in 2D (a compile-time count, so that
-    // the reads of all taps are one straight-line block the compiler can
-    // keep in flight together)
 #pragma unroll
-    for (int ia = 0; ia < (D3 ? W : 1); ++ia) {
-      const T wa = lane_value(wv, ia);
-      const C2<T>* row = tile + ia * plane;
+    for (int ib = 0; ib < (D3 ? W : 1); ++ib) {
+      const T wb = lane_value(wv, D3 ? 16 + ib : 0);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const C2<T> v = row[off[q]];
-        acc[q].x += wa * v.x;
-        acc[q].y += wa * v.y;
+        const C2<T> v = tile[off[q] + ib * E2];
+        acc[q].x += wb * v.x;
+        acc[q].y += wb * v.y;
       }
     }
     T sr = T(0), si = T(0);
@@ -310,6 +317,7 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.E0 = pl.E[0];
   a.E1 = pl.E[1];
   a.E2 = pl.E[2];
+  a.pstride = pl.pstride;
   a.items = pl.d_iitems;
   a.hdr = pl.nodes.hdr;
   a.coef = pl.nodes.coef;

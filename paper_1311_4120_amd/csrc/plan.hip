@@ -470,27 +470,31 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     pl.ntiles *= pl.nt[i];
   }
   // sub-bins: the power-of-two sub-tile whose staged neighbourhood fits the LDS
-  // budget with the fewest staged cells per sub-bin cell.  The last extent is
-  // padded so that (E2 - w2) is a multiple of 16: the interpolation's tap reads
-  // (lane -> tap pair (b, c), address b E2 + c) then fall in distinct banks
-  // within every group of 16 lanes, which the LDS (64 banks of 4 bytes) serves
-  // together for 16-byte reads.
+  // budget with the fewest staged cells per sub-bin cell.  LDS layout of the
+  // neighbourhood: rows of E2 = w2 + 16 elements along axis 2 (S2 >= 2 keeps
+  // E2 fixed at that value, which the kernel takes as a compile-time stride),
+  // planes of `pstride` >= E1 E2 elements along axis 0, with pstride = w (mod 16).
+  // The 3D kernel's lanes read tap pairs (a, c) at a pstride + c: consecutive
+  // lanes p hit p (mod 16), distinct banks for every 16 lanes, which the LDS
+  // (64 banks of 4 bytes) serves together for 16-byte reads; the 2D kernel's
+  // lanes read pairs (b, c) at b E2 + c = p (mod 16) likewise.
   {
     const int per_row = 16;
-    auto extents = [&](const int S[3], int E[3]) {
+    auto extents = [&](const int S[3], int E[3], int& pstride) {
       for (int i = 0; i < 3; ++i) E[i] = S[i] + pl.w[i] - 1;
       E[2] = pl.w[2] + per_row * ((S[2] - 1 + per_row - 1) / per_row);
-      if (E[2] < S[2] + pl.w[2] - 1) E[2] = S[2] + pl.w[2] - 1;
-      return (size_t)E[0] * E[1] * E[2] * 2 * pl.real_bytes;
+      pstride = E[1] * E[2];
+      pstride += ((pl.width - pstride) % 16 + 16) % 16;
+      return (size_t)E[0] * pstride * 2 * pl.real_bytes;
     };
     double best = 0.0;
     bool found = false;
     for (int s0 = pl.T[0]; s0 >= 1; s0 /= 2)
       for (int s1 = pl.T[1]; s1 >= 1; s1 /= 2)
-        for (int s2 = pl.T[2]; s2 >= 1; s2 /= 2) {
+        for (int s2 = pl.T[2]; s2 >= 2; s2 /= 2) {
           const int S[3] = {s0, s1, s2};
-          int E[3];
-          const size_t bytes = extents(S, E);
+          int E[3], ps;
+          const size_t bytes = extents(S, E, ps);
           if (bytes > kInterpLdsMax) continue;
           const double amp = (double)E[0] * E[1] * E[2] / ((double)s0 * s1 * s2);
           if (!found || amp < best * (1.0 - 1e-12)) {
@@ -500,10 +504,12 @@ Status build_plan(Plan& pl, const jgb_params* p) {
               pl.S[i] = S[i];
               pl.E[i] = E[i];
             }
+            pl.pstride = ps;
             pl.interp_lds = bytes;
           }
         }
     if (!found) return fail(JGB_ERR_UNSUPPORTED, "interpolation neighbourhood exceeds LDS");
+    if (pl.E[2] != pl.width + 16) return fail(JGB_ERR_UNSUPPORTED, "interpolation row length");
   }
   pl.nsub = (pl.T[0] / pl.S[0]) * (pl.T[1] / pl.S[1]) * (pl.T[2] / pl.S[2]);
 
