@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   constexpr int E2 = W + 16;  // staged row length (the plan guarantees a.E2 == E2)
   extern __shared__ unsigned char smem_raw[];
   C2<T>* tile = reinterpret_cast<C2<T>*>(smem_raw);
-  __shared__ T wbuf[kInterpWaves][64];
+  __shared__ alignas(16) T wbuf[kInterpWaves][64];
   __shared__ double ws[kInterpWaves];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -215,14 +215,22 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
       }
       acc[q] = C2<T>{T(0), T(0)};
     }
+    // the loop's weights (the same for every lane) come from the wave's copy
+    // of the record in LDS, two per broadcast read
 #pragma unroll
-    for (int ib = 0; ib < (D3 ? W : 1); ++ib) {
-      const T wb = lane_value(wv, D3 ? 16 + ib : 0);
+    for (int ib = 0; ib < (D3 ? W : 1); ib += 2) {
+      const C2<T> wpair = *reinterpret_cast<const C2<T>*>(wrow + (D3 ? 16 + ib : 0));
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const C2<T> v = tile[off[q] + ib * E2];
-        acc[q].x += wb * v.x;
-        acc[q].y += wb * v.y;
+      for (int h = 0; h < 2; ++h) {
+        if (D3 ? ib + h < W : h == 0) {
+          const T wb = h == 0 ? wpair.x : wpair.y;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const C2<T> v = tile[off[q] + (ib + h) * E2];
+            acc[q].x += wb * v.x;
+            acc[q].y += wb * v.y;
+          }
+        }
       }
     }
     T sr = T(0), si = T(0);
