@@ -24,6 +24,8 @@ constexpr int kMaxWidth = 16;
 constexpr int kMaxLine = 1024;
 // Output tile of the type-1 gather kernel: TX x TY lanes, TZ points per lane.
 constexpr int kTileZ = 16;
+// Output tile of the type-1 gather along axis 2 (the bins above stay kTileZ).
+constexpr int kGatherZ = 8;
 // Per-node kernel values, tabulated at plan time: w values per internal axis,
 // axis a at [a w, a w + w) of the node's record (a unit axis has the single
 // value 1 at tap 0 and zeros after it), then a zero at 3 w that a load may
@@ -131,6 +133,9 @@ struct Plan {
   size_t interp_lds = 0;     // bytes of the staged grid region
   int nt[3] = {1, 1, 1};     // tiles per axis
   int ntiles = 0;
+  int GT[3] = {1, 1, 1};     // gather output tile per axis (axis 2: kGatherZ)
+  int gnt[3] = {1, 1, 1};    // gather tiles per axis
+  int ngtiles = 0;
   int* d_bin_start = nullptr;  // ntiles + 1 offsets into the sorted node list
   int2* d_list = nullptr;      // per tile, the nodes whose footprint touches it (concatenated):
                                // (node, first tap relative to the tile per axis, 10 bits each)

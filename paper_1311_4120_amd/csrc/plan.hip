@@ -176,7 +176,7 @@ void spread_items(const Plan& pl, int chunk, std::vector<WorkItem>& items, std::
   multi.clear();
   nslots = 0;
   const std::vector<int64_t>& tc = pl.h_tcount;
-  for (int tile = 0; tile < pl.ntiles; ++tile) {
+  for (int tile = 0; tile < pl.ngtiles; ++tile) {
     const int64_t b = tc[tile], e = tc[tile + 1], L = e - b;
     if (L == 0) continue;  // stays zero (cleared at plan time)
     if (L <= chunk) {
@@ -469,6 +469,15 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     pl.nt[i] = (pl.nf[i] + pl.T[i] - 1) / pl.T[i];
     pl.ntiles *= pl.nt[i];
   }
+  // the gather's output tiles: the bins' (a0, a1) extent, kGatherZ along a2
+  pl.GT[0] = pl.T[0];
+  pl.GT[1] = pl.T[1];
+  pl.GT[2] = kGatherZ;
+  pl.ngtiles = 1;
+  for (int i = 0; i < 3; ++i) {
+    pl.gnt[i] = (pl.nf[i] + pl.GT[i] - 1) / pl.GT[i];
+    pl.ngtiles *= pl.gnt[i];
+  }
   // sub-bins: the power-of-two sub-tile whose staged neighbourhood fits the LDS
   // budget with the fewest staged cells per sub-bin cell.  LDS layout of the
   // neighbourhood: rows of E2 = w2 + 16 elements along axis 2 (S2 >= 2 keeps
@@ -565,7 +574,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   TRY_HIP(hipMemcpyAsync(hdr.data(), pl.nodes.hdr, sizeof(int4) * Mh, hipMemcpyDeviceToHost, pl.stream), "hdr copy");
   TRY_HIP(hipStreamSynchronize(pl.stream), "hdr sync");
   auto touched = [&](int a, int x0, int* out) {
-    const int nf = pl.nf[a], T = pl.T[a], w = pl.w[a];
+    const int nf = pl.nf[a], T = pl.GT[a], w = pl.w[a];
     int n = 0;
     for (int t = 0; t < w; ++t) {
       int tile = ((x0 + t) % nf) / T;
@@ -575,18 +584,18 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     }
     return n;
   };
-  std::vector<int64_t> tcount(pl.ntiles + 1, 0);
+  std::vector<int64_t> tcount(pl.ngtiles + 1, 0);
   {
     int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
     for (int64_t j = 0; j < Mh; ++j) {
       int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
       for (int a0 = 0; a0 < nx; ++a0)
         for (int a1 = 0; a1 < ny; ++a1)
-          for (int a2 = 0; a2 < nz; ++a2) tcount[(tx[a0] * pl.nt[1] + ty[a1]) * pl.nt[2] + tz[a2] + 1]++;
+          for (int a2 = 0; a2 < nz; ++a2) tcount[(tx[a0] * pl.gnt[1] + ty[a1]) * pl.gnt[2] + tz[a2] + 1]++;
     }
   }
-  for (int t = 0; t < pl.ntiles; ++t) tcount[t + 1] += tcount[t];
-  const int64_t nlist = tcount[pl.ntiles];
+  for (int t = 0; t < pl.ngtiles; ++t) tcount[t + 1] += tcount[t];
+  const int64_t nlist = tcount[pl.ngtiles];
   if (nlist > (int64_t)std::numeric_limits<int>::max()) return fail(JGB_ERR_UNSUPPORTED, "gather lists too long");
   // entry: node index and its first tap relative to the tile origin on each
   // axis, modulo the grid (10 bits each; nf <= 1024)
@@ -599,10 +608,10 @@ Status build_plan(Plan& pl, const jgb_params* p) {
       for (int a0 = 0; a0 < nx; ++a0)
         for (int a1 = 0; a1 < ny; ++a1)
           for (int a2 = 0; a2 < nz; ++a2) {
-            const int tile = (tx[a0] * pl.nt[1] + ty[a1]) * pl.nt[2] + tz[a2];
-            const int ex = ((hdr[j].x - tx[a0] * pl.T[0]) % pl.nf[0] + pl.nf[0]) % pl.nf[0];
-            const int ey = ((hdr[j].y - ty[a1] * pl.T[1]) % pl.nf[1] + pl.nf[1]) % pl.nf[1];
-            const int ez = ((hdr[j].z - tz[a2] * pl.T[2]) % pl.nf[2] + pl.nf[2]) % pl.nf[2];
+            const int tile = (tx[a0] * pl.gnt[1] + ty[a1]) * pl.gnt[2] + tz[a2];
+            const int ex = ((hdr[j].x - tx[a0] * pl.GT[0]) % pl.nf[0] + pl.nf[0]) % pl.nf[0];
+            const int ey = ((hdr[j].y - ty[a1] * pl.GT[1]) % pl.nf[1] + pl.nf[1]) % pl.nf[1];
+            const int ez = ((hdr[j].z - tz[a2] * pl.GT[2]) % pl.nf[2] + pl.nf[2]) % pl.nf[2];
             list[fill[tile]++] = make_int2((int)j, ex | (ey << 10) | (ez << 20));
           }
     }
@@ -625,7 +634,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     }
     TRY(dev_alloc(pl, &pl.d_items, sizeof(WorkItem) * std::max(pl.items_cap, 1)));
     TRY(dev_alloc(pl, &pl.d_multi, sizeof(int) * std::max(pl.multi_cap, 1)));
-    TRY(dev_alloc(pl, &pl.d_partials, (size_t)std::max(pl.slots_cap, 1) * 64 * kTileZ * 2 * pl.real_bytes));
+    TRY(dev_alloc(pl, &pl.d_partials, (size_t)std::max(pl.slots_cap, 1) * 64 * kGatherZ * 2 * pl.real_bytes));
     TRY(apply_spread_chunk(pl, pl.spread_chunk));
   }
 

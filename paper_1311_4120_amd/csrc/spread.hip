@@ -4,7 +4,7 @@
 //
 //   G[g] = sum_j uhat_j phi(g0 - s0_j) phi(g1 - s1_j) phi(g2 - s2_j)   (periodic)
 //
-// A block owns one output tile of T0 x T1 x kTileZ points (kTileZ along the
+// A block owns one output tile of T0 x T1 x kGatherZ points (kGatherZ along the
 // contiguous axis) and walks the tile's exact node list: every node whose
 // footprint touches the tile, with its first tap relative to the tile origin.
 // The tile update for a group of nodes is a rank-4 matrix product run on the
@@ -42,16 +42,10 @@ struct SpreadArgs {
 
 constexpr int kWaves = 4;
 
-// Matrix-core form of the gather.  For one tile and four nodes at a time,
-//
-//   G[m, z] += sum_k P[m, k] Q[k, z],   P[m, k] = phi_x(x_m - s_k) phi_y(y_m - s_k),
-//                                        Q[k, z] = phi_z(z - s_k) uhat_k,
-//
-// with m the 64 (a0, a1) points of the tile in four row blocks of 16 and z
-// the 16 points along a2: eight 16x16x4 products per four nodes (real and
-// imaginary parts of each row block).  Lane 16k + i supplies P[16b + i, k]
-// and Q[k, i], so every operand comes from an ordinary per-lane load; no
-// value has to be broadcast across the wavefront.
+// 16x16x4 matrix-core products D += A B: lane 16k + i supplies A[i][k] and
+// B[k][i] (so every operand of the gather is an ordinary per-lane load), and
+// lane l holds D[row(l, r)][l mod 16] in its result register r, with the row
+// mapping of each precision below.
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -82,32 +76,55 @@ __device__ __forceinline__ V load_at(const void* base, uint32_t byte_off) {
   return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
-// Operands of one group of four list entries, loaded one group ahead of their
-// use so that the loads overlap the previous group's products.  NX and NY are
-// the distinct axis-0 and axis-1 kernel values a lane needs over its four row
-// blocks (the tile shape makes one of them 1).  A tap outside the footprint,
-// or a lane past the end of the list, reads the zero that ends its node's
-// record, so nothing is masked after the loads.
+// DPP move within rows of 16 lanes: lane i reads lane i - 8 (lanes 0-7 of a
+// row read 0).
+template <typename T>
+__device__ __forceinline__ T row_shr8(T v);
+template <>
+__device__ __forceinline__ double row_shr8(double v) {
+  int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x118, 0xf, 0xf, false);
+  int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x118, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <>
+__device__ __forceinline__ float row_shr8(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));
+}
+
+// Operands of one group of four list entries, loaded one (fp64) or two (fp32)
+// groups ahead of their use so that the loads overlap earlier products.  NX
+// and NY are the distinct axis-0 and axis-1 kernel values a lane needs over its
+// four row blocks (the tile shape makes one of them 1).  A tap outside the
+// footprint, or a lane past the end of the list, reads the zero that ends its
+// node's record, so nothing is masked after the loads.
 template <typename T, int NX, int NY>
 struct GroupLoads {
   T z;             // axis-2 value at the lane's tile z
-  C2<T> u;         // weighted node value
+  T u;             // the real or imaginary part of the weighted node value
   T px[NX], py[NY];
 };
 
-// One block per work item (a tile and a range of its node list).  The four
-// wavefronts each take a contiguous quarter of the range; their partial tiles
-// are summed in LDS in a fixed order and written once.  T1 is the tile extent
-// on axis 1 (8 for 8 x 8 x 16 tiles, 64 for the 1 x 64 x 16 tiles of 2D
-// problems); lane li of row block b holds the point m = 16 b + li, at
-// (m / T1, m mod T1).
+// One block per work item (a tile and a range of its node list).  The tile is
+// T0 x T1 x kGatherZ points; for four listed nodes its update is
+//
+//   G[m, (z, part)] += sum_k P[m, k] Q[k, (z, part)],
+//   P[m, k] = phi_0(x_m - s_k) phi_1(y_m - s_k),   Q[k, (z, part)] = phi_2(z - s_k) part(uhat_k),
+//
+// with m the 64 points of the two outer axes in four row blocks of 16 and the
+// 16 columns the kGatherZ = 8 points of axis 2 times (real, imaginary): one
+// 16x16x4 product per row block, four per group.  Lane 16k + i supplies
+// P[16b + i, k] and Q[k, i].  A node's footprint covers 12 of an 8-deep tile's
+// z more often than of a 16-deep one, so less of the matrix-core work is spent
+// outside footprints.  The wavefronts split the list; their partial tiles are
+// summed in LDS in a fixed order and written once.  T1 is the tile extent on
+// axis 1 (8 for 3D, 64 for the 1 x 64 tiles of 2D problems).
 template <typename T, int T1>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int T0 = 64 / T1;
   constexpr int NX = (T1 == 8) ? 4 : 1;   // distinct x over the row blocks
   constexpr int NY = (T1 == 8) ? 1 : 4;   // distinct y over the row blocks
-  __shared__ T red[2][2 * 64 * kTileZ];
+  __shared__ T red[2][4 * 4 * 64];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const WorkItem item = a.items[blockIdx.x];
@@ -116,8 +133,10 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int t2 = tile % a.nt2;
   const int t1 = (tile / a.nt2) % a.nt1;
   const int t0 = tile / (a.nt2 * a.nt1);
-  const int o0 = t0 * T0, o1 = t1 * T1, o2 = t2 * kTileZ;
+  const int o0 = t0 * T0, o1 = t1 * T1, o2 = t2 * kGatherZ;
   const int li = lane & 15, lk = lane >> 4;
+  const int zl = li & (kGatherZ - 1);            // tile z of the lane's column
+  const uint32_t upart = li >= kGatherZ ? (uint32_t)sizeof(T) : 0u;  // imaginary part
   const int W = a.width;
   const uint32_t rbytes = (uint32_t)(a.rstride * sizeof(T));   // bytes per record
   const uint32_t zslot = (uint32_t)(3 * W * sizeof(T));         // byte offset of the zero
@@ -136,12 +155,9 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     if (o1 + ys[b] >= a.nf1) ys[b] = -(1 << 20);
   }
 
-  acc_t acc[4][2];
+  acc_t acc[4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    acc[b][0] = acc_t{T(0), T(0), T(0), T(0)};
-    acc[b][1] = acc_t{T(0), T(0), T(0), T(0)};
-  }
+  for (int b = 0; b < 4; ++b) acc[b] = acc_t{T(0), T(0), T(0), T(0)};
 
   // short lists use fewer wavefronts (less to sum at the end); the count
   // depends on the list length alone, so the summation order is fixed
@@ -162,9 +178,9 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     const uint32_t j = (uint32_t)ent.x;
     const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
     const uint32_t rec = j * rbytes;
-    r.u = load_at<C2<T>>(a.uhat, j * (uint32_t)sizeof(C2<T>));
+    r.u = load_at<T>(a.uhat, j * (uint32_t)sizeof(C2<T>) + upart);
     // tap d = (p - start) mod nf of a point p covers it iff d < w (w <= nf)
-    int dz = li - ez;
+    int dz = zl - ez;
     if (dz < 0) dz += a.nf2;
     const bool inz = valid && dz < a.w2;
     r.z = load_at<T>(a.wts, rec + (inz ? (uint32_t)((2 * W + dz) * sizeof(T)) : zslot));
@@ -185,17 +201,12 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     return r;
   };
 
-  // Loads run one group ahead of the products in fp64 and two in fp32 (where
-  // the registers allow it without costing occupancy); past the end the
-  // fetches re-read the last group and are discarded.
   auto mma_group = [&](const GroupLoads<T, NX, NY>& c) {
-    const T qr = c.z * c.u.x;
-    const T qi = c.z * c.u.y;
+    const T qv = c.z * c.u;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const T pv = c.px[NX == 4 ? b : 0] * c.py[NY == 4 ? b : 0];
-      acc[b][0] = Mfma<T>::mma(pv, qr, acc[b][0]);
-      acc[b][1] = Mfma<T>::mma(pv, qi, acc[b][1]);
+      acc[b] = Mfma<T>::mma(pv, qv, acc[b]);
     }
   };
   if (kb < ke) {
@@ -220,61 +231,54 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
 
   // fixed-order sum of the active wavefronts' partial tiles: w0 alone,
   // w0 + w1, or (w0 + w2) + (w1 + w3)
-  const int base = lane;  // element (b, part, r) at base + 64 * (8 b + 4 part + r)
+  const int base = lane;  // element (b, r) at base + 64 * (4 b + r)
   if (wave >= 2 && nw == kWaves) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        red[wave - 2][base + 64 * (b * 8 + r)] = acc[b][0][r];
-        red[wave - 2][base + 64 * (b * 8 + 4 + r)] = acc[b][1][r];
-      }
+      for (int r = 0; r < 4; ++r) red[wave - 2][base + 64 * (4 * b + r)] = acc[b][r];
   }
   __syncthreads();
   if (wave < 2 && nw == kWaves) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        acc[b][0][r] += red[wave][base + 64 * (b * 8 + r)];
-        acc[b][1][r] += red[wave][base + 64 * (b * 8 + 4 + r)];
-      }
+      for (int r = 0; r < 4; ++r) acc[b][r] += red[wave][base + 64 * (4 * b + r)];
   }
   __syncthreads();
   if (wave == 1 && nw >= 2) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        red[0][base + 64 * (b * 8 + r)] = acc[b][0][r];
-        red[0][base + 64 * (b * 8 + 4 + r)] = acc[b][1][r];
-      }
+      for (int r = 0; r < 4; ++r) red[0][base + 64 * (4 * b + r)] = acc[b][r];
   }
   __syncthreads();
   if (wave == 0 && nw >= 2) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        acc[b][0][r] += red[0][base + 64 * (b * 8 + r)];
-        acc[b][1][r] += red[0][base + 64 * (b * 8 + 4 + r)];
-      }
+      for (int r = 0; r < 4; ++r) acc[b][r] += red[0][base + 64 * (4 * b + r)];
   }
   if (wave != 0) return;
-  const int z = lane & 15;
+  // column li holds the real part of tile z = li (li < 8) or the imaginary
+  // part of z = li - 8: the lanes of the second half of each row of 16 take
+  // the real part from 8 lanes down and store the complex value
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const T vr = acc[b][0][r];
-      const T vi = acc[b][1][r];
-      const int m = 16 * b + Mfma<T>::row(lane, r);
-      const int x = m / T1, y = m % T1;
-      if (item.slot < 0) {
-        if (o0 + x < a.nf0 && o1 + y < a.nf1 && o2 + z < a.nf2)
-          a.G[((int64_t)(o0 + x) * a.nf1 + (o1 + y)) * a.nf2 + o2 + z] = C2<T>{vr, vi};
-      } else {
-        a.partials[((int64_t)item.slot * 64 + m) * kTileZ + z] = C2<T>{vr, vi};
+      const T vi = acc[b][r];
+      const T vr = row_shr8(vi);
+      if (li >= kGatherZ) {
+        const int z = li - kGatherZ;
+        const int m = 16 * b + Mfma<T>::row(lane, r);
+        const int x = m / T1, y = m % T1;
+        if (item.slot < 0) {
+          if (o0 + x < a.nf0 && o1 + y < a.nf1 && o2 + z < a.nf2)
+            a.G[((int64_t)(o0 + x) * a.nf1 + (o1 + y)) * a.nf2 + o2 + z] = C2<T>{vr, vi};
+        } else {
+          a.partials[((int64_t)item.slot * 64 + m) * kGatherZ + z] = C2<T>{vr, vi};
+        }
       }
     }
 }
@@ -284,23 +288,23 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_spread_reduce(const int* multi, int nmulti, int nf0, int nf1, int nf2,
                                                        int T0, int T1, int nt1, int nt2, const C2<T>* partials,
                                                        C2<T>* G) {
-  // four blocks per split tile, one tile point per thread; the slots are
+  // two blocks per split tile, one tile point per thread; the slots are
   // summed in slot order, their loads issued several at a time
-  const int m = blockIdx.x >> 2;
+  const int m = blockIdx.x >> 1;
   if (m >= nmulti) return;
-  const int idx = (blockIdx.x & 3) * 256 + threadIdx.x;  // < 64 kTileZ
+  const int idx = (blockIdx.x & 1) * 256 + threadIdx.x;  // < 64 kGatherZ
   const int tile = multi[3 * m], first = multi[3 * m + 1], count = multi[3 * m + 2];
   const int t2 = tile % nt2;
   const int t1 = (tile / nt2) % nt1;
   const int t0 = tile / (nt2 * nt1);
-  const int lane = idx / kTileZ, z = idx % kTileZ;
-  const int g0 = t0 * T0 + lane / T1, g1 = t1 * T1 + lane % T1, g2 = t2 * kTileZ + z;
+  const int lane = idx / kGatherZ, z = idx % kGatherZ;
+  const int g0 = t0 * T0 + lane / T1, g1 = t1 * T1 + lane % T1, g2 = t2 * kGatherZ + z;
   if (g0 >= nf0 || g1 >= nf1 || g2 >= nf2) return;
-  const C2<T>* p = partials + (int64_t)first * 64 * kTileZ + idx;
+  const C2<T>* p = partials + (int64_t)first * 64 * kGatherZ + idx;
   T sr = T(0), si = T(0);
 #pragma unroll 8
   for (int c = 0; c < count; ++c) {
-    const C2<T> v = p[(int64_t)c * 64 * kTileZ];
+    const C2<T> v = p[(int64_t)c * 64 * kGatherZ];
     sr += v.x;
     si += v.y;
   }
@@ -331,10 +335,10 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.w0 = pl.w[0];
   a.w1 = pl.w[1];
   a.w2 = pl.w[2];
-  a.nt1 = pl.nt[1];
+  a.nt1 = pl.gnt[1];
   a.width = pl.width;
   a.rstride = record_stride(pl.width);
-  a.nt2 = pl.nt[2];
+  a.nt2 = pl.gnt[2];
   a.list = pl.d_list;
   a.items = pl.d_items;
   a.nitems = pl.nitems;
@@ -345,9 +349,9 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   unsigned blocks = (unsigned)pl.nitems;
   if (blocks == 0) return hipSuccess;  // no node touches the grid: G stays zero
   stage_mark(pl, ST_SPREAD, 0, s);
-  if (pl.T[0] == 8 && pl.T[1] == 8)
+  if (pl.GT[0] == 8 && pl.GT[1] == 8)
     hipLaunchKernelGGL((k_spread_gather<T, 8>), dim3(blocks), dim3(256), 0, s, a);
-  else if (pl.T[0] == 1 && pl.T[1] == 64)
+  else if (pl.GT[0] == 1 && pl.GT[1] == 64)
     hipLaunchKernelGGL((k_spread_gather<T, 64>), dim3(blocks), dim3(256), 0, s, a);
   else
     return hipErrorInvalidValue;
@@ -355,9 +359,9 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
   stage_mark(pl, ST_SPREAD_REDUCE, 0, s);
-  static_assert(64 * kTileZ == 4 * 256, "four 256-thread blocks per tile");
-  hipLaunchKernelGGL(k_spread_reduce<T>, dim3(4 * pl.nmulti), dim3(256), 0, s, pl.d_multi, pl.nmulti, pl.nf[0], pl.nf[1],
-                     pl.nf[2], pl.T[0], pl.T[1], pl.nt[1], pl.nt[2], (const C2<T>*)pl.d_partials, (C2<T>*)pl.d_G);
+  static_assert(64 * kGatherZ == 2 * 256, "two 256-thread blocks per tile");
+  hipLaunchKernelGGL(k_spread_reduce<T>, dim3(2 * pl.nmulti), dim3(256), 0, s, pl.d_multi, pl.nmulti, pl.nf[0], pl.nf[1],
+                     pl.nf[2], pl.GT[0], pl.GT[1], pl.gnt[1], pl.gnt[2], (const C2<T>*)pl.d_partials, (C2<T>*)pl.d_G);
   stage_mark(pl, ST_SPREAD_REDUCE, 1, s);
   return hipGetLastError();
 }
