@@ -126,17 +126,9 @@ Status upload(Plan& pl, void* dst, const void* src, size_t bytes) {
 // block p to XCD p mod 8, each XCD with its own L2), so that neighbouring
 // items -- which read the same node records and grid halos -- share an L2.
 // Each class is padded to a multiple of eight with idle items.
-#ifndef JGB_ORDER
-#define JGB_ORDER 1
-#endif
 template <typename Item, typename Cost>
 std::vector<Item> dispatch_order(const std::vector<Item>& items, Cost cost, const Item& idle) {
   constexpr int kXcd = 8;
-  if (JGB_ORDER == 0) {
-    std::vector<Item> o = items;
-    std::stable_sort(o.begin(), o.end(), [&](const Item& x, const Item& y) { return cost(x) > cost(y); });
-    return o;
-  }
   auto cls = [&](const Item& it) { return (int)std::floor(std::log(1.0 + cost(it)) / std::log(1.5)); };
   std::vector<Item> o = items;
   std::stable_sort(o.begin(), o.end(), [&](const Item& x, const Item& y) { return cls(x) > cls(y); });
