@@ -6,7 +6,9 @@ spherical / polar Fourier quadrature nodes (eqs. 3.5, 3.7), the weighted sum
 back to the uniform grid (eq. 3.7, Algorithm 1), and the interaction energy
 (eq. gpe2 and the energy remark after Algorithm 2).  No NUFFT is used: every
 sum is evaluated directly, with per-axis phase tables and BLAS matrix products
-as the only library primitives.
+as the only library primitives.  `split` holds Algorithm 2 (Section 3.3), whose
+regular-grid part I1 is a padded FFT convolution (numpy's FFT as the library
+step), pinned against the same trapezoid sum done directly.
 
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
 import this package.  It shares no code with the HIP library: the two meet
@@ -25,10 +27,11 @@ from .direct import (rho_hat, rho_hat_separable, sum_to_grid, sum_to_points, pot
                      energy_physical, Result, evaluate, energy_gradient_rho,
                      energy_gradient_psi, apply_operator)
 from . import closed_forms
+from . import split
 
 __all__ = [
     "gauss_legendre", "radial_rule", "theta_rule", "phi_rule", "spherical_nodes",
     "polar_nodes", "fourier_nodes", "symbol", "coefficients", "rho_hat", "rho_hat_separable", "sum_to_grid",
     "sum_to_points", "potential", "energy_fourier", "energy_physical", "Result", "evaluate",
-    "energy_gradient_rho", "energy_gradient_psi", "apply_operator", "closed_forms",
+    "energy_gradient_rho", "energy_gradient_psi", "apply_operator", "closed_forms", "split",
 ]
