@@ -80,6 +80,21 @@ typedef enum { JGB_THETA_GL = 0, JGB_COSTHETA_GL = 1 } jgb_theta_rule;
  * and written to it (a JSON object keyed by grid, node counts, cutoff, width
  * and precision), so later plans of the same shape skip the timing. */
 #define JGB_FLAG_AUTOTUNE 1u
+/* Evaluate u by the partition-of-unity split of Algorithm 2 (Section 3.3,
+ * eq. 3.9) instead of Algorithm 1.  A smooth window p (eq. 3.10 in 3D,
+ * eq. 3.12 in 2D) splits the Fourier integral into
+ *   I1 = (2 pi)^{-d} int (1 - p) U^ rho^ e^{ik.x} dk,
+ * whose integrand is smooth, taken by the trapezoid rule on the regular
+ * frequency grid k_q = 2 pi q / (2 R_j) (the oversampled grid of step 3): a
+ * periodic convolution of the zero-padded density, by FFT, exact up to
+ * rounding; and
+ *   I2 = (2 pi)^{-d} int p U^ rho^ e^{ik.x} dk,
+ * Algorithm 1 on the plan's node set with c_j multiplied by p(k_j).  Because p
+ * decays on the scale of the box's Fourier spacing dk = 2 pi / max_j R_j, I2
+ * needs few nodes whatever N is.  The result matches the same discrete sums
+ * evaluated directly to eps (relative L2 of u, relative E).  See
+ * jgb_params.window and jgb_params.kmax for the scales. */
+#define JGB_FLAG_SPLIT 2u
 
 typedef struct jgb_plan_s* jgb_plan_t;
 
@@ -100,10 +115,21 @@ typedef struct {
   int32_t n_phi;           /* azimuthal trapezoid nodes: even, >= 2 (k -> -k closure) */
   int32_t theta_rule;      /* jgb_theta_rule */
   double kmax;             /* radius K of the Fourier ball; 0 -> pi / max_j h_j; must be
-                              in (0, pi / max_j h_j] otherwise */
+                              in (0, pi / max_j h_j] otherwise.  With JGB_FLAG_SPLIT it is
+                              the radius of I2's ball, and 0 means min(pi / max_j h_j,
+                              sqrt(40 a)) in 3D (p < 5e-18 beyond) or min(pi / max_j h_j, R1)
+                              in 2D (p < 1.1e-17 beyond) */
   int32_t device;          /* HIP device ordinal the plan lives on */
   void* stream;            /* hipStream_t for all work of this plan (NULL = default stream) */
   uint32_t flags;          /* JGB_FLAG_* (any other bit -> INVALID_ARG) */
+  double window[2];        /* JGB_FLAG_SPLIT only (both 0 otherwise): the window of Algorithm 2,
+                              with dk = 2 pi / max_j R_j.
+                              3D: window[0] = a of p(k) = exp(-|k|^2 / a) (eq. 3.10),
+                                  0 -> 2 dk^2; window[1] = 0.
+                              2D: window = {R0, R1} of p(k) = erfc(12 (|k| - (R0 + R1)/2)
+                                  / (R1 - R0)) / 2 (eq. 3.12), {0, 0} -> {0.8 dk, 10 dk};
+                                  otherwise 0 < R0 < R1.
+                              Values must be finite. */
 } jgb_params;
 
 /* Plan facts, for diagnostics and for sizing caller buffers. */
@@ -120,6 +146,8 @@ typedef struct {
   int64_t workspace_bytes; /* device memory owned by the plan */
   int32_t interp_chunk;    /* nodes per interpolation block at most */
   int32_t spread_chunk;    /* list entries per spreading block at most */
+  uint32_t flags;          /* the plan's JGB_FLAG_* */
+  double window[2];        /* JGB_FLAG_SPLIT: the window scales used (a, 0) or (R0, R1); else 0 */
 } jgb_info;
 
 /* Build a plan: validates the parameters, generates the Fourier nodes and
@@ -130,7 +158,8 @@ typedef struct {
  * UNSUPPORTED (valid but outside this build), OUT_OF_MEMORY, DEVICE. */
 jgb_status jgb_plan(const jgb_params* params, jgb_plan_t* out);
 
-/* u = U*rho on the grid (Algorithm 1, steps 4-5) and, if energy != NULL,
+/* u = U*rho on the grid (Algorithm 1, steps 4-5; with JGB_FLAG_SPLIT,
+ * Algorithm 2: u = I1 + I2) and, if energy != NULL,
  * E = (lambda/2) H sum rho u (physical-side trapezoid sum, energy remark).
  * rho, u: device arrays of prod N_j elements of the plan's dtype;
  * energy: device float64 or NULL.  rho and u must not overlap.
@@ -139,7 +168,9 @@ jgb_status jgb_potential(jgb_plan_t plan, const void* rho, void* u, double* ener
 
 /* E only, via the Fourier-side sum E = (lambda/2) sum_j c_j |rho^_j|^2, which
  * equals the physical-side sum exactly for real rho (substitute eq. 3.2 into
- * the energy).  Runs only the type-2 half of the pipeline.
+ * the energy).  Runs only the type-2 half of the pipeline.  With
+ * JGB_FLAG_SPLIT the sum gains the regular-grid part of I1,
+ * (lambda/2) (prod_j 2 R_j)^{-1} sum_q (1 - p(k_q)) U^(k_q) |rho^(k_q)|^2.
  * rho: device array; energy: device float64.  Enqueue only. */
 jgb_status jgb_energy(jgb_plan_t plan, const void* rho, double* energy);
 
@@ -178,7 +209,8 @@ jgb_status jgb_transform(jgb_plan_t plan, const void* rho, void* rhohat);
 /* Fourier nodes of the plan for diagnostics (Algorithm 1, step 3): all M
  * nodes in natural order.  k: device float64 array (M, dim); w: device float64
  * array of the quadrature weights W_j (measure dr dtheta dphi with sin(theta),
- * or dr dphi); c: device float64 array of c_j = (2pi)^{-d} W_j |k_j|^{d-1} U^(k_j).
+ * or dr dphi); c: device float64 array of c_j = (2pi)^{-d} W_j |k_j|^{d-1} U^(k_j)
+ * (times p(k_j) with JGB_FLAG_SPLIT).
  * Any of the three may be NULL.  Enqueue only. */
 jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* c);
 
@@ -196,10 +228,13 @@ jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* c);
  *   6 inverse FFT pass on axis 1          7 inverse FFT pass on axis 2
  *   8 inverse FFT pass on axis 3 with crop, deconvolution and energy terms
  *   9 energy reduction
+ *  10 JGB_FLAG_SPLIT: separation of the two real transforms on the tiles
+ *     the interpolation reads
+ *  11 JGB_FLAG_SPLIT: I1's symbol (or its energy sum) over the regular grid
  * (2D problems run no pass on a third axis: stages 2 and 6 stay 0.)
  * Errors: INVALID_ARG (NULL plan, max_calls < 1 or > 100000, NULL outputs),
  * OUT_OF_MEMORY (event creation), DEVICE. */
-#define JGB_NUM_STAGES 10
+#define JGB_NUM_STAGES 12
 jgb_status jgb_timing_begin(jgb_plan_t plan, int max_calls);
 jgb_status jgb_timing_end(jgb_plan_t plan, double* stage_ms, int* calls);
 

@@ -124,6 +124,10 @@ def i1_fft(rho, box, kernel, par, axis=None, sigma=SIGMA):
     pad = np.zeros(L, dtype=np.float64)
     idx = np.ix_(*[np.arange(-(N // 2), N - N // 2) % Lj for N, Lj in zip(n, L)])
     pad[idx] = rho
+    # Re: on a Nyquist plane the grid frequency is its own mirror on that axis,
+    # and a symbol that is not a function of |k| alone (the dipole's) takes
+    # different values at k and at the mirror of -k there; the real part uses
+    # their mean, as the real integral (I1 is real) requires
     conv = np.fft.ifftn(M * np.fft.fftn(pad))
     return conv[idx].real.copy()
 
@@ -144,6 +148,37 @@ def i2_coefficients(kernel, k, W, par, axis=None):
     d = k.shape[1]
     kabs = np.sqrt(np.einsum("ij,ij->i", k, k))
     return W * symbol(kernel, k, axis) * window(kabs, d, par) / (2.0 * np.pi) ** d
+
+
+def i1_energy(rho, box, kernel, par, axis=None, sigma=SIGMA):
+    """H sum_n rho_n I1_n in Fourier form: (prod_j sigma R_j)^{-1} sum_q M(k_q) |rho^(k_q)|^2
+    (substitute eq. 3.2 into the trapezoid sum of I1; rho real)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n = rho.shape
+    k, L = _grid_k(n, box, sigma)
+    M = split_symbol(kernel, k, par, axis).reshape(L)
+    pad = np.zeros(L, dtype=np.float64)
+    idx = np.ix_(*[np.arange(-(N // 2), N - N // 2) % Lj for N, Lj in zip(n, L)])
+    pad[idx] = rho
+    rh = _cell_volume(n, box) * np.fft.fftn(pad)
+    return float(np.sum(M * np.abs(rh) ** 2)) / np.prod([sigma * float(R) for R in box])
+
+
+def energy_split_fourier(problem, rho, par=None, rh=None):
+    """E = (lambda/2) [sum_j c_j p(k_j) |rho^_j|^2 + I1's Fourier-form share], equal to
+    the physical-side (lambda/2) H sum rho u for real rho.  rh: rho^ at I2's nodes,
+    if already known."""
+    rho = np.asarray(rho, dtype=np.float64)
+    par = default_window(problem.n, problem.box) if par is None else par
+    if problem.kmax <= 0:
+        problem = dataclasses.replace(problem, kmax=default_cutoff(problem.n, problem.box, par))
+    k, W = fourier_nodes(problem)
+    c = i2_coefficients(problem.kernel, k, W, par, problem.axis)
+    if rh is None:
+        rh = rho_hat(rho, problem.box, k)
+    e2 = float(np.sum(c * np.abs(rh) ** 2))
+    e1 = i1_energy(rho, problem.box, problem.kernel, par, problem.axis)
+    return 0.5 * problem.lam * (e1 + e2)
 
 
 def potential_split(problem, rho, par=None):

@@ -20,11 +20,12 @@ STATUS_NAMES = {0: "JGB_OK", 1: "JGB_ERR_INVALID_ARG", 2: "JGB_ERR_UNSUPPORTED",
                 3: "JGB_ERR_OUT_OF_MEMORY", 4: "JGB_ERR_DEVICE"}
 
 COULOMB_3D, COULOMB_2D, DIPOLE_3D = 0, 1, 2
-NUM_STAGES = 10
+NUM_STAGES = 12
 STAGE_NAMES = ["fwd_fft_z", "fwd_fft_y", "fwd_fft_x", "interp", "spread", "spread_reduce",
-               "inv_fft_x", "inv_fft_y", "inv_fft_z", "energy"]
+               "inv_fft_x", "inv_fft_y", "inv_fft_z", "energy", "split_unmix", "split_symbol"]
 FP64, MIXED = 0, 1
 FLAG_AUTOTUNE = 1
+FLAG_SPLIT = 2
 THETA_GL, COSTHETA_GL = 0, 1
 
 
@@ -47,6 +48,7 @@ class Params(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("flags", ctypes.c_uint32),
+        ("window", ctypes.c_double * 2),
     ]
 
 
@@ -64,6 +66,8 @@ class Info(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64),
         ("interp_chunk", ctypes.c_int32),
         ("spread_chunk", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("window", ctypes.c_double * 2),
     ]
 
 

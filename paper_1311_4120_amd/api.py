@@ -20,7 +20,7 @@ def _ptr(t):
 
 
 def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                 autotune=False):
+                 autotune=False, split=False, window=(0.0, 0.0)):
     dim = len(n)
     kern = _KERNELS.get(kernel, kernel)
     rule = _RULES.get(theta_rule, theta_rule)
@@ -47,7 +47,9 @@ def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, k
     p.kmax = float(kmax)
     p.device = dev
     p.stream = ctypes.c_void_p(st.cuda_stream)
-    p.flags = _lib.FLAG_AUTOTUNE if autotune else 0
+    p.flags = (_lib.FLAG_AUTOTUNE if autotune else 0) | (_lib.FLAG_SPLIT if split else 0)
+    for i in range(2):
+        p.window[i] = float(window[i]) if i < len(window) else 0.0
     return p, dev, st
 
 
@@ -58,14 +60,18 @@ class Plan:
     kernel:    "coulomb3d", "coulomb2d" or "dipole3d" (or the jgb_kernel ints)
     nodes:     (n_r, n_theta, n_phi) for 3D, (n_r, n_phi) for 2D
     precision: "fp64" or "mixed"
+    split:     evaluate by Algorithm 2 (window p, I1 on the regular grid, I2 on
+               the nodes); then kmax is I2's cut-off and window the scales
+               (3D: (a, 0); 2D: (R0, R1); zeros: the defaults)
     """
 
     def __init__(self, n: Sequence[int], box: Sequence[float], kernel, nodes: Sequence[int],
                  eps: float = 1e-10, precision: str = "fp64", lam: float = 1.0,
                  axis: Sequence[float] = (0.0, 0.0, 1.0), theta_rule="theta", kmax: float = 0.0,
-                 device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, autotune: bool = False):
+                 device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, autotune: bool = False,
+                 split: bool = False, window: Sequence[float] = (0.0, 0.0)):
         p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                                  autotune)
+                                  autotune, split, window)
         self._init_from(p, dev, st, box)
         h = ctypes.c_void_p()
         check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))
@@ -95,7 +101,7 @@ class Plan:
         info = _lib.Info()
         info.struct_size = ctypes.sizeof(_lib.Info)
         check(lib.jgb_plan_info(self._h, ctypes.byref(info)))
-        self.info = {f: (list(getattr(info, f)) if f in ("n", "nf") else getattr(info, f))
+        self.info = {f: (list(getattr(info, f)) if f in ("n", "nf", "window") else getattr(info, f))
                      for f, _ in _lib.Info._fields_ if f != "struct_size"}
 
 
@@ -224,7 +230,7 @@ class Batch:
     """Independent densities evaluated by one HIP graph launch.
 
     members: list of dicts of Plan keyword arguments (n, box, kernel, nodes, eps,
-    precision, lam, axis, theta_rule, kmax).  bind() takes the density tensors
+    precision, lam, axis, theta_rule, kmax, split, window).  bind() takes the density tensors
     and allocates the outputs; run() evaluates every member."""
 
     def __init__(self, members, nstreams=4, device=None, stream=None):
@@ -234,10 +240,11 @@ class Batch:
         boxes = []
         for i, m in enumerate(members):
             kw = dict(eps=1e-10, precision="fp64", lam=1.0, axis=(0.0, 0.0, 1.0), theta_rule="theta", kmax=0.0,
-                      autotune=False)
+                      autotune=False, split=False, window=(0.0, 0.0))
             kw.update(m)
             p, _, _ = _make_params(kw["n"], kw["box"], kw["kernel"], kw["nodes"], kw["eps"], kw["precision"],
-                                   kw["lam"], kw["axis"], kw["theta_rule"], kw["kmax"], dev, st, kw["autotune"])
+                                   kw["lam"], kw["axis"], kw["theta_rule"], kw["kmax"], dev, st, kw["autotune"],
+                                   kw["split"], kw["window"])
             arr[i] = p
             boxes.append(kw["box"])
         h = ctypes.c_void_p()

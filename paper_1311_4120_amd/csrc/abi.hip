@@ -66,13 +66,25 @@ size_t grid_bytes(const Plan& pl) {
   return (size_t)pl.n[0] * pl.n[1] * pl.n[2] * pl.real_bytes;
 }
 
+// Forward FFT and, for Algorithm 2, the separation of the type-2 spectrum
+// into the tiles the interpolation reads.
+template <typename T>
+jgb_status run_forward(Plan& pl, const void* rho, hipStream_t st) {
+  hipError_t e;
+  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, st)) != hipSuccess) return from_hip(e, "forward FFT");
+  if (pl.split && (e = jgb::launch_split_unmix<T>(pl, st)) != hipSuccess) return from_hip(e, "split separation");
+  return JGB_OK;
+}
+
 template <typename T>
 jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st) {
   hipError_t e;
-  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, st)) != hipSuccess) return from_hip(e, "forward FFT");
+  jgb_status c = run_forward<T>(pl, rho, st);
+  if (c != JGB_OK) return c;
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_POTENTIAL, nullptr, st)) != hipSuccess)
     return from_hip(e, "interpolation");
   if ((e = jgb::launch_spread<T>(pl, st)) != hipSuccess) return from_hip(e, "spreading");
+  if (pl.split && (e = jgb::launch_split_symbol<T>(pl, 0, 0, st)) != hipSuccess) return from_hip(e, "split symbol");
   if ((e = jgb::launch_fft_inverse<T>(pl, (T*)u, energy ? (const T*)rho : nullptr, st)) != hipSuccess)
     return from_hip(e, "inverse FFT");
   if (energy) {
@@ -89,10 +101,16 @@ jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy, hip
 template <typename T>
 jgb_status run_energy(Plan& pl, const void* rho, double* energy) {
   hipError_t e;
-  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
+  jgb_status c = run_forward<T>(pl, rho, pl.stream);
+  if (c != JGB_OK) return c;
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_ENERGY, nullptr, pl.stream)) != hipSuccess)
     return from_hip(e, "interpolation");
   int nb = jgb::interp_blocks(pl);
+  if (pl.split) {
+    // I1's share, sum_q M'(q) |rho^(k_q)|^2, as partials after the interpolation's
+    if ((e = jgb::launch_split_symbol<T>(pl, 1, nb, pl.stream)) != hipSuccess) return from_hip(e, "split energy");
+    nb += pl.nsym_blocks;
+  }
   jgb::stage_mark(pl, jgb::ST_ENERGY, 0, pl.stream);
   e = jgb::launch_energy_finalize(pl.d_eparts, nb, 0.5 * pl.p.lambda, energy, pl.stream);
   jgb::stage_mark(pl, jgb::ST_ENERGY, 1, pl.stream);
@@ -104,7 +122,8 @@ jgb_status run_energy(Plan& pl, const void* rho, double* energy) {
 template <typename T>
 jgb_status run_transform(Plan& pl, const void* rho, void* out) {
   hipError_t e;
-  if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, pl.stream)) != hipSuccess) return from_hip(e, "forward FFT");
+  jgb_status c = run_forward<T>(pl, rho, pl.stream);
+  if (c != JGB_OK) return c;
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_TRANSFORM, out, pl.stream)) != hipSuccess)
     return from_hip(e, "interpolation");
   jgb::call_done(pl);
@@ -474,6 +493,9 @@ jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info) {
   info->width = pl.width;
   info->beta = pl.beta;
   info->kmax = pl.K;
+  info->flags = pl.p.flags;
+  info->window[0] = pl.split ? pl.win[0] : 0.0;
+  info->window[1] = pl.split ? pl.win[1] : 0.0;
   info->workspace_bytes = (int64_t)pl.workspace_bytes;
   info->interp_chunk = pl.interp_chunk;
   info->spread_chunk = pl.spread_chunk;

@@ -70,7 +70,7 @@ struct WorkItem {
 
 enum Stage {
   ST_FWD_Z = 0, ST_FWD_Y, ST_FWD_X, ST_INTERP, ST_SPREAD, ST_SPREAD_REDUCE,
-  ST_INV_X, ST_INV_Y, ST_INV_Z, ST_ENERGY, ST_COUNT
+  ST_INV_X, ST_INV_Y, ST_INV_Z, ST_ENERGY, ST_SPLIT_UNMIX, ST_SPLIT_SYMBOL, ST_COUNT
 };
 
 // Event ring for per-stage timing (see jgb_timing_begin).
@@ -158,6 +158,18 @@ struct Plan {
   double* d_eparts = nullptr;  // energy partials
   int neparts = 0;
 
+  // Algorithm 2 (JGB_FLAG_SPLIT).  The forward FFT transforms rho H / phi^ +
+  // i rho H in one go; G's touched tiles first receive the part the
+  // interpolation needs, then the spreading result; F receives the combined
+  // spectrum that the inverse FFT turns into Re = I2 phi^ and Im = I1.
+  bool split = false;
+  double win[2] = {0.0, 0.0};      // 3D: (a, 0); 2D: (R0, R1)
+  int* d_touched = nullptr;        // gather tiles some node touches
+  int ntouched = 0;
+  unsigned char* d_tflag = nullptr;  // per gather tile: 1 if touched
+  double* d_splitk = nullptr;      // per internal axis a: k_a(q) for q < nf_a, then exp(-k_a(q)^2 / a)
+  int nsym_blocks = 0;             // blocks of the symbol kernel (also its energy partials)
+
   size_t workspace_bytes = 0;
   std::vector<void*> allocations;
 };
@@ -211,6 +223,13 @@ hipError_t launch_density(const Plan& pl, const void* psi, void* rho, hipStream_
 template <typename T>
 hipError_t launch_psi_gradient(const Plan& pl, const void* psi, const void* u, const double* gscale, double factor,
                                void* grad, hipStream_t s);
+// Algorithm 2: the tiles of G the interpolation reads get the transform of
+// rho H / phi^ alone; then the regular-grid symbol of I1 (mode 0: written into
+// F with the Hermitian part of G; mode 1: energy partials at d_eparts + eoff)
+template <typename T>
+hipError_t launch_split_unmix(const Plan& pl, hipStream_t s);
+template <typename T>
+hipError_t launch_split_symbol(const Plan& pl, int energy_mode, int eoff, hipStream_t s);
 int fft_inverse_z_blocks(const Plan& pl);
 int interp_blocks(const Plan& pl);
 hipError_t interp_prepare(const Plan& pl);

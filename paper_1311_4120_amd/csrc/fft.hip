@@ -17,6 +17,11 @@
 //     X: G  -> B2 [N0][nf1][nf2]
 //     Y: B2 -> B1 [N0][N1][nf2]
 //     Z: B1 -> u = Re(.) / (phi^0 phi^1 phi^2), and partial sums of rho u
+//
+// Algorithm 2 (JGB_FLAG_SPLIT) changes three things: the forward Z pass also
+// places rho H in the imaginary part (two real transforms in one complex
+// one), the inverse starts from F, which then holds the combined spectrum of
+// both halves, and the last pass adds the imaginary part (I1) to u.
 #include <cmath>
 
 #include "common.h"
@@ -151,6 +156,7 @@ struct PassArgs {
   int n1, n2;         // physical grid sizes of axes 1 and 2 (Z passes)
   const T* rho;       // inverse Z: density for the energy partial (nullable)
   double* eparts;     // inverse Z: per-block partials of sum rho u
+  int split;          // Z passes of Algorithm 2: forward imag = rho H; inverse u += imag
 };
 
 // Position on the fine grid of physical index i of a line of N: (i - N/2) mod L.
@@ -291,6 +297,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
         if constexpr (KIND == PASS_FWD_Z) {
           // deconvolution and cell volume, applied in float64
           const double d = fline[le[i] >> 16] * felem[le[i] & 0xffff];
+          if (a.split) v.y = (T)((double)v.x * a.scale);
           v.x = (T)((double)v.x * d);
         }
         lds[dst[i]] = v;
@@ -365,7 +372,8 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
       const int lo = (int)a.dic.div(line);
       const int64_t base = (int64_t)lo * a.out_os + (int64_t)(line - lo * (int)a.ic) * a.out_is + (int64_t)e * a.out_es;
       if constexpr (KIND == PASS_INV_Z) {
-        const double u = (double)buf[i].x * (fline[l] * felem[e]);
+        double u = (double)buf[i].x * (fline[l] * felem[e]);
+        if (a.split) u += (double)buf[i].y;
         ((T*)a.out)[base] = (T)u;
         eacc += (double)rho_v[i] * u;
       } else {
@@ -504,6 +512,7 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
     a.dec1 = pl.d_deconv[1];
     a.dec2 = pl.d_deconv[2];
     a.scale = pl.H;
+    a.split = pl.split ? 1 : 0;
     if ((e = run_pass<T, PASS_FWD_Z>(pl, ST_FWD_Z, a, s)) != hipSuccess) return e;
   }
   {  // Y: A1 -> A2 [n0][f1][f2]
@@ -548,10 +557,14 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
   const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
   const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
   const bool has_x = f0 > 1;
-  void* B2 = has_x ? pl.d_F : pl.d_G;  // (2D: the input grid itself)
+  // the input spectrum: the spreading grid, or F holding both halves of
+  // Algorithm 2; the X pass may run in place on F (each block reads all of its
+  // lines before it writes them back, and no two blocks share a line)
+  void* src = pl.split ? pl.d_F : pl.d_G;
+  void* B2 = has_x ? pl.d_F : src;  // (2D: the input grid itself)
   void* B1 = pl.d_W;
   hipError_t e;
-  if (has_x) {  // X: G -> B2 [n0][f1][f2]
+  if (has_x) {  // X: src -> B2 [n0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 0, T(1));
     a.nlines = f1 * f2;
     a.nin = (int)f0;
@@ -564,7 +577,7 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.out_is = 1;
     a.out_es = f1 * f2;
     a.lines_fastest = 1;
-    a.in = pl.d_G;
+    a.in = src;
     a.out = B2;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_X, a, s)) != hipSuccess) return e;
   }
@@ -605,6 +618,7 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.dec2 = pl.d_deconv[2];
     a.rho = rho_for_energy;
     a.eparts = rho_for_energy ? pl.d_eparts : nullptr;
+    a.split = pl.split ? 1 : 0;
     if ((e = run_pass<T, PASS_INV_Z>(pl, ST_INV_Z, a, s)) != hipSuccess) return e;
   }
   return hipSuccess;

@@ -330,7 +330,8 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.hdr = pl.nodes.hdr;
   a.coef = pl.nodes.coef;
   a.perm = pl.nodes.perm;
-  a.F = (const C2<T>*)pl.d_F;
+  // Algorithm 2: the type-2 spectrum was separated into G's touched tiles
+  a.F = (const C2<T>*)(pl.split ? pl.d_G : pl.d_F);
   a.mode = mode;
   a.uhat = (C2<T>*)pl.nodes.uhat;
   a.wts = (const T*)pl.nodes.wts;

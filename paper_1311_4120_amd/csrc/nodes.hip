@@ -15,6 +15,10 @@
 // (r, pi - theta, phi + pi) equals -k, carries the same weight and symbol, and
 // its transform is the complex conjugate for real rho.  The half set is
 // {phi index l < N_phi/2} and its coefficients carry the factor 2.
+//
+// For Algorithm 2 (JGB_FLAG_SPLIT) the coefficients also carry the window
+// p(k) of I2: exp(-|k|^2 / a) in 3D (eq. 3.10), erfc(12 (|k| - (R0 + R1)/2) /
+// (R1 - R0)) / 2 in 2D (eq. 3.12).
 #include <cmath>
 
 #include "common.h"
@@ -25,7 +29,9 @@ namespace {
 
 struct NodeParams {
   int dim, n_r, n_theta, n_phi, rule, kernel, width, rstride;
+  int split;       // multiply c_j by the window of Algorithm 2
   double K, beta;
+  double win[2];   // 3D: (a, 0); 2D: (R0, R1)
   double axis[3];
   double box[3];  // physical side lengths per internal axis (unit axis: 0)
   int nf[3], w[3], T[3], nt[3], S[3];
@@ -45,6 +51,9 @@ NodeParams make_params(const Plan& pl) {
   q.rstride = record_stride(pl.width);
   q.K = pl.K;
   q.beta = pl.beta;
+  q.split = pl.split ? 1 : 0;
+  q.win[0] = pl.win[0];
+  q.win[1] = pl.win[1];
   for (int i = 0; i < 3; ++i) q.axis[i] = pl.p.dipole_axis[i];
   for (int i = 0; i < 3; ++i) {
     q.box[i] = (pl.n[i] == 1) ? 0.0 : pl.box[i];
@@ -149,6 +158,14 @@ __device__ double symbol(const NodeParams& q, const double k[3]) {
   return 1.0;
 }
 
+// The window p(k) of Algorithm 2 (1 without JGB_FLAG_SPLIT).
+__device__ double window(const NodeParams& q, const double k[3]) {
+  if (!q.split) return 1.0;
+  const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+  if (q.dim == 3) return exp(-kk / q.win[0]);
+  return 0.5 * erfc(12.0 * (sqrt(kk) - 0.5 * (q.win[0] + q.win[1])) / (q.win[1] - q.win[0]));
+}
+
 __device__ void half_node(const NodeParams& q, int64_t h, double k[3], double& W) {
   int nph2 = q.n_phi / 2;
   int l = (int)(h % nph2);
@@ -228,7 +245,7 @@ __global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int4* hd
   f2[p] = (T)frac[2];
   double twopi_d = (q.dim == 3) ? 8.0 * M_PI * M_PI * M_PI : 4.0 * M_PI * M_PI;
   // factor 2: the node stands for itself and for -k (conjugate transform, same c)
-  coef[p] = 2.0 * W * symbol(q, k) / twopi_d;
+  coef[p] = 2.0 * W * symbol(q, k) * window(q, k) / twopi_d;
   T* rec = wts + p * q.rstride;
   for (int ax = 0; ax < 3; ++ax) {
     const int w = q.w[ax];
@@ -259,7 +276,7 @@ __global__ void k_node_export(NodeParams q, int64_t M, double* kout, double* wou
   if (wout) wout[j] = W;
   if (cout) {
     double twopi_d = (q.dim == 3) ? 8.0 * M_PI * M_PI * M_PI : 4.0 * M_PI * M_PI;
-    cout[j] = W * symbol(q, k) / twopi_d;
+    cout[j] = W * symbol(q, k) * window(q, k) / twopi_d;
   }
 }
 

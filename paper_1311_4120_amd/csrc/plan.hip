@@ -382,7 +382,19 @@ Status validate(const jgb_params* p) {
   double kn = M_PI / hmax;
   if (!(std::isfinite(p->kmax) && p->kmax >= 0)) return fail(JGB_ERR_INVALID_ARG, "kmax must be finite and >= 0");
   if (p->kmax > kn * (1 + 1e-12)) return fail(JGB_ERR_INVALID_ARG, "kmax must not exceed pi / max_j h_j");
-  if (p->flags & ~JGB_FLAG_AUTOTUNE) return fail(JGB_ERR_INVALID_ARG, "unknown flags");
+  if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT)) return fail(JGB_ERR_INVALID_ARG, "unknown flags");
+  for (int i = 0; i < 2; ++i)
+    if (!std::isfinite(p->window[i])) return fail(JGB_ERR_INVALID_ARG, "window must be finite");
+  if (!(p->flags & JGB_FLAG_SPLIT)) {
+    if (p->window[0] != 0.0 || p->window[1] != 0.0) return fail(JGB_ERR_INVALID_ARG, "window needs JGB_FLAG_SPLIT");
+  } else if (p->dim == 3) {
+    if (p->window[0] < 0.0 || p->window[1] != 0.0)
+      return fail(JGB_ERR_INVALID_ARG, "3D window: window[0] = a >= 0 (0: default), window[1] = 0");
+  } else {
+    const bool dflt = p->window[0] == 0.0 && p->window[1] == 0.0;
+    if (!dflt && !(p->window[0] > 0.0 && p->window[1] > p->window[0]))
+      return fail(JGB_ERR_INVALID_ARG, "2D window: {R0, R1} with 0 < R0 < R1, or {0, 0}");
+  }
   int64_t M = (int64_t)p->n_r * p->n_phi * (p->dim == 3 ? p->n_theta : 1);
   if (M / 2 > (int64_t)std::numeric_limits<int>::max() / 2) return fail(JGB_ERR_UNSUPPORTED, "too many nodes");
   int ndev = 0;
@@ -439,6 +451,26 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     hmax = std::max(hmax, pl.h[i]);
   }
   pl.K = (p->kmax > 0) ? p->kmax : M_PI / hmax;
+  pl.split = (p->flags & JGB_FLAG_SPLIT) != 0;
+  if (pl.split) {
+    // Algorithm 2's window in units of the box's Fourier spacing dk = 2 pi /
+    // max_j R_j (remarks after eqs. 3.10 and 3.12), and I2's ball: up to where
+    // the window is below 5e-18 (3D: exp(-40)) or 1.1e-17 (2D: erfc(6)/2)
+    double rmax = 0;
+    for (int i = 0; i < 3; ++i)
+      if (pl.n[i] > 1) rmax = std::max(rmax, pl.box[i]);
+    const double dk = 2.0 * M_PI / rmax;
+    if (pl.dim == 3) {
+      pl.win[0] = (p->window[0] > 0) ? p->window[0] : 2.0 * dk * dk;
+      pl.win[1] = 0.0;
+      if (p->kmax <= 0) pl.K = std::min(M_PI / hmax, std::sqrt(40.0 * pl.win[0]));
+    } else {
+      const bool dflt = p->window[0] == 0.0 && p->window[1] == 0.0;
+      pl.win[0] = dflt ? 0.8 * dk : p->window[0];
+      pl.win[1] = dflt ? 10.0 * dk : p->window[1];
+      if (p->kmax <= 0) pl.K = std::min(M_PI / hmax, pl.win[1]);
+    }
+  }
   accuracy_parameters(p->eps, pl.width, pl.beta);
   for (int i = 0; i < 3; ++i) pl.w[i] = (pl.n[i] == 1) ? 1 : pl.width;
   pl.n_r = p->n_r;
@@ -666,7 +698,42 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   // only the spreading writes G, and only tiles some node touches: the others
   // are cleared here once
   TRY_HIP(hipMemsetAsync(pl.d_G, 0, ngrid * 2 * pl.real_bytes, pl.stream), "clear spreading grid");
-  pl.neparts = std::max(fft_inverse_z_blocks(pl), pl.iitems_cap);
+  if (pl.split) {
+    // gather tiles some node touches: the interpolation reads only these, the
+    // spreading writes only these
+    std::vector<int> tl;
+    std::vector<unsigned char> tf(pl.ngtiles, 0);
+    for (int t = 0; t < pl.ngtiles; ++t)
+      if (pl.h_tcount[t + 1] > pl.h_tcount[t]) {
+        tl.push_back(t);
+        tf[t] = 1;
+      }
+    pl.ntouched = (int)tl.size();
+    TRY(dev_alloc(pl, &pl.d_touched, sizeof(int) * std::max<size_t>(tl.size(), 1)));
+    if (!tl.empty()) TRY(upload(pl, pl.d_touched, tl.data(), sizeof(int) * tl.size()));
+    TRY(dev_alloc(pl, &pl.d_tflag, (size_t)pl.ngtiles));
+    TRY(upload(pl, pl.d_tflag, tf.data(), (size_t)pl.ngtiles));
+    // per axis: the regular grid's frequencies k_q = 2 pi q' / (2 R), q' the
+    // signed index, and exp(-k_q^2 / a) (3D; 1 in 2D)
+    std::vector<double> kt;
+    for (int a = 0; a < 3; ++a) {
+      const int L = pl.nf[a];
+      std::vector<double> kv(L, 0.0), ev(L, 1.0);
+      if (pl.n[a] > 1)
+        for (int q = 0; q < L; ++q) {
+          const int sq = (q < L / 2) ? q : q - L;
+          kv[q] = 2.0 * M_PI * sq / (2.0 * pl.box[a]);
+          if (pl.dim == 3) ev[q] = std::exp(-kv[q] * kv[q] / pl.win[0]);
+        }
+      kt.insert(kt.end(), kv.begin(), kv.end());
+      kt.insert(kt.end(), ev.begin(), ev.end());
+    }
+    TRY(dev_alloc(pl, &pl.d_splitk, sizeof(double) * kt.size()));
+    TRY(upload(pl, pl.d_splitk, kt.data(), sizeof(double) * kt.size()));
+    const int64_t npts = (int64_t)(pl.nf[0] / 2 + 1) * pl.nf[1] * pl.nf[2];
+    pl.nsym_blocks = (int)std::min<int64_t>((npts + 255) / 256, 4096);
+  }
+  pl.neparts = std::max(fft_inverse_z_blocks(pl), pl.iitems_cap + pl.nsym_blocks);
   pl.neparts = std::max(pl.neparts, 1);
   TRY(dev_alloc(pl, &pl.d_eparts, sizeof(double) * pl.neparts));
   TRY_HIP(interp_prepare(pl), "interpolation LDS limit");

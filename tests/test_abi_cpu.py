@@ -46,6 +46,7 @@ def test_struct_layouts_match_c(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "jgb.h"\n'
                    'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(jgb_params), sizeof(jgb_info),'
                    ' offsetof(jgb_params, stream), offsetof(jgb_params, kmax), offsetof(jgb_info, workspace_bytes));'
+                   'printf("%zu %zu\\n", offsetof(jgb_params, window), offsetof(jgb_info, window));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -55,6 +56,8 @@ def test_struct_layouts_match_c(tmp_path):
     assert vals[2] == L.Params.stream.offset
     assert vals[3] == L.Params.kmax.offset
     assert vals[4] == L.Info.workspace_bytes.offset
+    assert vals[5] == L.Params.window.offset
+    assert vals[6] == L.Info.window.offset
 
 
 def _params(**kw):
@@ -77,7 +80,7 @@ def _params(**kw):
     p.stream = None
     p.flags = 0
     for k, v in kw.items():
-        if k in ("n", "box", "dipole_axis"):
+        if k in ("n", "box", "dipole_axis", "window"):
             for i, x in enumerate(v):
                 getattr(p, k)[i] = x
         else:
@@ -107,6 +110,13 @@ BAD = [
     ("theta rule", dict(theta_rule=5), 1),
     ("kmax too large", dict(kmax=100.0), 1),
     ("flags", dict(flags=6), 1),
+    ("window without split", dict(window=(1.0, 0.0)), 1),
+    ("window nan", dict(flags=2, window=(float("nan"), 0.0)), 1),
+    ("3D window[1]", dict(flags=2, window=(1.0, 2.0)), 1),
+    ("3D negative a", dict(flags=2, window=(-1.0, 0.0)), 1),
+    ("2D R0 >= R1", dict(flags=2, dim=2, kernel=1, window=(2.0, 1.0)), 1),
+    ("2D R0 = 0", dict(flags=2, dim=2, kernel=1, window=(0.0, 1.0)), 1),
+    ("split kmax too large", dict(flags=2, kmax=100.0), 1),
 ]
 
 
@@ -145,10 +155,12 @@ def test_valid_parameters_without_gpu_report_device_error():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     L = _lib()
-    p = _params()
-    h = ctypes.c_void_p()
-    assert L.lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)) == L.JGB_ERR_DEVICE
-    assert not h.value
+    for kw in (dict(), dict(flags=L.FLAG_SPLIT), dict(flags=L.FLAG_SPLIT, window=(0.7, 0.0)),
+               dict(flags=L.FLAG_SPLIT, dim=2, kernel=L.COULOMB_2D, window=(0.3, 4.0))):
+        p = _params(**kw)
+        h = ctypes.c_void_p()
+        assert L.lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)) == L.JGB_ERR_DEVICE, kw
+        assert not h.value
 
 
 def test_package_refuses_to_run_without_library(tmp_path, monkeypatch):

@@ -8,7 +8,8 @@
     Gaussian mixture (eq. 4.2), Example 4 (Coulomb) and Example 5 (dipole);
   * invariance: u does not depend on where the window splits the integral,
     while I1 and I2 individually do;
-  * agreement with Algorithm 1 at a node set that resolves the full integral.
+  * agreement with Algorithm 1 at a node set that resolves the full integral;
+  * the Fourier-side energy equals the physical-side one.
 """
 import json
 import os
@@ -161,6 +162,23 @@ def test_example5_dipole_closed_form():
     u3, _, _, _ = split.potential_split(wl.Problem("s5", 3, n, box, wl.DIPOLE_3D, 32, 32, 32,
                                                    axis=(0.0, 0.0, 1.0)), rho)
     assert rel(u3, u) > 1e-2
+
+
+@pytest.mark.parametrize("kernel,shape,box", [
+    (wl.COULOMB_3D, (12, 10, 8), (6.0, 5.0, 4.0)),
+    (wl.DIPOLE_3D, (10, 12, 8), (5.0, 6.0, 4.0)),
+    (wl.COULOMB_2D, (24, 20), (8.0, 6.0)),
+])
+def test_fourier_side_energy_equals_physical_side(kernel, shape, box):
+    """Substituting eq. 3.2 into H sum rho u gives the Fourier form exactly."""
+    rng = np.random.default_rng(29)
+    mix = wl.random_mixture(rng, 3, len(shape), -1.0, 1.0, 0.6, 0.9)
+    rho = mix.evaluate(shape, box)
+    axis = tuple(wl.unit_vector(rng)) if kernel == wl.DIPOLE_3D else (0.0, 0.0, 1.0)
+    q = wl.Problem("ef", len(shape), shape, box, kernel, 10, 8, 12, axis=axis, lam=1.7)
+    _, _, _, E = split.potential_split(q, rho)
+    Ef = split.energy_split_fourier(q, rho)
+    assert abs(Ef - E) < 1e-13 * abs(E)
 
 
 # ------------------------------------------------------------- invariance
