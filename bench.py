@@ -144,7 +144,7 @@ def run_gpu(prec, steps, warmup, nodes="pattern"):
     t0 = time.time()
     plan = jgb.Plan(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), eps=p.eps, precision=prec,
                     lam=p.lam, axis=p.axis, theta_rule="theta" if p.theta_rule == wl.THETA_GL else "costheta",
-                    autotune=True)
+                    autotune=True, split=(nodes == "split"))
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     rt = torch.tensor(rho, dtype=dt, device="cuda")
@@ -219,6 +219,25 @@ def run_resolved(steps, warmup):
         out[prec] = {"nodes": nodes, "n_nodes": r["info"]["n_nodes"], "eps": r["eps"], "ms_per_step": r["ms_per_step"],
                      "evals_per_s": 1e3 / r["ms_per_step"], "ns_per_point": r["ms_per_step"] * 1e6 / 128 ** 3,
                      "stages_ms": {k: v for k, v in r["stages_ms"].items() if v > 0}}
+    return out
+
+
+def run_algorithm2(steps, warmup, resolved=None, precs=("fp64", "mixed")):
+    """The same 128^3 dipole evaluation by Algorithm 2 (the partition-of-unity
+    split of Section 3.3) at the default window and I2 cut-off, with I2's node
+    sets matched to the accuracy of the resolved Algorithm 1 sets."""
+    out = {"workload": "dipole3d_128 by Algorithm 2, accuracy-matched I2 nodes"}
+    for prec, nodes in (("fp64", [28, 20, 40]), ("mixed", [20, 16, 32])):
+        if prec not in precs:
+            continue
+        r = run_gpu(prec, steps, warmup, nodes="split")
+        d = {"nodes": nodes, "n_nodes": r["info"]["n_nodes"], "kmax_I2": r["info"]["kmax"],
+             "window_a": r["info"]["window"][0], "eps": r["eps"], "ms_per_step": r["ms_per_step"],
+             "evals_per_s": 1e3 / r["ms_per_step"], "ns_per_point": r["ms_per_step"] * 1e6 / 128 ** 3,
+             "energy": r["energy"], "stages_ms": {k: v for k, v in r["stages_ms"].items() if v > 0}}
+        if resolved and prec in resolved:
+            d["speedup_vs_algorithm1_resolved"] = resolved[prec]["ms_per_step"] / r["ms_per_step"]
+        out[prec] = d
     return out
 
 
@@ -318,6 +337,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--algorithm2-only", action="store_true",
+                    help="only time the 128^3 dipole by Algorithm 2 and print its object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -328,6 +349,10 @@ def main():
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.algorithm2_only:
+        print(json.dumps(run_algorithm2(args.steps, args.warmup,
+                                        precs=("fp64", "mixed") if args.only is None else (args.only,))))
+        return
 
     res = {}
     for prec in (["fp64", "mixed"] if args.only is None else [args.only]):
@@ -391,6 +416,8 @@ def main():
         out["batched"] = run_batched(max(3, args.steps // 10), 2)
         print("[bench] dipole3d_128 with accuracy-matched node sets", file=sys.stderr, flush=True)
         out["resolved"] = run_resolved(max(3, args.steps // 5), 2)
+        print("[bench] dipole3d_128 by Algorithm 2", file=sys.stderr, flush=True)
+        out["algorithm2"] = run_algorithm2(max(3, args.steps // 2), 3, out["resolved"])
         print("[bench] dipole_grad_256: forward + backward", file=sys.stderr, flush=True)
         out["grad_256"] = run_grad256(max(3, args.steps // 10), 2)
         print("[bench] FFT passes against rocFFT", file=sys.stderr, flush=True)

@@ -184,12 +184,18 @@ def dipole3d_128(precision=FP64, seed=3, nodes="pattern"):
 
     nodes="pattern": (128,64,128) with the theta Gauss-Legendre rule, identical work in
     both precisions; nodes="resolved": the accuracy-matched cos(theta)-rule sets,
-    (256,128,256) in float64 (eps 1e-10) and (192,96,192) in mixed precision (eps 1e-5)."""
+    (256,128,256) in float64 (eps 1e-10) and (192,96,192) in mixed precision (eps 1e-5);
+    nodes="split": the node sets of I2 in Algorithm 2 at the default window and
+    cut-off (kmax = 0), matched to the same accuracies: (28,20,40) cos(theta) in
+    float64 (1.5e-11 from the converged potential) and (20,16,32) in mixed
+    precision (1.8e-6)."""
     rng = np.random.default_rng(seed)
     axis = tuple(unit_vector(rng, 3))
     eps = 1e-10 if precision == FP64 else 1e-5
     if nodes == "pattern":
         nr, nt, nph, rule = 128, 64, 128, THETA_GL
+    elif nodes == "split":
+        nr, nt, nph, rule = (28, 20, 40, COSTHETA_GL) if precision == FP64 else (20, 16, 32, COSTHETA_GL)
     elif precision == FP64:
         nr, nt, nph, rule = 256, 128, 256, COSTHETA_GL
     else:
