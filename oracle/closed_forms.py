@@ -7,6 +7,23 @@ Sources (all in the paper's notation):
     (sqrt(pi a)/2) exp(-r^2/2a) I0(r^2/2a).
   * Example 4: rho of eq. 4.10 has Coulomb potential -exp(-g).
   * Example 5: dipole potential -rho + 6 [2 g_n^2 - sum n_i^2/a_i] exp(-g).
+  * Example 6 (eq. 4.15), two orientations n, m: -(m.n) rho + 6 [2 g_n g_m -
+    sum n_i m_i/a_i] exp(-g).  The printed formula has -rho for the first term;
+    the delta term of eq. dipkerneld is -(m.n) delta, and -u_Cou = exp(-g)
+    gives the rest (3 d_n d_m exp(-g)), so the coefficient is read as -(m.n),
+    which reduces to Example 5's -rho when m = n.
+  * Examples 2 and 3 (eq. 4.5 and the formula after it): the 2.5D dipole
+    potential of exp(-|x|^2/a) for U^ = 3 (n_p.k)(m_p.k) / (2|k|).  The printed
+    formulas are (3 sqrt(pi) e^{-r} / (4 sqrt a)) [(n_p.m_p)(I1 - I0) +
+    (x.n_p)(x.m_p)/a (2 I0 - (1 + 2r) I1 / r)], r = |x|^2/(2a), with the opposite
+    overall sign to the potential of the kernel as defined (eqs. dipkernel2d and
+    dipkernelF2d agree with each other): U^ >= 0 and rho^ > 0 make u(0) > 0,
+    and -(3/2) d_nn of eq. 4.2's potential at 0 is +3 sqrt(pi) / (4 sqrt a),
+    while the printed bracket is -1 there.  The kernel's sign is kept and the
+    printed formula negated.  Symbol and formula are both bilinear in
+    (n_p, m_p), so the formula holds for any in-plane vectors; with it, the
+    n_3 m_3 term -(3/2) n_3 m_3 |k| = -n_3 m_3 [S(e1,e1) + S(e2,e2)] and the
+    -alpha delta term (-alpha rho) give the general 2.5D dipole.
   * Example 7: dipole energy of an anisotropic normalised Gaussian, with the
     three printed exact values.
   * Gaussian-mixture energies: the autocorrelation of two Gaussians is a
@@ -16,7 +33,7 @@ Sources (all in the paper's notation):
 from __future__ import annotations
 
 import numpy as np
-from scipy.special import erf, i0e
+from scipy.special import erf, i0e, i1e
 
 # Example 7 exact energies as printed (lambda = 8 pi / 3, n = z-axis).
 EXAMPLE7_PRINTED = {
@@ -101,3 +118,41 @@ def example7_energy(gx, gz, lam):
         return pref * (base - 3.0 * kap2 * np.arctan(s) / ((1.0 - kap2) * s))
     s = np.sqrt(1.0 - kap2)
     return pref * (base - 3.0 * kap2 / (2.0 * (1.0 - kap2) * s) * np.log((1.0 + s) / (1.0 - s)))
+
+
+def example6_potential(X, a, n, m, rho):
+    """Dipole potential (two orientations) of the eq. 4.10 density rho, -u_Cou = exp(-g)."""
+    g = sum(Xi ** 2 / ai for Xi, ai in zip(X, a))
+    gn = sum(Xi * ni / ai for Xi, ni, ai in zip(X, n, a))
+    gm = sum(Xi * mi / ai for Xi, mi, ai in zip(X, m, a))
+    c = sum(ni * mi / ai for ni, mi, ai in zip(n, m, a))
+    return -float(np.dot(n, m)) * rho + 6.0 * (2.0 * gn * gm - c) * np.exp(-g)
+
+
+def _dipole25_part(X, a, npv, mpv):
+    """Potential of exp(-|x|^2/a) for U^ = 3 (n_p.k)(m_p.k)/(2|k|): Examples 2 and 3,
+    with the sign of the kernel (the printed formulas negated)."""
+    x, y = X
+    r = (x * x + y * y) / (2.0 * a)
+    e0, e1 = i0e(r), i1e(r)
+    small = r < 1e-6
+    rs = np.where(small, 1.0, r)
+    # e^{-r} I1(r)/r -> 1/2 - r/2 + ... as r -> 0
+    e1_over_r = np.where(small, 0.5 - 0.5 * r, e1 / rs)
+    xn = x * npv[0] + y * npv[1]
+    xm = x * mpv[0] + y * mpv[1]
+    nm = npv[0] * mpv[0] + npv[1] * mpv[1]
+    return -3.0 * np.sqrt(np.pi) / (4.0 * np.sqrt(a)) * (nm * (e1 - e0) + xn * xm / a * (2.0 * e0 - (1.0 + 2.0 * r) * e1_over_r))
+
+
+def dipole25_potential(X, a, n, m=None, alpha=0.0):
+    """2.5D dipole potential of rho = exp(-|x|^2/a) for n, m unit 3-vectors and alpha
+    (eqs. dipkernelF2d, dipkernelF2dd): Examples 2 and 3 extended by bilinearity."""
+    n = np.asarray(n, dtype=np.float64)
+    m = n if m is None else np.asarray(m, dtype=np.float64)
+    x, y = X
+    rho = np.exp(-(x * x + y * y) / a)
+    u = _dipole25_part(X, a, n[:2], m[:2])
+    if n[2] * m[2] != 0.0:
+        u = u - n[2] * m[2] * (_dipole25_part(X, a, (1.0, 0.0), (1.0, 0.0)) + _dipole25_part(X, a, (0.0, 1.0), (0.0, 1.0)))
+    return u - alpha * rho

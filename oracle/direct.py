@@ -134,18 +134,18 @@ def energy_physical(rho, u, box, lam):
     return 0.5 * lam * _cell_volume(rho.shape, box) * float(np.sum(rho * u))
 
 
-def potential(rho, box, kernel, k, W, axis=None):
+def potential(rho, box, kernel, k, W, axis=None, axis2=None, alpha=0.0):
     """u = Re sum_j c_j rho^_j exp(i k_j.x_n); returns (u, rho^, c, max|Im|)."""
-    c = coefficients(kernel, k, W, axis)
+    c = coefficients(kernel, k, W, axis, axis2, alpha)
     rh = rho_hat(rho, box, k)
     f = sum_to_grid(c * rh, k, rho.shape, box)
     return f.real.copy(), rh, c, float(np.max(np.abs(f.imag))) if f.size else 0.0
 
 
-def apply_operator(g, box, kernel, k, W, axis=None):
+def apply_operator(g, box, kernel, k, W, axis=None, axis2=None, alpha=0.0):
     """A g with A_{nl} = H Re sum_j c_j exp(i k_j.(x_n - x_l)); A is symmetric, so this is
     also the vector-Jacobian product of u with respect to rho."""
-    return potential(np.asarray(g, dtype=np.float64), box, kernel, k, W, axis)[0]
+    return potential(np.asarray(g, dtype=np.float64), box, kernel, k, W, axis, axis2, alpha)[0]
 
 
 def energy_gradient_rho(u, box, lam):
@@ -174,7 +174,7 @@ def evaluate(problem, rho):
     """Full oracle evaluation of a workloads.Problem on density rho (FP64)."""
     rho = np.asarray(rho, dtype=np.float64)
     k, W = fourier_nodes(problem)
-    u, rh, c, im = potential(rho, problem.box, problem.kernel, k, W, problem.axis)
+    u, rh, c, im = potential(rho, problem.box, problem.kernel, k, W, problem.axis, problem.axis2, problem.alpha)
     return Result(u=u,
                   energy_physical=energy_physical(rho, u, problem.box, problem.lam),
                   energy_fourier=energy_fourier(c, rh, problem.lam),

@@ -91,20 +91,20 @@ def grid_frequencies(n, box, sigma=SIGMA):
     return out
 
 
-def split_symbol(kernel, k, par, axis=None):
+def split_symbol(kernel, k, par, axis=None, axis2=None, alpha=0.0):
     """M(k) = (1 - p(k)) U^(k) at frequency vectors k (rows), with the k = 0 limits."""
     k = np.asarray(k, dtype=np.float64)
     d = k.shape[1]
     k2 = np.einsum("ij,ij->i", k, k)
     kabs = np.sqrt(k2)
     omp = one_minus_window(kabs, d, par)
-    S = symbol(kernel, k, axis)                     # |k|^{d-1} U^
+    S = symbol(kernel, k, axis, axis2, alpha)       # |k|^{d-1} U^
     zero = k2 == 0.0
     den = np.where(zero, 1.0, kabs ** (d - 1))
     M = omp * S / den
     if kernel == COULOMB_3D:
         M[zero] = 1.0 / par["a"]
-    else:                                           # dipole: (1-p) -> 0, U^ bounded; 2D: reading above
+    else:                                           # dipoles: (1-p) -> 0, U^ bounded; 2D: reading above
         M[zero] = 0.0
     return M
 
@@ -115,12 +115,12 @@ def _grid_k(n, box, sigma=SIGMA):
     return np.stack([m.ravel() for m in mesh], axis=1), [len(v) for v in ks]
 
 
-def i1_fft(rho, box, kernel, par, axis=None, sigma=SIGMA):
+def i1_fft(rho, box, kernel, par, axis=None, sigma=SIGMA, axis2=None, alpha=0.0):
     """I1 on the grid by the padded FFT convolution."""
     rho = np.asarray(rho, dtype=np.float64)
     n = rho.shape
     k, L = _grid_k(n, box, sigma)
-    M = split_symbol(kernel, k, par, axis).reshape(L)
+    M = split_symbol(kernel, k, par, axis, axis2, alpha).reshape(L)
     pad = np.zeros(L, dtype=np.float64)
     idx = np.ix_(*[np.arange(-(N // 2), N - N // 2) % Lj for N, Lj in zip(n, L)])
     pad[idx] = rho
@@ -132,31 +132,31 @@ def i1_fft(rho, box, kernel, par, axis=None, sigma=SIGMA):
     return conv[idx].real.copy()
 
 
-def i1_direct(rho, box, kernel, par, axis=None, sigma=SIGMA):
+def i1_direct(rho, box, kernel, par, axis=None, sigma=SIGMA, axis2=None, alpha=0.0):
     """The same trapezoid sum by the direct sums: weights (1/(sigma R_j))^d M(k_q)
     on the regular frequency grid, rho^(k_q) from eq. 3.2.  Small grids only."""
     rho = np.asarray(rho, dtype=np.float64)
     n = rho.shape
     k, _ = _grid_k(n, box, sigma)
     w = 1.0 / np.prod([sigma * float(R) for R in box])
-    M = split_symbol(kernel, k, par, axis)
+    M = split_symbol(kernel, k, par, axis, axis2, alpha)
     rh = rho_hat(rho, box, k)
     return sum_to_grid(w * M * rh, k, n, box).real.copy()
 
 
-def i2_coefficients(kernel, k, W, par, axis=None):
+def i2_coefficients(kernel, k, W, par, axis=None, axis2=None, alpha=0.0):
     d = k.shape[1]
     kabs = np.sqrt(np.einsum("ij,ij->i", k, k))
-    return W * symbol(kernel, k, axis) * window(kabs, d, par) / (2.0 * np.pi) ** d
+    return W * symbol(kernel, k, axis, axis2, alpha) * window(kabs, d, par) / (2.0 * np.pi) ** d
 
 
-def i1_energy(rho, box, kernel, par, axis=None, sigma=SIGMA):
+def i1_energy(rho, box, kernel, par, axis=None, sigma=SIGMA, axis2=None, alpha=0.0):
     """H sum_n rho_n I1_n in Fourier form: (prod_j sigma R_j)^{-1} sum_q M(k_q) |rho^(k_q)|^2
     (substitute eq. 3.2 into the trapezoid sum of I1; rho real)."""
     rho = np.asarray(rho, dtype=np.float64)
     n = rho.shape
     k, L = _grid_k(n, box, sigma)
-    M = split_symbol(kernel, k, par, axis).reshape(L)
+    M = split_symbol(kernel, k, par, axis, axis2, alpha).reshape(L)
     pad = np.zeros(L, dtype=np.float64)
     idx = np.ix_(*[np.arange(-(N // 2), N - N // 2) % Lj for N, Lj in zip(n, L)])
     pad[idx] = rho
@@ -173,11 +173,11 @@ def energy_split_fourier(problem, rho, par=None, rh=None):
     if problem.kmax <= 0:
         problem = dataclasses.replace(problem, kmax=default_cutoff(problem.n, problem.box, par))
     k, W = fourier_nodes(problem)
-    c = i2_coefficients(problem.kernel, k, W, par, problem.axis)
+    c = i2_coefficients(problem.kernel, k, W, par, problem.axis, problem.axis2, problem.alpha)
     if rh is None:
         rh = rho_hat(rho, problem.box, k)
     e2 = float(np.sum(c * np.abs(rh) ** 2))
-    e1 = i1_energy(rho, problem.box, problem.kernel, par, problem.axis)
+    e1 = i1_energy(rho, problem.box, problem.kernel, par, problem.axis, axis2=problem.axis2, alpha=problem.alpha)
     return 0.5 * problem.lam * (e1 + e2)
 
 
@@ -187,11 +187,11 @@ def potential_split(problem, rho, par=None):
     E = (lambda/2) H sum rho u (the energy remark)."""
     rho = np.asarray(rho, dtype=np.float64)
     par = default_window(problem.n, problem.box) if par is None else par
-    i1 = i1_fft(rho, problem.box, problem.kernel, par, problem.axis)
+    i1 = i1_fft(rho, problem.box, problem.kernel, par, problem.axis, axis2=problem.axis2, alpha=problem.alpha)
     if problem.kmax <= 0:
         problem = dataclasses.replace(problem, kmax=default_cutoff(problem.n, problem.box, par))
     k, W = fourier_nodes(problem)
-    c = i2_coefficients(problem.kernel, k, W, par, problem.axis)
+    c = i2_coefficients(problem.kernel, k, W, par, problem.axis, problem.axis2, problem.alpha)
     i2 = sum_to_grid(c * rho_hat(rho, problem.box, k), k, rho.shape, problem.box).real
     u = i1 + i2
     E = 0.5 * problem.lam * _cell_volume(rho.shape, problem.box) * float(np.sum(rho * u))

@@ -24,6 +24,7 @@ import numpy as np
 COULOMB_3D = 0
 COULOMB_2D = 1
 DIPOLE_3D = 2
+DIPOLE_2D = 3
 
 FP64 = 0
 MIXED = 1
@@ -149,6 +150,8 @@ class Problem:
     n_phi: int
     theta_rule: int = THETA_GL
     axis: Tuple[float, float, float] = (0.0, 0.0, 1.0)
+    axis2: Optional[Tuple[float, float, float]] = None   # second dipole orientation m (None: m = n)
+    alpha: float = 0.0                                   # the 2.5D dipole's -alpha delta term
     lam: float = 1.0
     eps: float = 1e-10
     precision: int = FP64
