@@ -54,12 +54,18 @@ typedef enum {
   JGB_ERR_DEVICE = 4         /* a HIP runtime call or kernel launch failed     */
 } jgb_status;
 
-/* The interaction kernels of eq. int3dd handled by this library.
+/* The interaction kernels of eq. int3dd handled by this library, with n the
+ * dipole axis and m the second orientation (m = n unless dipole_axis2 is set):
  *   JGB_COULOMB_3D : U = 1/(4 pi |x|),  U^ = 1/|k|^2             (eq. Cou3D)
  *   JGB_COULOMB_2D : U = 1/(2 pi |x|) in the plane, U^ = 1/|k|    (eq. Cou2D)
- *   JGB_DIPOLE_3D  : U = (3/4pi)(1 - 3 (x.n)^2/|x|^2)/|x|^3,
- *                    U^ = -1 + 3 (n.k)^2/|k|^2                    (eqs. dipkernel, dipkernelF) */
-typedef enum { JGB_COULOMB_3D = 0, JGB_COULOMB_2D = 1, JGB_DIPOLE_3D = 2 } jgb_kernel;
+ *   JGB_DIPOLE_3D  : U = (3/4pi)(m.n - 3 (x.n)(x.m)/|x|^2)/|x|^3,
+ *                    U^ = -(m.n) + 3 (n.k)(m.k)/|k|^2
+ *                    (eqs. dipkernel, dipkernelF; dipkerneld, dipkerneldF)
+ *   JGB_DIPOLE_2D  : the 2.5D dipole in the plane, n and m unit 3-vectors with
+ *                    in-plane parts n_p, m_p and normal parts n_3, m_3,
+ *                    U^ = -alpha + 3 [(n_p.k)(m_p.k) - n_3 m_3 |k|^2] / (2|k|)
+ *                    (eqs. dipkernel2d, dipkernelF2d; dipkernel2dd, dipkernelF2dd) */
+typedef enum { JGB_COULOMB_3D = 0, JGB_COULOMB_2D = 1, JGB_DIPOLE_3D = 2, JGB_DIPOLE_2D = 3 } jgb_kernel;
 
 /* JGB_FP64: every step in float64.
  * JGB_MIXED: grids, FFTs and kernel taps in float32; nodes, weights, symbol,
@@ -104,7 +110,8 @@ typedef struct {
   int64_t n[3];            /* N_j: even, 8 <= N_j <= 512, 2 N_j of the form 2^a 3^b 5^c;
                               n[2] ignored when dim == 2 */
   double box[3];           /* R_j > 0, full side lengths of B = prod [-R_j/2, R_j/2) */
-  int32_t kernel;          /* jgb_kernel; JGB_COULOMB_2D needs dim == 2, the others dim == 3 */
+  int32_t kernel;          /* jgb_kernel; JGB_COULOMB_2D and JGB_DIPOLE_2D need dim == 2,
+                              the others dim == 3 */
   double dipole_axis[3];   /* unit vector n (| |n| - 1 | <= 1e-12); ignored for Coulomb */
   double lambda;           /* interaction constant of eq. gpe2, finite */
   double eps;              /* requested relative L2 accuracy of u (and relative accuracy of E)
@@ -130,6 +137,10 @@ typedef struct {
                                   / (R1 - R0)) / 2 (eq. 3.12), {0, 0} -> {0.8 dk, 10 dk};
                                   otherwise 0 < R0 < R1.
                               Values must be finite. */
+  double dipole_axis2[3];  /* second dipole orientation m: all zero -> m = n; otherwise a unit
+                              vector like dipole_axis.  Ignored for Coulomb. */
+  double alpha;            /* JGB_DIPOLE_2D: the constant of the -alpha delta term; finite.
+                              Ignored for the other kernels (must still be finite). */
 } jgb_params;
 
 /* Plan facts, for diagnostics and for sizing caller buffers. */

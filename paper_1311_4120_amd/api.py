@@ -11,7 +11,8 @@ import torch
 from . import _lib
 from ._lib import check, lib
 
-_KERNELS = {"coulomb3d": _lib.COULOMB_3D, "coulomb2d": _lib.COULOMB_2D, "dipole3d": _lib.DIPOLE_3D}
+_KERNELS = {"coulomb3d": _lib.COULOMB_3D, "coulomb2d": _lib.COULOMB_2D, "dipole3d": _lib.DIPOLE_3D,
+            "dipole2d": _lib.DIPOLE_2D}
 _RULES = {"theta": _lib.THETA_GL, "costheta": _lib.COSTHETA_GL}
 
 
@@ -20,7 +21,7 @@ def _ptr(t):
 
 
 def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                 autotune=False, split=False, window=(0.0, 0.0)):
+                 autotune=False, split=False, window=(0.0, 0.0), axis2=None, alpha=0.0):
     dim = len(n)
     kern = _KERNELS.get(kernel, kernel)
     rule = _RULES.get(theta_rule, theta_rule)
@@ -50,6 +51,9 @@ def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, k
     p.flags = (_lib.FLAG_AUTOTUNE if autotune else 0) | (_lib.FLAG_SPLIT if split else 0)
     for i in range(2):
         p.window[i] = float(window[i]) if i < len(window) else 0.0
+    for i in range(3):
+        p.dipole_axis2[i] = float(axis2[i]) if axis2 is not None and i < len(axis2) else 0.0
+    p.alpha = float(alpha)
     return p, dev, st
 
 
@@ -57,7 +61,10 @@ class Plan:
     """A planned free-space convolution u = U*rho on one uniform grid.
 
     n, box:    grid points N_j and full side lengths R_j (2 or 3 axes)
-    kernel:    "coulomb3d", "coulomb2d" or "dipole3d" (or the jgb_kernel ints)
+    kernel:    "coulomb3d", "coulomb2d", "dipole3d" or "dipole2d" (or the jgb_kernel ints)
+    axis:      dipole orientation n (a unit 3-vector, also for "dipole2d")
+    axis2:     second orientation m (None: m = n)
+    alpha:     the 2.5D dipole's constant
     nodes:     (n_r, n_theta, n_phi) for 3D, (n_r, n_phi) for 2D
     precision: "fp64" or "mixed"
     split:     evaluate by Algorithm 2 (window p, I1 on the regular grid, I2 on
@@ -69,9 +76,10 @@ class Plan:
                  eps: float = 1e-10, precision: str = "fp64", lam: float = 1.0,
                  axis: Sequence[float] = (0.0, 0.0, 1.0), theta_rule="theta", kmax: float = 0.0,
                  device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, autotune: bool = False,
-                 split: bool = False, window: Sequence[float] = (0.0, 0.0)):
+                 split: bool = False, window: Sequence[float] = (0.0, 0.0),
+                 axis2: Optional[Sequence[float]] = None, alpha: float = 0.0):
         p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                                  autotune, split, window)
+                                  autotune, split, window, axis2, alpha)
         self._init_from(p, dev, st, box)
         h = ctypes.c_void_p()
         check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))
@@ -230,7 +238,7 @@ class Batch:
     """Independent densities evaluated by one HIP graph launch.
 
     members: list of dicts of Plan keyword arguments (n, box, kernel, nodes, eps,
-    precision, lam, axis, theta_rule, kmax, split, window).  bind() takes the density tensors
+    precision, lam, axis, theta_rule, kmax, split, window, axis2, alpha).  bind() takes the density tensors
     and allocates the outputs; run() evaluates every member."""
 
     def __init__(self, members, nstreams=4, device=None, stream=None):
@@ -240,11 +248,11 @@ class Batch:
         boxes = []
         for i, m in enumerate(members):
             kw = dict(eps=1e-10, precision="fp64", lam=1.0, axis=(0.0, 0.0, 1.0), theta_rule="theta", kmax=0.0,
-                      autotune=False, split=False, window=(0.0, 0.0))
+                      autotune=False, split=False, window=(0.0, 0.0), axis2=None, alpha=0.0)
             kw.update(m)
             p, _, _ = _make_params(kw["n"], kw["box"], kw["kernel"], kw["nodes"], kw["eps"], kw["precision"],
                                    kw["lam"], kw["axis"], kw["theta_rule"], kw["kmax"], dev, st, kw["autotune"],
-                                   kw["split"], kw["window"])
+                                   kw["split"], kw["window"], kw["axis2"], kw["alpha"])
             arr[i] = p
             boxes.append(kw["box"])
         h = ctypes.c_void_p()

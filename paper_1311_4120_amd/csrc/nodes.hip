@@ -6,10 +6,11 @@
 //             Gauss-Legendre in cos(theta) on [-1, 1]
 //   azimuth : trapezoidal rule phi_l = 2 pi l / N_phi
 //
-// The symbol is carried with the Jacobian, S(k) = |k|^{d-1} U^(k), which is a
-// polynomial for every kernel here (1 for Coulomb, 3 (n.k)^2 - |k|^2 for the
-// dipole; Section 3.1 after eq. 3.5), so it is evaluated exactly and U^ is
-// never formed.
+// The symbol is carried with the Jacobian, S(k) = |k|^{d-1} U^(k), which is
+// smooth for every kernel here (Section 3.1 after eq. 3.5): 1 for Coulomb,
+// 3 (n.k)(m.k) - (m.n)|k|^2 for the 3D dipole, and -alpha |k| + (3/2)
+// [(n_p.k)(m_p.k) - n_3 m_3 |k|^2] for the 2.5D dipole (linear along each ray).
+// It is evaluated as written and U^ is never formed.
 //
 // Only half of the node set is processed downstream: with N_phi even the node
 // (r, pi - theta, phi + pi) equals -k, carries the same weight and symbol, and
@@ -33,6 +34,8 @@ struct NodeParams {
   double K, beta;
   double win[2];   // 3D: (a, 0); 2D: (R0, R1)
   double axis[3];
+  double axis2[3];  // second orientation m (= n unless given)
+  double alpha;     // 2.5D dipole constant
   double box[3];  // physical side lengths per internal axis (unit axis: 0)
   int nf[3], w[3], T[3], nt[3], S[3];
   const double* gl_r;
@@ -55,6 +58,8 @@ NodeParams make_params(const Plan& pl) {
   q.win[0] = pl.win[0];
   q.win[1] = pl.win[1];
   for (int i = 0; i < 3; ++i) q.axis[i] = pl.p.dipole_axis[i];
+  for (int i = 0; i < 3; ++i) q.axis2[i] = pl.axis2[i];
+  q.alpha = pl.p.alpha;
   for (int i = 0; i < 3; ++i) {
     q.box[i] = (pl.n[i] == 1) ? 0.0 : pl.box[i];
     q.nf[i] = pl.nf[i];
@@ -149,11 +154,20 @@ __device__ void full_node(const NodeParams& q, int a, int b, int l, double k[3],
   }
 }
 
-// S(k) = |k|^{d-1} U^(k) for the kernels of eq. int3dd handled here.
+// S(k) = |k|^{d-1} U^(k) for the kernels of eq. int3dd handled here (k in
+// physical coordinates; 2D nodes have k[2] = 0).
 __device__ double symbol(const NodeParams& q, const double k[3]) {
+  const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
   if (q.kernel == JGB_DIPOLE_3D) {
-    double nk = q.axis[0] * k[0] + q.axis[1] * k[1] + q.axis[2] * k[2];
-    return 3.0 * nk * nk - (k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    const double nk = q.axis[0] * k[0] + q.axis[1] * k[1] + q.axis[2] * k[2];
+    const double mk = q.axis2[0] * k[0] + q.axis2[1] * k[1] + q.axis2[2] * k[2];
+    const double mn = q.axis[0] * q.axis2[0] + q.axis[1] * q.axis2[1] + q.axis[2] * q.axis2[2];
+    return 3.0 * nk * mk - mn * kk;
+  }
+  if (q.kernel == JGB_DIPOLE_2D) {
+    const double nk = q.axis[0] * k[0] + q.axis[1] * k[1];
+    const double mk = q.axis2[0] * k[0] + q.axis2[1] * k[1];
+    return -q.alpha * sqrt(kk) + 1.5 * (nk * mk - q.axis[2] * q.axis2[2] * kk);
   }
   return 1.0;
 }

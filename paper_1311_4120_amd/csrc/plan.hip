@@ -354,21 +354,26 @@ Status validate(const jgb_params* p) {
     if (!is_235(2 * n)) return fail(JGB_ERR_UNSUPPORTED, "2 n[j] must factor into 2, 3 and 5");
     if (!(std::isfinite(p->box[j]) && p->box[j] > 0)) return fail(JGB_ERR_INVALID_ARG, "box[j] must be finite and > 0");
   }
-  if (p->kernel == JGB_COULOMB_2D) {
-    if (p->dim != 2) return fail(JGB_ERR_INVALID_ARG, "JGB_COULOMB_2D needs dim == 2");
+  if (p->kernel == JGB_COULOMB_2D || p->kernel == JGB_DIPOLE_2D) {
+    if (p->dim != 2) return fail(JGB_ERR_INVALID_ARG, "2D kernels need dim == 2");
   } else if (p->kernel == JGB_COULOMB_3D || p->kernel == JGB_DIPOLE_3D) {
     if (p->dim != 3) return fail(JGB_ERR_INVALID_ARG, "3D kernels need dim == 3");
   } else {
     return fail(JGB_ERR_INVALID_ARG, "unknown kernel");
   }
-  if (p->kernel == JGB_DIPOLE_3D) {
-    double nn = 0;
+  if (p->kernel == JGB_DIPOLE_3D || p->kernel == JGB_DIPOLE_2D) {
+    double nn = 0, mm = 0;
     for (int i = 0; i < 3; ++i) {
       if (!std::isfinite(p->dipole_axis[i])) return fail(JGB_ERR_INVALID_ARG, "dipole_axis not finite");
+      if (!std::isfinite(p->dipole_axis2[i])) return fail(JGB_ERR_INVALID_ARG, "dipole_axis2 not finite");
       nn += p->dipole_axis[i] * p->dipole_axis[i];
+      mm += p->dipole_axis2[i] * p->dipole_axis2[i];
     }
     if (std::fabs(std::sqrt(nn) - 1.0) > 1e-12) return fail(JGB_ERR_INVALID_ARG, "dipole_axis must be a unit vector");
+    if (mm != 0.0 && std::fabs(std::sqrt(mm) - 1.0) > 1e-12)
+      return fail(JGB_ERR_INVALID_ARG, "dipole_axis2 must be zero or a unit vector");
   }
+  if (!std::isfinite(p->alpha)) return fail(JGB_ERR_INVALID_ARG, "alpha must be finite");
   if (!std::isfinite(p->lambda)) return fail(JGB_ERR_INVALID_ARG, "lambda must be finite");
   if (!(p->eps >= 1e-13 && p->eps <= 1e-2)) return fail(JGB_ERR_INVALID_ARG, "eps must be in [1e-13, 1e-2]");
   if (p->precision != JGB_FP64 && p->precision != JGB_MIXED) return fail(JGB_ERR_INVALID_ARG, "unknown precision");
@@ -451,6 +456,12 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     hmax = std::max(hmax, pl.h[i]);
   }
   pl.K = (p->kmax > 0) ? p->kmax : M_PI / hmax;
+  {
+    // the second dipole orientation: m = n unless given
+    double mm = 0;
+    for (int i = 0; i < 3; ++i) mm += p->dipole_axis2[i] * p->dipole_axis2[i];
+    for (int i = 0; i < 3; ++i) pl.axis2[i] = (mm != 0.0) ? p->dipole_axis2[i] : p->dipole_axis[i];
+  }
   pl.split = (p->flags & JGB_FLAG_SPLIT) != 0;
   if (pl.split) {
     // Algorithm 2's window in units of the box's Fourier spacing dk = 2 pi /

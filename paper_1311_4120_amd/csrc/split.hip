@@ -86,7 +86,9 @@ struct SymbolArgs {
   uint32_t npoints;    // (nf0/2 + 1) nf1 nf2: planes q0 = 0 .. nf0/2
   int kernel, dim;
   double a, r0, r1;    // window: a (3D) or R0, R1 (2D)
-  double axis[3];      // dipole axis in internal coordinates
+  double axis[3];      // dipole orientations n and m (physical coordinates)
+  double axis2[3];
+  double alpha;        // 2.5D dipole constant
   double inv_vol;      // 1 / prod_j (2 R_j)
   const double* kt;    // per axis: k_a(q) for q < nf_a, then exp(-k_a(q)^2 / a)
   int koff[3], eoff[3];
@@ -97,9 +99,10 @@ struct SymbolArgs {
 };
 
 // M'(q) = (1 - p(k_q)) U^(k_q) / prod_j (2 R_j), with its k = 0 limit (1/a for
-// the 3D Coulomb kernel; 0 for the dipole, where 1 - p vanishes and U^ is
-// bounded, and for the 2D kernel, where 1 - p is below 1e-20 at the default
-// scales).  In 3D the window is the product of per-axis tables, so 1 - p is
+// the 3D Coulomb kernel; 0 for the dipoles, where 1 - p vanishes and U^ is
+// bounded, and for the 2D Coulomb kernel, where 1 - p is below 1e-20 at the
+// default scales).  In 2D the physical frequency is (k1, k2) of the internal
+// axes (a1, a2).  In 3D the window is the product of per-axis tables, so 1 - p is
 // 1 minus that product: at the grid's smallest nonzero |k| the subtraction
 // costs under four bits at the default scale a = 2 dk^2.
 __device__ inline double split_symbol(const SymbolArgs& s, int q0, int q1, int q2) {
@@ -110,11 +113,16 @@ __device__ inline double split_symbol(const SymbolArgs& s, int q0, int q1, int q
     const double omp = 1.0 - s.kt[s.eoff[0] + q0] * s.kt[s.eoff[1] + q1] * s.kt[s.eoff[2] + q2];
     if (s.kernel == JGB_COULOMB_3D) return s.inv_vol * omp / kk;
     const double nk = s.axis[0] * k0 + s.axis[1] * k1 + s.axis[2] * k2;
-    return s.inv_vol * omp * (3.0 * nk * nk / kk - 1.0);
+    const double mk = s.axis2[0] * k0 + s.axis2[1] * k1 + s.axis2[2] * k2;
+    const double mn = s.axis[0] * s.axis2[0] + s.axis[1] * s.axis2[1] + s.axis[2] * s.axis2[2];
+    return s.inv_vol * omp * (3.0 * nk * mk / kk - mn);
   }
   const double kabs = sqrt(kk);
   const double omp = 0.5 * erfc(-12.0 * (kabs - 0.5 * (s.r0 + s.r1)) / (s.r1 - s.r0));
-  return s.inv_vol * omp / kabs;
+  if (s.kernel == JGB_COULOMB_2D) return s.inv_vol * omp / kabs;
+  const double nk = s.axis[0] * k1 + s.axis[1] * k2;
+  const double mk = s.axis2[0] * k1 + s.axis2[1] * k2;
+  return s.inv_vol * omp * (-s.alpha + 1.5 * (nk * mk - s.axis[2] * s.axis2[2] * kk) / kabs);
 }
 
 // Over the pairs {q, -q} (planes q0 <= nf0/2; in the planes that are their
@@ -142,11 +150,12 @@ __global__ void __launch_bounds__(256) k_split_symbol(SymbolArgs s) {
     const bool self = (im == iq);
     const C2<T> zq = F[iq], zm = F[im];
     // On a Nyquist plane (q_a = nf_a / 2) the grid frequency is its own mirror
-    // on that axis, so k(-q) is not -k(q) there and the dipole symbol, which
-    // is not a function of |k| alone, differs between q and -q.  I1 is real,
-    // so the sum takes the mean of the two (the Hermitian part of M B).
+    // on that axis, so k(-q) is not -k(q) there and a dipole symbol, which is
+    // not a function of |k| alone, differs between q and -q.  I1 is real, so
+    // the sum takes the mean of the two (the Hermitian part of M B).
     double M = split_symbol(s, q0, q1, q2);
-    if (s.kernel == JGB_DIPOLE_3D && (2 * q0 == g.nf0 || 2 * q1 == g.nf1 || 2 * q2 == g.nf2))
+    if ((s.kernel == JGB_DIPOLE_3D || s.kernel == JGB_DIPOLE_2D) &&
+        (2 * q0 == g.nf0 || 2 * q1 == g.nf1 || 2 * q2 == g.nf2))
       M = 0.5 * (M + split_symbol(s, m0, m1, m2));
     // D(q) = Z(q) - conj Z(-q) = 2 i B(q); D(-q) = -conj D(q)
     const T dx = zq.x - zm.x, dy = zq.y + zm.y;
@@ -198,6 +207,8 @@ hipError_t launch_split_symbol(const Plan& pl, int energy_mode, int eoff, hipStr
   a.r0 = pl.win[0];
   a.r1 = pl.win[1];
   for (int i = 0; i < 3; ++i) a.axis[i] = pl.p.dipole_axis[i];
+  for (int i = 0; i < 3; ++i) a.axis2[i] = pl.axis2[i];
+  a.alpha = pl.p.alpha;
   double vol = 1.0;
   for (int i = 0; i < 3; ++i)
     if (pl.n[i] > 1) vol *= 2.0 * pl.box[i];

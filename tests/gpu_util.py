@@ -15,10 +15,11 @@ def say(*a):
 def make_plan(problem, **kw):
     import paper_1311_4120_amd as jgb
     nodes = (problem.n_r, problem.n_theta, problem.n_phi) if problem.dim == 3 else (problem.n_r, problem.n_phi)
-    kernel = {wl.COULOMB_3D: "coulomb3d", wl.COULOMB_2D: "coulomb2d", wl.DIPOLE_3D: "dipole3d"}[problem.kernel]
+    kernel = {wl.COULOMB_3D: "coulomb3d", wl.COULOMB_2D: "coulomb2d", wl.DIPOLE_3D: "dipole3d",
+              wl.DIPOLE_2D: "dipole2d"}[problem.kernel]
     args = dict(eps=problem.eps, precision="fp64" if problem.precision == wl.FP64 else "mixed",
                 lam=problem.lam, axis=problem.axis, theta_rule="theta" if problem.theta_rule == wl.THETA_GL else "costheta",
-                kmax=problem.kmax)
+                kmax=problem.kmax, axis2=problem.axis2, alpha=problem.alpha)
     args.update(kw)
     return jgb.Plan(problem.n, problem.box, kernel, nodes, **args)
 

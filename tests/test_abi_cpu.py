@@ -46,7 +46,8 @@ def test_struct_layouts_match_c(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "jgb.h"\n'
                    'int main(){printf("%zu %zu %zu %zu %zu\\n", sizeof(jgb_params), sizeof(jgb_info),'
                    ' offsetof(jgb_params, stream), offsetof(jgb_params, kmax), offsetof(jgb_info, workspace_bytes));'
-                   'printf("%zu %zu\\n", offsetof(jgb_params, window), offsetof(jgb_info, window));'
+                   'printf("%zu %zu %zu %zu\\n", offsetof(jgb_params, window), offsetof(jgb_info, window),'
+                   ' offsetof(jgb_params, dipole_axis2), offsetof(jgb_params, alpha));'
                    'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -58,6 +59,8 @@ def test_struct_layouts_match_c(tmp_path):
     assert vals[4] == L.Info.workspace_bytes.offset
     assert vals[5] == L.Params.window.offset
     assert vals[6] == L.Info.window.offset
+    assert vals[7] == L.Params.dipole_axis2.offset
+    assert vals[8] == L.Params.alpha.offset
 
 
 def _params(**kw):
@@ -80,7 +83,7 @@ def _params(**kw):
     p.stream = None
     p.flags = 0
     for k, v in kw.items():
-        if k in ("n", "box", "dipole_axis", "window"):
+        if k in ("n", "box", "dipole_axis", "window", "dipole_axis2"):
             for i, x in enumerate(v):
                 getattr(p, k)[i] = x
         else:
@@ -117,6 +120,11 @@ BAD = [
     ("2D R0 >= R1", dict(flags=2, dim=2, kernel=1, window=(2.0, 1.0)), 1),
     ("2D R0 = 0", dict(flags=2, dim=2, kernel=1, window=(0.0, 1.0)), 1),
     ("split kmax too large", dict(flags=2, kmax=100.0), 1),
+    ("dipole2d needs dim 2", dict(kernel=3), 1),
+    ("dipole_axis2 not unit", dict(kernel=2, dipole_axis2=(0.5, 0.0, 0.0)), 1),
+    ("dipole_axis2 nan", dict(kernel=2, dipole_axis2=(float("nan"), 0.0, 1.0)), 1),
+    ("alpha nan", dict(alpha=float("nan")), 1),
+    ("dipole2d axis not unit", dict(dim=2, kernel=3, dipole_axis=(0.6, 0.0, 0.0)), 1),
 ]
 
 
@@ -156,7 +164,9 @@ def test_valid_parameters_without_gpu_report_device_error():
         pytest.skip("a GPU is present")
     L = _lib()
     for kw in (dict(), dict(flags=L.FLAG_SPLIT), dict(flags=L.FLAG_SPLIT, window=(0.7, 0.0)),
-               dict(flags=L.FLAG_SPLIT, dim=2, kernel=L.COULOMB_2D, window=(0.3, 4.0))):
+               dict(flags=L.FLAG_SPLIT, dim=2, kernel=L.COULOMB_2D, window=(0.3, 4.0)),
+               dict(kernel=L.DIPOLE_3D, dipole_axis2=(1.0, 0.0, 0.0)),
+               dict(dim=2, kernel=L.DIPOLE_2D, dipole_axis=(0.6, 0.0, 0.8), alpha=0.5)):
         p = _params(**kw)
         h = ctypes.c_void_p()
         assert L.lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)) == L.JGB_ERR_DEVICE, kw
