@@ -8,7 +8,9 @@ back to the uniform grid (eq. 3.7, Algorithm 1), and the interaction energy
 sum is evaluated directly, with per-axis phase tables and BLAS matrix products
 as the only library primitives.  `split` holds Algorithm 2 (Section 3.3), whose
 regular-grid part I1 is a padded FFT convolution (numpy's FFT as the library
-step), pinned against the same trapezoid sum done directly.
+step), pinned against the same trapezoid sum done directly.  `gpe` holds the
+time-splitting driver for the Gross-Pitaevskii equation that repeatedly
+evaluates the potential (Strang splitting, real and imaginary time).
 
 Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may
 import this package.  It shares no code with the HIP library: the two meet
@@ -28,10 +30,11 @@ from .direct import (rho_hat, rho_hat_separable, sum_to_grid, sum_to_points, pot
                      energy_gradient_psi, apply_operator)
 from . import closed_forms
 from . import split
+from . import gpe
 
 __all__ = [
     "gauss_legendre", "radial_rule", "theta_rule", "phi_rule", "spherical_nodes",
     "polar_nodes", "fourier_nodes", "symbol", "coefficients", "rho_hat", "rho_hat_separable", "sum_to_grid",
     "sum_to_points", "potential", "energy_fourier", "energy_physical", "Result", "evaluate",
-    "energy_gradient_rho", "energy_gradient_psi", "apply_operator", "closed_forms", "split",
+    "energy_gradient_rho", "energy_gradient_psi", "apply_operator", "closed_forms", "split", "gpe",
 ]
