@@ -286,6 +286,59 @@ jgb_status jgb_batch_plan(jgb_batch_t batch, int i, jgb_plan_t* plan);
 /* Synchronise, then free the graph, streams, events and member plans. */
 jgb_status jgb_batch_destroy(jgb_batch_t batch);
 
+/* ---------------------------------------------------------------- GPE driver
+ * Time splitting for the Gross-Pitaevskii (or Schroedinger-Poisson) equation
+ *   i psi_t = [-1/2 Lap + V + beta |psi|^2 + lambda Phi] psi,   Phi = U * |psi|^2,
+ * the application that evaluates the potential of eq. gpe many times for a
+ * changing rho = |psi|^2 (Section 1).  One step of length dt is Strang
+ * splitting: N(dt/2), K(dt), N(dt/2) with
+ *   N(h): psi <- exp(-i h (V + beta |psi|^2 + lambda Phi)) psi
+ *   K(h): psi <- IDFT(exp(-i h |k|^2 / 2) DFT(psi)),  k_j = 2 pi q_j / R_j
+ * (the Laplacian periodic on the box: psi must be negligible at its edges).
+ * N keeps |psi|, so Phi is evaluated once per step (plus once per call).  In
+ * imaginary time (the ground-state flow) the factors are exp(-h ...) and
+ * exp(-h |k|^2 / 2), Phi is evaluated before each half-step, and psi is
+ * renormalised to H sum |psi|^2 = 1 after every step.  psi is a device complex
+ * array (interleaved re, im) of the plan's real dtype on the grid. */
+typedef struct jgb_gpe_s* jgb_gpe_t;
+
+typedef struct {
+  uint32_t struct_size;    /* = sizeof(jgb_gpe_params) */
+  jgb_params potential;    /* the plan of Phi: grid, box, kernel, nodes, accuracy, precision,
+                              flags (JGB_FLAG_SPLIT allowed); its lambda is the lambda above;
+                              its device and stream are the driver's */
+  double trap[3];          /* V = (1/2) sum_j trap_j^2 x_j^2 when V is NULL (2D: trap[0..1]) */
+  const void* V;           /* optional device real array of V on the grid (plan's dtype);
+                              caller-owned, read at every step; NULL -> the harmonic trap */
+  double beta;             /* local interaction constant, finite */
+  double dt;               /* time step (imaginary time: d tau), finite, nonzero (negative runs
+                              real time backward) */
+  int32_t imaginary;       /* 0: real time; 1: imaginary time with renormalisation */
+} jgb_gpe_params;
+
+/* Create the driver: its own stream (default priority), the potential's plan on
+ * it, and workspace for rho, Phi and the energy sums.  Errors as jgb_plan, plus
+ * INVALID_ARG for the driver's own fields. */
+jgb_status jgb_gpe_create(const jgb_gpe_params* params, jgb_gpe_t* out);
+
+/* Advance psi in place by nsteps steps (nsteps >= 0).  use_graph = 1 captures
+ * one step into a HIP graph on the first call for this psi and replays it
+ * (one launch per step); 0 enqueues every kernel directly (same result).
+ * Ordered after earlier work on params.potential.stream, and later work on
+ * that stream is ordered after it.  Enqueue only. */
+jgb_status jgb_gpe_step(jgb_gpe_t gpe, void* psi, int nsteps, int use_graph);
+
+/* Energies of psi into out (device float64[7]):
+ *   {norm, kinetic, trap, local, nonlocal, total, mu}
+ * norm = H sum |psi|^2, kinetic = (H / (2 N)) sum_q |k_q|^2 |DFT(psi)_q|^2,
+ * trap = H sum V |psi|^2, local = (beta/2) H sum |psi|^4,
+ * nonlocal = (lambda/2) H sum Phi |psi|^2 (eq. gpe2), total = their sum,
+ * mu = (kinetic + trap + 2 local + 2 nonlocal) / norm.  Enqueue only. */
+jgb_status jgb_gpe_energy(jgb_gpe_t gpe, const void* psi, double* out);
+
+/* Synchronise and free the driver (and its plan).  NULL is accepted. */
+jgb_status jgb_gpe_destroy(jgb_gpe_t gpe);
+
 /* Copy plan facts into *info (host memory, info->struct_size must be set). */
 jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info);
 

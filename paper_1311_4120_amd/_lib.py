@@ -73,6 +73,21 @@ class Info(ctypes.Structure):
     ]
 
 
+class GpeParams(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("potential", Params),
+        ("trap", ctypes.c_double * 3),
+        ("V", ctypes.c_void_p),
+        ("beta", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("imaginary", ctypes.c_int32),
+    ]
+
+
+GPE_ENERGY_NAMES = ["norm", "kinetic", "trap", "local", "nonlocal", "total", "mu"]
+
+
 class JgbError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
@@ -105,6 +120,10 @@ def _load():
         "jgb_batch_plan": (st, [P, ctypes.c_int, ctypes.POINTER(P)]),
         "jgb_batch_destroy": (st, [P]),
         "jgb_timing_end": (st, [P, P, P]),
+        "jgb_gpe_create": (st, [ctypes.POINTER(GpeParams), ctypes.POINTER(P)]),
+        "jgb_gpe_step": (st, [P, P, ctypes.c_int, ctypes.c_int]),
+        "jgb_gpe_energy": (st, [P, P, P]),
+        "jgb_gpe_destroy": (st, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -297,3 +297,76 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class GPE:
+    """Time splitting for i psi_t = [-1/2 Lap + V + beta |psi|^2 + lam Phi] psi,
+    Phi = U * |psi|^2 by the potential plan given by the Plan keyword arguments
+    (n, box, kernel, nodes, eps, precision, lam, axis, axis2, alpha, theta_rule,
+    kmax, split, window).  trap: harmonic frequencies (V = sum trap_j^2 x_j^2 / 2)
+    used unless V (a real tensor on the grid) is given; imaginary: the
+    ground-state flow with renormalisation.  step() advances psi in place."""
+
+    def __init__(self, n, box, kernel, nodes, dt, beta=0.0, trap=(0.0, 0.0, 0.0), V=None, imaginary=False,
+                 device=None, stream=None, **plan_kw):
+        kw = dict(eps=1e-10, precision="fp64", lam=1.0, axis=(0.0, 0.0, 1.0), theta_rule="theta", kmax=0.0,
+                  autotune=False, split=False, window=(0.0, 0.0), axis2=None, alpha=0.0)
+        kw.update(plan_kw)
+        p, dev, st = _make_params(n, box, kernel, nodes, kw["eps"], kw["precision"], kw["lam"], kw["axis"],
+                                  kw["theta_rule"], kw["kmax"], device, stream, kw["autotune"], kw["split"],
+                                  kw["window"], kw["axis2"], kw["alpha"])
+        g = _lib.GpeParams()
+        g.struct_size = ctypes.sizeof(_lib.GpeParams)
+        g.potential = p
+        for i in range(3):
+            g.trap[i] = float(trap[i]) if i < len(trap) else 0.0
+        self.n = tuple(int(v) for v in n)
+        self.device = torch.device("cuda", dev)
+        self.stream = st
+        self.dtype = torch.float64 if p.precision == _lib.FP64 else torch.float32
+        self.cdtype = torch.complex128 if self.dtype == torch.float64 else torch.complex64
+        self.V = None
+        if V is not None:
+            if not isinstance(V, torch.Tensor) or V.dtype != self.dtype or tuple(V.shape) != self.n \
+                    or V.device != self.device or not V.is_contiguous():
+                raise ValueError("V must be a contiguous %s tensor of shape %s on %s" % (self.dtype, self.n, self.device))
+            self.V = V
+            g.V = ctypes.c_void_p(V.data_ptr())
+        g.beta = float(beta)
+        g.dt = float(dt)
+        g.imaginary = 1 if imaginary else 0
+        h = ctypes.c_void_p()
+        check(lib.jgb_gpe_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+
+    def _check(self, psi):
+        if not isinstance(psi, torch.Tensor) or psi.dtype != self.cdtype or tuple(psi.shape) != self.n \
+                or psi.device != self.device or not psi.is_contiguous():
+            raise ValueError("psi must be a contiguous %s tensor of shape %s on %s" % (self.cdtype, self.n, self.device))
+
+    def step(self, psi, nsteps=1, graph=True):
+        """Advance psi in place by nsteps Strang steps."""
+        self._check(psi)
+        check(lib.jgb_gpe_step(self._h, _ptr(psi), int(nsteps), 1 if graph else 0))
+        return psi
+
+    def energy(self, psi):
+        """{norm, kinetic, trap, local, nonlocal, total, mu} of psi (float64 tensor of 7 on the device
+        and a dict of floats)."""
+        self._check(psi)
+        out = torch.empty(7, dtype=torch.float64, device=self.device)
+        check(lib.jgb_gpe_energy(self._h, _ptr(psi), _ptr(out)))
+        vals = out.cpu().tolist()
+        return out, dict(zip(_lib.GPE_ENERGY_NAMES, vals))
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.jgb_gpe_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

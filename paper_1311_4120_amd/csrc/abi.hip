@@ -28,9 +28,6 @@ const char* get_error() { return g_last_error.c_str(); }
 
 using jgb::Plan;
 
-struct jgb_plan_s {
-  Plan pl;
-};
 
 struct jgb_batch_s {
   std::vector<jgb_plan_s*> plans;
@@ -129,6 +126,14 @@ jgb_status run_transform(Plan& pl, const void* rho, void* out) {
   jgb::call_done(pl);
   return JGB_OK;
 }
+
+}  // namespace
+
+jgb_status jgb::potential_pipeline(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st) {
+  return pl.fp64 ? run_potential<double>(pl, rho, u, energy, st) : run_potential<float>(pl, rho, u, energy, st);
+}
+
+namespace {
 
 jgb_status check_plan(jgb_plan_t plan) {
   if (!plan) return report(JGB_ERR_INVALID_ARG, "plan is NULL");

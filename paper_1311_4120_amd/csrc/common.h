@@ -193,7 +193,7 @@ __host__ __device__ inline T es_kernel(T x, T two_over_w, T beta) {
 // Record the stage's start / end event of the current call when timing is on.
 inline void stage_mark(const Plan& pl, int stage, int which, hipStream_t s) {
   Timing& t = pl.timing;
-  if (!t.on || t.calls >= t.max_calls) return;
+  if (stage < 0 || !t.on || t.calls >= t.max_calls) return;
   size_t i = (size_t)t.calls * ST_COUNT + stage;
   (void)hipEventRecord(t.ev[2 * i + which], s);
   if (which == 1) t.used[i] = 1;
@@ -231,9 +231,19 @@ template <typename T>
 hipError_t launch_split_unmix(const Plan& pl, hipStream_t s);
 template <typename T>
 hipError_t launch_split_symbol(const Plan& pl, int energy_mode, int eoff, hipStream_t s);
+// periodic complex FFT of the plan's N grid in place (sign -1 or +1)
+template <typename T>
+hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, int sign, hipStream_t s);
+// u = U*rho (and E) by the plan's pipeline, enqueued on stream st
+jgb_status potential_pipeline(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st);
 int fft_inverse_z_blocks(const Plan& pl);
 int interp_blocks(const Plan& pl);
 hipError_t interp_prepare(const Plan& pl);
 hipError_t launch_energy_finalize(const double* parts, int n, double scale, double* out, hipStream_t s);
 
 }  // namespace jgb
+
+// The opaque plan handle of the C ABI.
+struct jgb_plan_s {
+  jgb::Plan pl;
+};

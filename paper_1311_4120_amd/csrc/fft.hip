@@ -126,7 +126,12 @@ __device__ inline void dft(C2<T>* v, T s) {
   if constexpr (R == 8) dft8(v, s);
 }
 
-enum PassKind { PASS_FWD_Z = 0, PASS_COMPLEX = 1, PASS_INV_Z = 2 };
+// FWD_Z / INV_Z: the oversampled grid's first and last passes (real in or out,
+// deconvolution factors); COMPLEX: a complex pass along a strided axis;
+// COMPLEX_Z: a complex pass along the contiguous axis (the periodic FFT).
+enum PassKind { PASS_FWD_Z = 0, PASS_COMPLEX = 1, PASS_INV_Z = 2, PASS_COMPLEX_Z = 3 };
+template <int KIND>
+constexpr bool has_factors() { return KIND == PASS_FWD_Z || KIND == PASS_INV_Z; }
 
 template <typename T>
 struct PassArgs {
@@ -230,7 +235,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
   double* fline = reinterpret_cast<double*>(smem_raw + (size_t)LB * ldl * sizeof(C2<T>));
   double* felem = fline + LB;
 
-  if constexpr (KIND != PASS_COMPLEX) {
+  if constexpr (has_factors<KIND>()) {
     const int ne = (KIND == PASS_FWD_Z) ? a.nin : a.nout;
     for (int t = threadIdx.x; t < LB + ne; t += NT) {
       if (t < LB) {
@@ -253,7 +258,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
       lds[l * ldl + (N - N / 2) + e] = C2<T>{T(0), T(0)};
     }
   }
-  if constexpr (KIND != PASS_COMPLEX) __syncthreads();  // factors staged
+  if constexpr (has_factors<KIND>()) __syncthreads();  // factors staged
 
   // load
   {
@@ -462,7 +467,7 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   a.dn1 = FastDiv((uint32_t)(a.n1 > 0 ? a.n1 : 1));
   unsigned blocks = (unsigned)((a.nlines + a.LB - 1) / a.LB);
   size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
-  if (KIND != PASS_COMPLEX) smem += sizeof(double) * (a.LB + a.L);  // deconvolution factors
+  if (has_factors<KIND>()) smem += sizeof(double) * (a.LB + a.L);  // deconvolution factors
   constexpr int NT = pass_threads<T>();
   constexpr int MAXV = pass_elems<T>();
   stage_mark(pl, stage, 0, s);
@@ -623,6 +628,60 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
   }
   return hipSuccess;
 }
+
+// Periodic complex FFT of a grid of n0 x n1 x n2 points in place (no padding,
+// no crop): the GPE driver's kinetic step.  tw[a]: exp(-2 pi i t / n_a), t < n_a.
+template <typename T>
+hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, int sign, hipStream_t s) {
+  const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
+  const T sg = (T)sign;
+  hipError_t e;
+  auto common = [&](int axis) {
+    PassArgs<T> a{};
+    a.L = pl.n[axis];
+    a.nin = a.nout = a.L;
+    a.sign = sg;
+    a.tw = (const C2<T>*)tw[axis];
+    a.n1 = (int)n1;
+    a.n2 = (int)n2;
+    a.in = data;
+    a.out = data;
+    return a;
+  };
+  {  // axis 2, contiguous: lines [n0][n1]
+    PassArgs<T> a = common(2);
+    a.nlines = n0 * n1;
+    a.ic = 1;
+    a.in_os = a.out_os = n2;
+    a.in_is = a.out_is = 0;
+    a.in_es = a.out_es = 1;
+    if ((e = run_pass<T, PASS_COMPLEX_Z>(pl, -1, a, s)) != hipSuccess) return e;
+  }
+  {  // axis 1: lines [n0][n2]
+    PassArgs<T> a = common(1);
+    a.nlines = n0 * n2;
+    a.ic = n2;
+    a.in_os = a.out_os = n1 * n2;
+    a.in_is = a.out_is = 1;
+    a.in_es = a.out_es = n2;
+    a.lines_fastest = 1;
+    if ((e = run_pass<T, PASS_COMPLEX>(pl, -1, a, s)) != hipSuccess) return e;
+  }
+  if (n0 > 1) {  // axis 0: lines [n1 n2]
+    PassArgs<T> a = common(0);
+    a.nlines = n1 * n2;
+    a.ic = n1 * n2;
+    a.in_os = a.out_os = 0;
+    a.in_is = a.out_is = 1;
+    a.in_es = a.out_es = n1 * n2;
+    a.lines_fastest = 1;
+    if ((e = run_pass<T, PASS_COMPLEX>(pl, -1, a, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_fft_periodic<double>(const Plan&, void* const[3], void*, int, hipStream_t);
+template hipError_t launch_fft_periodic<float>(const Plan&, void* const[3], void*, int, hipStream_t);
 
 int fft_inverse_z_blocks(const Plan& pl) {
   int lb = pl.fp64 ? lines_per_block<double>(pl.nf[2]) : lines_per_block<float>(pl.nf[2]);
