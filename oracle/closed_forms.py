@@ -26,6 +26,9 @@ Sources (all in the paper's notation):
     -alpha delta term (-alpha rho) give the general 2.5D dipole.
   * Example 7: dipole energy of an anisotropic normalised Gaussian, with the
     three printed exact values.
+  * 2D Poisson (U = -(1/2pi) log|x|) potential of exp(-|x|^2/a): by the
+    shell theorem (the mean of log|x - y| over |y| = s is log max(|x|, s)),
+    u(r) = -(a/4) [2 log r + E1(r^2/a)], u(0) = (a/4)(gamma - log a).
   * Gaussian-mixture energies: the autocorrelation of two Gaussians is a
     Gaussian, (pi a_i a_j/(a_i+a_j))^{d/2} exp(-|z-(c_i-c_j)|^2/(a_i+a_j)), so
     E = (lambda/2) sum_ij A_i A_j (pi a_i a_j/(a_i+a_j))^{d/2} u_{a_i+a_j}(|c_i-c_j|).
@@ -33,7 +36,7 @@ Sources (all in the paper's notation):
 from __future__ import annotations
 
 import numpy as np
-from scipy.special import erf, i0e, i1e
+from scipy.special import erf, exp1, i0e, i1e
 
 # Example 7 exact energies as printed (lambda = 8 pi / 3, n = z-axis).
 EXAMPLE7_PRINTED = {
@@ -68,9 +71,20 @@ def coulomb2d_gaussian_energy(a=1.0, lam=1.0):
     return lam * np.pi ** 1.5 * a ** 1.5 / (4.0 * np.sqrt(2.0))
 
 
-def mixture_potential(mix, X, d):
-    """u(x) = sum_g A_g u_{a_g}(|x - c_g|), a_g = sigma_g^2."""
-    f = coulomb3d_gaussian if d == 3 else coulomb2d_gaussian
+def poisson2d_gaussian(r, a=1.0):
+    """Potential of exp(-|x|^2/a) under U = -(1/2 pi) log|x| in the plane."""
+    r = np.asarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    small = r < 1e-8
+    rs = r[~small]
+    out[~small] = -0.25 * a * (2.0 * np.log(rs) + exp1(rs * rs / a))
+    out[small] = 0.25 * a * (0.57721566490153286061 - np.log(a))
+    return out
+
+
+def mixture_potential(mix, X, d, poisson=False):
+    """u(x) = sum_g A_g u_{a_g}(|x - c_g|), a_g = sigma_g^2 (poisson: the 2D log kernel)."""
+    f = coulomb3d_gaussian if d == 3 else (poisson2d_gaussian if poisson else coulomb2d_gaussian)
     out = 0.0
     for A, c, s in zip(mix.amps, mix.centers, mix.widths):
         r = np.sqrt(sum((Xi - ci) ** 2 for Xi, ci in zip(X, c)))

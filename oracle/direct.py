@@ -23,8 +23,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .quadrature import fourier_nodes
-from .symbols import coefficients
+from .quadrature import fourier_nodes, default_kmax
+from .symbols import coefficients, origin_coefficient
 
 _CHUNK_ELEMS = 1 << 23   # complex elements per intermediate block (128 MB)
 
@@ -171,11 +171,17 @@ class Result:
 
 
 def evaluate(problem, rho):
-    """Full oracle evaluation of a workloads.Problem on density rho (FP64)."""
+    """Full oracle evaluation of a workloads.Problem on density rho (FP64).  A kernel
+    with a node at k = 0 (the 2D Poisson one) adds c_0 rho^(0) to u and
+    (lambda/2) c_0 rho^(0)^2 to the Fourier-side energy."""
     rho = np.asarray(rho, dtype=np.float64)
     k, W = fourier_nodes(problem)
     u, rh, c, im = potential(rho, problem.box, problem.kernel, k, W, problem.axis, problem.axis2, problem.alpha)
+    K = problem.kmax if problem.kmax > 0 else default_kmax(problem.n, problem.box)
+    c0 = origin_coefficient(problem.kernel, K, problem.n_r)
+    r0 = _cell_volume(rho.shape, problem.box) * float(np.sum(rho))
+    u = u + c0 * r0
     return Result(u=u,
                   energy_physical=energy_physical(rho, u, problem.box, problem.lam),
-                  energy_fourier=energy_fourier(c, rh, problem.lam),
+                  energy_fourier=energy_fourier(c, rh, problem.lam) + 0.5 * problem.lam * c0 * r0 * r0,
                   rhohat=rh, c=c, k=k, W=W, imag_max=im)

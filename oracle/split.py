@@ -29,7 +29,8 @@ FFT form (padding, index order, normalisation).  At k = 0, M takes its limit:
 bounded), and 0 for the 2D Coulomb kernel (1 - p2 is below 1e-20 there for
 the default scales; the limit of (1 - p2)/|k| itself does not exist).
 
-I2 is Algorithm 1 with the coefficients c_j = (2 pi)^{-d} W_j S(k_j) p(k_j).
+I2 is Algorithm 1 with the coefficients c_j = (2 pi)^{-d} W_j S(k_j) p(k_j) (and,
+for the 2D Poisson kernel, its node at k = 0, where p = 1).
 """
 from __future__ import annotations
 
@@ -40,7 +41,7 @@ from scipy.special import erfc
 
 from .direct import _axes, _cell_volume, rho_hat, sum_to_grid
 from .quadrature import fourier_nodes
-from .symbols import COULOMB_2D, COULOMB_3D, DIPOLE_3D, symbol
+from .symbols import COULOMB_2D, COULOMB_3D, DIPOLE_3D, origin_coefficient, symbol
 
 SIGMA = 2
 
@@ -176,7 +177,8 @@ def energy_split_fourier(problem, rho, par=None, rh=None):
     c = i2_coefficients(problem.kernel, k, W, par, problem.axis, problem.axis2, problem.alpha)
     if rh is None:
         rh = rho_hat(rho, problem.box, k)
-    e2 = float(np.sum(c * np.abs(rh) ** 2))
+    r0 = _cell_volume(rho.shape, problem.box) * float(np.sum(rho))
+    e2 = float(np.sum(c * np.abs(rh) ** 2)) + origin_coefficient(problem.kernel, problem.kmax, problem.n_r) * r0 * r0
     e1 = i1_energy(rho, problem.box, problem.kernel, par, problem.axis, axis2=problem.axis2, alpha=problem.alpha)
     return 0.5 * problem.lam * (e1 + e2)
 
@@ -193,6 +195,8 @@ def potential_split(problem, rho, par=None):
     k, W = fourier_nodes(problem)
     c = i2_coefficients(problem.kernel, k, W, par, problem.axis, problem.axis2, problem.alpha)
     i2 = sum_to_grid(c * rho_hat(rho, problem.box, k), k, rho.shape, problem.box).real
+    # the node at k = 0 of the 2D Poisson kernel belongs to I2 (p(0) = 1)
+    i2 = i2 + origin_coefficient(problem.kernel, problem.kmax, problem.n_r) * _cell_volume(rho.shape, problem.box) * float(np.sum(rho))
     u = i1 + i2
     E = 0.5 * problem.lam * _cell_volume(rho.shape, problem.box) * float(np.sum(rho * u))
     return u, i1, i2, E

@@ -25,6 +25,7 @@ COULOMB_3D = 0
 COULOMB_2D = 1
 DIPOLE_3D = 2
 DIPOLE_2D = 3
+POISSON_2D = 4
 
 FP64 = 0
 MIXED = 1
