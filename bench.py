@@ -241,6 +241,46 @@ def run_algorithm2(steps, warmup, resolved=None, precs=("fp64", "mixed")):
     return out
 
 
+def run_gpe(steps, warmup):
+    """Real-time Strang steps of a dipolar condensate on the 128^3 grid of the
+    dipole workload: psi with axes (1, 1.5, 0.7) normalised, trap (1, 1, 2),
+    beta = 100, lambda = 30 (dipole axis of the workload), dt = 1e-3, the
+    potential by Algorithm 2 with the accuracy-matched I2 nodes.  One step =
+    two local phase kernels, a periodic FFT pair with the kinetic multiplier,
+    and one potential evaluation, replayed from one HIP graph."""
+    import torch
+
+    import paper_1311_4120_amd as jgb
+    import workloads as wl
+
+    out = {"workload": "dipolar GPE on dipole3d_128's grid, real time, potential by Algorithm 2",
+           "dt": 1e-3, "beta": 100.0, "lambda": 30.0, "trap": [1.0, 1.0, 2.0]}
+    for prec in ("fp64", "mixed"):
+        p, rho = wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED, nodes="split")
+        cdt = torch.complex128 if prec == "fp64" else torch.complex64
+        H = float(np.prod([b / m for b, m in zip(p.box, p.n)]))
+        psi0 = np.sqrt(rho)
+        psi0 = psi0 / np.sqrt(H * np.sum(psi0 ** 2))
+        drv = jgb.GPE(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), dt=1e-3, beta=100.0,
+                      trap=(1.0, 1.0, 2.0), eps=p.eps, precision=prec, lam=30.0, axis=p.axis,
+                      theta_rule="costheta", split=True)
+        psi = torch.tensor(psi0, dtype=cdt, device="cuda")
+        drv.step(psi, warmup)
+        torch.cuda.synchronize()
+        _, e0 = drv.energy(psi)
+        t0 = time.perf_counter()
+        drv.step(psi, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        _, e1 = drv.energy(psi)
+        drv.close()
+        out[prec] = {"nodes": [p.n_r, p.n_theta, p.n_phi], "eps": p.eps, "ms_per_step": 1e3 * wall / steps,
+                     "steps_per_s": steps / wall, "potential_evals_per_step": 1,
+                     "norm_drift": abs(e1["norm"] - e0["norm"]), "energy_drift_rel": abs(e1["total"] / e0["total"] - 1),
+                     "energy": e1["total"], "mu": e1["mu"]}
+    return out
+
+
 def run_grad256(steps, warmup):
     """Differentiable dipolar energy on 256^3 (psi = 6 wave packets, complex64,
     mixed precision, nodes (256,128,256)): one step = E(|psi|^2) forward and
@@ -339,6 +379,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--algorithm2-only", action="store_true",
                     help="only time the 128^3 dipole by Algorithm 2 and print its object")
+    ap.add_argument("--gpe-only", action="store_true", help="only time the GPE driver and print its object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy (PMC byte-counter calibration)")
     args = ap.parse_args()
@@ -349,6 +390,9 @@ def main():
         print("bench.py measures one GPU only: the path runs on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.gpe_only:
+        print(json.dumps(run_gpe(args.steps, args.warmup)))
+        return
     if args.algorithm2_only:
         print(json.dumps(run_algorithm2(args.steps, args.warmup,
                                         precs=("fp64", "mixed") if args.only is None else (args.only,))))
@@ -418,6 +462,8 @@ def main():
         out["resolved"] = run_resolved(max(3, args.steps // 5), 2)
         print("[bench] dipole3d_128 by Algorithm 2", file=sys.stderr, flush=True)
         out["algorithm2"] = run_algorithm2(max(3, args.steps // 2), 3, out["resolved"])
+        print("[bench] dipolar GPE, real-time steps", file=sys.stderr, flush=True)
+        out["gpe"] = run_gpe(max(10, args.steps), 3)
         print("[bench] dipole_grad_256: forward + backward", file=sys.stderr, flush=True)
         out["grad_256"] = run_grad256(max(3, args.steps // 10), 2)
         print("[bench] FFT passes against rocFFT", file=sys.stderr, flush=True)

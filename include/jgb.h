@@ -64,8 +64,18 @@ typedef enum {
  *   JGB_DIPOLE_2D  : the 2.5D dipole in the plane, n and m unit 3-vectors with
  *                    in-plane parts n_p, m_p and normal parts n_3, m_3,
  *                    U^ = -alpha + 3 [(n_p.k)(m_p.k) - n_3 m_3 |k|^2] / (2|k|)
- *                    (eqs. dipkernel2d, dipkernelF2d; dipkernel2dd, dipkernelF2dd) */
-typedef enum { JGB_COULOMB_3D = 0, JGB_COULOMB_2D = 1, JGB_DIPOLE_3D = 2, JGB_DIPOLE_2D = 3 } jgb_kernel;
+ *                    (eqs. dipkernel2d, dipkernelF2d; dipkernel2dd, dipkernelF2dd)
+ *   JGB_POISSON_2D : U = -(1/2pi) log|x| in the plane, U^ = 1/|k|^2, the example
+ *                    of a symbol the Jacobian does not cancel (end of Section 4).
+ *                    The radial integrand g(r)/r is not integrable at 0; the log
+ *                    kernel fixes its finite part, and the radial rule is the
+ *                    Gauss-Legendre one with a node at k = 0 of coefficient
+ *                    c_0 = (log K - sum_a w_a / r_a + gamma - log 2) / (2 pi)
+ *                    (jgb_info.origin_coef): u gains c_0 rho^(0), rho^(0) = H sum rho,
+ *                    exact for g polynomial of degree <= 2 n_r. */
+typedef enum {
+  JGB_COULOMB_3D = 0, JGB_COULOMB_2D = 1, JGB_DIPOLE_3D = 2, JGB_DIPOLE_2D = 3, JGB_POISSON_2D = 4
+} jgb_kernel;
 
 /* JGB_FP64: every step in float64.
  * JGB_MIXED: grids, FFTs and kernel taps in float32; nodes, weights, symbol,
@@ -110,8 +120,8 @@ typedef struct {
   int64_t n[3];            /* N_j: even, 8 <= N_j <= 512, 2 N_j of the form 2^a 3^b 5^c;
                               n[2] ignored when dim == 2 */
   double box[3];           /* R_j > 0, full side lengths of B = prod [-R_j/2, R_j/2) */
-  int32_t kernel;          /* jgb_kernel; JGB_COULOMB_2D and JGB_DIPOLE_2D need dim == 2,
-                              the others dim == 3 */
+  int32_t kernel;          /* jgb_kernel; JGB_COULOMB_2D, JGB_DIPOLE_2D and JGB_POISSON_2D need
+                              dim == 2, the others dim == 3 */
   double dipole_axis[3];   /* unit vector n (| |n| - 1 | <= 1e-12); ignored for Coulomb */
   double lambda;           /* interaction constant of eq. gpe2, finite */
   double eps;              /* requested relative L2 accuracy of u (and relative accuracy of E)
@@ -159,6 +169,7 @@ typedef struct {
   int32_t spread_chunk;    /* list entries per spreading block at most */
   uint32_t flags;          /* the plan's JGB_FLAG_* */
   double window[2];        /* JGB_FLAG_SPLIT: the window scales used (a, 0) or (R0, R1); else 0 */
+  double origin_coef;      /* c_0 of the node at k = 0 (JGB_POISSON_2D; 0 for the others) */
 } jgb_info;
 
 /* Build a plan: validates the parameters, generates the Fourier nodes and

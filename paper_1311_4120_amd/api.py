@@ -12,7 +12,7 @@ from . import _lib
 from ._lib import check, lib
 
 _KERNELS = {"coulomb3d": _lib.COULOMB_3D, "coulomb2d": _lib.COULOMB_2D, "dipole3d": _lib.DIPOLE_3D,
-            "dipole2d": _lib.DIPOLE_2D}
+            "dipole2d": _lib.DIPOLE_2D, "poisson2d": _lib.POISSON_2D}
 _RULES = {"theta": _lib.THETA_GL, "costheta": _lib.COSTHETA_GL}
 
 
@@ -61,7 +61,7 @@ class Plan:
     """A planned free-space convolution u = U*rho on one uniform grid.
 
     n, box:    grid points N_j and full side lengths R_j (2 or 3 axes)
-    kernel:    "coulomb3d", "coulomb2d", "dipole3d" or "dipole2d" (or the jgb_kernel ints)
+    kernel:    "coulomb3d", "coulomb2d", "dipole3d", "dipole2d" or "poisson2d" (or the jgb_kernel ints)
     axis:      dipole orientation n (a unit 3-vector, also for "dipole2d")
     axis2:     second orientation m (None: m = n)
     alpha:     the 2.5D dipole's constant

@@ -69,6 +69,7 @@ template <typename T>
 jgb_status run_forward(Plan& pl, const void* rho, hipStream_t st) {
   hipError_t e;
   if ((e = jgb::launch_fft_forward<T>(pl, (const T*)rho, st)) != hipSuccess) return from_hip(e, "forward FFT");
+  if (pl.c0 != 0.0 && (e = jgb::launch_origin(pl, st)) != hipSuccess) return from_hip(e, "origin node");
   if (pl.split && (e = jgb::launch_split_unmix<T>(pl, st)) != hipSuccess) return from_hip(e, "split separation");
   return JGB_OK;
 }
@@ -87,7 +88,7 @@ jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy, hip
   if (energy) {
     double scale = 0.5 * pl.p.lambda * pl.H;
     jgb::stage_mark(pl, jgb::ST_ENERGY, 0, st);
-    e = jgb::launch_energy_finalize(pl.d_eparts, jgb::fft_inverse_z_blocks(pl), scale, energy, st);
+    e = jgb::launch_energy_finalize(pl.d_eparts, jgb::fft_inverse_z_blocks(pl), scale, nullptr, energy, st);
     jgb::stage_mark(pl, jgb::ST_ENERGY, 1, st);
     if (e != hipSuccess) return from_hip(e, "energy");
   }
@@ -109,7 +110,9 @@ jgb_status run_energy(Plan& pl, const void* rho, double* energy) {
     nb += pl.nsym_blocks;
   }
   jgb::stage_mark(pl, jgb::ST_ENERGY, 0, pl.stream);
-  e = jgb::launch_energy_finalize(pl.d_eparts, nb, 0.5 * pl.p.lambda, energy, pl.stream);
+  // the node at k = 0 adds c0 rho^(0)^2
+  e = jgb::launch_energy_finalize(pl.d_eparts, nb, 0.5 * pl.p.lambda, pl.c0 != 0.0 ? pl.d_origin + 1 : nullptr,
+                                  energy, pl.stream);
   jgb::stage_mark(pl, jgb::ST_ENERGY, 1, pl.stream);
   if (e != hipSuccess) return from_hip(e, "energy");
   jgb::call_done(pl);
@@ -501,6 +504,7 @@ jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info) {
   info->flags = pl.p.flags;
   info->window[0] = pl.split ? pl.win[0] : 0.0;
   info->window[1] = pl.split ? pl.win[1] : 0.0;
+  info->origin_coef = pl.c0;
   info->workspace_bytes = (int64_t)pl.workspace_bytes;
   info->interp_chunk = pl.interp_chunk;
   info->spread_chunk = pl.spread_chunk;

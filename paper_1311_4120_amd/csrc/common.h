@@ -159,6 +159,13 @@ struct Plan {
   double* d_eparts = nullptr;  // energy partials
   int neparts = 0;
 
+  // the node at k = 0 of the 2D Poisson kernel: u += c0 H sum rho.  The first
+  // forward pass writes per-block sums of rho (d_mparts, as many as the last
+  // inverse pass has blocks); d_origin = {c0 H sum rho, c0 (H sum rho)^2}.
+  double c0 = 0.0;
+  double* d_mparts = nullptr;
+  double* d_origin = nullptr;
+
   // Algorithm 2 (JGB_FLAG_SPLIT).  The forward FFT transforms rho H / phi^ +
   // i rho H in one go; G's touched tiles first receive the part the
   // interpolation needs, then the spreading result; F receives the combined
@@ -225,8 +232,9 @@ template <typename T>
 hipError_t launch_psi_gradient(const Plan& pl, const void* psi, const void* u, const double* gscale, double factor,
                                void* grad, hipStream_t s);
 // Algorithm 2: the tiles of G the interpolation reads get the transform of
-// rho H / phi^ alone; then the regular-grid symbol of I1 (mode 0: written into
-// F with the Hermitian part of G; mode 1: energy partials at d_eparts + eoff)
+// rho H / phi^ alone; then the regular-grid symbol of I1 (mode 0: the inverse
+// FFT's spectrum written into F with the Hermitian part of G; mode 1: I1's
+// Fourier-side energy partials at d_eparts + eoff)
 template <typename T>
 hipError_t launch_split_unmix(const Plan& pl, hipStream_t s);
 template <typename T>
@@ -239,7 +247,11 @@ jgb_status potential_pipeline(Plan& pl, const void* rho, void* u, double* energy
 int fft_inverse_z_blocks(const Plan& pl);
 int interp_blocks(const Plan& pl);
 hipError_t interp_prepare(const Plan& pl);
-hipError_t launch_energy_finalize(const double* parts, int n, double scale, double* out, hipStream_t s);
+// out = scale (sum of the n parts + *extra); extra may be null
+hipError_t launch_energy_finalize(const double* parts, int n, double scale, const double* extra, double* out,
+                                  hipStream_t s);
+// d_origin from d_mparts (the node at k = 0)
+hipError_t launch_origin(const Plan& pl, hipStream_t s);
 
 }  // namespace jgb
 

@@ -162,6 +162,8 @@ struct PassArgs {
   const T* rho;       // inverse Z: density for the energy partial (nullable)
   double* eparts;     // inverse Z: per-block partials of sum rho u
   int split;          // Z passes of Algorithm 2: forward imag = rho H; inverse u += imag
+  double* mparts;     // forward Z: per-block sums of rho (the node at k = 0), nullable
+  const double* shift;  // inverse Z: constant added to u (the node at k = 0), nullable
 };
 
 // Position on the fine grid of physical index i of a line of N: (i - N/2) mod L.
@@ -260,6 +262,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
   }
   if constexpr (has_factors<KIND>()) __syncthreads();  // factors staged
 
+  double macc = 0.0;  // forward Z: the block's sum of rho
   // load
   {
     const int total_in = LB * a.nin;
@@ -302,6 +305,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
         if constexpr (KIND == PASS_FWD_Z) {
           // deconvolution and cell volume, applied in float64
           const double d = fline[le[i] >> 16] * felem[le[i] & 0xffff];
+          macc += (double)v.x;
           if (a.split) v.y = (T)((double)v.x * a.scale);
           v.x = (T)((double)v.x * d);
         }
@@ -329,6 +333,10 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
 
   // store: LDS reads first, then the global stores
   double eacc = 0.0;
+  double ushift = 0.0;
+  if constexpr (KIND == PASS_INV_Z) {
+    if (a.shift) ushift = *a.shift;
+  }
   {
     const int total_out = LB * a.nout;
     C2<T> buf[MAXV];
@@ -377,7 +385,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
       const int lo = (int)a.dic.div(line);
       const int64_t base = (int64_t)lo * a.out_os + (int64_t)(line - lo * (int)a.ic) * a.out_is + (int64_t)e * a.out_es;
       if constexpr (KIND == PASS_INV_Z) {
-        double u = (double)buf[i].x * (fline[l] * felem[e]);
+        double u = (double)buf[i].x * (fline[l] * felem[e]) + ushift;
         if (a.split) u += (double)buf[i].y;
         ((T*)a.out)[base] = (T)u;
         eacc += (double)rho_v[i] * u;
@@ -387,6 +395,21 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
     }
   }
 
+  if constexpr (KIND == PASS_FWD_Z) {
+    if (a.mparts) {
+      // deterministic block sum of rho: wave shuffle, then waves in order
+      for (int off = 32; off > 0; off >>= 1) macc += __shfl_xor(macc, off, 64);
+      __shared__ double msum[NT / 64];
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) msum[threadIdx.x >> 6] = macc;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += msum[i];
+        a.mparts[blockIdx.x] = s;
+      }
+    }
+  }
   if constexpr (KIND == PASS_INV_Z) {
     if (a.eparts) {
       // deterministic block sum: wave shuffle, then waves in order
@@ -518,6 +541,7 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
     a.dec2 = pl.d_deconv[2];
     a.scale = pl.H;
     a.split = pl.split ? 1 : 0;
+    a.mparts = (pl.c0 != 0.0) ? pl.d_mparts : nullptr;
     if ((e = run_pass<T, PASS_FWD_Z>(pl, ST_FWD_Z, a, s)) != hipSuccess) return e;
   }
   {  // Y: A1 -> A2 [n0][f1][f2]
@@ -624,6 +648,7 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.rho = rho_for_energy;
     a.eparts = rho_for_energy ? pl.d_eparts : nullptr;
     a.split = pl.split ? 1 : 0;
+    a.shift = (pl.c0 != 0.0) ? pl.d_origin : nullptr;
     if ((e = run_pass<T, PASS_INV_Z>(pl, ST_INV_Z, a, s)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -682,6 +707,31 @@ hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, in
 
 template hipError_t launch_fft_periodic<double>(const Plan&, void* const[3], void*, int, hipStream_t);
 template hipError_t launch_fft_periodic<float>(const Plan&, void* const[3], void*, int, hipStream_t);
+
+// d_origin = {c0 H sum rho, c0 (H sum rho)^2} from the first forward pass's
+// per-block sums (one block, fixed order).
+__global__ void __launch_bounds__(256) k_origin(const double* parts, int n, double H, double c0, double* out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += parts[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r0 = H * s[0];
+    out[0] = c0 * r0;
+    out[1] = c0 * r0 * r0;
+  }
+}
+
+hipError_t launch_origin(const Plan& pl, hipStream_t s) {
+  hipLaunchKernelGGL(k_origin, dim3(1), dim3(256), 0, s, pl.d_mparts, fft_inverse_z_blocks(pl), pl.H, pl.c0,
+                     pl.d_origin);
+  return hipGetLastError();
+}
 
 int fft_inverse_z_blocks(const Plan& pl) {
   int lb = pl.fp64 ? lines_per_block<double>(pl.nf[2]) : lines_per_block<float>(pl.nf[2]);

@@ -8,8 +8,10 @@
 //
 // The symbol is carried with the Jacobian, S(k) = |k|^{d-1} U^(k), which is
 // smooth for every kernel here (Section 3.1 after eq. 3.5): 1 for Coulomb,
-// 3 (n.k)(m.k) - (m.n)|k|^2 for the 3D dipole, and -alpha |k| + (3/2)
-// [(n_p.k)(m_p.k) - n_3 m_3 |k|^2] for the 2.5D dipole (linear along each ray).
+// 3 (n.k)(m.k) - (m.n)|k|^2 for the 3D dipole, -alpha |k| + (3/2)
+// [(n_p.k)(m_p.k) - n_3 m_3 |k|^2] for the 2.5D dipole (linear along each ray),
+// and 1/|k| for the 2D Poisson kernel, whose singular radial integrand is
+// completed by the node at k = 0 (plan.hip).
 // It is evaluated as written and U^ is never formed.
 //
 // Only half of the node set is processed downstream: with N_phi even the node
@@ -169,6 +171,7 @@ __device__ double symbol(const NodeParams& q, const double k[3]) {
     const double mk = q.axis2[0] * k[0] + q.axis2[1] * k[1];
     return -q.alpha * sqrt(kk) + 1.5 * (nk * mk - q.axis[2] * q.axis2[2] * kk);
   }
+  if (q.kernel == JGB_POISSON_2D) return 1.0 / sqrt(kk);  // radial nodes are interior: kk > 0
   return 1.0;
 }
 

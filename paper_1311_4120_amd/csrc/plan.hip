@@ -354,7 +354,7 @@ Status validate(const jgb_params* p) {
     if (!is_235(2 * n)) return fail(JGB_ERR_UNSUPPORTED, "2 n[j] must factor into 2, 3 and 5");
     if (!(std::isfinite(p->box[j]) && p->box[j] > 0)) return fail(JGB_ERR_INVALID_ARG, "box[j] must be finite and > 0");
   }
-  if (p->kernel == JGB_COULOMB_2D || p->kernel == JGB_DIPOLE_2D) {
+  if (p->kernel == JGB_COULOMB_2D || p->kernel == JGB_DIPOLE_2D || p->kernel == JGB_POISSON_2D) {
     if (p->dim != 2) return fail(JGB_ERR_INVALID_ARG, "2D kernels need dim == 2");
   } else if (p->kernel == JGB_COULOMB_3D || p->kernel == JGB_DIPOLE_3D) {
     if (p->dim != 3) return fail(JGB_ERR_INVALID_ARG, "3D kernels need dim == 3");
@@ -562,6 +562,18 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   TRY(dev_alloc(pl, &pl.d_gl_t, 2 * sizeof(double) * pl.n_theta));
   TRY_HIP(launch_gl_roots(pl.n_r, pl.d_gl_r, pl.stream), "gl roots");
   TRY_HIP(launch_gl_roots(pl.n_theta, pl.d_gl_t, pl.stream), "gl roots");
+  if (p->kernel == JGB_POISSON_2D) {
+    // the node at k = 0 of the finite-part radial rule: with r_a = K (1 + s_a)/2
+    // and w_a = K omega_a / 2, sum_a w_a / r_a = sum_a omega_a / (1 + s_a)
+    std::vector<double> gl(2 * pl.n_r);
+    TRY_HIP(hipMemcpyAsync(gl.data(), pl.d_gl_r, sizeof(double) * 2 * pl.n_r, hipMemcpyDeviceToHost, pl.stream),
+            "gl copy");
+    TRY_HIP(hipStreamSynchronize(pl.stream), "gl sync");
+    double swr = 0.0;
+    for (int a = 0; a < pl.n_r; ++a) swr += gl[pl.n_r + a] / (1.0 + gl[a]);
+    const double euler_gamma = 0.57721566490153286061;
+    pl.c0 = (std::log(pl.K) - swr + euler_gamma - std::log(2.0)) / (2.0 * M_PI);
+  }
 
   // bin keys of the half node set, stable counting sort on the host
   const int64_t Mh = pl.Mh;
@@ -743,6 +755,10 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     TRY(upload(pl, pl.d_splitk, kt.data(), sizeof(double) * kt.size()));
     const int64_t npts = (int64_t)(pl.nf[0] / 2 + 1) * pl.nf[1] * pl.nf[2];
     pl.nsym_blocks = (int)std::min<int64_t>((npts + 255) / 256, 4096);
+  }
+  if (pl.c0 != 0.0) {
+    TRY(dev_alloc(pl, &pl.d_mparts, sizeof(double) * std::max(fft_inverse_z_blocks(pl), 1)));
+    TRY(dev_alloc(pl, &pl.d_origin, sizeof(double) * 2));
   }
   pl.neparts = std::max(fft_inverse_z_blocks(pl), pl.iitems_cap + pl.nsym_blocks);
   pl.neparts = std::max(pl.neparts, 1);

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) k_spread_reduce(const int* multi, int nmu
   G[((int64_t)g0 * nf1 + g1) * nf2 + g2] = C2<T>{sr, si};
 }
 
-__global__ void k_energy_finalize(const double* parts, int n, double scale, double* out) {
+__global__ void k_energy_finalize(const double* parts, int n, double scale, const double* extra, double* out) {
   __shared__ double s[256];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc += parts[i];
@@ -321,7 +321,7 @@ __global__ void k_energy_finalize(const double* parts, int n, double scale, doub
     if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = scale * s[0];
+  if (threadIdx.x == 0) *out = scale * (s[0] + (extra ? *extra : 0.0));
 }
 
 }  // namespace
@@ -366,8 +366,9 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_energy_finalize(const double* parts, int n, double scale, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_finalize, dim3(1), dim3(256), 0, s, parts, n, scale, out);
+hipError_t launch_energy_finalize(const double* parts, int n, double scale, const double* extra, double* out,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_finalize, dim3(1), dim3(256), 0, s, parts, n, scale, extra, out);
   return hipGetLastError();
 }
 

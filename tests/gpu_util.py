@@ -16,7 +16,7 @@ def make_plan(problem, **kw):
     import paper_1311_4120_amd as jgb
     nodes = (problem.n_r, problem.n_theta, problem.n_phi) if problem.dim == 3 else (problem.n_r, problem.n_phi)
     kernel = {wl.COULOMB_3D: "coulomb3d", wl.COULOMB_2D: "coulomb2d", wl.DIPOLE_3D: "dipole3d",
-              wl.DIPOLE_2D: "dipole2d"}[problem.kernel]
+              wl.DIPOLE_2D: "dipole2d", wl.POISSON_2D: "poisson2d"}[problem.kernel]
     args = dict(eps=problem.eps, precision="fp64" if problem.precision == wl.FP64 else "mixed",
                 lam=problem.lam, axis=problem.axis, theta_rule="theta" if problem.theta_rule == wl.THETA_GL else "costheta",
                 kmax=problem.kmax, axis2=problem.axis2, alpha=problem.alpha)

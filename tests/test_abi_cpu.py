@@ -125,6 +125,7 @@ BAD = [
     ("dipole_axis2 nan", dict(kernel=2, dipole_axis2=(float("nan"), 0.0, 1.0)), 1),
     ("alpha nan", dict(alpha=float("nan")), 1),
     ("dipole2d axis not unit", dict(dim=2, kernel=3, dipole_axis=(0.6, 0.0, 0.0)), 1),
+    ("poisson2d needs dim 2", dict(kernel=4), 1),
 ]
 
 
