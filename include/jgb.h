@@ -49,7 +49,7 @@ extern "C" {
 typedef enum {
   JGB_OK = 0,
   JGB_ERR_INVALID_ARG = 1,   /* a parameter or pointer violates its contract */
-  JGB_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement   */
+  JGB_ERR_UNSUPPORTED = 2,   /* valid request this library does not implement */
   JGB_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed; nothing leaked */
   JGB_ERR_DEVICE = 4         /* a HIP runtime call or kernel launch failed     */
 } jgb_status;
@@ -177,7 +177,7 @@ typedef struct {
  * deconvolution factors and allocates the workspace.  Synchronises the plan's
  * stream before returning.  On success *out owns all plan memory.
  * Errors: INVALID_ARG (NULL pointers, any rule in jgb_params broken),
- * UNSUPPORTED (valid but outside this build), OUT_OF_MEMORY, DEVICE. */
+ * UNSUPPORTED (valid but outside this library's limits), OUT_OF_MEMORY, DEVICE. */
 jgb_status jgb_plan(const jgb_params* params, jgb_plan_t* out);
 
 /* u = U*rho on the grid (Algorithm 1, steps 4-5; with JGB_FLAG_SPLIT,
