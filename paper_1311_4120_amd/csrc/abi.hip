@@ -82,7 +82,6 @@ jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy, hip
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_POTENTIAL, nullptr, st)) != hipSuccess)
     return from_hip(e, "interpolation");
   if ((e = jgb::launch_spread<T>(pl, st)) != hipSuccess) return from_hip(e, "spreading");
-  if (pl.split && (e = jgb::launch_split_symbol<T>(pl, 0, 0, st)) != hipSuccess) return from_hip(e, "split symbol");
   if ((e = jgb::launch_fft_inverse<T>(pl, (T*)u, energy ? (const T*)rho : nullptr, st)) != hipSuccess)
     return from_hip(e, "inverse FFT");
   if (energy) {
@@ -106,7 +105,7 @@ jgb_status run_energy(Plan& pl, const void* rho, double* energy) {
   int nb = jgb::interp_blocks(pl);
   if (pl.split) {
     // I1's share, sum_q M'(q) |rho^(k_q)|^2, as partials after the interpolation's
-    if ((e = jgb::launch_split_symbol<T>(pl, 1, nb, pl.stream)) != hipSuccess) return from_hip(e, "split energy");
+    if ((e = jgb::launch_split_energy<T>(pl, nb, pl.stream)) != hipSuccess) return from_hip(e, "split energy");
     nb += pl.nsym_blocks;
   }
   jgb::stage_mark(pl, jgb::ST_ENERGY, 0, pl.stream);

@@ -232,13 +232,12 @@ template <typename T>
 hipError_t launch_psi_gradient(const Plan& pl, const void* psi, const void* u, const double* gscale, double factor,
                                void* grad, hipStream_t s);
 // Algorithm 2: the tiles of G the interpolation reads get the transform of
-// rho H / phi^ alone; then the regular-grid symbol of I1 (mode 0: the inverse
-// FFT's spectrum written into F with the Hermitian part of G; mode 1: I1's
-// Fourier-side energy partials at d_eparts + eoff)
+// rho H / phi^ alone; I1's Fourier-side energy partials go to d_eparts + eoff
+// (the inverse FFT's first pass forms its own spectrum)
 template <typename T>
 hipError_t launch_split_unmix(const Plan& pl, hipStream_t s);
 template <typename T>
-hipError_t launch_split_symbol(const Plan& pl, int energy_mode, int eoff, hipStream_t s);
+hipError_t launch_split_energy(const Plan& pl, int eoff, hipStream_t s);
 // periodic complex FFT of the plan's N grid in place (sign -1 or +1)
 template <typename T>
 hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, int sign, hipStream_t s);

@@ -24,7 +24,7 @@
 // both halves, and the last pass adds the imaginary part (I1) to u.
 #include <cmath>
 
-#include "common.h"
+#include "splitsym.h"
 
 namespace jgb {
 
@@ -164,6 +164,14 @@ struct PassArgs {
   int split;          // Z passes of Algorithm 2: forward imag = rho H; inverse u += imag
   double* mparts;     // forward Z: per-block sums of rho (the node at k = 0), nullable
   const double* shift;  // inverse Z: constant added to u (the node at k = 0), nullable
+  // the paired first inverse pass of Algorithm 2 (k_fft_pair_pass): lines are
+  // (a, b) of an A x B set, element stride es_in / es_out; P lines and their
+  // mirrors per block; nb1 blocks for the rows 0 < a < A/2 (cb per row), then cs
+  // per row for the rows that are their own mirror (a = 0 and a = A/2)
+  int P, A, B, nb1, cb, cs, dim3;
+  int64_t es_in, es_out;
+  const void* G;
+  SplitSym sym;
 };
 
 // Position on the fine grid of physical index i of a line of N: (i - N/2) mod L.
@@ -427,6 +435,203 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
   }
 }
 
+// Algorithm 2's first inverse pass.  A block takes P lines (a, b) of one row a
+// and their mirrors ((A - a) mod A, (B - b) mod B), so that the element q of a
+// line and its mirror -q (element (L - e) mod L of the mirror line) sit in the
+// block's LDS together.  It forms the spectrum of the inverse FFT there,
+//   Y(q) = (G(q) + conj G(-q)) / 2 + M'(q) (Z(q) - conj Z(-q)) / 2   (splitsym.h),
+// each thread writing Y at q and at -q, transforms both lines and stores the
+// cropped outputs in place.  Every line is owned by one block; a line that is
+// its own mirror sits in two rows of its block, which end up equal.  Registers
+// are capped at 128 (four waves per SIMD), so that two blocks share a CU.
+template <typename T, int MAXV, int NT>
+__global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
+  const int L = a.L;
+  const int ldl = L + 1;
+  const int P = a.P;
+  const int LB = 2 * P;
+  // the block's row and chunk
+  int ar, c;
+  bool self;
+  if ((int)blockIdx.x < a.nb1) {
+    ar = 1 + (int)blockIdx.x / a.cb;
+    c = (int)blockIdx.x % a.cb;
+    self = false;
+  } else {
+    const int sb = (int)blockIdx.x - a.nb1;
+    ar = (sb / a.cs == 0) ? 0 : a.A / 2;
+    c = sb % a.cs;
+    self = true;
+  }
+  // line slot l < P: own line (ar, c P + l); l >= P: the mirror of slot l - P
+  auto line_of = [&](int l, int& la, int& lb) {
+    const int j = (l < P) ? l : l - P;
+    int bq = c * P + j;
+    const bool valid = self ? (bq <= a.B / 2) : (bq < a.B);
+    if (!valid) bq = 0;
+    if (l < P) {
+      la = ar;
+      lb = bq;
+    } else {
+      la = (a.A - ar) % a.A;
+      lb = (a.B - bq) % a.B;
+    }
+    return valid;
+  };
+  const C2<T>* Z = (const C2<T>*)a.in;
+  const SplitSym& sy = a.sym;
+  // tables after the lines: the element axis's frequencies and window values,
+  // per line slot the constant parts of |k|^2, p, n.k and m.k, and the line's
+  // row of gather-tile flags along the element axis
+  const int ea = a.dim3 ? 0 : 1;                              // the element axis
+  const int gse = a.dim3 ? sy.gs0 : sy.gs1;                    // its tile shift
+  const int ngte = (L + (1 << gse) - 1) >> gse;                // its tiles
+  double* sk = reinterpret_cast<double*>(smem_raw + (size_t)LB * ldl * sizeof(C2<T>));
+  double* se = sk + L;
+  double* lkk = se + L;
+  double* lw = lkk + LB;
+  double* lnk = lw + LB;
+  double* lmk = lnk + LB;
+  unsigned char* ltf = reinterpret_cast<unsigned char*>(lmk + LB);  // LB x ngte
+  // load both line sets, all loads issued before the LDS writes
+  {
+    const int total_in = LB * L;
+    C2<T> buf[MAXV];
+    int dst[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx0 = threadIdx.x + i * NT;
+      const bool ok = idx0 < total_in;
+      const int idx = ok ? idx0 : 0;
+      const int e = (int)a.dLB.div(idx);
+      const int l = idx - e * LB;
+      int la, lb;
+      const bool valid = line_of(l, la, lb) && ok;
+      const C2<T> v = Z[(int64_t)e * a.es_in + (int64_t)la * a.B + lb];
+      buf[i] = valid ? v : C2<T>{T(0), T(0)};
+      dst[i] = ok ? l * ldl + e : -1;
+    }
+    for (int t = threadIdx.x; t < L + LB + LB * ngte; t += NT) {
+      if (t < L) {
+        sk[t] = sy.kt[sy.koff[ea] + t];
+        se[t] = sy.kt[sy.eoff[ea] + t];
+      } else if (t < L + LB) {
+        const int l = t - L;
+        int la, lb;
+        line_of(l, la, lb);
+        const double k2 = sy.kt[sy.koff[2] + lb];
+        double k1 = 0.0, w = 1.0;
+        if (a.dim3) {
+          k1 = sy.kt[sy.koff[1] + la];
+          w = sy.kt[sy.eoff[1] + la] * sy.kt[sy.eoff[2] + lb];
+        }
+        lkk[l] = k1 * k1 + k2 * k2;
+        lw[l] = w;
+        // n.k over the physical axes: 3D (x1, x2, x3) = (a0, a1, a2), the
+        // element carrying n_1; 2D (x1, x2) = (a1, a2), the element again n_1
+        lnk[l] = a.dim3 ? sy.axis[1] * k1 + sy.axis[2] * k2 : sy.axis[1] * k2;
+        lmk[l] = a.dim3 ? sy.axis2[1] * k1 + sy.axis2[2] * k2 : sy.axis2[1] * k2;
+      } else {
+        const int r = t - L - LB;
+        const int l = r / ngte, te = r - l * ngte;
+        int la, lb;
+        line_of(l, la, lb);
+        const int tile = a.dim3 ? ((te * sy.gnt1 + (la >> sy.gs1)) * sy.gnt2 + (lb >> sy.gs2))
+                                : (te * sy.gnt2 + (lb >> sy.gs2));
+        ltf[l * ngte + te] = sy.tflag[tile];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (dst[i] >= 0) lds[dst[i]] = buf[i];
+  }
+  __syncthreads();
+  // form Y at every element pair (own line l, element e) <-> (mirror slot l + P, (L - e) mod L)
+  {
+    const C2<T>* G = (const C2<T>*)a.G;
+    const bool dip = sy.kernel == JGB_DIPOLE_3D || sy.kernel == JGB_DIPOLE_2D;
+    for (int idx = threadIdx.x; idx < P * L; idx += NT) {
+      const int e = idx / P;
+      const int l = idx - e * P;
+      int la, lb;
+      if (!line_of(l, la, lb)) continue;
+      const int em = (L - e) % L;
+      const int lm = l + P;
+      const double ke = sk[e];
+      double M = split_symbol_core(sy, ke * ke + lkk[l], se[e] * lw[l], sy.axis[0] * ke + lnk[l],
+                                   sy.axis2[0] * ke + lmk[l]);
+      if (dip) {
+        // the mean with the mirror's symbol (equal to it bit for bit off the
+        // Nyquist planes, where the mirror's k is exactly -k)
+        const double km = sk[em];
+        M = 0.5 * (M + split_symbol_core(sy, km * km + lkk[lm], se[em] * lw[lm], sy.axis[0] * km + lnk[lm],
+                                         sy.axis2[0] * km + lmk[lm]));
+      }
+      C2<T>* pq = lds + l * ldl + e;
+      C2<T>* pm = lds + lm * ldl + em;
+      const C2<T> zq = *pq, zm = *pm;
+      const T hm = (T)(0.5 * M);
+      // D(q) = Z(q) - conj Z(-q) = 2 i B(q); D(-q) = -conj D(q)
+      const T dx = zq.x - zm.x, dy = zq.y + zm.y;
+      C2<T> gq{T(0), T(0)}, gm{T(0), T(0)};
+      if (ltf[l * ngte + (e >> gse)]) {
+        const int q0 = a.dim3 ? e : 0, q1 = a.dim3 ? la : e;
+        gq = G[((int64_t)q0 * sy.nf1 + q1) * sy.nf2 + lb];
+      }
+      if (ltf[lm * ngte + (em >> gse)]) {
+        int ma, mb;
+        line_of(lm, ma, mb);
+        const int m0 = a.dim3 ? em : 0, m1 = a.dim3 ? ma : em;
+        gm = G[((int64_t)m0 * sy.nf1 + m1) * sy.nf2 + mb];
+      }
+      *pq = C2<T>{T(0.5) * (gq.x + gm.x) + hm * dx, T(0.5) * (gq.y - gm.y) + hm * dy};
+      *pm = C2<T>{T(0.5) * (gm.x + gq.x) - hm * dx, T(0.5) * (gm.y - gq.y) + hm * dy};
+    }
+  }
+  __syncthreads();
+  // FFT stages over the 2P lines
+  int Ns = 1;
+  for (int st = 0; st < a.nrad; ++st) {
+    const int R = a.rad[st];
+    const FastDiv& dNs = a.dNs[st];
+    const int tws = a.tws[st];
+    switch (R) {
+      case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+      default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+    }
+    Ns *= R;
+  }
+  // store the cropped outputs of both line sets
+  {
+    const int total_out = LB * a.nout;
+    C2<T> buf[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx0 = threadIdx.x + i * NT;
+      const int idx = idx0 < total_out ? idx0 : 0;
+      const int e = (int)a.dLB.div(idx);
+      const int l = idx - e * LB;
+      buf[i] = lds[l * ldl + fine_pos(e, a.nout, L)];
+    }
+    C2<T>* out = (C2<T>*)a.out;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      const int idx = threadIdx.x + i * NT;
+      if (idx >= total_out) continue;
+      const int e = (int)a.dLB.div(idx);
+      const int l = idx - e * LB;
+      int la, lb;
+      if (!line_of(l, la, lb)) continue;
+      out[(int64_t)e * a.es_out + (int64_t)la * a.B + lb] = buf[i];
+    }
+  }
+}
+
 void factor(int L, int* rad, int& nrad) {
   nrad = 0;
   int m = L;
@@ -495,6 +700,39 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   constexpr int MAXV = pass_elems<T>();
   stage_mark(pl, stage, 0, s);
   hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
+  stage_mark(pl, stage, 1, s);
+  return hipGetLastError();
+}
+
+// The paired first inverse pass of Algorithm 2 along the internal axis `axis`
+// (0 in 3D: lines (q1, q2); 1 in 2D: lines q2), from Z in F to `out`.
+template <typename T>
+hipError_t run_pair_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
+  factor(a.L, a.rad, a.nrad);
+  {
+    int Ns = 1;
+    for (int st = 0; st < a.nrad; ++st) {
+      a.dNs[st] = FastDiv((uint32_t)Ns);
+      a.tws[st] = a.L / (Ns * a.rad[st]);
+      Ns *= a.rad[st];
+    }
+  }
+  const int lb = lines_per_block<T>(a.L);
+  a.P = lb / 2 > 0 ? lb / 2 : 1;
+  a.LB = 2 * a.P;
+  a.dLB = FastDiv((uint32_t)a.LB);
+  a.cb = (a.B + a.P - 1) / a.P;
+  a.cs = (a.B / 2 + 1 + a.P - 1) / a.P;
+  a.nb1 = (a.A > 1) ? (a.A / 2 - 1) * a.cb : 0;
+  const unsigned blocks = (unsigned)(a.nb1 + (a.A > 1 ? 2 : 1) * a.cs);
+  const int gse = a.dim3 ? a.sym.gs0 : a.sym.gs1;
+  const int ngte = (a.L + (1 << gse) - 1) >> gse;
+  const size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>) + sizeof(double) * (2 * a.L + 4 * a.LB) +
+                      (size_t)a.LB * ngte;
+  constexpr int NT = pass_threads<T>();
+  constexpr int MAXV = pass_elems<T>();
+  stage_mark(pl, stage, 0, s);
+  hipLaunchKernelGGL((k_fft_pair_pass<T, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
   stage_mark(pl, stage, 1, s);
   return hipGetLastError();
 }
@@ -586,13 +824,30 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
   const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
   const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
   const bool has_x = f0 > 1;
-  // the input spectrum: the spreading grid, or F holding both halves of
-  // Algorithm 2; the X pass may run in place on F (each block reads all of its
-  // lines before it writes them back, and no two blocks share a line)
+  // the input spectrum: the spreading grid, or for Algorithm 2 the forward
+  // spectrum Z in F (with G); the first pass may run in place on F (each block
+  // reads all of its lines before it writes them back, and no two blocks share
+  // a line)
   void* src = pl.split ? pl.d_F : pl.d_G;
   void* B2 = has_x ? pl.d_F : src;  // (2D: the input grid itself)
   void* B1 = pl.d_W;
   hipError_t e;
+  // Algorithm 2: the first pass forms its spectrum from Z (in F) and G, line
+  // pairs at a time (k_fft_pair_pass)
+  auto pair_args = [&](int axis) {
+    PassArgs<T> a = base_args<T>(pl, axis, T(1));
+    a.nin = (int)pl.nf[axis];
+    a.nout = (int)pl.n[axis];
+    a.A = has_x ? (int)f1 : 1;
+    a.B = (int)f2;
+    a.es_in = has_x ? f1 * f2 : f2;
+    a.es_out = a.es_in;
+    a.dim3 = has_x ? 1 : 0;
+    a.in = pl.d_F;
+    a.G = pl.d_G;
+    a.sym = make_split_sym(pl);
+    return a;
+  };
   if (has_x) {  // X: src -> B2 [n0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 0, T(1));
     a.nlines = f1 * f2;
@@ -608,9 +863,20 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.lines_fastest = 1;
     a.in = src;
     a.out = B2;
-    if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_X, a, s)) != hipSuccess) return e;
+    if (pl.split) {
+      PassArgs<T> b = pair_args(0);
+      b.out = B2;
+      e = run_pair_pass<T>(pl, ST_INV_X, b, s);
+    } else {
+      e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_X, a, s);
+    }
+    if (e != hipSuccess) return e;
   }
-  {  // Y: B2 -> B1 [n0][n1][f2]
+  if (pl.split && !has_x) {  // 2D Algorithm 2: Y: F -> B1 [1][n1][f2], paired
+    PassArgs<T> b = pair_args(1);
+    b.out = B1;
+    if ((e = run_pair_pass<T>(pl, ST_INV_Y, b, s)) != hipSuccess) return e;
+  } else {  // Y: B2 -> B1 [n0][n1][f2]
     PassArgs<T> a = base_args<T>(pl, 1, T(1));
     a.nlines = n0 * f2;
     a.nin = (int)f1;

@@ -11,9 +11,10 @@
 // a real field; I2 = Re of the type-1 sum of the spreading grid G, which is the
 // inverse transform of G's Hermitian part (G(q) + conj G(-q)) / 2.  Both go
 // into one spectrum Y = Herm(G) + i M' B, so a single inverse FFT returns
-// I2 phi^ in its real part and I1 in its imaginary part.  This file holds the
-// separation of A for the interpolation, the pass that writes Y into F, and
-// the Fourier-side energy of I1.
+// I2 phi^ in its real part and I1 in its imaginary part; its first pass forms
+// Y with each line and its mirror in LDS (fft.hip, k_fft_pair_pass).  This file
+// holds the separation of A for the interpolation and the Fourier-side energy
+// of I1.
 //
 // Index conventions: internal axes (a0, a1, a2), a2 contiguous; the mirror of
 // fine index q on an axis of nf points is (nf - q) mod nf, and the signed
@@ -63,19 +64,15 @@ __global__ void __launch_bounds__(256) k_split_unmix(SplitSym g, const int* touc
   }
 }
 
-// Over the pairs {q, -q} (planes q0 <= nf0/2; in the planes that are their
-// own mirror, the member with the smaller linear index takes the pair):
-//   MODE 0: F(q) <- Y(q) = Herm(G)(q) + M'(q) (Z(q) - conj Z(-q)) / 2, and the
-//           same at -q, in place (each pair is read and written by one
-//           thread; G is read only at touched tiles);
-//   MODE 1: energy partials of I1 per block, sum_q M'(q) |B(q)|^2 with
-//           |B(q)|^2 = |Z(q) - conj Z(-q)|^2 / 4 (a pair counts twice unless
-//           it is its own mirror); nothing written.
-// A thread walks its pairs with a stride of the grid, consecutive threads on
+// Energy partials of I1 per block, sum_q M'(q) |B(q)|^2 with |B(q)|^2 =
+// |Z(q) - conj Z(-q)|^2 / 4, over the pairs {q, -q} (planes q0 <= nf0/2; in
+// the planes that are their own mirror, the member with the smaller linear
+// index takes the pair, which counts twice unless it is its own mirror).  A
+// thread walks its pairs with a stride of the grid, consecutive threads on
 // consecutive q2 (the mirrors run backwards, still contiguous).
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_split_symbol(SplitSym s, FastDiv d12, FastDiv d2, uint32_t npoints,
-                                                      C2<T>* F, const C2<T>* __restrict__ G, double* eparts) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_split_energy(SplitSym s, FastDiv d12, FastDiv d2, uint32_t npoints,
+                                                      const C2<T>* __restrict__ F, double* eparts) {
   const uint32_t nf12 = (uint32_t)s.nf1 * s.nf2;
   double eacc = 0.0;
   const uint32_t stride = gridDim.x * 256u;
@@ -88,31 +85,17 @@ __global__ void __launch_bounds__(256) k_split_symbol(SplitSym s, FastDiv d12, F
     const int64_t iq = ((int64_t)q0 * s.nf1 + q1) * s.nf2 + q2;
     const int64_t im = ((int64_t)m0 * s.nf1 + m1) * s.nf2 + m2;
     if (m0 == q0 && im < iq) continue;
-    const bool self = (im == iq);
     const C2<T> zq = F[iq], zm = F[im];
     const double M = split_symbol_even(s, q0, q1, q2, m0, m1, m2);
-    if constexpr (MODE == 1) {
-      const double dx = (double)zq.x - zm.x, dy = (double)zq.y + zm.y;
-      eacc += (self ? 0.25 : 0.5) * M * (dx * dx + dy * dy);
-    } else {
-      // D(q) = Z(q) - conj Z(-q) = 2 i B(q); D(-q) = -conj D(q)
-      const T dx = zq.x - zm.x, dy = zq.y + zm.y;
-      C2<T> gq{T(0), T(0)}, gm{T(0), T(0)};
-      if (s.tflag[split_tile(s, q0, q1, q2)]) gq = G[iq];
-      if (s.tflag[split_tile(s, m0, m1, m2)]) gm = G[im];
-      const T hm = (T)(0.5 * M);
-      F[iq] = C2<T>{T(0.5) * (gq.x + gm.x) + hm * dx, T(0.5) * (gq.y - gm.y) + hm * dy};
-      if (!self) F[im] = C2<T>{T(0.5) * (gm.x + gq.x) - hm * dx, T(0.5) * (gm.y - gq.y) + hm * dy};
-    }
+    const double dx = (double)zq.x - zm.x, dy = (double)zq.y + zm.y;
+    eacc += (im == iq ? 0.25 : 0.5) * M * (dx * dx + dy * dy);
   }
-  if constexpr (MODE == 1) {
-    // deterministic block sum: wave shuffle, then the four waves in order
-    for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
-    __shared__ double wsum[4];
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = eacc;
-    __syncthreads();
-    if (threadIdx.x == 0) eparts[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
-  }
+  // deterministic block sum: wave shuffle, then the four waves in order
+  for (int off = 32; off > 0; off >>= 1) eacc += __shfl_xor(eacc, off, 64);
+  __shared__ double wsum[4];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = eacc;
+  __syncthreads();
+  if (threadIdx.x == 0) eparts[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
 }
 
 }  // namespace
@@ -163,24 +146,19 @@ hipError_t launch_split_unmix(const Plan& pl, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_split_symbol(const Plan& pl, int energy_mode, int eoff, hipStream_t s) {
+hipError_t launch_split_energy(const Plan& pl, int eoff, hipStream_t s) {
   const uint32_t npoints = (uint32_t)(pl.nf[0] / 2 + 1) * pl.nf[1] * pl.nf[2];
-  const SplitSym sym = make_split_sym(pl);
-  const FastDiv d12((uint32_t)pl.nf[1] * pl.nf[2]), d2((uint32_t)pl.nf[2]);
   stage_mark(pl, ST_SPLIT_SYMBOL, 0, s);
-  if (energy_mode)
-    hipLaunchKernelGGL((k_split_symbol<T, 1>), dim3(pl.nsym_blocks), dim3(256), 0, s, sym, d12, d2, npoints,
-                       (C2<T>*)pl.d_F, (const C2<T>*)pl.d_G, pl.d_eparts + eoff);
-  else
-    hipLaunchKernelGGL((k_split_symbol<T, 0>), dim3(pl.nsym_blocks), dim3(256), 0, s, sym, d12, d2, npoints,
-                       (C2<T>*)pl.d_F, (const C2<T>*)pl.d_G, pl.d_eparts + eoff);
+  hipLaunchKernelGGL(k_split_energy<T>, dim3(pl.nsym_blocks), dim3(256), 0, s, make_split_sym(pl),
+                     FastDiv((uint32_t)pl.nf[1] * pl.nf[2]), FastDiv((uint32_t)pl.nf[2]), npoints,
+                     (const C2<T>*)pl.d_F, pl.d_eparts + eoff);
   stage_mark(pl, ST_SPLIT_SYMBOL, 1, s);
   return hipGetLastError();
 }
 
 template hipError_t launch_split_unmix<double>(const Plan&, hipStream_t);
 template hipError_t launch_split_unmix<float>(const Plan&, hipStream_t);
-template hipError_t launch_split_symbol<double>(const Plan&, int, int, hipStream_t);
-template hipError_t launch_split_symbol<float>(const Plan&, int, int, hipStream_t);
+template hipError_t launch_split_energy<double>(const Plan&, int, hipStream_t);
+template hipError_t launch_split_energy<float>(const Plan&, int, hipStream_t);
 
 }  // namespace jgb

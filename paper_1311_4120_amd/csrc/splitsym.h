@@ -1,5 +1,6 @@
 // Algorithm 2's regular-grid spectrum (Section 3.3, eq. 3.9): the symbol of I1
-// and the geometry of the pass that forms the inverse FFT's input (split.hip).
+// and the tile geometry, shared by the inverse FFT's first pass (fft.hip),
+// which forms the spectrum, and the energy kernel (split.hip).
 //
 // The forward FFT of rho H / phi^ + i rho H gives Z = A + i B, with
 // B(q) = (Z(q) - conj Z(-q)) / (2 i) = rho^(k_q) at k_q = 2 pi q' / (2 R_j)
