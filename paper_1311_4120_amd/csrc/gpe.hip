@@ -21,6 +21,9 @@
 #include "common.h"
 
 namespace jgb {
+
+Status validate(const jgb_params* p);
+
 namespace {
 
 template <typename T>
@@ -416,6 +419,11 @@ jgb_status jgb_gpe_create(const jgb_gpe_params* params, jgb_gpe_t* out) {
   if (params->imaginary != 0 && params->imaginary != 1) return gpe_report(JGB_ERR_INVALID_ARG, "imaginary must be 0 or 1");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(params->trap[i])) return gpe_report(JGB_ERR_INVALID_ARG, "trap must be finite");
+  {
+    // the potential's parameters are checked before any device work
+    jgb::Status v = jgb::validate(&params->potential);
+    if (v.code != JGB_OK) return gpe_report(v.code, "potential plan: " + v.msg);
+  }
   jgb_gpe_s* q = new (std::nothrow) jgb_gpe_s();
   if (!q) return gpe_report(JGB_ERR_OUT_OF_MEMORY, "host allocation failed");
   q->device = params->potential.device;

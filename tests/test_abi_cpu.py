@@ -192,3 +192,68 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def _gpe_params(**kw):
+    L = _lib()
+    g = L.GpeParams()
+    g.struct_size = ctypes.sizeof(L.GpeParams)
+    g.potential = _params()
+    g.dt = 0.01
+    g.beta = 1.0
+    g.imaginary = 0
+    for k, v in kw.items():
+        if k == "trap":
+            for i, x in enumerate(v):
+                g.trap[i] = x
+        else:
+            setattr(g, k, v)
+    return g
+
+
+GPE_BAD = [
+    ("struct_size", dict(struct_size=8)),
+    ("dt zero", dict(dt=0.0)),
+    ("dt nan", dict(dt=float("nan"))),
+    ("beta inf", dict(beta=float("inf"))),
+    ("imaginary flag", dict(imaginary=2)),
+    ("trap nan", dict(trap=(1.0, float("nan"), 1.0))),
+]
+
+
+@pytest.mark.parametrize("name,kw", GPE_BAD, ids=[b[0] for b in GPE_BAD])
+def test_gpe_invalid_parameters(name, kw):
+    L = _lib()
+    g = _gpe_params(**kw)
+    h = ctypes.c_void_p()
+    assert L.lib.jgb_gpe_create(ctypes.byref(g), ctypes.byref(h)) == L.JGB_ERR_INVALID_ARG
+    assert not h.value
+    assert L.lib.jgb_last_error()
+
+
+def test_gpe_null_arguments_and_layout(tmp_path):
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.lib.jgb_gpe_create(None, ctypes.byref(h)) == L.JGB_ERR_INVALID_ARG
+    assert L.lib.jgb_gpe_step(None, None, 1, 1) == L.JGB_ERR_INVALID_ARG
+    assert L.lib.jgb_gpe_energy(None, None, None) == L.JGB_ERR_INVALID_ARG
+    assert L.lib.jgb_gpe_destroy(None) == L.JGB_OK
+    src = tmp_path / "g.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "jgb.h"\n'
+                   'int main(){printf("%zu %zu %zu %zu\\n", sizeof(jgb_gpe_params), offsetof(jgb_gpe_params, V),'
+                   ' offsetof(jgb_gpe_params, dt), offsetof(jgb_gpe_params, imaginary)); return 0;}\n')
+    exe = tmp_path / "g"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert vals == [ctypes.sizeof(L.GpeParams), L.GpeParams.V.offset, L.GpeParams.dt.offset,
+                    L.GpeParams.imaginary.offset]
+
+
+def test_gpe_invalid_potential_is_reported():
+    # the driver's own fields are valid, the potential's are not: the plan's error comes back
+    L = _lib()
+    g = _gpe_params()
+    g.potential.dim = 5
+    h = ctypes.c_void_p()
+    assert L.lib.jgb_gpe_create(ctypes.byref(g), ctypes.byref(h)) == L.JGB_ERR_INVALID_ARG
+    assert b"potential plan" in L.lib.jgb_last_error()
