@@ -125,13 +125,19 @@ Status upload(Plan& pl, void* dst, const void* src, size_t bytes) {
 // and are cut into eight contiguous runs, one per XCD (the hardware hands
 // block p to XCD p mod 8, each XCD with its own L2), so that neighbouring
 // items -- which read the same node records and grid halos -- share an L2.
-// Each class is padded to a multiple of eight with idle items.
-template <typename Item, typename Cost>
-std::vector<Item> dispatch_order(const std::vector<Item>& items, Cost cost, const Item& idle) {
+// Each class is padded to a multiple of eight with idle items.  The spatial
+// order is that of `key` (the Morton code of the tile's or bin's coordinates),
+// so that the items a CU group has in flight at once form a compact 3D block
+// rather than a thin slab, and a node's neighbouring tiles meet in one L2.
+template <typename Item, typename Cost, typename Key>
+std::vector<Item> dispatch_order(const std::vector<Item>& items, Cost cost, const Item& idle, Key key) {
   constexpr int kXcd = 8;
   auto cls = [&](const Item& it) { return (int)std::floor(std::log(1.0 + cost(it)) / std::log(1.5)); };
   std::vector<Item> o = items;
-  std::stable_sort(o.begin(), o.end(), [&](const Item& x, const Item& y) { return cls(x) > cls(y); });
+  std::stable_sort(o.begin(), o.end(), [&](const Item& x, const Item& y) {
+    const int cx = cls(x), cy = cls(y);
+    return cx != cy ? cx > cy : key(x) < key(y);
+  });
   std::vector<Item> out;
   size_t b = 0;
   while (b < o.size()) {
@@ -150,6 +156,15 @@ std::vector<Item> dispatch_order(const std::vector<Item>& items, Cost cost, cons
   return out;
 }
 
+// Morton code of three 10-bit coordinates (bits interleaved, a2 lowest).
+uint64_t morton3(uint32_t a0, uint32_t a1, uint32_t a2) {
+  uint64_t m = 0;
+  for (int b = 0; b < 10; ++b)
+    m |= ((uint64_t)((a2 >> b) & 1) << (3 * b)) | ((uint64_t)((a1 >> b) & 1) << (3 * b + 1)) |
+         ((uint64_t)((a0 >> b) & 1) << (3 * b + 2));
+  return m;
+}
+
 // Interpolation work items: nonempty sub-bins, split into runs of at most
 // chunk nodes.
 std::vector<Plan::InterpItem> interp_items(const Plan& pl, int chunk) {
@@ -157,8 +172,14 @@ std::vector<Plan::InterpItem> interp_items(const Plan& pl, int chunk) {
   const std::vector<int>& ss = pl.h_sub_start;
   for (size_t k = 0; k + 1 < ss.size(); ++k)
     for (int b = ss[k]; b < ss[k + 1]; b += chunk) iit.push_back(Plan::InterpItem{(int)k, b, std::min(ss[k + 1], b + chunk)});
+  const int nsub = pl.nsub, n12 = pl.nt[1] * pl.nt[2];
+  auto key = [&](const Plan::InterpItem& it) {
+    const int bin = it.sub / nsub;
+    const int b0 = bin / n12, r = bin - b0 * n12, b1 = r / pl.nt[2], b2 = r - b1 * pl.nt[2];
+    return (morton3(b0, b1, b2) << 8) | (uint64_t)(it.sub - bin * nsub);
+  };
   return dispatch_order(iit, [](const Plan::InterpItem& it) { return (double)(it.end - it.begin); },
-                        Plan::InterpItem{-1, 0, 0});
+                        Plan::InterpItem{-1, 0, 0}, key);
 }
 
 // Gather work items: one block per tile, tiles with longer lists split into
@@ -186,8 +207,13 @@ void spread_items(const Plan& pl, int chunk, std::vector<WorkItem>& items, std::
       nslots += k;
     }
   }
+  const int n12 = pl.gnt[1] * pl.gnt[2];
+  auto key = [&](const WorkItem& it) {
+    const int t0 = it.tile / n12, r = it.tile - t0 * n12, t1 = r / pl.gnt[2], t2 = r - t1 * pl.gnt[2];
+    return morton3(t0, t1, t2);
+  };
   items = dispatch_order(items, [](const WorkItem& it) { return (double)(it.vend - it.vbegin); },
-                         WorkItem{-1, 0, 0, -1});
+                         WorkItem{-1, 0, 0, -1}, key);
 }
 
 Status apply_interp_chunk(Plan& pl, int chunk) {
