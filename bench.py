@@ -159,6 +159,17 @@ def run_gpu(prec, steps, warmup, nodes="pattern"):
         u, E = plan.potential(rt, out=u)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # per-step durations (HIP events around each call on the plan's stream), in
+    # a separate run: median and the p10-p90 range
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in evs:
+        a.record(plan.stream)
+        plan.potential(rt, out=u)
+        b.record(plan.stream)
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    step_pct = {"p10": float(np.percentile(per, 10)), "median": float(np.median(per)),
+                "p90": float(np.percentile(per, 90))}
     # per-stage durations from HIP events on the plan's stream, in a separate
     # run of the same steps
     plan.timing_begin(steps)
@@ -169,7 +180,7 @@ def run_gpu(prec, steps, warmup, nodes="pattern"):
     energy = float(E.item())
     info = plan.info
     plan.close()
-    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "stages_ms": stages, "calls": ncalls,
+    return {"wall_s": wall, "ms_per_step": 1e3 * wall / steps, "step_ms": step_pct, "stages_ms": stages, "calls": ncalls,
             "plan_s": plan_s, "energy": energy, "info": info, "eps": p.eps,
             "tuned": {"interp_chunk": info["interp_chunk"], "spread_chunk": info["spread_chunk"]}}
 
@@ -440,6 +451,7 @@ def main():
                    "n_nodes": r["info"]["n_nodes"], "eps": r["eps"], "width": r["info"]["width"],
                    "oversampled_grid": r["info"]["nf"]},
         "ns_per_point": r["ms_per_step"] * 1e6 / npts,
+        "step_ms": r["step_ms"],
         "energy": r["energy"],
         "plan_s": r["plan_s"],
         "autotuned": r["tuned"],
@@ -451,6 +463,7 @@ def main():
     if "mixed" in res and head == "fp64":
         m = res["mixed"]
         out["mixed"] = {"value": 1e3 / m["ms_per_step"], "unit": "evals/s", "ms_per_step": m["ms_per_step"],
+                        "step_ms": m["step_ms"],
                         "ns_per_point": m["ms_per_step"] * 1e6 / npts, "eps": m["eps"],
                         "width": m["info"]["width"], "energy": m["energy"],
                         "speedup_vs_fp64": r["ms_per_step"] / m["ms_per_step"],
