@@ -657,17 +657,41 @@ void factor(int L, int* rad, int& nrad) {
   }
 }
 
-// Block shape: 512 threads with at most 8 (fp64) or 16 (fp32) complex elements
-// each, so 4096 or 8192 elements (64 KB) staged per block; up to 16 or 32
-// lines, which makes every strided-pass row of a block 256 contiguous bytes.
-template <typename T>
-constexpr int pass_threads() { return 512; }
-template <typename T>
-constexpr int pass_elems() { return sizeof(T) == 8 ? 8 : 16; }
+// Block shapes (threads x complex elements per thread; the staged elements
+// cap / L give the lines per block).  Measured on the 256-point lines of the
+// 128^3 grids: the strided passes keep every row of a block at 128 contiguous
+// bytes (8 fp64 or 16 fp32 lines) with four or more blocks per CU, the Z
+// passes stage 2048 elements per block, and the paired pass of Algorithm 2
+// keeps the 512 x 8 or 16 shape its register budget was tuned for.  Every cap
+// holds a whole line of the largest grid (nf = 1024).
+constexpr int PASS_PAIR = 9;
+template <typename T, int KIND = PASS_PAIR>
+constexpr int pass_threads() {
+  if (KIND == PASS_COMPLEX) return sizeof(T) == 8 ? 256 : 512;
+  if (KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 256;
+  return 512;
+}
+template <typename T, int KIND = PASS_PAIR>
+constexpr int pass_elems() {
+  if (KIND == PASS_COMPLEX || KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 8;
+  return sizeof(T) == 8 ? 8 : 16;
+}
+template <typename T, int KIND>
+constexpr int pass_cap() { return pass_threads<T, KIND>() * pass_elems<T, KIND>(); }
+static_assert(pass_cap<double, PASS_COMPLEX>() >= 1024 && pass_cap<float, PASS_COMPLEX>() >= 1024 &&
+                  pass_cap<double, PASS_FWD_Z>() >= 1024 && pass_cap<float, PASS_FWD_Z>() >= 1024 &&
+                  pass_cap<double, PASS_COMPLEX_Z>() >= 1024 && pass_cap<float, PASS_PAIR>() >= 1024,
+              "a block must stage at least one line of nf = 1024 points");
+// The first forward and last inverse passes run the same lines with the same
+// shape: their per-block partial sums (d_mparts, d_eparts) are counted once,
+// by fft_inverse_z_blocks.
+static_assert(pass_cap<double, PASS_FWD_Z>() == pass_cap<double, PASS_INV_Z>() &&
+                  pass_cap<float, PASS_FWD_Z>() == pass_cap<float, PASS_INV_Z>(),
+              "the Z passes share their block shape");
 
-template <typename T>
+template <typename T, int KIND = PASS_PAIR>
 int lines_per_block(int L) {
-  const int cap = pass_elems<T>() * pass_threads<T>();  // complex elements staged per block
+  const int cap = pass_elems<T, KIND>() * pass_threads<T, KIND>();  // complex elements staged per block
   const int maxlb = sizeof(T) == 8 ? 16 : 32;
   int lb = cap / L;
   if (lb > maxlb) lb = maxlb;
@@ -678,7 +702,7 @@ int lines_per_block(int L) {
 template <typename T, int KIND>
 hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   factor(a.L, a.rad, a.nrad);
-  a.LB = lines_per_block<T>(a.L);
+  a.LB = lines_per_block<T, KIND>(a.L);
   {
     int Ns = 1;
     for (int st = 0; st < a.nrad; ++st) {
@@ -696,8 +720,8 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   unsigned blocks = (unsigned)((a.nlines + a.LB - 1) / a.LB);
   size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
   if (has_factors<KIND>()) smem += sizeof(double) * (a.LB + a.L);  // deconvolution factors
-  constexpr int NT = pass_threads<T>();
-  constexpr int MAXV = pass_elems<T>();
+  constexpr int NT = pass_threads<T, KIND>();
+  constexpr int MAXV = pass_elems<T, KIND>();
   stage_mark(pl, stage, 0, s);
   hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
   stage_mark(pl, stage, 1, s);
@@ -1000,7 +1024,7 @@ hipError_t launch_origin(const Plan& pl, hipStream_t s) {
 }
 
 int fft_inverse_z_blocks(const Plan& pl) {
-  int lb = pl.fp64 ? lines_per_block<double>(pl.nf[2]) : lines_per_block<float>(pl.nf[2]);
+  int lb = pl.fp64 ? lines_per_block<double, PASS_INV_Z>(pl.nf[2]) : lines_per_block<float, PASS_INV_Z>(pl.nf[2]);
   int64_t nl = (int64_t)pl.n[0] * pl.n[1];
   return (int)((nl + lb - 1) / lb);
 }
