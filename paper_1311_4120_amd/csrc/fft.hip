@@ -169,6 +169,7 @@ struct PassArgs {
   // mirrors per block; nb1 blocks for the rows 0 < a < A/2 (cb per row), then cs
   // per row for the rows that are their own mirror (a = 0 and a = A/2)
   int P, A, B, nb1, cb, cs, dim3;
+  FastDiv dP;
   int64_t es_in, es_out;
   const void* G;
   SplitSym sym;
@@ -466,6 +467,7 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
     self = true;
   }
   // line slot l < P: own line (ar, c P + l); l >= P: the mirror of slot l - P
+  // (ar <= A/2 and bq < B, so the mirror indices need no division)
   auto line_of = [&](int l, int& la, int& lb) {
     const int j = (l < P) ? l : l - P;
     int bq = c * P + j;
@@ -475,8 +477,8 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
       la = ar;
       lb = bq;
     } else {
-      la = (a.A - ar) % a.A;
-      lb = (a.B - bq) % a.B;
+      la = ar ? a.A - ar : 0;
+      lb = bq ? a.B - bq : 0;
     }
     return valid;
   };
@@ -553,18 +555,19 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
     const C2<T>* G = (const C2<T>*)a.G;
     const bool dip = sy.kernel == JGB_DIPOLE_3D || sy.kernel == JGB_DIPOLE_2D;
     for (int idx = threadIdx.x; idx < P * L; idx += NT) {
-      const int e = idx / P;
+      const int e = (int)a.dP.div(idx);
       const int l = idx - e * P;
       int la, lb;
       if (!line_of(l, la, lb)) continue;
-      const int em = (L - e) % L;
+      const int em = e ? L - e : 0;
       const int lm = l + P;
       const double ke = sk[e];
       double M = split_symbol_core(sy, ke * ke + lkk[l], se[e] * lw[l], sy.axis[0] * ke + lnk[l],
                                    sy.axis2[0] * ke + lmk[l]);
-      if (dip) {
-        // the mean with the mirror's symbol (equal to it bit for bit off the
-        // Nyquist planes, where the mirror's k is exactly -k)
+      if (dip && (2 * e == L || 2 * lb == a.B || (a.dim3 && 2 * la == a.A))) {
+        // on a Nyquist plane, the mean with the mirror's symbol; off them the
+        // mirror's k is exactly -k (the frequencies are 2 pi q' / (2 R) with
+        // q' a signed integer) and its symbol equals M bit for bit
         const double km = sk[em];
         M = 0.5 * (M + split_symbol_core(sy, km * km + lkk[lm], se[em] * lw[lm], sy.axis[0] * km + lnk[lm],
                                          sy.axis2[0] * km + lmk[lm]));
@@ -745,6 +748,7 @@ hipError_t run_pair_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s
   a.P = lb / 2 > 0 ? lb / 2 : 1;
   a.LB = 2 * a.P;
   a.dLB = FastDiv((uint32_t)a.LB);
+  a.dP = FastDiv((uint32_t)a.P);
   a.cb = (a.B + a.P - 1) / a.P;
   a.cs = (a.B / 2 + 1 + a.P - 1) / a.P;
   a.nb1 = (a.A > 1) ? (a.A / 2 - 1) * a.cb : 0;
