@@ -453,15 +453,26 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
   const int ldl = L + 1;
   const int P = a.P;
   const int LB = 2 * P;
+  // The logical block: workgroups are dealt round robin to the eight XCDs, so
+  // workgroup w runs on XCD w mod 8; the logical ids are dealt out in runs,
+  // one run per XCD, so that neighbouring chunks share an L2 (a chunk's mirror
+  // run is misaligned by one element and shares its edge segments with the
+  // next chunk's).
+  int bid;
+  {
+    const int nb = (int)gridDim.x, w = (int)blockIdx.x;
+    const int x = w & 7, q = nb >> 3, r = nb & 7;
+    bid = x * q + (x < r ? x : r) + (w >> 3);
+  }
   // the block's row and chunk
   int ar, c;
   bool self;
-  if ((int)blockIdx.x < a.nb1) {
-    ar = 1 + (int)blockIdx.x / a.cb;
-    c = (int)blockIdx.x % a.cb;
+  if (bid < a.nb1) {
+    ar = 1 + bid / a.cb;
+    c = bid % a.cb;
     self = false;
   } else {
-    const int sb = (int)blockIdx.x - a.nb1;
+    const int sb = bid - a.nb1;
     ar = (sb / a.cs == 0) ? 0 : a.A / 2;
     c = sb % a.cs;
     self = true;
