@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
 // each thread writing Y at q and at -q, transforms both lines and stores the
 // cropped outputs in place.  Every line is owned by one block; a line that is
 // its own mirror sits in two rows of its block, which end up equal.  Registers
-// are capped at 128 (four waves per SIMD), so that two blocks share a CU.
+// are capped at 128 (four waves per SIMD).
 template <typename T, int MAXV, int NT>
 __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
@@ -676,13 +676,15 @@ void factor(int L, int* rad, int& nrad) {
 // 128^3 grids: the strided passes keep every row of a block at 128 contiguous
 // bytes (8 fp64 or 16 fp32 lines) with four or more blocks per CU, the Z
 // passes stage 2048 elements per block, and the paired pass of Algorithm 2
-// keeps the 512 x 8 or 16 shape its register budget was tuned for.  Every cap
-// holds a whole line of the largest grid (nf = 1024).
+// runs 256 threads (4 fp64 or 8 fp32 line pairs).  Every cap holds a whole
+// line of the largest grid (nf = 1024), the paired pass's a line and its
+// mirror.
 constexpr int PASS_PAIR = 9;
 template <typename T, int KIND = PASS_PAIR>
 constexpr int pass_threads() {
   if (KIND == PASS_COMPLEX) return sizeof(T) == 8 ? 256 : 512;
   if (KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 256;
+  if (KIND == PASS_PAIR) return 256;
   return 512;
 }
 template <typename T, int KIND = PASS_PAIR>
@@ -694,7 +696,8 @@ template <typename T, int KIND>
 constexpr int pass_cap() { return pass_threads<T, KIND>() * pass_elems<T, KIND>(); }
 static_assert(pass_cap<double, PASS_COMPLEX>() >= 1024 && pass_cap<float, PASS_COMPLEX>() >= 1024 &&
                   pass_cap<double, PASS_FWD_Z>() >= 1024 && pass_cap<float, PASS_FWD_Z>() >= 1024 &&
-                  pass_cap<double, PASS_COMPLEX_Z>() >= 1024 && pass_cap<float, PASS_PAIR>() >= 1024,
+                  pass_cap<double, PASS_COMPLEX_Z>() >= 1024 && pass_cap<double, PASS_PAIR>() >= 2048 &&
+                  pass_cap<float, PASS_PAIR>() >= 2048,
               "a block must stage at least one line of nf = 1024 points");
 // The first forward and last inverse passes run the same lines with the same
 // shape: their per-block partial sums (d_mparts, d_eparts) are counted once,
