@@ -274,7 +274,7 @@ def run_gpe(steps, warmup):
         psi0 = psi0 / np.sqrt(H * np.sum(psi0 ** 2))
         drv = jgb.GPE(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), dt=1e-3, beta=100.0,
                       trap=(1.0, 1.0, 2.0), eps=p.eps, precision=prec, lam=30.0, axis=p.axis,
-                      theta_rule="costheta", split=True)
+                      theta_rule="costheta", split=True, autotune=True)
         psi = torch.tensor(psi0, dtype=cdt, device="cuda")
         drv.step(psi, warmup)
         torch.cuda.synchronize()

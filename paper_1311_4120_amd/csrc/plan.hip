@@ -601,6 +601,11 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     pl.c0 = (std::log(pl.K) - swr + euler_gamma - std::log(2.0)) / (2.0 * M_PI);
   }
 
+  // two work items per CU fill a launch
+  int ncu = 0;
+  TRY_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl.device), "CU count");
+  const int fill_items = 2 * std::max(ncu, 1);
+
   // bin keys of the half node set, stable counting sort on the host
   const int64_t Mh = pl.Mh;
   int* d_keys = nullptr;
@@ -624,6 +629,10 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   {
     pl.iitems_cap = 0;
     for (int c : kInterpChunks) pl.iitems_cap = std::max(pl.iitems_cap, (int)interp_items(pl, c).size());
+    // the untuned chunk: the default, halved while a launch would have fewer
+    // than two work items per CU (small node sets, such as I2's)
+    while (pl.interp_chunk > kInterpChunks[0] && (int)interp_items(pl, pl.interp_chunk).size() < fill_items)
+      pl.interp_chunk /= 2;
     TRY(dev_alloc(pl, &pl.d_iitems, sizeof(Plan::InterpItem) * std::max(pl.iitems_cap, 1)));
     TRY(apply_interp_chunk(pl, pl.interp_chunk));
   }
@@ -704,6 +713,11 @@ Status build_plan(Plan& pl, const jgb_params* p) {
       pl.items_cap = std::max(pl.items_cap, (int)items.size());
       pl.multi_cap = std::max(pl.multi_cap, (int)multi.size());
       pl.slots_cap = std::max(pl.slots_cap, nslots);
+    }
+    while (pl.spread_chunk > kSpreadChunks[0]) {
+      spread_items(pl, pl.spread_chunk, items, multi, nslots);
+      if ((int)items.size() >= fill_items) break;
+      pl.spread_chunk /= 2;
     }
     TRY(dev_alloc(pl, &pl.d_items, sizeof(WorkItem) * std::max(pl.items_cap, 1)));
     TRY(dev_alloc(pl, &pl.d_multi, sizeof(int) * std::max(pl.multi_cap, 1)));

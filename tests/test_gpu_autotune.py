@@ -40,3 +40,32 @@ def test_autotune_and_cache(prec, tmp_path, monkeypatch):
     assert e < (1e-13 if prec == "fp64" else 1e-6)
     for pl in (tuned, again, plain):
         pl.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_untuned_chunks_fill_the_device(prec):
+    """I2's small node set (Algorithm 2 on the 128^3 headline grid): the
+    untuned plan halves the default chunks until a launch has two work items
+    per CU, and its result still meets the plan's tolerance against the
+    density's semi-closed dipole potential; the 1 048 576-node pattern set
+    keeps the defaults."""
+    p, rho = wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED, nodes="split")
+    plan = make_plan(p, split=True)
+    ic, sc = plan.info["interp_chunk"], plan.info["spread_chunk"]
+    say("split plan, untuned chunks: interp %d spread %d" % (ic, sc))
+    assert ic < 512 or sc < 4096
+    big = make_plan(wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED)[0])
+    assert (big.info["interp_chunk"], big.info["spread_chunk"]) == (512, 4096)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    u, E = plan.potential(torch.tensor(rho, dtype=dt, device="cuda"))
+    from oracle import closed_forms as cf
+    x = wl.grid_axes(p.n, p.box)
+    idx = np.array([[64, 64, 64], [0, 0, 0], [40, 80, 70], [100, 30, 64]])
+    pts = np.stack([x[i][idx[:, i]] for i in range(3)], axis=1)
+    ref = cf.dipole3d_gaussian_potential(pts, (1.0, 1.5, 0.7), p.axis)
+    ug = u.cpu().numpy()
+    err = np.max(np.abs(ug[tuple(idx.T)] - ref)) / np.max(np.abs(ug))
+    say("   max err / max|u| %.2e" % err)
+    assert err < p.eps
+    plan.close()
+    big.close()
