@@ -77,8 +77,15 @@ jgb_status run_forward(Plan& pl, const void* rho, hipStream_t st) {
 template <typename T>
 jgb_status run_potential(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st) {
   hipError_t e;
-  jgb_status c = run_forward<T>(pl, rho, st);
-  if (c != JGB_OK) return c;
+  if (pl.split) {
+    // Algorithm 2: the forward spectrum is never stored whole (the paired
+    // passes along the last axis recompute it)
+    if ((e = jgb::launch_split_forward<T>(pl, (const T*)rho, st)) != hipSuccess) return from_hip(e, "forward FFT");
+    if (pl.c0 != 0.0 && (e = jgb::launch_origin(pl, st)) != hipSuccess) return from_hip(e, "origin node");
+  } else {
+    jgb_status c = run_forward<T>(pl, rho, st);
+    if (c != JGB_OK) return c;
+  }
   if ((e = jgb::launch_interp<T>(pl, jgb::INTERP_POTENTIAL, nullptr, st)) != hipSuccess)
     return from_hip(e, "interpolation");
   if ((e = jgb::launch_spread<T>(pl, st)) != hipSuccess) return from_hip(e, "spreading");

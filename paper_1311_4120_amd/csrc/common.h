@@ -168,13 +168,17 @@ struct Plan {
 
   // Algorithm 2 (JGB_FLAG_SPLIT).  The forward FFT transforms rho H / phi^ +
   // i rho H in one go; G's touched tiles first receive the part the
-  // interpolation needs, then the spreading result; F receives the combined
-  // spectrum that the inverse FFT turns into Re = I2 phi^ and Im = I1.
+  // interpolation needs, then the spreading result; the inverse FFT's first
+  // pass forms the combined spectrum, which it turns into Re = I2 phi^ and
+  // Im = I1.  The energy-only and transform calls keep the whole forward
+  // spectrum in F (the Fourier-side energy of I1 sums over all of it).
   bool split = false;
   double win[2] = {0.0, 0.0};      // 3D: (a, 0); 2D: (R0, R1)
   int* d_touched = nullptr;        // gather tiles some node touches
   int ntouched = 0;
   unsigned char* d_tflag = nullptr;  // per gather tile: 1 if touched
+  int* d_ublocks = nullptr;        // logical blocks of the unmix pass (fft.hip)
+  int nublocks = 0;
   double* d_splitk = nullptr;      // per internal axis a: k_a(q) for q < nf_a, then exp(-k_a(q)^2 / a)
   int nsym_blocks = 0;             // blocks of the symbol kernel (also its energy partials)
 
@@ -222,6 +226,13 @@ template <typename T>
 hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s);
 template <typename T>
 hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hipStream_t s);
+// Algorithm 2's potential: the forward passes but the last, then the paired
+// unmix pass along the last axis, which writes A into G's touched tiles (the
+// inverse's first pass recomputes Z from the same input, so Z is not stored)
+template <typename T>
+hipError_t launch_split_forward(const Plan& pl, const T* rho, hipStream_t s);
+// the unmix pass's logical blocks for the touched-tile flags tf
+std::vector<int> split_unmix_blocks(const Plan& pl, const std::vector<unsigned char>& tf);
 template <typename T>
 hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t s);
 template <typename T>

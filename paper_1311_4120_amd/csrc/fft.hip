@@ -164,12 +164,13 @@ struct PassArgs {
   int split;          // Z passes of Algorithm 2: forward imag = rho H; inverse u += imag
   double* mparts;     // forward Z: per-block sums of rho (the node at k = 0), nullable
   const double* shift;  // inverse Z: constant added to u (the node at k = 0), nullable
-  // the paired first inverse pass of Algorithm 2 (k_fft_pair_pass): lines are
+  // the paired passes of Algorithm 2 (k_fft_pair_pass): lines are
   // (a, b) of an A x B set, element stride es_in / es_out; P lines and their
   // mirrors per block; nb1 blocks for the rows 0 < a < A/2 (cb per row), then cs
   // per row for the rows that are their own mirror (a = 0 and a = A/2)
   int P, A, B, nb1, cb, cs, dim3;
   FastDiv dP;
+  const int* blist;   // the unmix pass's logical blocks
   int64_t es_in, es_out;
   const void* G;
   SplitSym sym;
@@ -436,16 +437,25 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
   }
 }
 
-// Algorithm 2's first inverse pass.  A block takes P lines (a, b) of one row a
-// and their mirrors ((A - a) mod A, (B - b) mod B), so that the element q of a
-// line and its mirror -q (element (L - e) mod L of the mirror line) sit in the
-// block's LDS together.  It forms the spectrum of the inverse FFT there,
-//   Y(q) = (G(q) + conj G(-q)) / 2 + M'(q) (Z(q) - conj Z(-q)) / 2   (splitsym.h),
-// each thread writing Y at q and at -q, transforms both lines and stores the
-// cropped outputs in place.  Every line is owned by one block; a line that is
-// its own mirror sits in two rows of its block, which end up equal.  Registers
-// are capped at 128 (four waves per SIMD).
-template <typename T, int MAXV, int NT>
+// Algorithm 2's paired passes along the last forward / first inverse axis.  A
+// block takes P lines (a, b) of one row a and their mirrors
+// ((A - a) mod A, (B - b) mod B), loads the lines' N inputs from the output of
+// the forward pass before (the other axes already transformed), zero-pads them
+// to L in LDS and runs the forward transform there, so that Z(q) and Z(-q)
+// (element (L - e) mod L of the mirror line) sit in the block's LDS together.
+//   PAIR_UNMIX: writes A = (Z(q) + conj Z(-q)) / 2 into the gather tiles of G
+//     that the interpolation reads (only blocks with such a tile run);
+//   PAIR_FUSED: forms the inverse transform's spectrum
+//       Y(q) = (G(q) + conj G(-q)) / 2 + M'(q) (Z(q) - conj Z(-q)) / 2  (splitsym.h),
+//     each thread writing Y at q and at -q, transforms both lines back and
+//     stores the cropped outputs.
+// Z is never stored: the unmix pass touches a few lines, and the fused pass
+// reads the N-point inputs instead of the L-point spectrum.  Every line is
+// owned by one block; a line that is its own mirror sits in two rows of its
+// block, which end up equal.  Registers are capped at 128 (four waves per SIMD).
+enum PairMode { PAIR_UNMIX = 0, PAIR_FUSED = 1 };
+
+template <typename T, int MODE, int MAXV, int NT>
 __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
@@ -453,13 +463,15 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
   const int ldl = L + 1;
   const int P = a.P;
   const int LB = 2 * P;
-  // The logical block: workgroups are dealt round robin to the eight XCDs, so
-  // workgroup w runs on XCD w mod 8; the logical ids are dealt out in runs,
-  // one run per XCD, so that neighbouring chunks share an L2 (a chunk's mirror
-  // run is misaligned by one element and shares its edge segments with the
-  // next chunk's).
+  // The logical block.  Unmix: from the plan's list.  Fused: workgroups are
+  // dealt round robin to the eight XCDs, so workgroup w runs on XCD w mod 8;
+  // the logical ids are dealt out in runs, one run per XCD, so that
+  // neighbouring chunks share an L2 (a chunk's mirror run is misaligned by one
+  // element and shares its edge segments with the next chunk's).
   int bid;
-  {
+  if constexpr (MODE == PAIR_UNMIX) {
+    bid = a.blist[blockIdx.x];
+  } else {
     const int nb = (int)gridDim.x, w = (int)blockIdx.x;
     const int x = w & 7, q = nb >> 3, r = nb & 7;
     bid = x * q + (x < r ? x : r) + (w >> 3);
@@ -493,7 +505,7 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
     }
     return valid;
   };
-  const C2<T>* Z = (const C2<T>*)a.in;
+  const C2<T>* X = (const C2<T>*)a.in;
   const SplitSym& sy = a.sym;
   // tables after the lines: the element axis's frequencies and window values,
   // per line slot the constant parts of |k|^2, p, n.k and m.k, and the line's
@@ -508,9 +520,15 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
   double* lnk = lw + LB;
   double* lmk = lnk + LB;
   unsigned char* ltf = reinterpret_cast<unsigned char*>(lmk + LB);  // LB x ngte
-  // load both line sets, all loads issued before the LDS writes
+  const int N = a.nin;
+  // zero the padding of every line: fine positions [N - N/2, L - N/2)
+  for (int idx = threadIdx.x; idx < LB * (L - N); idx += NT) {
+    const int e = (int)a.dLB.div(idx), l = idx - e * LB;
+    lds[l * ldl + (N - N / 2) + e] = C2<T>{T(0), T(0)};
+  }
+  // load the N inputs of both line sets, all loads issued before the LDS writes
   {
-    const int total_in = LB * L;
+    const int total_in = LB * N;
     C2<T> buf[MAXV];
     int dst[MAXV];
 #pragma unroll
@@ -522,9 +540,9 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
       const int l = idx - e * LB;
       int la, lb;
       const bool valid = line_of(l, la, lb) && ok;
-      const C2<T> v = Z[(int64_t)e * a.es_in + (int64_t)la * a.B + lb];
+      const C2<T> v = X[(int64_t)e * a.es_in + (int64_t)la * a.B + lb];
       buf[i] = valid ? v : C2<T>{T(0), T(0)};
-      dst[i] = ok ? l * ldl + e : -1;
+      dst[i] = ok ? l * ldl + fine_pos(e, N, L) : -1;
     }
     for (int t = threadIdx.x; t < L + LB + LB * ngte; t += NT) {
       if (t < L) {
@@ -561,9 +579,51 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
       if (dst[i] >= 0) lds[dst[i]] = buf[i];
   }
   __syncthreads();
+  // forward transform of the 2P lines (sign -1): Z
+  {
+    int Ns = 1;
+    for (int st = 0; st < a.nrad; ++st) {
+      const int R = a.rad[st];
+      const FastDiv& dNs = a.dNs[st];
+      const int tws = a.tws[st];
+      switch (R) {
+        case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
+        case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
+        case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
+        case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
+        default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
+      }
+      Ns *= R;
+    }
+  }
+  C2<T>* G = (C2<T>*)a.G;
+  if constexpr (MODE == PAIR_UNMIX) {
+    // A at every element pair (own line l, element e) <-> (mirror slot l + P,
+    // (L - e) mod L) whose gather tile the interpolation reads; A(-q) = conj A(q)
+    for (int idx = threadIdx.x; idx < P * L; idx += NT) {
+      const int e = (int)a.dP.div(idx);
+      const int l = idx - e * P;
+      int la, lb;
+      if (!line_of(l, la, lb)) continue;
+      const int em = e ? L - e : 0;
+      const int lm = l + P;
+      const C2<T> zq = lds[l * ldl + e], zm = lds[lm * ldl + em];
+      const C2<T> aq{T(0.5) * (zq.x + zm.x), T(0.5) * (zq.y - zm.y)};
+      if (ltf[l * ngte + (e >> gse)]) {
+        const int q0 = a.dim3 ? e : 0, q1 = a.dim3 ? la : e;
+        G[((int64_t)q0 * sy.nf1 + q1) * sy.nf2 + lb] = aq;
+      }
+      if (ltf[lm * ngte + (em >> gse)]) {
+        int ma, mb;
+        line_of(lm, ma, mb);
+        const int m0 = a.dim3 ? em : 0, m1 = a.dim3 ? ma : em;
+        G[((int64_t)m0 * sy.nf1 + m1) * sy.nf2 + mb] = C2<T>{aq.x, -aq.y};
+      }
+    }
+    return;
+  }
   // form Y at every element pair (own line l, element e) <-> (mirror slot l + P, (L - e) mod L)
   {
-    const C2<T>* G = (const C2<T>*)a.G;
     const bool dip = sy.kernel == JGB_DIPOLE_3D || sy.kernel == JGB_DIPOLE_2D;
     for (int idx = threadIdx.x; idx < P * L; idx += NT) {
       const int e = (int)a.dP.div(idx);
@@ -605,20 +665,22 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
     }
   }
   __syncthreads();
-  // FFT stages over the 2P lines
-  int Ns = 1;
-  for (int st = 0; st < a.nrad; ++st) {
-    const int R = a.rad[st];
-    const FastDiv& dNs = a.dNs[st];
-    const int tws = a.tws[st];
-    switch (R) {
-      case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+  // inverse transform of the 2P lines (sign +1)
+  {
+    int Ns = 1;
+    for (int st = 0; st < a.nrad; ++st) {
+      const int R = a.rad[st];
+      const FastDiv& dNs = a.dNs[st];
+      const int tws = a.tws[st];
+      switch (R) {
+        case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
+        case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
+        case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
+        case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
+        default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
+      }
+      Ns *= R;
     }
-    Ns *= R;
   }
   // store the cropped outputs of both line sets
   {
@@ -745,10 +807,11 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The paired first inverse pass of Algorithm 2 along the internal axis `axis`
-// (0 in 3D: lines (q1, q2); 1 in 2D: lines q2), from Z in F to `out`.
+// The paired passes of Algorithm 2 along the internal axis `axis` (0 in 3D:
+// lines (q1, q2); 1 in 2D: lines q2): block geometry, shared with the plan's
+// list of unmix blocks.
 template <typename T>
-hipError_t run_pair_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
+unsigned pair_geometry(PassArgs<T>& a) {
   factor(a.L, a.rad, a.nrad);
   {
     int Ns = 1;
@@ -766,7 +829,17 @@ hipError_t run_pair_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s
   a.cb = (a.B + a.P - 1) / a.P;
   a.cs = (a.B / 2 + 1 + a.P - 1) / a.P;
   a.nb1 = (a.A > 1) ? (a.A / 2 - 1) * a.cb : 0;
-  const unsigned blocks = (unsigned)(a.nb1 + (a.A > 1 ? 2 : 1) * a.cs);
+  return (unsigned)(a.nb1 + (a.A > 1 ? 2 : 1) * a.cs);
+}
+
+template <typename T, int MODE>
+hipError_t run_pair_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
+  unsigned blocks = pair_geometry<T>(a);
+  if (MODE == PAIR_UNMIX) {
+    blocks = (unsigned)pl.nublocks;
+    a.blist = pl.d_ublocks;
+    if (blocks == 0) return hipSuccess;
+  }
   const int gse = a.dim3 ? a.sym.gs0 : a.sym.gs1;
   const int ngte = (a.L + (1 << gse) - 1) >> gse;
   const size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>) + sizeof(double) * (2 * a.L + 4 * a.LB) +
@@ -774,7 +847,7 @@ hipError_t run_pair_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s
   constexpr int NT = pass_threads<T>();
   constexpr int MAXV = pass_elems<T>();
   stage_mark(pl, stage, 0, s);
-  hipLaunchKernelGGL((k_fft_pair_pass<T, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
+  hipLaunchKernelGGL((k_fft_pair_pass<T, MODE, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
   stage_mark(pl, stage, 1, s);
   return hipGetLastError();
 }
@@ -790,10 +863,30 @@ PassArgs<T> base_args(const Plan& pl, int axis, T sign) {
   return a;
 }
 
-}  // namespace
-
+// Algorithm 2's paired passes run along the last forward axis (a0 in 3D, a1 in
+// 2D) on the output of the forward pass before it, which sits in W: 3D
+// [n0][f1][f2], 2D [1][n1][f2].
 template <typename T>
-hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
+PassArgs<T> split_pair_args(const Plan& pl, int axis) {
+  const bool has_x = pl.nf[0] > 1;
+  PassArgs<T> a = base_args<T>(pl, axis, T(1));
+  a.nin = (int)pl.n[axis];
+  a.nout = (int)pl.n[axis];
+  a.A = has_x ? (int)pl.nf[1] : 1;
+  a.B = (int)pl.nf[2];
+  a.es_in = has_x ? (int64_t)pl.nf[1] * pl.nf[2] : pl.nf[2];
+  a.es_out = a.es_in;
+  a.dim3 = has_x ? 1 : 0;
+  a.in = pl.d_W;
+  a.G = pl.d_G;
+  a.sym = make_split_sym(pl);
+  return a;
+}
+
+// The forward passes; with last = false the pass along the last axis (a0 in
+// 3D, a1 in 2D) is left to Algorithm 2's paired passes.
+template <typename T>
+hipError_t forward_passes(const Plan& pl, const T* rho, hipStream_t s, bool last) {
   const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
   const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
   const bool has_x = f0 > 1;
@@ -824,7 +917,7 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
     a.mparts = (pl.c0 != 0.0) ? pl.d_mparts : nullptr;
     if ((e = run_pass<T, PASS_FWD_Z>(pl, ST_FWD_Z, a, s)) != hipSuccess) return e;
   }
-  {  // Y: A1 -> A2 [n0][f1][f2]
+  if (has_x || last) {  // Y: A1 -> A2 [n0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 1, T(-1));
     a.nlines = n0 * f2;
     a.nin = (int)n1;
@@ -841,7 +934,7 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
     a.out = A2;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_FWD_Y, a, s)) != hipSuccess) return e;
   }
-  if (has_x) {  // X: A2 -> F [f0][f1][f2]
+  if (has_x && last) {  // X: A2 -> F [f0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 0, T(-1));
     a.nlines = f1 * f2;
     a.nin = (int)n0;
@@ -861,35 +954,89 @@ hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
   return hipSuccess;
 }
 
+}  // namespace
+
+template <typename T>
+hipError_t launch_fft_forward(const Plan& pl, const T* rho, hipStream_t s) {
+  return forward_passes<T>(pl, rho, s, true);
+}
+
+template <typename T>
+hipError_t launch_split_forward(const Plan& pl, const T* rho, hipStream_t s) {
+  hipError_t e = forward_passes<T>(pl, rho, s, false);
+  if (e != hipSuccess) return e;
+  return run_pair_pass<T, PAIR_UNMIX>(pl, ST_SPLIT_UNMIX, split_pair_args<T>(pl, pl.nf[0] > 1 ? 0 : 1), s);
+}
+
+std::vector<int> split_unmix_blocks(const Plan& pl, const std::vector<unsigned char>& tf) {
+  const int axis = pl.nf[0] > 1 ? 0 : 1;
+  PassArgs<double> a = base_args<double>(pl, axis, 1.0);
+  const SplitSym sy = make_split_sym(pl);
+  a.A = pl.nf[0] > 1 ? (int)pl.nf[1] : 1;
+  a.B = (int)pl.nf[2];
+  a.dim3 = pl.nf[0] > 1 ? 1 : 0;
+  unsigned nblocks;
+  if (pl.fp64) {
+    nblocks = pair_geometry<double>(a);
+  } else {
+    PassArgs<float> b{};
+    b.L = a.L;
+    b.A = a.A;
+    b.B = a.B;
+    nblocks = pair_geometry<float>(b);
+    a.P = b.P;
+    a.cb = b.cb;
+    a.cs = b.cs;
+    a.nb1 = b.nb1;
+  }
+  const int gse = a.dim3 ? sy.gs0 : sy.gs1;
+  const int ngte = (a.L + (1 << gse) - 1) >> gse;
+  std::vector<int> out;
+  for (int bid = 0; bid < (int)nblocks; ++bid) {
+    int ar, c;
+    bool self;
+    if (bid < a.nb1) {
+      ar = 1 + bid / a.cb;
+      c = bid % a.cb;
+      self = false;
+    } else {
+      const int sb = bid - a.nb1;
+      ar = (sb / a.cs == 0) ? 0 : a.A / 2;
+      c = sb % a.cs;
+      self = true;
+    }
+    bool any = false;
+    for (int l = 0; l < 2 * a.P && !any; ++l) {
+      const int j = l < a.P ? l : l - a.P;
+      const int bq = c * a.P + j;
+      if (!(self ? (bq <= a.B / 2) : (bq < a.B))) continue;
+      const int la = l < a.P ? ar : (ar ? a.A - ar : 0);
+      const int lb = l < a.P ? bq : (bq ? a.B - bq : 0);
+      for (int te = 0; te < ngte && !any; ++te) {
+        const int tile = a.dim3 ? ((te * sy.gnt1 + (la >> sy.gs1)) * sy.gnt2 + (lb >> sy.gs2))
+                                : (te * sy.gnt2 + (lb >> sy.gs2));
+        any = tf[tile] != 0;
+      }
+    }
+    if (any) out.push_back(bid);
+  }
+  return out;
+}
+
 template <typename T>
 hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hipStream_t s) {
   const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
   const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
   const bool has_x = f0 > 1;
-  // the input spectrum: the spreading grid, or for Algorithm 2 the forward
-  // spectrum Z in F (with G); the first pass may run in place on F (each block
-  // reads all of its lines before it writes them back, and no two blocks share
-  // a line)
-  void* src = pl.split ? pl.d_F : pl.d_G;
+  // the input spectrum: the spreading grid; Algorithm 2's first pass instead
+  // forms its spectrum from the forward passes' output in W and from G, line
+  // pairs at a time (k_fft_pair_pass), and in 2D runs in place on W (each
+  // block reads all of its lines before it writes them back, and no two blocks
+  // share a line)
+  void* src = pl.d_G;
   void* B2 = has_x ? pl.d_F : src;  // (2D: the input grid itself)
   void* B1 = pl.d_W;
   hipError_t e;
-  // Algorithm 2: the first pass forms its spectrum from Z (in F) and G, line
-  // pairs at a time (k_fft_pair_pass)
-  auto pair_args = [&](int axis) {
-    PassArgs<T> a = base_args<T>(pl, axis, T(1));
-    a.nin = (int)pl.nf[axis];
-    a.nout = (int)pl.n[axis];
-    a.A = has_x ? (int)f1 : 1;
-    a.B = (int)f2;
-    a.es_in = has_x ? f1 * f2 : f2;
-    a.es_out = a.es_in;
-    a.dim3 = has_x ? 1 : 0;
-    a.in = pl.d_F;
-    a.G = pl.d_G;
-    a.sym = make_split_sym(pl);
-    return a;
-  };
   if (has_x) {  // X: src -> B2 [n0][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 0, T(1));
     a.nlines = f1 * f2;
@@ -906,18 +1053,18 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.in = src;
     a.out = B2;
     if (pl.split) {
-      PassArgs<T> b = pair_args(0);
+      PassArgs<T> b = split_pair_args<T>(pl, 0);
       b.out = B2;
-      e = run_pair_pass<T>(pl, ST_INV_X, b, s);
+      e = run_pair_pass<T, PAIR_FUSED>(pl, ST_INV_X, b, s);
     } else {
       e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_X, a, s);
     }
     if (e != hipSuccess) return e;
   }
-  if (pl.split && !has_x) {  // 2D Algorithm 2: Y: F -> B1 [1][n1][f2], paired
-    PassArgs<T> b = pair_args(1);
+  if (pl.split && !has_x) {  // 2D Algorithm 2: Y: W -> B1 = W [1][n1][f2], paired
+    PassArgs<T> b = split_pair_args<T>(pl, 1);
     b.out = B1;
-    if ((e = run_pair_pass<T>(pl, ST_INV_Y, b, s)) != hipSuccess) return e;
+    if ((e = run_pair_pass<T, PAIR_FUSED>(pl, ST_INV_Y, b, s)) != hipSuccess) return e;
   } else {  // Y: B2 -> B1 [n0][n1][f2]
     PassArgs<T> a = base_args<T>(pl, 1, T(1));
     a.nlines = n0 * f2;
@@ -1048,6 +1195,8 @@ int fft_inverse_z_blocks(const Plan& pl) {
 }
 
 template hipError_t launch_fft_forward<double>(const Plan&, const double*, hipStream_t);
+template hipError_t launch_split_forward<double>(const Plan&, const double*, hipStream_t);
+template hipError_t launch_split_forward<float>(const Plan&, const float*, hipStream_t);
 template hipError_t launch_fft_forward<float>(const Plan&, const float*, hipStream_t);
 template hipError_t launch_fft_inverse<double>(const Plan&, double*, const double*, hipStream_t);
 template hipError_t launch_fft_inverse<float>(const Plan&, float*, const float*, hipStream_t);

@@ -776,6 +776,13 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     if (!tl.empty()) TRY(upload(pl, pl.d_touched, tl.data(), sizeof(int) * tl.size()));
     TRY(dev_alloc(pl, &pl.d_tflag, (size_t)pl.ngtiles));
     TRY(upload(pl, pl.d_tflag, tf.data(), (size_t)pl.ngtiles));
+    // the unmix pass's blocks: those whose line pairs cross a touched tile
+    {
+      std::vector<int> ub = split_unmix_blocks(pl, tf);
+      pl.nublocks = (int)ub.size();
+      TRY(dev_alloc(pl, &pl.d_ublocks, sizeof(int) * std::max<size_t>(ub.size(), 1)));
+      if (!ub.empty()) TRY(upload(pl, pl.d_ublocks, ub.data(), sizeof(int) * ub.size()));
+    }
     // per axis: the regular grid's frequencies k_q = 2 pi q' / (2 R), q' the
     // signed index, and exp(-k_q^2 / a) (3D; 1 in 2D)
     std::vector<double> kt;
