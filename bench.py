@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+# LDS: 128 bytes per clock per CU, 256 CUs at 2.4 GHz
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
 METRIC = "potential evals/s + ns/grid-pt at 128³: FP64 ε=1e-10 vs mixed FP32 ε=1e-5"
 
 
@@ -60,6 +62,12 @@ def stage_work(info, prec, energy=True):
     }
     fl = {"interp": 5.0 * Mh * w ** 3, "spread": 5.0 * Mh * w ** 3}
     return by, fl
+
+
+def lds_bytes(info, prec):
+    """LDS bytes the interpolation reads per launch: one grid value per tap."""
+    cb = 16 if prec == "fp64" else 8
+    return info["n_half"] * info["width"] ** 3 * cb
 
 
 # Kernel sources whose measured HBM traffic a stage's roofline may quote: the
@@ -357,7 +365,7 @@ def cpu_baseline(sample_nodes=32768):
     """The oracle (direct O(N M) sums) on a bounded sample of the same workload:
     the type-2 sum at every 32nd node and the type-1 sum from those nodes to the
     whole grid, extrapolated linearly in the node count to a full evaluation."""
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     import oracle
     import workloads as wl
@@ -374,10 +382,34 @@ def cpu_baseline(sample_nodes=32768):
     t = time.perf_counter() - t0
     full = t * len(k) / len(idx)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    # the same sums on one BLAS thread, at an 8 times smaller sample
+    idx1 = idx[::8]
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        rh1 = oracle.rho_hat(rho, p.box, k[idx1])
+        c1 = oracle.coefficients(p.kernel, k[idx1], W[idx1], p.axis)
+        oracle.sum_to_grid(c1 * rh1, k[idx1], p.n, p.box)
+        t1 = time.perf_counter() - t1
+    full1 = t1 * len(k) / len(idx1)
+    # the two small workloads, one whole oracle evaluation each (u both ways and E)
+    small = {}
+    p1, rho1 = wl.coulomb3d_32()
+    p2, rho2, _ = wl.coulomb2d_256()
+    for name, (pp, rr) in (("coulomb3d_32", (p1, rho1)), ("coulomb2d_256", (p2, rho2))):
+        ts = time.perf_counter()
+        oracle.evaluate(pp, rr)
+        ts = time.perf_counter() - ts
+        small[name] = {"s_per_eval": ts, "evals_per_s": 1.0 / ts}
     return {"value": 1.0 / full, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
             "sample": "type-2 sum at %d of %d nodes (every %d-th) + type-1 sum from them to all 128^3 points, "
                       "%.1f s, extrapolated x%.1f to one full evaluation (%.0f s); O(N M) direct sums"
-                      % (len(idx), len(k), stride, t, len(k) / len(idx), full)}
+                      % (len(idx), len(k), stride, t, len(k) / len(idx), full),
+            "one_thread": {"value": 1.0 / full1, "unit": "evals/s", "cores": 1,
+                           "sample": "the same sums at %d nodes, %.1f s, extrapolated x%.0f (%.0f s)"
+                                     % (len(idx1), t1, len(k) / len(idx1), full1)},
+            "full_small": small,
+            "context": "the paper's Algorithm 2 timings on its Xeon workstation: about 7.3 us per grid point "
+                       "at 2 097 152 points (another machine and code; context only)"}
 
 
 def main():
@@ -431,6 +463,16 @@ def main():
         d = {"ms": v, "GB/s": by.get(k, 0) / (v * 1e-3) / 1e9 if k in by else None}
         if k in fl:
             d["TFLOP/s"] = fl[k] / (v * 1e-3) / 1e12
+        if k in by:
+            # the fraction of the stage's own bounding roofline: HBM for the FFT
+            # passes; for the tap kernels the longest of HBM, arithmetic and
+            # (interpolation) LDS reads
+            rf = roofline(k, v, by, fl, head)
+            d["bound"], d["frac"] = rf["bound"], rf["frac"]
+            if k == "interp":
+                t_lds = lds_bytes(r["info"], head) / (LDS_PEAK_TBS * 1e12)
+                if t_lds / (v * 1e-3) > d["frac"]:
+                    d["bound"], d["frac"] = "lds", t_lds / (v * 1e-3)
         stages[k] = d
     total_bytes = sum(by.values())
     out = {
