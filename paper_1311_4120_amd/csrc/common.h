@@ -26,6 +26,9 @@ constexpr int kMaxLine = 1024;
 constexpr int kTileZ = 16;
 // Output tile of the type-1 gather along axis 2 (the bins above stay kTileZ).
 constexpr int kGatherZ = 8;
+// Offset added to the signed tile-relative footprint starts of the gather lists
+// (when the plan's grid needs no wrap-around, Plan::gather_nowrap).
+constexpr int kGatherBias = 512;
 // Per-node kernel values, tabulated at plan time: w values per internal axis,
 // axis a at [a w, a w + w) of the node's record (a unit axis has the single
 // value 1 at tap 0 and zeros after it), then a zero at 3 w that a load may
@@ -141,6 +144,7 @@ struct Plan {
   int2* d_list = nullptr;      // per tile, the nodes whose footprint touches it (concatenated):
                                // (node, first tap relative to the tile per axis, 10 bits each)
   int64_t nlist = 0;
+  bool gather_nowrap = false;  // list starts are signed, plus kGatherBias (else modulo nf)
   WorkItem* d_items = nullptr;
   int nitems = 0;
   int nslots = 0;

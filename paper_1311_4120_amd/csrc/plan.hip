@@ -680,7 +680,19 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   const int64_t nlist = tcount[pl.ngtiles];
   if (nlist > (int64_t)std::numeric_limits<int>::max()) return fail(JGB_ERR_UNSUPPORTED, "gather lists too long");
   // entry: node index and its first tap relative to the tile origin on each
-  // axis, modulo the grid (10 bits each; nf <= 1024)
+  // axis (10 bits each).  When every axis has nf >= T + w - 1 the start of a
+  // footprint that touches the tile has exactly one representative in
+  // [-(w - 1), T - 1], stored plus kGatherBias, and the gather needs no
+  // reduction modulo nf; otherwise it is stored modulo nf (nf <= 1024).
+  pl.gather_nowrap = true;
+  for (int a = 0; a < 3; ++a) pl.gather_nowrap &= pl.nf[a] >= pl.GT[a] + pl.w[a] - 1;
+  auto start_code = [&](int a, int rel) {
+    const int nf = pl.nf[a];
+    int e = ((rel % nf) + nf) % nf;
+    if (!pl.gather_nowrap) return e;
+    if (e > pl.GT[a] - 1) e -= nf;
+    return e + kGatherBias;
+  };
   std::vector<int2> list(nlist + 1, make_int2(0, 0));  // one spare entry
   {
     std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
@@ -691,9 +703,11 @@ Status build_plan(Plan& pl, const jgb_params* p) {
         for (int a1 = 0; a1 < ny; ++a1)
           for (int a2 = 0; a2 < nz; ++a2) {
             const int tile = (tx[a0] * pl.gnt[1] + ty[a1]) * pl.gnt[2] + tz[a2];
-            const int ex = ((hdr[j].x - tx[a0] * pl.GT[0]) % pl.nf[0] + pl.nf[0]) % pl.nf[0];
-            const int ey = ((hdr[j].y - ty[a1] * pl.GT[1]) % pl.nf[1] + pl.nf[1]) % pl.nf[1];
-            const int ez = ((hdr[j].z - tz[a2] * pl.GT[2]) % pl.nf[2] + pl.nf[2]) % pl.nf[2];
+            const int ex = start_code(0, hdr[j].x - tx[a0] * pl.GT[0]);
+            const int ey = start_code(1, hdr[j].y - ty[a1] * pl.GT[1]);
+            const int ez = start_code(2, hdr[j].z - tz[a2] * pl.GT[2]);
+            if (ex < 0 || ex > 1023 || ey < 0 || ey > 1023 || ez < 0 || ez > 1023)
+              return fail(JGB_ERR_UNSUPPORTED, "gather list start out of range");
             list[fill[tile]++] = make_int2((int)j, ex | (ey << 10) | (ez << 20));
           }
     }

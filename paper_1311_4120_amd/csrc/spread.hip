@@ -118,7 +118,9 @@ struct GroupLoads {
 // outside footprints.  The wavefronts split the list; their partial tiles are
 // summed in LDS in a fixed order and written once.  T1 is the tile extent on
 // axis 1 (8 for 3D, 64 for the 1 x 64 tiles of 2D problems).
-template <typename T, int T1>
+// NOWRAP: the list's starts are signed, plus kGatherBias, and a tap offset
+// is the point minus the start (no reduction modulo nf).
+template <typename T, int T1, bool NOWRAP>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int T0 = 64 / T1;
@@ -143,17 +145,20 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
 
   // the lane's x values (per row block when NX = 4) and y values (per row
   // block when NY = 4); points off the grid never take a value
+  // (plus kGatherBias when the starts carry it)
+  constexpr int bias = NOWRAP ? kGatherBias : 0;
   int xs[NX], ys[NY];
 #pragma unroll
   for (int b = 0; b < NX; ++b) {
-    xs[b] = (16 * b + li) / T1;
-    if (o0 + xs[b] >= a.nf0) xs[b] = -(1 << 20);
+    xs[b] = (16 * b + li) / T1 + bias;
+    if (o0 + xs[b] - bias >= a.nf0) xs[b] = -(1 << 20);
   }
 #pragma unroll
   for (int b = 0; b < NY; ++b) {
-    ys[b] = (16 * b + li) % T1;
-    if (o1 + ys[b] >= a.nf1) ys[b] = -(1 << 20);
+    ys[b] = (16 * b + li) % T1 + bias;
+    if (o1 + ys[b] - bias >= a.nf1) ys[b] = -(1 << 20);
   }
+  const int zb = zl + bias;
 
   acc_t acc[4];
 #pragma unroll
@@ -179,22 +184,23 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
     const uint32_t rec = j * rbytes;
     r.u = load_at<T>(a.uhat, j * (uint32_t)sizeof(C2<T>) + upart);
-    // tap d = (p - start) mod nf of a point p covers it iff d < w (w <= nf)
-    int dz = zl - ez;
-    if (dz < 0) dz += a.nf2;
-    const bool inz = valid && dz < a.w2;
+    // tap d = (p - start) mod nf of a point p covers it iff d < w (w <= nf);
+    // with signed starts d = p - start, and a negative d fails the unsigned test
+    int dz = zb - ez;
+    if (!NOWRAP && dz < 0) dz += a.nf2;
+    const bool inz = valid && (uint32_t)dz < (uint32_t)a.w2;
     r.z = load_at<T>(a.wts, rec + (inz ? (uint32_t)((2 * W + dz) * sizeof(T)) : zslot));
 #pragma unroll
     for (int b = 0; b < NX; ++b) {
       int dx = xs[b] - ex;
-      if (dx < 0) dx += a.nf0;
+      if (!NOWRAP && dx < 0) dx += a.nf0;
       const bool in = valid && (uint32_t)dx < (uint32_t)a.w0;
       r.px[b] = load_at<T>(a.wts, rec + (in ? (uint32_t)(dx * sizeof(T)) : zslot));
     }
 #pragma unroll
     for (int b = 0; b < NY; ++b) {
       int dy = ys[b] - ey;
-      if (dy < 0) dy += a.nf1;
+      if (!NOWRAP && dy < 0) dy += a.nf1;
       const bool in = valid && (uint32_t)dy < (uint32_t)a.w1;
       r.py[b] = load_at<T>(a.wts, rec + (in ? (uint32_t)((W + dy) * sizeof(T)) : zslot));
     }
@@ -349,12 +355,19 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   unsigned blocks = (unsigned)pl.nitems;
   if (blocks == 0) return hipSuccess;  // no node touches the grid: G stays zero
   stage_mark(pl, ST_SPREAD, 0, s);
-  if (pl.GT[0] == 8 && pl.GT[1] == 8)
-    hipLaunchKernelGGL((k_spread_gather<T, 8>), dim3(blocks), dim3(256), 0, s, a);
-  else if (pl.GT[0] == 1 && pl.GT[1] == 64)
-    hipLaunchKernelGGL((k_spread_gather<T, 64>), dim3(blocks), dim3(256), 0, s, a);
-  else
+  if (pl.GT[0] == 8 && pl.GT[1] == 8) {
+    if (pl.gather_nowrap)
+      hipLaunchKernelGGL((k_spread_gather<T, 8, true>), dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_spread_gather<T, 8, false>), dim3(blocks), dim3(256), 0, s, a);
+  } else if (pl.GT[0] == 1 && pl.GT[1] == 64) {
+    if (pl.gather_nowrap)
+      hipLaunchKernelGGL((k_spread_gather<T, 64, true>), dim3(blocks), dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_spread_gather<T, 64, false>), dim3(blocks), dim3(256), 0, s, a);
+  } else {
     return hipErrorInvalidValue;
+  }
   stage_mark(pl, ST_SPREAD, 1, s);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
