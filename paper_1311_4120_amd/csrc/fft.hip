@@ -3,8 +3,8 @@
 //
 // Each 3D FFT is three passes of batched 1D transforms, one per axis.  A pass
 // stages LB lines of length L in LDS, runs a Stockham autosort FFT with radices
-// 2, 3, 4, 5, 8 (twiddles from a float64 table rounded to the working type),
-// and writes the lines back.  Zero padding is never stored: forward passes
+// 8, 4, 2, 3, 5 (also 16 in Algorithm 2's float32 paired passes; twiddles from
+// a float64 table rounded to the working type), and writes the lines back.  Zero padding is never stored: forward passes
 // place the N nonzero inputs of a line at fine indices (m mod L),
 // m in [-N/2, N/2), and zero the rest in LDS; inverse passes write only those N
 // outputs (the crop to the physical grid).
@@ -117,6 +117,40 @@ __device__ inline void dft8(C2<T>* v, T s) {
   v[7] = csub(e[3], o3);
 }
 
+// Radix 16 as 4 x 4: with n = 4 n1 + n2 and k = k1 + 4 k2,
+// y_k = sum_n2 w16^(n2 k1) [sum_n1 x_(4 n1 + n2) w4^(n1 k1)] w4^(n2 k2).
+template <typename T>
+__device__ inline void dft16(C2<T>* v, T s) {
+  const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);  // cos, sin of pi/8
+  const T r = T(0.70710678118654752440);
+  C2<T> a[4][4];  // a[n2][k1]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    C2<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+    dft4(t, s);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = t[k1];
+  }
+  // twiddles w16^m = (cos(2 pi m / 16), s sin(2 pi m / 16)) for m = n2 k1
+  const C2<T> w1{c1, s * s1}, w2{r, s * r}, w3{s1, s * c1}, w6{-r, s * r}, w9{-c1, -s * s1};
+  a[1][1] = cmul(a[1][1], w1);
+  a[1][2] = cmul(a[1][2], w2);
+  a[1][3] = cmul(a[1][3], w3);
+  a[2][1] = cmul(a[2][1], w2);
+  a[2][2] = cmul_is(a[2][2], s);
+  a[2][3] = cmul(a[2][3], w6);
+  a[3][1] = cmul(a[3][1], w3);
+  a[3][2] = cmul(a[3][2], w6);
+  a[3][3] = cmul(a[3][3], w9);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C2<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4(t, s);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+  }
+}
+
 template <typename T, int R>
 __device__ inline void dft(C2<T>* v, T s) {
   if constexpr (R == 2) dft2(v, s);
@@ -124,6 +158,7 @@ __device__ inline void dft(C2<T>* v, T s) {
   if constexpr (R == 4) dft4(v, s);
   if constexpr (R == 5) dft5(v, s);
   if constexpr (R == 8) dft8(v, s);
+  if constexpr (R == 16) dft16(v, s);
 }
 
 // FWD_Z / INV_Z: the oversampled grid's first and last passes (real in or out,
@@ -587,6 +622,11 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
       const FastDiv& dNs = a.dNs[st];
       const int tws = a.tws[st];
       switch (R) {
+        case 16:
+          // float32 only: the radix-16 stage's registers would cost the float64
+          // kernels occupancy (the plan never gives them radix 16)
+          if constexpr (sizeof(T) == 4) stage<T, 16, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1));
+          break;
         case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
         case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
         case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(-1)); break;
@@ -673,6 +713,11 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
       const FastDiv& dNs = a.dNs[st];
       const int tws = a.tws[st];
       switch (R) {
+        case 16:
+          // float32 only: the radix-16 stage's registers would cost the float64
+          // kernels occupancy (the plan never gives them radix 16)
+          if constexpr (sizeof(T) == 4) stage<T, 16, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1));
+          break;
         case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
         case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
         case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, T(1)); break;
@@ -708,9 +753,13 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
   }
 }
 
-void factor(int L, int* rad, int& nrad) {
+void factor(int L, int* rad, int& nrad, bool radix16 = false) {
   nrad = 0;
   int m = L;
+  while (radix16 && m % 16 == 0) {
+    rad[nrad++] = 16;
+    m /= 16;
+  }
   while (m % 8 == 0) {
     rad[nrad++] = 8;
     m /= 8;
@@ -812,7 +861,9 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
 // list of unmix blocks.
 template <typename T>
 unsigned pair_geometry(PassArgs<T>& a) {
-  factor(a.L, a.rad, a.nrad);
+  // float32: radix 16 (two stages for L = 256 instead of three; the pass runs
+  // two transforms per line, and fewer LDS round trips pay there)
+  factor(a.L, a.rad, a.nrad, sizeof(T) == 4);
   {
     int Ns = 1;
     for (int st = 0; st < a.nrad; ++st) {
