@@ -316,6 +316,14 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
     int le[MAXV];  // Z pass: line (high bits) and element (low 16 bits)
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
+      // slots past the block's inputs (padded passes load N of L) issue nothing;
+      // the test is uniform across the block
+      if (i * NT >= total_in) {
+        buf[i] = C2<T>{T(0), T(0)};
+        dst[i] = -1;
+        le[i] = 0;
+        continue;
+      }
       const int idx0 = threadIdx.x + i * NT;
       const bool ok = idx0 < total_in;
       const int idx = ok ? idx0 : 0;
@@ -387,6 +395,10 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
     C2<T> buf[MAXV];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
+      if (i * NT >= total_out) {  // cropped passes store N of L (uniform test)
+        buf[i] = C2<T>{T(0), T(0)};
+        continue;
+      }
       const int idx0 = threadIdx.x + i * NT;
       const int idx = idx0 < total_out ? idx0 : 0;
       int l, e;
@@ -405,6 +417,10 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
       // density values for the energy partials, loaded together
 #pragma unroll
       for (int i = 0; i < MAXV; ++i) {
+        if (i * NT >= total_out) {
+          rho_v[i] = T(0);
+          continue;
+        }
         const int idx0 = threadIdx.x + i * NT;
         const int idx = idx0 < total_out ? idx0 : 0;
         const int l = (int)a.dnout.div(idx), e = idx - l * a.nout;
@@ -568,6 +584,11 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
     int dst[MAXV];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
+      if (i * NT >= total_in) {  // uniform: the inputs are N of L per line
+        buf[i] = C2<T>{T(0), T(0)};
+        dst[i] = -1;
+        continue;
+      }
       const int idx0 = threadIdx.x + i * NT;
       const bool ok = idx0 < total_in;
       const int idx = ok ? idx0 : 0;
@@ -733,6 +754,10 @@ __global__ void __launch_bounds__(NT, 4) k_fft_pair_pass(PassArgs<T> a) {
     C2<T> buf[MAXV];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
+      if (i * NT >= total_out) {
+        buf[i] = C2<T>{T(0), T(0)};
+        continue;
+      }
       const int idx0 = threadIdx.x + i * NT;
       const int idx = idx0 < total_out ? idx0 : 0;
       const int e = (int)a.dLB.div(idx);
