@@ -4,10 +4,10 @@
 // Each 3D FFT is three passes of batched 1D transforms, one per axis.  A pass
 // stages LB lines of length L in LDS, runs a Stockham autosort FFT with radices
 // 8, 4, 2, 3, 5 (also 16 in Algorithm 2's float32 paired passes; twiddles from
-// a float64 table rounded to the working type), and writes the lines back.  Zero padding is never stored: forward passes
-// place the N nonzero inputs of a line at fine indices (m mod L),
-// m in [-N/2, N/2), and zero the rest in LDS; inverse passes write only those N
-// outputs (the crop to the physical grid).
+// a float64 table rounded to the working type), and writes the lines back.
+// Zero padding is never stored: forward passes place the N nonzero inputs of a
+// line at fine indices (m mod L), m in [-N/2, N/2), and zero the rest in LDS;
+// inverse passes write only those N outputs (the crop to the physical grid).
 //
 //   forward (type-2 front, sign -1):
 //     Z: rho (N0 N1 N2 reals) x H/(phi^0 phi^1 phi^2)  -> A1 [N0][N1][nf2]
@@ -18,10 +18,15 @@
 //     Y: B2 -> B1 [N0][N1][nf2]
 //     Z: B1 -> u = Re(.) / (phi^0 phi^1 phi^2), and partial sums of rho u
 //
-// Algorithm 2 (JGB_FLAG_SPLIT) changes three things: the forward Z pass also
+// Algorithm 2 (JGB_FLAG_SPLIT) changes four things: the forward Z pass also
 // places rho H in the imaginary part (two real transforms in one complex
-// one), the inverse starts from F, which then holds the combined spectrum of
-// both halves, and the last pass adds the imaginary part (I1) to u.
+// one); the potential's forward FFT stops before the last axis (X in 3D, Y in
+// 2D) and a paired unmix pass along it writes the type-2 grid into the tiles
+// the interpolation reads; the inverse's first pass is a fused paired pass that
+// transforms the same inputs forward again, forms the combined spectrum of both
+// halves and transforms it back (so the full forward spectrum is never
+// stored); and the last pass adds the imaginary part (I1) to u.  The
+// energy-only and transform calls run the full forward FFT into F.
 #include <cmath>
 
 #include "splitsym.h"
