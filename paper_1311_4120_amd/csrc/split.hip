@@ -12,9 +12,10 @@
 // inverse transform of G's Hermitian part (G(q) + conj G(-q)) / 2.  Both go
 // into one spectrum Y = Herm(G) + i M' B, so a single inverse FFT returns
 // I2 phi^ in its real part and I1 in its imaginary part; its first pass forms
-// Y with each line and its mirror in LDS (fft.hip, k_fft_pair_pass).  This file
-// holds the separation of A for the interpolation and the Fourier-side energy
-// of I1.
+// Y with each line and its mirror in LDS (fft.hip, k_fft_pair_pass), where the
+// potential's path also separates A.  This file holds the separation of A from
+// a stored spectrum (the energy-only and transform calls) and the Fourier-side
+// energy of I1.
 //
 // Index conventions: internal axes (a0, a1, a2), a2 contiguous; the mirror of
 // fine index q on an axis of nf points is (nf - q) mod nf, and the signed
