@@ -169,3 +169,24 @@ def test_split_dipole128_sampled(prec):
     say("   sampled relL2(u) %.2e  E %.2e" % (e, eE))
     assert e < eps and eE < eps
     plan.close()
+
+
+@pytest.mark.parametrize("name", ["dipole3d", "coulomb2d"])
+def test_split_calls_interleave(name):
+    """The potential path (forward passes but the last, paired unmix, fused
+    first inverse pass) and the energy and transform paths (full forward
+    spectrum, separate unmix) share the plan's grids: a potential after an
+    energy and a transform call equals the first potential bit for bit."""
+    p, window = CASES[name]
+    rho = _rho(p)
+    plan = _plan(p, window, 1e-10, "fp64")
+    rt = torch.tensor(rho, dtype=torch.float64, device="cuda")
+    u1, E1 = plan.potential(rt)
+    u1 = u1.clone()
+    plan.energy(rt)
+    plan.transform(rt)
+    u2, E2 = plan.potential(rt)
+    torch.cuda.synchronize()
+    say("split interleaved calls", name, "max |u2 - u1| %.1e" % (u2 - u1).abs().max().item())
+    assert torch.equal(u1, u2) and E1.item() == E2.item()
+    plan.close()
