@@ -256,6 +256,12 @@ hipError_t launch_split_energy(const Plan& pl, int eoff, hipStream_t s);
 // periodic complex FFT of the plan's N grid in place (sign -1 or +1)
 template <typename T>
 hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, int sign, hipStream_t s);
+// the GPE kinetic step in place: forward FFT, multiplier exp(-i h |k|^2 / 2) / N
+// (imaginary: exp(-h |k|^2 / 2) / N), inverse FFT, with the last forward and
+// the first inverse pass fused; kt: k per internal axis at offsets koff
+template <typename T>
+hipError_t launch_fft_periodic_kinetic(const Plan& pl, void* const tw[3], void* data, const double* kt,
+                                       const int koff[3], double h, int imaginary, double inv_n, hipStream_t s);
 // u = U*rho (and E) by the plan's pipeline, enqueued on stream st
 jgb_status potential_pipeline(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st);
 int fft_inverse_z_blocks(const Plan& pl);

@@ -169,7 +169,10 @@ __device__ inline void dft(C2<T>* v, T s) {
 // FWD_Z / INV_Z: the oversampled grid's first and last passes (real in or out,
 // deconvolution factors); COMPLEX: a complex pass along a strided axis;
 // COMPLEX_Z: a complex pass along the contiguous axis (the periodic FFT).
-enum PassKind { PASS_FWD_Z = 0, PASS_COMPLEX = 1, PASS_INV_Z = 2, PASS_COMPLEX_Z = 3 };
+// KINETIC: the GPE driver's kinetic step along one strided axis: the forward
+// transform, the multiplier exp(-i h |k|^2 / 2) / N (imaginary time:
+// exp(-h |k|^2 / 2) / N), and the inverse transform, in LDS.
+enum PassKind { PASS_FWD_Z = 0, PASS_COMPLEX = 1, PASS_INV_Z = 2, PASS_COMPLEX_Z = 3, PASS_KINETIC = 4 };
 template <int KIND>
 constexpr bool has_factors() { return KIND == PASS_FWD_Z || KIND == PASS_INV_Z; }
 
@@ -214,6 +217,15 @@ struct PassArgs {
   int64_t es_in, es_out;
   const void* G;
   SplitSym sym;
+  // the kinetic pass: k per internal axis in kt (offsets koff), the pass's
+  // axis kax (0, or 1 when axis 0 is a unit axis), a line's two other axes
+  // (a, b) = (line / nb, line mod nb) with the divisor in dkb
+  const double* kt;
+  int koff[3];
+  int kax;
+  FastDiv dkb;
+  double kin_h, inv_n;
+  int kin_imag;
 };
 
 // Position on the fine grid of physical index i of a line of N: (i - N/2) mod L.
@@ -275,7 +287,7 @@ __device__ inline void stage(C2<T>* lds, int ldl, int L, int LB, int Ns, const F
 // consecutive lines, the Z passes along the contiguous axis.
 template <typename T, int KIND, int MAXV, int NT>
 __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
-  constexpr bool LINES_FASTEST = (KIND == PASS_COMPLEX);
+  constexpr bool LINES_FASTEST = (KIND == PASS_COMPLEX || KIND == PASS_KINETIC);
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
   const int L = a.L;
@@ -374,19 +386,53 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
   __syncthreads();
 
   // FFT stages
-  int Ns = 1;
-  for (int st = 0; st < a.nrad; ++st) {
-    const int R = a.rad[st];
-    const FastDiv& dNs = a.dNs[st];
-    const int tws = a.tws[st];
-    switch (R) {
-      case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
-      default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, a.sign); break;
+  auto transform = [&](T sign) {
+    int Ns = 1;
+    for (int st = 0; st < a.nrad; ++st) {
+      const int R = a.rad[st];
+      const FastDiv& dNs = a.dNs[st];
+      const int tws = a.tws[st];
+      switch (R) {
+        case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
+        case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
+        case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
+        case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
+        default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
+      }
+      Ns *= R;
     }
-    Ns *= R;
+  };
+  if constexpr (KIND == PASS_KINETIC) {
+    transform(T(-1));
+    // the multiplier at every element, |k|^2 summed in axis order
+    for (int idx = threadIdx.x; idx < LB * L; idx += NT) {
+      const int e = (int)a.dLB.div(idx), l = idx - e * LB;
+      const int line = line0 + l;
+      if (line >= a.nlines) continue;
+      const int ia = (int)a.dkb.div(line), ib = line - ia * (int)a.dkb.d;
+      const double ke = a.kt[a.koff[a.kax] + e];
+      const double kb = a.kt[a.koff[2] + ib];
+      const double kx = a.kax == 0 ? ke : a.kt[a.koff[0] + ia];
+      const double ky = a.kax == 0 ? a.kt[a.koff[1] + ia] : ke;
+      const double ex = 0.5 * a.kin_h * (kx * kx + ky * ky + kb * kb);
+      double fr, fi;
+      if (a.kin_imag) {
+        fr = exp(-ex) * a.inv_n;
+        fi = 0.0;
+      } else {
+        sincos(-ex, &fi, &fr);
+        fr *= a.inv_n;
+        fi *= a.inv_n;
+      }
+      C2<T>* pv = lds + l * ldl + e;
+      const C2<T> p = *pv;
+      const double re = fr * p.x - fi * p.y, im = fr * p.y + fi * p.x;
+      *pv = C2<T>{(T)re, (T)im};
+    }
+    __syncthreads();
+    transform(T(1));
+  } else {
+    transform(a.sign);
   }
 
   // store: LDS reads first, then the global stores
@@ -823,14 +869,14 @@ void factor(int L, int* rad, int& nrad, bool radix16 = false) {
 constexpr int PASS_PAIR = 9;
 template <typename T, int KIND = PASS_PAIR>
 constexpr int pass_threads() {
-  if (KIND == PASS_COMPLEX) return sizeof(T) == 8 ? 256 : 512;
+  if (KIND == PASS_COMPLEX || KIND == PASS_KINETIC) return sizeof(T) == 8 ? 256 : 512;
   if (KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 256;
   if (KIND == PASS_PAIR) return 256;
   return 512;
 }
 template <typename T, int KIND = PASS_PAIR>
 constexpr int pass_elems() {
-  if (KIND == PASS_COMPLEX || KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 8;
+  if (KIND == PASS_COMPLEX || KIND == PASS_KINETIC || KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 8;
   return sizeof(T) == 8 ? 8 : 16;
 }
 template <typename T, int KIND>
@@ -1243,6 +1289,81 @@ hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, in
 
 template hipError_t launch_fft_periodic<double>(const Plan&, void* const[3], void*, int, hipStream_t);
 template hipError_t launch_fft_periodic<float>(const Plan&, void* const[3], void*, int, hipStream_t);
+
+// The GPE kinetic step in place: forward passes along a2 (and a1 in 3D), one
+// kinetic pass along the last axis (a0, or a1 when a0 is a unit axis) that
+// transforms forward, multiplies and transforms back, then the inverse passes
+// in reverse order.  kt: k per internal axis at offsets koff.
+template <typename T>
+hipError_t launch_fft_periodic_kinetic(const Plan& pl, void* const tw[3], void* data, const double* kt,
+                                       const int koff[3], double h, int imaginary, double inv_n, hipStream_t s) {
+  const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
+  const bool has_x = n0 > 1;
+  auto common = [&](int axis, T sg) {
+    PassArgs<T> a{};
+    a.L = pl.n[axis];
+    a.nin = a.nout = a.L;
+    a.sign = sg;
+    a.tw = (const C2<T>*)tw[axis];
+    a.n1 = (int)n1;
+    a.n2 = (int)n2;
+    a.in = data;
+    a.out = data;
+    a.kt = kt;
+    for (int i = 0; i < 3; ++i) a.koff[i] = koff[i];
+    a.kin_h = h;
+    a.inv_n = inv_n;
+    a.kin_imag = imaginary;
+    a.dkb = FastDiv((uint32_t)n2);  // a line's other two axes: (line / n2, line mod n2)
+    return a;
+  };
+  auto pass_z = [&](T sg) {  // axis 2, contiguous: lines [n0][n1]
+    PassArgs<T> a = common(2, sg);
+    a.nlines = n0 * n1;
+    a.ic = 1;
+    a.in_os = a.out_os = n2;
+    a.in_is = a.out_is = 0;
+    a.in_es = a.out_es = 1;
+    return run_pass<T, PASS_COMPLEX_Z>(pl, -1, a, s);
+  };
+  auto pass_y = [&](T sg, bool kinetic) {  // axis 1: lines [n0][n2], line = i0 n2 + i2
+    PassArgs<T> a = common(1, sg);
+    a.nlines = n0 * n2;
+    a.ic = n2;
+    a.in_os = a.out_os = n1 * n2;
+    a.in_is = a.out_is = 1;
+    a.in_es = a.out_es = n2;
+    a.lines_fastest = 1;
+    a.kax = 1;
+    return kinetic ? run_pass<T, PASS_KINETIC>(pl, -1, a, s) : run_pass<T, PASS_COMPLEX>(pl, -1, a, s);
+  };
+  auto pass_x_kinetic = [&]() {  // axis 0: lines [n1 n2], line = i1 n2 + i2
+    PassArgs<T> a = common(0, T(-1));
+    a.nlines = n1 * n2;
+    a.ic = n1 * n2;
+    a.in_os = a.out_os = 0;
+    a.in_is = a.out_is = 1;
+    a.in_es = a.out_es = n1 * n2;
+    a.lines_fastest = 1;
+    a.kax = 0;
+    return run_pass<T, PASS_KINETIC>(pl, -1, a, s);
+  };
+  hipError_t e;
+  if ((e = pass_z(T(-1))) != hipSuccess) return e;
+  if (has_x) {
+    if ((e = pass_y(T(-1), false)) != hipSuccess) return e;
+    if ((e = pass_x_kinetic()) != hipSuccess) return e;
+    if ((e = pass_y(T(1), false)) != hipSuccess) return e;
+  } else {
+    if ((e = pass_y(T(-1), true)) != hipSuccess) return e;
+  }
+  return pass_z(T(1));
+}
+
+template hipError_t launch_fft_periodic_kinetic<double>(const Plan&, void* const[3], void*, const double*,
+                                                        const int[3], double, int, double, hipStream_t);
+template hipError_t launch_fft_periodic_kinetic<float>(const Plan&, void* const[3], void*, const double*,
+                                                       const int[3], double, int, double, hipStream_t);
 
 // d_origin = {c0 H sum rho, c0 (H sum rho)^2} from the first forward pass's
 // per-block sums (one block, fixed order).

@@ -83,31 +83,6 @@ __global__ void __launch_bounds__(256) k_gpe_local(Grid g, C2<T>* psi, const T* 
   }
 }
 
-// K's multiplier on the DFT of psi, with the inverse DFT's 1/N folded in:
-// exp(-i h |k|^2 / 2) / N or exp(-h |k|^2 / 2) / N.  kt: k_a(q) per axis.
-template <typename T>
-__global__ void __launch_bounds__(256) k_gpe_kinetic(Grid g, C2<T>* ph, const double* kt, int off1, int off2,
-                                                     double h, int imaginary, double inv_n) {
-  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < g.npts; i += gridDim.x * 256u) {
-    int i0, i1, i2;
-    coords(g, i, i0, i1, i2);
-    const double k0 = kt[i0], k1 = kt[off1 + i1], k2 = kt[off2 + i2];
-    const double e = 0.5 * h * (k0 * k0 + k1 * k1 + k2 * k2);
-    double fr, fi;
-    if (imaginary) {
-      fr = exp(-e) * inv_n;
-      fi = 0.0;
-    } else {
-      sincos(-e, &fi, &fr);
-      fr *= inv_n;
-      fi *= inv_n;
-    }
-    C2<T> p = ph[i];
-    const double re = fr * p.x - fi * p.y, im = fr * p.y + fi * p.x;
-    ph[i] = C2<T>{(T)re, (T)im};
-  }
-}
-
 // Per-block partial sums of |psi|^2, V |psi|^2, |psi|^4 and Phi |psi|^2
 // (phi may be null: that sum is 0), in a fixed order.
 template <typename T>
@@ -289,14 +264,9 @@ jgb_status enqueue_local(jgb_gpe_s* q, void* psi, double h, bool write_rho) {
 template <typename T>
 jgb_status enqueue_kinetic(jgb_gpe_s* q, void* psi, double h) {
   Plan& pl = q->plan->pl;
-  hipError_t e = jgb::launch_fft_periodic<T>(pl, q->tw, psi, -1, q->st);
-  if (e != hipSuccess) return gpe_hip(e, "kinetic FFT");
-  const unsigned nb = blocks_for(q->g.npts);
-  hipLaunchKernelGGL(jgb::k_gpe_kinetic<T>, dim3(nb), dim3(256), 0, q->st, q->g, (jgb::C2<T>*)psi, q->kt,
-                     q->koff[1], q->koff[2], h, q->imaginary, 1.0 / (double)q->g.npts);
-  if ((e = hipGetLastError()) != hipSuccess) return gpe_hip(e, "kinetic multiplier");
-  e = jgb::launch_fft_periodic<T>(pl, q->tw, psi, +1, q->st);
-  return gpe_hip(e, "kinetic inverse FFT");
+  hipError_t e = jgb::launch_fft_periodic_kinetic<T>(pl, q->tw, psi, q->kt, q->koff, h, q->imaginary,
+                                                     1.0 / (double)q->g.npts, q->st);
+  return gpe_hip(e, "kinetic step");
 }
 
 // One Strang step, enqueued on q->st (the captured body of the graph).  Real
