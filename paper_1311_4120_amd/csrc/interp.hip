@@ -74,18 +74,17 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, 0xf, false));
 }
 
-// Sum over the 64 lanes: inclusive scans within rows of 16 (row_shr 1, 2, 4, 8),
-// then row 0 and 2 totals into rows 1 and 3 (row_bcast:15), then the first
-// half's total into rows 2 and 3 (row_bcast:31); lane 63 ends with the sum.
+// Sums over each half of the wavefront: the same scans within rows of 16, then
+// the row 0 and 2 totals into rows 1 and 3; lane 31 ends with the sum of lanes
+// 0-31 and lane 63 with that of lanes 32-63.
 template <typename T>
-__device__ __forceinline__ T wave_total(T v) {
+__device__ __forceinline__ T half_totals(T v) {
   v += dpp<0x111, 0xf>(v);
   v += dpp<0x112, 0xf>(v);
   v += dpp<0x114, 0xf>(v);
   v += dpp<0x118, 0xf>(v);
   v += dpp<0x142, 0xa>(v);
-  v += dpp<0x143, 0xc>(v);
-  return lane_value(v, 63);
+  return v;
 }
 
 // D3: three spreading axes; a 2D problem has one tap on axis 0.
@@ -94,7 +93,7 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   constexpr int E2 = W + 16;  // staged row length (the plan guarantees a.E2 == E2)
   extern __shared__ unsigned char smem_raw[];
   C2<T>* tile = reinterpret_cast<C2<T>*>(smem_raw);
-  __shared__ alignas(16) T wbuf[kInterpWaves][64];
+  __shared__ alignas(16) T wbuf[kInterpWaves][96];
   __shared__ double ws[kInterpWaves];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -154,13 +153,20 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   }
   __syncthreads();
 
-  constexpr int NP = W * W;             // tap pairs of the two axes the lanes own
-  constexpr int NQ = (NP + 63) / 64;    // pairs per lane
-  const T* wrow = wbuf[wave];
+  // Two nodes per wavefront: lanes 0-31 take the wave's node j, lanes 32-63
+  // its next one, j + kInterpWaves, so that the reductions and the per-node
+  // bookkeeping are shared by two nodes.  Each half reads its node's copy of
+  // the record in LDS (48 values: axis a's taps at 16 a), node j's at
+  // wbuf[wave][0, 48), the other's at [48, 96).
+  constexpr int NP = W * W;             // tap pairs of the two axes a half owns
+  constexpr int NQ = (NP + 31) / 32;    // pairs per lane
+  constexpr int KW = kInterpWaves;
+  const int half = lane >> 5, hl = lane & 31;
+  const T* wrow = wbuf[wave] + 48 * half;
   double eacc = 0.0;
-  // node data are fetched one node ahead: the record (lane 16 axis + tap), the
-  // footprint start and the coefficient of node j + kInterpWaves go out before
-  // node j's taps are read from LDS
+  // node data are fetched one pair ahead: the records (lane 16 axis + tap), the
+  // footprint starts and the coefficients of the next pair go out before this
+  // pair's taps are read from LDS
   const int ax = lane >> 4, tap = lane & 15;
   const bool wlane = ax < 3 && tap < W;
   const int woff = wlane ? ax * W + tap : 0;  // inside the node's record for every lane
@@ -171,28 +177,31 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     asm volatile("" : "+v"(jj));
     return jj;
   };
+  // the half's node: j, or j + KW (node j when there is none: read, not used)
   int4 h_next{};
-  T wv_next = T(0);
+  T wa_next = T(0), wb_next = T(0);
   double c_next = 0.0;
+  auto fetch = [&](int jj) {
+    const bool second = jj + KW < item.end;
+    const int jn = vec_index(half && second ? jj + KW : jj);
+    h_next = a.hdr[jn];
+    wa_next = fetch_w(vec_index(jj));
+    wb_next = second ? fetch_w(vec_index(jj + KW)) : T(0);
+    if (a.mode != INTERP_TRANSFORM) c_next = a.coef[jn];
+  };
   int j = item.begin + wave;
-  if (j < item.end) {
-    const int jv = vec_index(j);
-    h_next = a.hdr[jv];
-    wv_next = fetch_w(jv);
-    if (a.mode != INTERP_TRANSFORM) c_next = a.coef[jv];
-  }
-  for (; j < item.end; j += kInterpWaves) {
+  if (j < item.end) fetch(j);
+  for (; j < item.end; j += 2 * KW) {
+    const bool second = j + KW < item.end;
     const int4 h = h_next;
-    const T wv = wlane ? wv_next : T(0);
+    const T wa = wlane ? wa_next : T(0), wb2 = wlane ? wb_next : T(0);
     const double c = c_next;
-    if (j + kInterpWaves < item.end) {
-      const int jv = vec_index(j + kInterpWaves);
-      h_next = a.hdr[jv];
-      wv_next = fetch_w(jv);
-      if (a.mode != INTERP_TRANSFORM) c_next = a.coef[jv];
-    }
+    if (j + 2 * KW < item.end) fetch(j + 2 * KW);
     const int lx0 = h.x - ox, ly0 = h.y - oy, lz0 = h.z - oz;  // in [0, S)
-    wbuf[wave][lane] = wv;
+    if (lane < 48) {
+      wbuf[wave][lane] = wa;
+      wbuf[wave][48 + lane] = wb2;
+    }
     __builtin_amdgcn_wave_barrier();
 
     // 3D: lane owns tap pair (a, c) of axes 0 and 2 and walks the W taps of
@@ -203,7 +212,7 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     T wyz[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int p = lane + 64 * q;
+      const int p = hl + 32 * q;
       const bool ok = p < NP;
       const int pa = ok ? p / W : 0, pc = ok ? p % W : 0;
       if constexpr (D3) {
@@ -215,20 +224,20 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
       }
       acc[q] = C2<T>{T(0), T(0)};
     }
-    // the loop's weights (the same for every lane) come from the wave's copy
-    // of the record in LDS, two per broadcast read
+    // the loop's weights (the same for every lane of a half) come from the
+    // half's copy of the record in LDS, two per broadcast read
 #pragma unroll
     for (int ib = 0; ib < (D3 ? W : 1); ib += 2) {
       const C2<T> wpair = *reinterpret_cast<const C2<T>*>(wrow + (D3 ? 16 + ib : 0));
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (D3 ? ib + h < W : h == 0) {
-          const T wb = h == 0 ? wpair.x : wpair.y;
+      for (int hh = 0; hh < 2; ++hh) {
+        if (D3 ? ib + hh < W : hh == 0) {
+          const T wbv = hh == 0 ? wpair.x : wpair.y;
 #pragma unroll
           for (int q = 0; q < NQ; ++q) {
-            const C2<T> v = tile[off[q] + (ib + h) * E2];
-            acc[q].x += wb * v.x;
-            acc[q].y += wb * v.y;
+            const C2<T> v = tile[off[q] + (ib + hh) * E2];
+            acc[q].x += wbv * v.x;
+            acc[q].y += wbv * v.y;
           }
         }
       }
@@ -239,19 +248,26 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
       sr += wyz[q] * acc[q].x;
       si += wyz[q] * acc[q].y;
     }
-    sr = wave_total(sr);
-    si = wave_total(si);
-    if (lane == 0) {
+    // lane 31 ends with the first half's sum, lane 63 with the second's
+    sr = half_totals(sr);
+    si = half_totals(si);
+    const T ar = lane_value(sr, 31), ai = lane_value(si, 31);
+    const T br = lane_value(sr, 63), bi = lane_value(si, 63);
+    if (lane == 0 || (lane == 32 && second)) {
+      const int jj = lane == 0 ? j : j + KW;
+      const T vr = lane == 0 ? ar : br, vi = lane == 0 ? ai : bi;
       if (a.mode == INTERP_TRANSFORM) {
-        a.out[a.perm[j]] = C2<T>{sr, si};
+        a.out[a.perm[jj]] = C2<T>{vr, vi};
       } else {
-        double re = (double)sr, im = (double)si;
+        double re = (double)vr, im = (double)vi;
         eacc += c * (re * re + im * im);
-        if (a.mode == INTERP_POTENTIAL) a.uhat[j] = C2<T>{(T)(c * re), (T)(c * im)};
+        if (a.mode == INTERP_POTENTIAL) a.uhat[jj] = C2<T>{(T)(c * re), (T)(c * im)};
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
+  // the wave's energy: lane 0's nodes, then lane 32's
+  eacc = lane_value(eacc, 0) + lane_value(eacc, 32);
 
   if (a.mode != INTERP_TRANSFORM && a.eparts) {
     if (lane == 0) ws[wave] = eacc;
