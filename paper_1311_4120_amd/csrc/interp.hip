@@ -11,11 +11,12 @@
 // One block per sub-bin (or a slice of a crowded one): the block stages the
 // grid region every footprint of the sub-bin can touch -- the sub-bin plus
 // w - 1 cells on the high side of each axis -- in LDS with coalesced loads,
-// then each wavefront interpolates one node at a time from LDS.  Lanes 0..47
-// first read the node's 3 x w tabulated kernel values (lane 16a + i holds phi
-// for axis a, tap i); lanes then own (b, c) tap pairs of the two inner axes
-// and loop over the outer one, and the per-lane sums are reduced across the
-// wavefront.
+// then each wavefront interpolates two nodes at a time from LDS, one per half
+// of 32 lanes.  Lanes 0..47 first read both nodes' 3 x w tabulated kernel
+// values (lane 16a + i holds phi for axis a, tap i) into the wave's LDS copy;
+// the lanes of a half then own (b, c) tap pairs of the two inner axes of its
+// node and loop over the outer one, and the per-lane sums are reduced within
+// each half.
 #include "common.h"
 
 namespace jgb {
