@@ -25,7 +25,8 @@ symmetry, self-adjointness).
 from .quadrature import (gauss_legendre, radial_rule, theta_rule, phi_rule,
                          spherical_nodes, polar_nodes, fourier_nodes)
 from .symbols import symbol, coefficients
-from .direct import (rho_hat, rho_hat_separable, sum_to_grid, sum_to_points, potential, energy_fourier,
+from .direct import (rho_hat, rho_hat_separable, rho_hat_separable_sum, sum_to_grid, sum_to_points,
+                     sum_to_lattice, potential, energy_fourier,
                      energy_physical, Result, evaluate, energy_gradient_rho,
                      energy_gradient_psi, apply_operator)
 from . import closed_forms
@@ -34,7 +35,7 @@ from . import gpe
 
 __all__ = [
     "gauss_legendre", "radial_rule", "theta_rule", "phi_rule", "spherical_nodes",
-    "polar_nodes", "fourier_nodes", "symbol", "coefficients", "rho_hat", "rho_hat_separable", "sum_to_grid",
-    "sum_to_points", "potential", "energy_fourier", "energy_physical", "Result", "evaluate",
+    "polar_nodes", "fourier_nodes", "symbol", "coefficients", "rho_hat", "rho_hat_separable", "rho_hat_separable_sum", "sum_to_grid",
+    "sum_to_points", "sum_to_lattice", "potential", "energy_fourier", "energy_physical", "Result", "evaluate",
     "energy_gradient_rho", "energy_gradient_psi", "apply_operator", "closed_forms", "split", "gpe",
 ]

@@ -86,6 +86,33 @@ def rho_hat_separable(factors, box, k):
     return H * out
 
 
+def rho_hat_separable_sum(coefs, factors, box, k):
+    """rho^_j for a density given as a finite sum of separable terms,
+    rho_n = sum_t coef_t prod_i f_{t,i}[n_i], the factors complex in general
+    (rho = |psi|^2 of a sum of Gaussian wave packets is such a sum; the total is
+    real).  By linearity of eq. 3.2 and the per-axis factorisation of the
+    exponential, rho^_j = H sum_t coef_t prod_i sum_{n_i} f_{t,i}[n_i]
+    exp(-i k_{j,i} x_{n_i}), which is what is evaluated: one phase table per
+    axis, contracted with every term's factor on that axis."""
+    k = np.asarray(k, dtype=np.float64)
+    coefs = np.asarray(coefs, dtype=np.complex128)
+    d = len(factors[0])
+    n = [len(f) for f in factors[0]]
+    x = _axes(n, box)
+    H = _cell_volume(n, box)
+    F = [np.stack([np.asarray(ft[i], dtype=np.complex128) for ft in factors], axis=1) for i in range(d)]  # (N_i, T)
+    M = k.shape[0]
+    out = np.empty(M, dtype=np.complex128)
+    B = max(1, _CHUNK_ELEMS // max(max(n), len(coefs)))
+    for s in range(0, M, B):
+        kb = k[s:s + B]
+        acc = np.ones((kb.shape[0], len(coefs)), dtype=np.complex128)
+        for i in range(d):
+            acc *= np.exp(-1j * np.outer(kb[:, i], x[i])) @ F[i]
+        out[s:s + B] = acc @ coefs
+    return H * out
+
+
 def sum_to_grid(v, k, n, box):
     """Type-1 sum f_n = sum_j v_j exp(+i k_j . x_n) on the whole grid (complex)."""
     v = np.asarray(v, dtype=np.complex128)
@@ -124,6 +151,33 @@ def sum_to_points(v, k, n, box, index):
     for s in range(0, M, B):
         out += v[s:s + B] @ np.exp(1j * (k[s:s + B] @ X.T))
     return out
+
+
+def sum_to_lattice(v, k, n, box, index_lists):
+    """Type-1 sum f = sum_j v_j exp(+i k_j . x) at the product set of grid
+    indices index_lists[0] x index_lists[1] (x index_lists[2]): the sum of
+    sum_to_grid restricted to a subset of the grid (a sub-lattice, or a line
+    when the other lists have one index), with the same per-axis phase tables.
+    Returns an array of shape (len(index_lists[0]), len(index_lists[1]), ...)."""
+    v = np.asarray(v, dtype=np.complex128)
+    k = np.asarray(k, dtype=np.float64)
+    d = len(n)
+    ax = _axes(n, box)
+    x = [ax[j][np.asarray(index_lists[j], dtype=np.int64)] for j in range(d)]
+    L = [len(xj) for xj in x]
+    rest = int(np.prod(L[1:]))
+    out = np.zeros((L[0], rest), dtype=np.complex128)
+    M = k.shape[0]
+    B = max(1, _CHUNK_ELEMS // max(rest, max(L), 1))
+    for s in range(0, M, B):
+        kb = k[s:s + B]
+        P = [np.exp(1j * np.outer(kb[:, j], x[j])) for j in range(d)]
+        if d == 2:
+            Q = v[s:s + B, None] * P[1]
+        else:
+            Q = (v[s:s + B, None, None] * P[1][:, :, None] * P[2][:, None, :]).reshape(kb.shape[0], rest)
+        out += P[0].T @ Q
+    return out.reshape(tuple(L))
 
 
 def energy_fourier(c, rhohat, lam):

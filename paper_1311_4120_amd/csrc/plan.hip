@@ -370,6 +370,8 @@ Status autotune(Plan& pl) {
 
 }  // namespace
 
+void accuracy_parameters(double eps, int& w, double& beta);
+
 Status validate(const jgb_params* p) {
   if (!p) return fail(JGB_ERR_INVALID_ARG, "params is NULL");
   if (p->struct_size != sizeof(jgb_params)) return fail(JGB_ERR_INVALID_ARG, "params.struct_size != sizeof(jgb_params)");
@@ -428,6 +430,16 @@ Status validate(const jgb_params* p) {
   }
   int64_t M = (int64_t)p->n_r * p->n_phi * (p->dim == 3 ? p->n_theta : 1);
   if (M / 2 > (int64_t)std::numeric_limits<int>::max() / 2) return fail(JGB_ERR_UNSUPPORTED, "too many nodes");
+  {
+    // the spreading kernel addresses the per-node tables (kernel-value records
+    // and weighted values of the half node set) by 32-bit byte offsets
+    int w;
+    double beta;
+    accuracy_parameters(p->eps, w, beta);
+    const uint64_t rb = p->precision == JGB_FP64 ? 8 : 4, Mh = (uint64_t)(M / 2);
+    if (Mh * (uint64_t)record_stride(w) * rb >= (1ull << 32) || Mh * 2 * rb >= (1ull << 32))
+      return fail(JGB_ERR_UNSUPPORTED, "node tables of 4 GiB or more (too many nodes for this eps and precision)");
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -678,7 +690,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   }
   for (int t = 0; t < pl.ngtiles; ++t) tcount[t + 1] += tcount[t];
   const int64_t nlist = tcount[pl.ngtiles];
-  if (nlist > (int64_t)std::numeric_limits<int>::max()) return fail(JGB_ERR_UNSUPPORTED, "gather lists too long");
+  // the gather addresses its list by 32-bit byte offsets (8 bytes per entry)
+  if ((nlist + 1) * 8 >= ((int64_t)1 << 32)) return fail(JGB_ERR_UNSUPPORTED, "gather lists too long");
   // entry: node index and its first tap relative to the tile origin on each
   // axis (10 bits each).  When every axis has nf >= T + w - 1 the start of a
   // footprint that touches the tile has exactly one representative in

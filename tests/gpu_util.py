@@ -38,3 +38,30 @@ def half_index(problem):
         return ((a * problem.n_theta + b) * nph + l).ravel()
     a, l = np.meshgrid(np.arange(problem.n_r), np.arange(nph // 2), indexing="ij")
     return (a * nph + l).ravel()
+
+
+def load_sampled(name):
+    """The oracle's values at sampled outputs of a large workload (written by
+    tests/golden/make_sampled.py, which calls only the oracle)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sampled_%s.npz" % name)
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def sampled_errors(u, ref):
+    """u (the whole grid, numpy) against the sampled oracle values: the random
+    sub-lattice, the three axis lines through the centre and the random points.
+    Returns (rel-L2 over all samples, max error / max |u| of the grid, sample count)."""
+    got, want = [], []
+    lat = (ref["lattice0"], ref["lattice1"], ref["lattice2"])
+    got.append(u[np.ix_(*lat)].ravel())
+    want.append(ref["u_lattice"].ravel())
+    c = ref["center"]
+    got += [u[:, c[1], c[2]], u[c[0], :, c[2]], u[c[0], c[1], :]]
+    want += [ref["u_line0"], ref["u_line1"], ref["u_line2"]]
+    got.append(u[tuple(ref["points"].T)])
+    want.append(ref["u_points"])
+    g = np.concatenate(got)
+    w = np.concatenate(want)
+    return rel_l2(g, w), float(np.max(np.abs(g - w)) / np.max(np.abs(u))), g.size

@@ -126,6 +126,9 @@ BAD = [
     ("alpha nan", dict(alpha=float("nan")), 1),
     ("dipole2d axis not unit", dict(dim=2, kernel=3, dipole_axis=(0.6, 0.0, 0.0)), 1),
     ("poisson2d needs dim 2", dict(kernel=4), 1),
+    # 33.5 M half-set nodes x 320-byte fp64 records: past the 32-bit table offsets
+    ("node tables over 4 GiB", dict(n_r=512, n_theta=256, n_phi=512), 2),
+    ("node tables over 4 GiB, mixed", dict(precision=1, eps=1e-5, n_r=1024, n_theta=512, n_phi=512), 2),
 ]
 
 

@@ -11,7 +11,7 @@ import workloads as wl
 from gpu_util import make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
-torch = pytest.importorskip("torch")
+import torch  # noqa: E402
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

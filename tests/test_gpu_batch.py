@@ -8,10 +8,10 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import rel_l2, say
+from gpu_util import load_sampled, rel_l2, sampled_errors, say
 
 pytestmark = pytest.mark.gpu
-torch = pytest.importorskip("torch")
+import torch  # noqa: E402
 
 
 def _members():
@@ -112,11 +112,22 @@ def test_batched_coulomb_workload():
         worst = max(worst, abs(E[i].item() / Ec - 1))
     say("   worst energy deviation from the closed form %.2e" % worst)
     assert worst < 1e-3
-    # the smallest member against the oracle itself
+    # the smallest member against the whole-grid oracle
     i = min(range(64), key=lambda k: members[k][0].npoints)
     p, mix = members[i]
     res = oracle.evaluate(p, rhos[i].double().cpu().numpy())
     e = rel_l2(u[i].cpu().numpy(), res.u)
     say("   member %d (%s) relL2 vs oracle %.2e" % (i, p.n, e))
     assert e < 1e-5
+    # one member of each grid size (64^3 .. 160^3) against the oracle's sampled
+    # values (4096 sub-lattice points, three axis lines, 512 random points) and
+    # its Fourier-side energy
+    for i in (7, 3, 0, 1):
+        ref = load_sampled("batched_coulomb_%d" % i)
+        assert tuple(ref["n"]) == members[i][0].n
+        e, emax, ns = sampled_errors(u[i].cpu().numpy().astype(np.float64), ref)
+        eE = abs(E[i].item() / float(ref["energy"]) - 1)
+        say("   member %d (%s): %d sampled points relL2 %.2e max/|u|max %.2e  E %.2e" % (i, members[i][0].n, ns, e,
+                                                                                      emax, eE))
+        assert e < 1e-5 and emax < 1e-5 and eE < 1e-5
     b.close()

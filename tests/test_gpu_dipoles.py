@@ -12,7 +12,7 @@ from oracle import split
 from gpu_util import make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
-torch = pytest.importorskip("torch")
+import torch  # noqa: E402
 
 
 def _unit(v):

@@ -17,7 +17,7 @@ import workloads as wl
 from gpu_util import half_index, make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
-torch = pytest.importorskip("torch")
+import torch  # noqa: E402
 
 
 def _axis(seed):

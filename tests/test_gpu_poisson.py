@@ -13,7 +13,7 @@ from oracle.symbols import origin_coefficient
 from gpu_util import make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
-torch = pytest.importorskip("torch")
+import torch  # noqa: E402
 
 CASES = {
     "poisson2d": wl.Problem("p1", 2, (64, 48), (16.0, 12.0), wl.POISSON_2D, 32, 1, 48),

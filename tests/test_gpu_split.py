@@ -20,7 +20,7 @@ from oracle import split
 from gpu_util import half_index, make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
-torch = pytest.importorskip("torch")
+import torch  # noqa: E402
 
 
 def _axis(seed):

@@ -82,6 +82,54 @@ def test_separable_rho_hat_equals_general_sum():
                        atol=1e-12 * np.max(np.abs(rho2)) * np.prod(box[:2]))
 
 
+def test_lattice_sum_brute_force():
+    # the type-1 sum at a product set of grid indices (and at a line) equals brute force there
+    rng = np.random.default_rng(13)
+    shape, box = (5, 4, 6), (3.0, 2.5, 4.0)
+    k = rng.uniform(-2, 2, size=(11, 3))
+    v = rng.standard_normal(11) + 1j * rng.standard_normal(11)
+    ref = _brute_sum(v, k, shape, box)
+    lists = [np.array([4, 0, 2]), np.array([1, 3]), np.array([5, 0, 3, 2])]
+    got = oracle.sum_to_lattice(v, k, shape, box, lists)
+    assert got.shape == (3, 2, 4)
+    assert np.allclose(got, ref[np.ix_(*lists)], rtol=0, atol=1e-12)
+    line = oracle.sum_to_lattice(v, k, shape, box, [np.arange(5), [2], [3]])
+    assert np.allclose(line[:, 0, 0], ref[:, 2, 3], rtol=0, atol=1e-12)
+    got2 = oracle.sum_to_lattice(v[:7], k[:7, :2], (6, 5), (4.0, 2.5), [np.array([5, 1]), np.array([0, 4, 2])])
+    ref2 = _brute_sum(v[:7], k[:7, :2], (6, 5), (4.0, 2.5))
+    assert np.allclose(got2, ref2[np.ix_([5, 1], [0, 4, 2])], rtol=0, atol=1e-12)
+
+
+def test_separable_terms_rho_hat_equals_general_sum():
+    # |psi|^2 of complex wave packets as a sum of complex separable terms: its
+    # transform by the per-term regrouping equals the general sum on the assembled
+    # density, and equals brute force on a tiny grid
+    rng = np.random.default_rng(16)
+    pk = wl.random_wave_packets(rng, p=3, lo=-1.0, hi=1.0)
+    n, box = (11, 9, 13), (6.0, 5.0, 7.0)
+    psi = pk.evaluate(n, box)
+    rho = np.abs(psi) ** 2
+    coefs, factors = pk.density_terms(n, box)
+    assert len(coefs) == 9
+    k = rng.uniform(-2.5, 2.5, size=(40, 3))
+    a = oracle.rho_hat_separable_sum(coefs, factors, box, k)
+    b = oracle.rho_hat(rho, box, k)
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
+    # the transform of a real density is Hermitian: rho^(-k) = conj rho^(k)
+    am = oracle.rho_hat_separable_sum(coefs, factors, box, -k)
+    assert np.max(np.abs(am - np.conj(a))) < 1e-12 * np.max(np.abs(a))
+    n3, box3 = (3, 4, 3), (2.0, 3.0, 2.5)
+    c3, f3 = pk.density_terms(n3, box3)
+    k3 = k[:5]
+    assert np.allclose(oracle.rho_hat_separable_sum(c3, f3, box3, k3),
+                       _brute_rho_hat(np.abs(pk.evaluate(n3, box3)) ** 2, box3, k3), rtol=0, atol=1e-13)
+    # a real Gaussian mixture through the same route
+    mix = wl.random_mixture(rng, 3, 3, -1.0, 1.0, 0.8, 1.5)
+    cm, fm = mix.density_terms(n, box)
+    assert np.max(np.abs(oracle.rho_hat_separable_sum(cm, fm, box, k)
+                         - oracle.rho_hat(mix.evaluate(n, box), box, k))) < 1e-12 * np.max(np.abs(b))
+
+
 def test_rho_hat_of_shifted_gaussian():
     # rho = exp(-|x-c|^2): the trapezoid sum converges to pi^{3/2} exp(-|k|^2/4) exp(-i k.c);
     # the phase pins the sign of the exponent and the grid offset x_n = -R/2 + n h

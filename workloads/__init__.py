@@ -93,6 +93,18 @@ class Mixture:
         return out
 
 
+    def density_terms(self, n, box):
+        """The same density as a sum of separable terms: A exp(-|x-c|^2/sigma^2) =
+        A prod_i exp(-(x_i-c_i)^2/sigma^2).  Returns (coefficients, per-term lists
+        of per-axis samples)."""
+        axes = grid_axes(n, box)
+        coefs, factors = [], []
+        for A, c, s in zip(self.amps, self.centers, self.widths):
+            coefs.append(complex(A))
+            factors.append([np.exp(-(x - ci) ** 2 / s ** 2) for x, ci in zip(axes, c)])
+        return np.array(coefs), factors
+
+
 def random_mixture(rng, g, d, center_lo, center_hi, width_lo, width_hi, amp_lo=0.5, amp_hi=2.0):
     centers = rng.uniform(center_lo, center_hi, size=(g, d))
     widths = rng.uniform(width_lo, width_hi, size=g)
@@ -121,6 +133,30 @@ class WavePackets:
             kx = sum(Xi * ki for Xi, ki in zip(X, k))
             psi += a * np.exp(1j * th) * np.exp(-r2 / (2 * s * s)) * np.exp(1j * kx)
         return psi.astype(dtype)
+
+
+    def packet_factors(self, n, box):
+        """Per packet: the complex amplitude a e^{i theta} and the per-axis samples
+        exp(-(x_i-c_i)^2/(2 s^2)) exp(i k0_i x_i), whose product over axes times
+        the amplitude is the packet on the grid."""
+        axes = grid_axes(n, box)
+        out = []
+        for a, th, c, s, k in zip(self.amps, self.phases, self.centers, self.widths, self.k0):
+            f = [np.exp(-(x - ci) ** 2 / (2 * s * s)) * np.exp(1j * x * ki) for x, ci, ki in zip(axes, c, k)]
+            out.append((a * np.exp(1j * th), f))
+        return out
+
+    def density_terms(self, n, box):
+        """rho = |psi|^2 as the sum over packet pairs (p, q) of the separable terms
+        amp_p conj(amp_q) prod_i f_{p,i} conj(f_{q,i}).  Returns (coefficients,
+        per-term lists of per-axis samples)."""
+        pf = self.packet_factors(n, box)
+        coefs, factors = [], []
+        for ap, fp in pf:
+            for aq, fq in pf:
+                coefs.append(ap * np.conj(aq))
+                factors.append([a * np.conj(b) for a, b in zip(fp, fq)])
+        return np.array(coefs), factors
 
 
 def random_wave_packets(rng, p=6, lo=-6.0, hi=6.0):
