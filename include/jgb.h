@@ -188,6 +188,24 @@ jgb_status jgb_plan(const jgb_params* params, jgb_plan_t* out);
  * Enqueue only (asynchronous on the plan's stream). */
 jgb_status jgb_potential(jgb_plan_t plan, const void* rho, void* u, double* energy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as jgb_potential, bit for bit, with every per-call buffer (the
+ * oversampled grids, the FFT pass intermediate, the gather's partial tiles,
+ * the weighted node values and the partial sums) taken from one file-scope
+ * device array of JGB_NOALLOC_SCRATCH_BYTES per GPU, held from library load
+ * until the process ends, instead of the plan's workspace.  The call
+ * allocates nothing; the plan (made beforehand by jgb_plan) supplies its node
+ * tables and lists.  Arguments and layout as jgb_potential.
+ * Errors: INVALID_ARG as jgb_potential; UNSUPPORTED when the plan's per-call
+ * buffers exceed the array (for cubic grids about 64^3 in float64, 80^3 in
+ * mixed precision; jgb_info.workspace_bytes is an upper bound); DEVICE.
+ * Every call on one GPU shares that GPU's array and overwrites it: two calls
+ * that overlap in time on one GPU (different streams, threads or plans) race
+ * and give wrong results.  Enqueue only. */
+#define JGB_NOALLOC_SCRATCH_BYTES (128u << 20)
+jgb_status jgb_potential_noalloc(jgb_plan_t plan, const void* rho, void* u, double* energy);
+
 /* E only, via the Fourier-side sum E = (lambda/2) sum_j c_j |rho^_j|^2, which
  * equals the physical-side sum exactly for real rho (substitute eq. 3.2 into
  * the energy).  Runs only the type-2 half of the pipeline.  With

@@ -89,6 +89,9 @@ class GpeParams(ctypes.Structure):
 GPE_ENERGY_NAMES = ["norm", "kinetic", "trap", "local", "nonlocal", "total", "mu"]
 
 
+NOALLOC_SCRATCH_BYTES = 128 << 20   # JGB_NOALLOC_SCRATCH_BYTES
+
+
 class JgbError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
@@ -105,6 +108,7 @@ def _load():
     sig = {
         "jgb_plan": (st, [ctypes.POINTER(Params), ctypes.POINTER(P)]),
         "jgb_potential": (st, [P, P, P, P]),
+        "jgb_potential_noalloc": (st, [P, P, P, P]),
         "jgb_energy": (st, [P, P, P]),
         "jgb_potential_backward": (st, [P, P, P]),
         "jgb_transform": (st, [P, P, P]),

@@ -129,6 +129,18 @@ class Plan:
         check(lib.jgb_potential(self._h, _ptr(rho), _ptr(u), _ptr(E) if energy else None))
         return u, E
 
+    def potential_noalloc(self, rho, out, energy=None):
+        """potential() through jgb_potential_noalloc: the library allocates
+        nothing during the call (its per-call buffers live in a fixed device
+        array shared by every call on the GPU); out (and energy, a 0-d float64
+        tensor, if given) must be allocated by the caller."""
+        self._check_grid(rho, "rho")
+        self._check_grid(out, "out")
+        if energy is not None and (energy.dtype != torch.float64 or energy.device != self.device or energy.numel() != 1):
+            raise ValueError("energy must be a float64 scalar tensor on %s" % self.device)
+        check(lib.jgb_potential_noalloc(self._h, _ptr(rho), _ptr(out), _ptr(energy) if energy is not None else None))
+        return out, energy
+
     def energy(self, rho, out=None):
         self._check_grid(rho, "rho")
         E = torch.empty((), dtype=torch.float64, device=self.device) if out is None else out

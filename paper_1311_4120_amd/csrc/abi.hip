@@ -5,6 +5,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 #include <string>
@@ -138,6 +139,70 @@ jgb_status run_transform(Plan& pl, const void* rho, void* out) {
 
 }  // namespace
 
+// ------------------------------------------------ the allocation-free variant
+//
+// jgb_potential_noalloc runs jgb_potential's pipeline with its per-call
+// buffers (grids, pass intermediate, partial tiles, node values, partial
+// sums) carved from one file-scope device array instead of the plan's own.
+// Each device holds its own copy of the array; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)JGB_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of this device's scratch array, looked up once per
+// device with that device current (the caller has made it current).
+hipError_t scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (unsigned char*)g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// zero n16 16-byte words (a fill kernel rather than a memset node, so that the
+// call stays safe to capture in a graph)
+__global__ void k_zero16(uint4* p, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// the plan's per-call buffers, swapped for views into the scratch array for
+// the duration of one call and restored afterwards
+struct ScratchSwap {
+  Plan& pl;
+  void *F, *G, *W, *partials, *uhat;
+  double *eparts, *mparts, *origin;
+  explicit ScratchSwap(Plan& p)
+      : pl(p), F(p.d_F), G(p.d_G), W(p.d_W), partials(p.d_partials), uhat(p.nodes.uhat), eparts(p.d_eparts),
+        mparts(p.d_mparts), origin(p.d_origin) {}
+  ~ScratchSwap() {
+    pl.d_F = F;
+    pl.d_G = G;
+    pl.d_W = W;
+    pl.d_partials = partials;
+    pl.nodes.uhat = uhat;
+    pl.d_eparts = eparts;
+    pl.d_mparts = mparts;
+    pl.d_origin = origin;
+  }
+};
+
+}  // namespace
+
 jgb_status jgb::potential_pipeline(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st) {
   return pl.fp64 ? run_potential<double>(pl, rho, u, energy, st) : run_potential<float>(pl, rho, u, energy, st);
 }
@@ -188,6 +253,42 @@ jgb_status jgb_potential(jgb_plan_t plan, const void* rho, void* u, double* ener
   if (!rho || !u) return report(JGB_ERR_INVALID_ARG, "rho and u must not be NULL");
   size_t nb = grid_bytes(pl);
   if (overlap(rho, nb, u, nb)) return report(JGB_ERR_INVALID_ARG, "rho and u overlap");
+  return pl.fp64 ? run_potential<double>(pl, rho, u, energy, pl.stream)
+                 : run_potential<float>(pl, rho, u, energy, pl.stream);
+}
+
+jgb_status jgb_potential_noalloc(jgb_plan_t plan, const void* rho, void* u, double* energy) {
+  jgb_status c = check_plan(plan);
+  if (c != JGB_OK) return c;
+  Plan& pl = plan->pl;
+  if (!rho || !u) return report(JGB_ERR_INVALID_ARG, "rho and u must not be NULL");
+  size_t nb = grid_bytes(pl);
+  if (overlap(rho, nb, u, nb)) return report(JGB_ERR_INVALID_ARG, "rho and u overlap");
+  size_t off[Plan::WS_COUNT + 1];
+  off[0] = 0;
+  for (int i = 0; i < Plan::WS_COUNT; ++i) off[i + 1] = off[i] + align256(pl.ws_bytes[i]);
+  if (off[Plan::WS_COUNT] > kScratchBytes)
+    return report(JGB_ERR_UNSUPPORTED, "the plan's per-call workspace (" + std::to_string(off[Plan::WS_COUNT]) +
+                                           " bytes) exceeds the allocation-free scratch (" +
+                                           std::to_string(kScratchBytes) + " bytes)");
+  unsigned char* base = nullptr;
+  hipError_t e = scratch_address(pl.device, &base);
+  if (e != hipSuccess) return from_hip(e, "hipGetSymbolAddress(scratch)");
+  // only the spreading writes G, and only the tiles some node touches: the
+  // others must read zero, whatever an earlier call left in the array
+  const size_t n16 = off[Plan::WS_G + 1] / 16 - off[Plan::WS_G] / 16;
+  hipLaunchKernelGGL(k_zero16, dim3((unsigned)std::min<size_t>((n16 + 255) / 256, 8192)), dim3(256), 0, pl.stream,
+                     (uint4*)(base + off[Plan::WS_G]), n16);
+  if ((e = hipGetLastError()) != hipSuccess) return from_hip(e, "scratch clear");
+  ScratchSwap keep(pl);
+  pl.d_F = base + off[Plan::WS_F];
+  pl.d_G = base + off[Plan::WS_G];
+  pl.d_W = base + off[Plan::WS_W];
+  pl.d_partials = base + off[Plan::WS_PARTIALS];
+  pl.nodes.uhat = base + off[Plan::WS_UHAT];
+  pl.d_eparts = (double*)(base + off[Plan::WS_EPARTS]);
+  pl.d_mparts = pl.ws_bytes[Plan::WS_MPARTS] ? (double*)(base + off[Plan::WS_MPARTS]) : nullptr;
+  pl.d_origin = pl.ws_bytes[Plan::WS_ORIGIN] ? (double*)(base + off[Plan::WS_ORIGIN]) : nullptr;
   return pl.fp64 ? run_potential<double>(pl, rho, u, energy, pl.stream)
                  : run_potential<float>(pl, rho, u, energy, pl.stream);
 }

@@ -188,6 +188,12 @@ struct Plan {
 
   size_t workspace_bytes = 0;
   std::vector<void*> allocations;
+
+  // Bytes of each per-call buffer the compute calls write besides the
+  // caller's outputs, as allocated: F, G, W, the gather's partial tiles, the
+  // weighted node values, and the energy, origin-sum and origin partials.
+  enum { WS_F = 0, WS_G, WS_W, WS_PARTIALS, WS_UHAT, WS_EPARTS, WS_MPARTS, WS_ORIGIN, WS_COUNT };
+  size_t ws_bytes[WS_COUNT] = {};
 };
 
 // ----------------------------------------------------------------- kernel shape

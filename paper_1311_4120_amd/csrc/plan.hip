@@ -653,7 +653,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   TRY(dev_alloc(pl, &pl.nodes.hdr, sizeof(int4) * Mh));
   for (int i = 0; i < 3; ++i) TRY(dev_alloc(pl, &pl.nodes.frac[i], pl.real_bytes * Mh));
   TRY(dev_alloc(pl, &pl.nodes.coef, sizeof(double) * Mh));
-  TRY(dev_alloc(pl, &pl.nodes.uhat, 2 * pl.real_bytes * Mh));
+  pl.ws_bytes[Plan::WS_UHAT] = 2 * pl.real_bytes * Mh;
+  TRY(dev_alloc(pl, &pl.nodes.uhat, pl.ws_bytes[Plan::WS_UHAT]));
   TRY(dev_alloc(pl, &pl.nodes.wts, (size_t)record_stride(pl.width) * pl.real_bytes * Mh));
   TRY_HIP(hipMemsetAsync(pl.nodes.wts, 0, (size_t)record_stride(pl.width) * pl.real_bytes * Mh, pl.stream),
           "clear kernel values");
@@ -748,7 +749,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     }
     TRY(dev_alloc(pl, &pl.d_items, sizeof(WorkItem) * std::max(pl.items_cap, 1)));
     TRY(dev_alloc(pl, &pl.d_multi, sizeof(int) * std::max(pl.multi_cap, 1)));
-    TRY(dev_alloc(pl, &pl.d_partials, (size_t)std::max(pl.slots_cap, 1) * 64 * kGatherZ * 2 * pl.real_bytes));
+    pl.ws_bytes[Plan::WS_PARTIALS] = (size_t)std::max(pl.slots_cap, 1) * 64 * kGatherZ * 2 * pl.real_bytes;
+    TRY(dev_alloc(pl, &pl.d_partials, pl.ws_bytes[Plan::WS_PARTIALS]));
     TRY(apply_spread_chunk(pl, pl.spread_chunk));
   }
 
@@ -782,9 +784,11 @@ Status build_plan(Plan& pl, const jgb_params* p) {
 
   // grids and energy partials
   size_t ngrid = (size_t)pl.nf[0] * pl.nf[1] * pl.nf[2];
-  TRY(dev_alloc(pl, &pl.d_F, ngrid * 2 * pl.real_bytes));
-  TRY(dev_alloc(pl, &pl.d_G, ngrid * 2 * pl.real_bytes));
-  TRY(dev_alloc(pl, &pl.d_W, (size_t)pl.n[0] * pl.nf[1] * pl.nf[2] * 2 * pl.real_bytes));
+  pl.ws_bytes[Plan::WS_F] = pl.ws_bytes[Plan::WS_G] = ngrid * 2 * pl.real_bytes;
+  pl.ws_bytes[Plan::WS_W] = (size_t)pl.n[0] * pl.nf[1] * pl.nf[2] * 2 * pl.real_bytes;
+  TRY(dev_alloc(pl, &pl.d_F, pl.ws_bytes[Plan::WS_F]));
+  TRY(dev_alloc(pl, &pl.d_G, pl.ws_bytes[Plan::WS_G]));
+  TRY(dev_alloc(pl, &pl.d_W, pl.ws_bytes[Plan::WS_W]));
   // only the spreading writes G, and only tiles some node touches: the others
   // are cleared here once
   TRY_HIP(hipMemsetAsync(pl.d_G, 0, ngrid * 2 * pl.real_bytes, pl.stream), "clear spreading grid");
@@ -831,12 +835,15 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     pl.nsym_blocks = (int)std::min<int64_t>((npts + 255) / 256, 4096);
   }
   if (pl.c0 != 0.0) {
-    TRY(dev_alloc(pl, &pl.d_mparts, sizeof(double) * std::max(fft_inverse_z_blocks(pl), 1)));
-    TRY(dev_alloc(pl, &pl.d_origin, sizeof(double) * 2));
+    pl.ws_bytes[Plan::WS_MPARTS] = sizeof(double) * std::max(fft_inverse_z_blocks(pl), 1);
+    pl.ws_bytes[Plan::WS_ORIGIN] = sizeof(double) * 2;
+    TRY(dev_alloc(pl, &pl.d_mparts, pl.ws_bytes[Plan::WS_MPARTS]));
+    TRY(dev_alloc(pl, &pl.d_origin, pl.ws_bytes[Plan::WS_ORIGIN]));
   }
   pl.neparts = std::max(fft_inverse_z_blocks(pl), pl.iitems_cap + pl.nsym_blocks);
   pl.neparts = std::max(pl.neparts, 1);
-  TRY(dev_alloc(pl, &pl.d_eparts, sizeof(double) * pl.neparts));
+  pl.ws_bytes[Plan::WS_EPARTS] = sizeof(double) * pl.neparts;
+  TRY(dev_alloc(pl, &pl.d_eparts, pl.ws_bytes[Plan::WS_EPARTS]));
   TRY_HIP(interp_prepare(pl), "interpolation LDS limit");
   if (p->flags & JGB_FLAG_AUTOTUNE) TRY(autotune(pl));
   TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");

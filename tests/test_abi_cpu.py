@@ -150,6 +150,7 @@ def test_null_arguments():
     p = _params()
     assert L.lib.jgb_plan(ctypes.byref(p), None) == L.JGB_ERR_INVALID_ARG
     assert L.lib.jgb_potential(None, None, None, None) == L.JGB_ERR_INVALID_ARG
+    assert L.lib.jgb_potential_noalloc(None, None, None, None) == L.JGB_ERR_INVALID_ARG
     assert L.lib.jgb_energy(None, None, None) == L.JGB_ERR_INVALID_ARG
     assert L.lib.jgb_potential_backward(None, None, None) == L.JGB_ERR_INVALID_ARG
     assert L.lib.jgb_transform(None, None, None) == L.JGB_ERR_INVALID_ARG
@@ -260,3 +261,9 @@ def test_gpe_invalid_potential_is_reported():
     h = ctypes.c_void_p()
     assert L.lib.jgb_gpe_create(ctypes.byref(g), ctypes.byref(h)) == L.JGB_ERR_INVALID_ARG
     assert b"potential plan" in L.lib.jgb_last_error()
+
+
+def test_noalloc_scratch_size_matches_header():
+    L = _lib()
+    m = re.search(r"#define JGB_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == L.NOALLOC_SCRATCH_BYTES
