@@ -184,12 +184,13 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // the duration of one call and restored afterwards
 struct ScratchSwap {
   Plan& pl;
-  void *F, *G, *W, *partials, *uhat;
+  void *F, *G, *W, *partials, *uhat, *ipart;
   double *eparts, *mparts, *origin;
   explicit ScratchSwap(Plan& p)
-      : pl(p), F(p.d_F), G(p.d_G), W(p.d_W), partials(p.d_partials), uhat(p.nodes.uhat), eparts(p.d_eparts),
-        mparts(p.d_mparts), origin(p.d_origin) {}
+      : pl(p), F(p.d_F), G(p.d_G), W(p.d_W), partials(p.d_partials), uhat(p.nodes.uhat), ipart(p.d_ipart),
+        eparts(p.d_eparts), mparts(p.d_mparts), origin(p.d_origin) {}
   ~ScratchSwap() {
+    pl.d_ipart = ipart;
     pl.d_F = F;
     pl.d_G = G;
     pl.d_W = W;
@@ -289,6 +290,7 @@ jgb_status jgb_potential_noalloc(jgb_plan_t plan, const void* rho, void* u, doub
   pl.d_eparts = (double*)(base + off[Plan::WS_EPARTS]);
   pl.d_mparts = pl.ws_bytes[Plan::WS_MPARTS] ? (double*)(base + off[Plan::WS_MPARTS]) : nullptr;
   pl.d_origin = pl.ws_bytes[Plan::WS_ORIGIN] ? (double*)(base + off[Plan::WS_ORIGIN]) : nullptr;
+  pl.d_ipart = pl.ws_bytes[Plan::WS_IPART] ? base + off[Plan::WS_IPART] : nullptr;
   return pl.fp64 ? run_potential<double>(pl, rho, u, energy, pl.stream)
                  : run_potential<float>(pl, rho, u, energy, pl.stream);
 }

@@ -29,12 +29,14 @@ constexpr int kGatherZ = 8;
 // Offset added to the signed tile-relative footprint starts of the gather lists
 // (when the plan's grid needs no wrap-around, Plan::gather_nowrap).
 constexpr int kGatherBias = 512;
-// Per-node kernel values, tabulated at plan time: w values per internal axis,
-// axis a at [a w, a w + w) of the node's record (a unit axis has the single
-// value 1 at tap 0 and zeros after it), then a zero at 3 w that a load may
-// point at instead of masking its result; records are rec_stride values apart,
-// 3 w + 1 rounded up to a multiple of 4.
-inline int record_stride(int width) { return (3 * width + 1 + 3) / 4 * 4; }
+// Per-node kernel values, tabulated at plan time: for each internal axis a,
+// the w values of its taps at [a (w + 1), a (w + 1) + w) of the node's record
+// followed by a zero (a unit axis has the single value 1 at tap 0 and zeros
+// after it), so that tap d of axis a is read at a (w + 1) + min(d, w) for any
+// d taken as unsigned -- a tap off the footprint on either side reads the
+// zero, with no mask.  Records are record_stride values apart, 3 (w + 1)
+// rounded up to a multiple of 4.
+inline int record_stride(int width) { return (3 * (width + 1) + 3) / 4 * 4; }
 
 // ----------------------------------------------------------------- errors
 
@@ -152,6 +154,18 @@ struct Plan {
   int nmulti = 0;
   void* d_partials = nullptr;  // nslots tiles of complex T
 
+  // Interpolation by tiles (3D): the gather's tiles, lists and work items
+  // drive a matrix-core contraction of each tile's grid values with the
+  // kernel values of 16 listed nodes at a time; every list entry yields the
+  // node's partial sum over that tile (d_ipart, in list order), and a second
+  // kernel sums each node's partials in a fixed order through the node-major
+  // index d_nstart / d_npos (node j's entries are d_npos[d_nstart[j] ..
+  // d_nstart[j + 1])).
+  bool tile_interp = false;
+  int* d_nstart = nullptr;     // Mh + 1 offsets into d_npos
+  int* d_npos = nullptr;       // nlist list positions, node-major
+  void* d_ipart = nullptr;     // nlist complex T: per list entry, the tile's share of the node's value
+
   // FFT tables
   void* d_tw[3] = {nullptr, nullptr, nullptr};      // exp(-2 pi i t / nf) for t < nf, complex T
   double* d_deconv[3] = {nullptr, nullptr, nullptr};// 1 / phi^(m) for m in [-n/2, n/2)
@@ -192,7 +206,7 @@ struct Plan {
   // Bytes of each per-call buffer the compute calls write besides the
   // caller's outputs, as allocated: F, G, W, the gather's partial tiles, the
   // weighted node values, and the energy, origin-sum and origin partials.
-  enum { WS_F = 0, WS_G, WS_W, WS_PARTIALS, WS_UHAT, WS_EPARTS, WS_MPARTS, WS_ORIGIN, WS_COUNT };
+  enum { WS_F = 0, WS_G, WS_W, WS_PARTIALS, WS_UHAT, WS_EPARTS, WS_MPARTS, WS_ORIGIN, WS_IPART, WS_COUNT };
   size_t ws_bytes[WS_COUNT] = {};
 };
 

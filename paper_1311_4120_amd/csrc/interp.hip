@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   // pair's taps are read from LDS
   const int ax = lane >> 4, tap = lane & 15;
   const bool wlane = ax < 3 && tap < W;
-  const int woff = wlane ? ax * W + tap : 0;  // inside the node's record for every lane
+  const int woff = wlane ? ax * (W + 1) + tap : 0;  // inside the node's record for every lane
   auto fetch_w = [&](int jj) { return a.wts[(int64_t)jj * a.rstride + woff]; };
   // a per-lane (vector) load of a value every lane needs, so that it is
   // counted with the other global loads and not with the LDS traffic
@@ -281,6 +281,228 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   }
 }
 
+// ------------------------------------------------------------------ by tiles
+//
+// The interpolation as the transpose of the gather's tile product.  For an
+// output tile of the gather (8 x 8 x 8 points) and 16 nodes of its list,
+//
+//   D[(z, part), i] = sum_m B[(z, part), m] P[m, i],
+//   B[(z, part), m] = part(F[x_m, y_m, z]),   P[m, i] = phi_0(x_m - s_i) phi_1(y_m - s_i),
+//
+// over the 64 points m of the tile's two outer axes: sixteen 16x16x4
+// matrix-core products, with B (the tile's grid values) loaded once per work
+// item and held in registers while the list streams through.  Column i of D
+// weighted by phi_2(z - s_i) and summed over z and the two parts is the tile's
+// share of node i's transform, stored per list entry; k_interp_reduce adds
+// each node's shares in a fixed order.  Lane 16k + j supplies A[j][k] and
+// B[k][j], so lane j + 16k holds node j's kernel values; the result register
+// r of lane l holds D[row(l, r)][l mod 16], column l mod 16 being the lane's
+// own node, so the weighting by phi_2 needs no exchange between lanes.
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct TileMfma;
+template <>
+struct TileMfma<double> {
+  typedef d4v acc_t;
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * r + (l >> 4); }
+};
+template <>
+struct TileMfma<float> {
+  typedef f4v acc_t;
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+template <typename T>
+struct TileArgs {
+  int nf0, nf1, nf2;
+  int w0, w1, w2;
+  int nt1, nt2;
+  int width, rstride;
+  int lstride;        // values between the LDS copies of two records (>= rstride; see the launcher)
+  const int2* list;
+  const WorkItem* items;
+  const T* F;         // oversampled grid, interleaved (re, im)
+  const T* wts;
+  C2<T>* ipart;
+};
+
+template <typename V>
+__device__ __forceinline__ V tload(const void* base, uint32_t byte_off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+constexpr int kTileWaves = 4;
+
+template <typename T, bool NOWRAP>
+__global__ void __launch_bounds__(256) k_interp_tile(TileArgs<T> a) {
+  typedef typename TileMfma<T>::acc_t acc_t;
+  extern __shared__ unsigned char smem_raw[];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // the wave's copies of its group's 16 node records
+  T* recs = reinterpret_cast<T*>(smem_raw) + (size_t)wave * 16 * a.lstride;
+  const WorkItem item = a.items[blockIdx.x];
+  if (item.tile < 0) return;  // idle slot of the dispatch order
+  const int tile = item.tile;
+  const int t2 = tile % a.nt2;
+  const int t1 = (tile / a.nt2) % a.nt1;
+  const int t0 = tile / (a.nt2 * a.nt1);
+  const int o0 = t0 * 8, o1 = t1 * 8, o2 = t2 * 8;
+  const int j16 = lane & 15, k4 = lane >> 4;
+
+  // B: the tile's grid values, product t covering points m = 4t .. 4t + 3
+  // (x = t / 2, y = 4 (t mod 2) + k) and rows j = (z, part) = (j mod 8, j / 8);
+  // points off the grid read zero
+  T B[16];
+  {
+    const int z = j16 & 7, part = j16 >> 3;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int gx = o0 + (t >> 1), gy = o1 + ((t & 1) << 2) + k4, gz = o2 + z;
+      const bool in = gx < a.nf0 && gy < a.nf1 && gz < a.nf2;
+      B[t] = in ? a.F[2 * (((int64_t)gx * a.nf1 + gy) * a.nf2 + gz) + part] : T(0);
+    }
+  }
+  // the tile z and part of the lane's result registers
+  int zr[4], pr[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = TileMfma<T>::row(lane, r);
+    zr[r] = row & 7;
+    pr[r] = row >> 3;
+  }
+
+  constexpr int bias = NOWRAP ? kGatherBias : 0;
+  constexpr int kChunk = 16 / sizeof(T);  // values per 16-byte copy
+  const int W = a.width;
+  const int nchunk = a.rstride / kChunk;  // 16-byte pieces of a record
+  const uint32_t rbytes = (uint32_t)(a.rstride * sizeof(T));
+  const T* myrec = recs + j16 * a.lstride;
+  const int vb = item.vbegin, ve = item.vend;
+  for (int g0 = vb + 16 * wave; g0 < ve; g0 += 16 * kTileWaves) {
+    const int idx = g0 + j16;
+    const bool valid = idx < ve;
+    const int2 ent = tload<int2>(a.list, (uint32_t)(valid ? idx : ve - 1) * 8u);
+    const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
+    // copy node j16's record into the wave's LDS: the four lanes of the node
+    // take every fourth 16-byte piece (coalesced runs instead of one scattered
+    // load per kernel value)
+    {
+      const uint32_t rec = (uint32_t)ent.x * rbytes;
+      __builtin_amdgcn_wave_barrier();  // the previous group's reads are done
+      for (int c = k4; c < nchunk; c += 4) {
+        const uint4 v = tload<uint4>(a.wts, rec + (uint32_t)c * 16u);
+        *reinterpret_cast<uint4*>(recs + j16 * a.lstride + c * kChunk) = v;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    // node j16's kernel values at the tile's 8 x, the lane's 2 y and the z of
+    // its result registers; taps outside the footprint read the zero after
+    // their axis's values (a lane past the end of the list computes from a
+    // copy of the last entry and stores nothing)
+    auto tap = [&](int d, int axis_nf, int axis) {
+      if (!NOWRAP && d < 0) d += axis_nf;
+      return myrec[axis * (W + 1) + (int)min((uint32_t)d, (uint32_t)W)];
+    };
+    T px[8], py[2], pz[4];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) px[x] = tap(x + bias - ex, a.nf0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) py[h] = tap(k4 + 4 * h + bias - ey, a.nf1, 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pz[r] = tap(zr[r] + bias - ez, a.nf2, 2);
+    acc_t acc = acc_t{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc = TileMfma<T>::mma(B[t], px[t >> 1] * py[t & 1], acc);
+    T re = T(0), im = T(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (pr[r] == 0)
+        re += acc[r] * pz[r];
+      else
+        im += acc[r] * pz[r];
+    }
+    // the other three lane rows hold the node's other z
+    re += __shfl_xor(re, 16, 64);
+    im += __shfl_xor(im, 16, 64);
+    re += __shfl_xor(re, 32, 64);
+    im += __shfl_xor(im, 32, 64);
+    if (k4 == 0 && valid) a.ipart[idx] = C2<T>{re, im};
+  }
+}
+
+template <typename T>
+struct ReduceArgs {
+  int Mh;
+  const int* nstart;
+  const int* npos;
+  const C2<T>* ipart;
+  const double* coef;
+  const int* perm;
+  int mode;
+  C2<T>* uhat;
+  C2<T>* out;
+  double* eparts;
+};
+
+// Sum each node's tile shares in the order of its list entries (fixed), then
+// the epilogue of the interpolation: c_j rho^_j, or the transform itself, and
+// the Fourier-side energy partials.
+// LPN lanes per node: lane i of a node's LPN loads its entries i, i + LPN,
+// ... (all of them in flight at once), then a fixed-order tree sum over the
+// LPN lanes (LPN = 1, 4 or 8).
+template <typename T, int LPN>
+__global__ void __launch_bounds__(256) k_interp_reduce(ReduceArgs<T> a) {
+  __shared__ double ws[4];
+  const int j = blockIdx.x * (256 / LPN) + (int)(threadIdx.x / LPN);
+  const int li = threadIdx.x % LPN;
+  double sr = 0.0, si = 0.0;
+  if (j < a.Mh) {
+    const int b = a.nstart[j], e = a.nstart[j + 1];
+    for (int q = b + li; q < e; q += LPN) {
+      const C2<T> v = a.ipart[a.npos[q]];
+      sr += (double)v.x;
+      si += (double)v.y;
+    }
+  }
+  if (LPN >= 4) {
+    sr += dpp<0xB1, 0xf>(sr);   // quad_perm [1,0,3,2]
+    si += dpp<0xB1, 0xf>(si);
+    sr += dpp<0x4E, 0xf>(sr);   // quad_perm [2,3,0,1]
+    si += dpp<0x4E, 0xf>(si);
+  }
+  if (LPN == 8) {
+    sr += dpp<0x141, 0xf>(sr);  // row_half_mirror: the other quad of the 8
+    si += dpp<0x141, 0xf>(si);
+  }
+  double eacc = 0.0;
+  if (j < a.Mh && li == 0) {
+    if (a.mode == INTERP_TRANSFORM) {
+      a.out[a.perm[j]] = C2<T>{(T)sr, (T)si};
+    } else {
+      const double c = a.coef[j];
+      const double re = (double)(T)sr, im = (double)(T)si;
+      if (a.mode == INTERP_ENERGY) eacc = c * (re * re + im * im);
+      if (a.mode == INTERP_POTENTIAL) a.uhat[j] = C2<T>{(T)(c * re), (T)(c * im)};
+    }
+  }
+  if (a.mode != INTERP_ENERGY || !a.eparts) return;
+  // block sum: shuffles within waves, then the four waves through LDS
+  for (int off = 32; off >= 1; off >>= 1) eacc += __shfl_down(eacc, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = eacc;
+  __syncthreads();
+  if (threadIdx.x == 0) a.eparts[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
 template <typename T, int W>
 hipError_t launch_w(const InterpArgs<T>& a, bool d3, unsigned blocks, size_t smem, hipStream_t s) {
   if (d3)
@@ -301,7 +523,93 @@ hipError_t allow_lds(size_t smem) {
 
 }  // namespace
 
-int interp_blocks(const Plan& pl) { return pl.niitems; }
+// Values between the LDS copies of two node records in k_interp_tile: the
+// record length rounded so that copies stay 16-byte aligned, plus whole
+// 16-byte steps until the 16 copies of a wave start in 16 distinct pairs of
+// 4-byte banks (the lanes of one read touch one value of each copy).
+template <typename T>
+int tile_lds_stride(int rstride) {
+  const int step = 16 / (int)sizeof(T);
+  for (int s = rstride; s < rstride + 16 * step; s += step) {
+    bool ok = true;
+    for (int i = 0; i < 16 && ok; ++i)
+      for (int k = 0; k < i && ok; ++k) {
+        const int bi = (i * s * (int)sizeof(T) / 4) % 64, bk = (k * s * (int)sizeof(T) / 4) % 64;
+        const int span = (int)sizeof(T) / 4;
+        ok = !(bi < bk + span && bk < bi + span);
+      }
+    if (ok) return s;
+  }
+  return rstride;
+}
+
+// lanes per node of the reduction: about the mean number of list entries
+// per node, a power of two up to 8
+int reduce_lanes(const Plan& pl) {
+  const double mean = pl.Mh > 0 ? (double)pl.nlist / (double)pl.Mh : 0.0;
+  return mean >= 10.0 ? 8 : (mean >= 4.0 ? 4 : 1);
+}
+
+int interp_blocks(const Plan& pl) {
+  if (!pl.tile_interp) return pl.niitems;
+  const int64_t per = 256 / reduce_lanes(pl);
+  return (int)((pl.Mh + per - 1) / per);
+}
+
+template <typename T>
+hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipStream_t s) {
+  TileArgs<T> a{};
+  a.nf0 = pl.nf[0];
+  a.nf1 = pl.nf[1];
+  a.nf2 = pl.nf[2];
+  a.w0 = pl.w[0];
+  a.w1 = pl.w[1];
+  a.w2 = pl.w[2];
+  a.nt1 = pl.gnt[1];
+  a.nt2 = pl.gnt[2];
+  a.width = pl.width;
+  a.rstride = record_stride(pl.width);
+  a.lstride = tile_lds_stride<T>(a.rstride);
+  a.list = pl.d_list;
+  a.items = pl.d_items;
+  // Algorithm 2: the type-2 spectrum was separated into G's touched tiles
+  a.F = (const T*)(pl.split ? pl.d_G : pl.d_F);
+  a.wts = (const T*)pl.nodes.wts;
+  a.ipart = (C2<T>*)pl.d_ipart;
+  stage_mark(pl, ST_INTERP, 0, s);
+  if (pl.nitems > 0) {
+    const size_t smem = (size_t)kTileWaves * 16 * a.lstride * sizeof(T);
+    if (pl.gather_nowrap)
+      hipLaunchKernelGGL((k_interp_tile<T, true>), dim3((unsigned)pl.nitems), dim3(256), smem, s, a);
+    else
+      hipLaunchKernelGGL((k_interp_tile<T, false>), dim3((unsigned)pl.nitems), dim3(256), smem, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  ReduceArgs<T> r{};
+  r.Mh = (int)pl.Mh;
+  r.nstart = pl.d_nstart;
+  r.npos = pl.d_npos;
+  r.ipart = (const C2<T>*)pl.d_ipart;
+  r.coef = pl.nodes.coef;
+  r.perm = pl.nodes.perm;
+  r.mode = mode;
+  r.uhat = (C2<T>*)pl.nodes.uhat;
+  r.out = (C2<T>*)out;
+  r.eparts = pl.d_eparts;
+  const unsigned rb = (unsigned)interp_blocks(pl);
+  if (rb > 0) {
+    const int lpn = reduce_lanes(pl);
+    if (lpn == 8)
+      hipLaunchKernelGGL((k_interp_reduce<T, 8>), dim3(rb), dim3(256), 0, s, r);
+    else if (lpn == 4)
+      hipLaunchKernelGGL((k_interp_reduce<T, 4>), dim3(rb), dim3(256), 0, s, r);
+    else
+      hipLaunchKernelGGL((k_interp_reduce<T, 1>), dim3(rb), dim3(256), 0, s, r);
+  }
+  stage_mark(pl, ST_INTERP, 1, s);
+  return hipGetLastError();
+}
 
 // Let the plan's interpolation kernel use its staged-region size of LDS
 // (called once at plan time, outside any stream capture).
@@ -320,6 +628,7 @@ hipError_t interp_prepare(const Plan& pl) {
 
 template <typename T>
 hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t s) {
+  if (pl.tile_interp) return launch_interp_tiles<T>(pl, mode, out, s);
   InterpArgs<T> a{};
   a.nf0 = pl.nf[0];
   a.nf1 = pl.nf[1];

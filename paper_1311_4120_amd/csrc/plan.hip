@@ -708,10 +708,19 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     return e + kGatherBias;
   };
   std::vector<int2> list(nlist + 1, make_int2(0, 0));  // one spare entry
+  // node-major index of the list for the tile interpolation: node j's entries
+  // are generated together below, in the order of its tiles
+  pl.tile_interp = pl.dim == 3 && pl.GT[0] == 8 && pl.GT[1] == 8 && pl.GT[2] == 8;
+  std::vector<int> nstart, npos;
+  if (pl.tile_interp) {
+    nstart.assign(Mh + 1, 0);
+    npos.reserve(nlist);
+  }
   {
     std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
     int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
     for (int64_t j = 0; j < Mh; ++j) {
+      if (pl.tile_interp) nstart[j] = (int)npos.size();
       int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
       for (int a0 = 0; a0 < nx; ++a0)
         for (int a1 = 0; a1 < ny; ++a1)
@@ -722,9 +731,19 @@ Status build_plan(Plan& pl, const jgb_params* p) {
             const int ez = start_code(2, hdr[j].z - tz[a2] * pl.GT[2]);
             if (ex < 0 || ex > 1023 || ey < 0 || ey > 1023 || ez < 0 || ez > 1023)
               return fail(JGB_ERR_UNSUPPORTED, "gather list start out of range");
+            if (pl.tile_interp) npos.push_back((int)fill[tile]);
             list[fill[tile]++] = make_int2((int)j, ex | (ey << 10) | (ez << 20));
           }
     }
+    if (pl.tile_interp) nstart[Mh] = (int)npos.size();
+  }
+  if (pl.tile_interp) {
+    TRY(dev_alloc(pl, &pl.d_nstart, sizeof(int) * (Mh + 1)));
+    TRY(upload(pl, pl.d_nstart, nstart.data(), sizeof(int) * (Mh + 1)));
+    TRY(dev_alloc(pl, &pl.d_npos, sizeof(int) * std::max<int64_t>(nlist, 1)));
+    if (nlist) TRY(upload(pl, pl.d_npos, npos.data(), sizeof(int) * nlist));
+    pl.ws_bytes[Plan::WS_IPART] = (size_t)std::max<int64_t>(nlist, 1) * 2 * pl.real_bytes;
+    TRY(dev_alloc(pl, &pl.d_ipart, pl.ws_bytes[Plan::WS_IPART]));
   }
   TRY(dev_alloc(pl, &pl.d_list, sizeof(int2) * list.size()));
   TRY(upload(pl, pl.d_list, list.data(), sizeof(int2) * list.size()));
@@ -840,7 +859,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     TRY(dev_alloc(pl, &pl.d_mparts, pl.ws_bytes[Plan::WS_MPARTS]));
     TRY(dev_alloc(pl, &pl.d_origin, pl.ws_bytes[Plan::WS_ORIGIN]));
   }
-  pl.neparts = std::max(fft_inverse_z_blocks(pl), pl.iitems_cap + pl.nsym_blocks);
+  pl.neparts = std::max(fft_inverse_z_blocks(pl), std::max(pl.iitems_cap, interp_blocks(pl)) + pl.nsym_blocks);
   pl.neparts = std::max(pl.neparts, 1);
   pl.ws_bytes[Plan::WS_EPARTS] = sizeof(double) * pl.neparts;
   TRY(dev_alloc(pl, &pl.d_eparts, pl.ws_bytes[Plan::WS_EPARTS]));

@@ -14,6 +14,8 @@
 // Tiles whose candidate list is longer than the chunk cap (the bins near
 // k = 0, where every radial shell crowds into a few cells) are split into
 // work items that write partial tiles; a second kernel sums them in order.
+#include <algorithm>
+
 #include "common.h"
 
 namespace jgb {
@@ -31,6 +33,7 @@ struct SpreadArgs {
   int w0, w1, w2;
   int nt1, nt2;
   int width, rstride;  // taps per axis in a node record, values per record
+  int lstride;         // values between the LDS copies of two records
   const int2* list;
   const WorkItem* items;
   int nitems;
@@ -91,19 +94,6 @@ __device__ __forceinline__ float row_shr8(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));
 }
 
-// Operands of one group of four list entries, loaded one (fp64) or two (fp32)
-// groups ahead of their use so that the loads overlap earlier products.  NX
-// and NY are the distinct axis-0 and axis-1 kernel values a lane needs over its
-// four row blocks (the tile shape makes one of them 1).  A tap outside the
-// footprint, or a lane past the end of the list, reads the zero that ends its
-// node's record, so nothing is masked after the loads.
-template <typename T, int NX, int NY>
-struct GroupLoads {
-  T z;             // axis-2 value at the lane's tile z
-  T u;             // the real or imaginary part of the weighted node value
-  T px[NX], py[NY];
-};
-
 // One block per work item (a tile and a range of its node list).  The tile is
 // T0 x T1 x kGatherZ points; for four listed nodes its update is
 //
@@ -113,20 +103,38 @@ struct GroupLoads {
 // with m the 64 points of the two outer axes in four row blocks of 16 and the
 // 16 columns the kGatherZ = 8 points of axis 2 times (real, imaginary): one
 // 16x16x4 product per row block, four per group.  Lane 16k + i supplies
-// P[16b + i, k] and Q[k, i].  A node's footprint covers 12 of an 8-deep tile's
+// P[16b + i, k] and Q[k, i].  NX and NY are the distinct axis-0 and axis-1
+// kernel values a lane needs over its four row blocks (the tile shape makes
+// one of them 1); a tap outside the footprint, or a lane past the end of the
+// list, reads the zero that ends its node's record, so nothing is masked
+// afterwards.  A node's footprint covers 12 of an 8-deep tile's
 // z more often than of a 16-deep one, so less of the matrix-core work is spent
 // outside footprints.  The wavefronts split the list; their partial tiles are
 // summed in LDS in a fixed order and written once.  T1 is the tile extent on
 // axis 1 (8 for 3D, 64 for the 1 x 64 tiles of 2D problems).
 // NOWRAP: the list's starts are signed, plus kGatherBias, and a tap offset
 // is the point minus the start (no reduction modulo nf).
+//
+// The node data reach the lanes through LDS: for 16 list entries at a time a
+// wave copies the 16 node records whole (four lanes per record, 16-byte
+// pieces), their weighted values and the entries, and the four groups of four
+// then read their kernel values from there.  Scattered 4- or 8-byte loads of
+// single kernel values would cost the address unit one cache line per lane
+// group and instruction, which is what bounds a gather over tabulated values.
+template <typename T>
+struct GatherLds {
+  static __host__ __device__ int wave_values(int lstride) {  // T values per wave, 16-byte multiple
+    return 16 * lstride + 32 + 32 * (int)(sizeof(int2) / sizeof(T));
+  }
+};
+
 template <typename T, int T1, bool NOWRAP>
 __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int T0 = 64 / T1;
   constexpr int NX = (T1 == 8) ? 4 : 1;   // distinct x over the row blocks
   constexpr int NY = (T1 == 8) ? 1 : 4;   // distinct y over the row blocks
-  __shared__ T red[2][4 * 4 * 64];
+  extern __shared__ unsigned char smem_raw[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const WorkItem item = a.items[blockIdx.x];
@@ -138,10 +146,12 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int o0 = t0 * T0, o1 = t1 * T1, o2 = t2 * kGatherZ;
   const int li = lane & 15, lk = lane >> 4;
   const int zl = li & (kGatherZ - 1);            // tile z of the lane's column
-  const uint32_t upart = li >= kGatherZ ? (uint32_t)sizeof(T) : 0u;  // imaginary part
+  const int upart = li >= kGatherZ ? 1 : 0;      // imaginary part
   const int W = a.width;
-  const uint32_t rbytes = (uint32_t)(a.rstride * sizeof(T));   // bytes per record
-  const uint32_t zslot = (uint32_t)(3 * W * sizeof(T));         // byte offset of the zero
+  // the wave's staging area: 16 records, 16 weighted values, 16 entries
+  T* recs = reinterpret_cast<T*>(smem_raw) + (size_t)wave * GatherLds<T>::wave_values(a.lstride);
+  T* uh = recs + 16 * a.lstride;
+  int2* ents = reinterpret_cast<int2*>(uh + 32);
 
   // the lane's x values (per row block when NX = 4) and y values (per row
   // block when NY = 4); points off the grid never take a value
@@ -172,98 +182,87 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   const int kb = wave < nw ? item.vbegin + wave * q : item.vend;
   const int ke = (kb + q < item.vend) ? kb + q : item.vend;
 
-  // Issue the loads of the group whose entries start at g.  Lanes past the end
-  // read entry ke - 1 (>= kb, a valid index whenever the wave has work) and
-  // point every value load at the record's zero.
-  auto fetch = [&](int g) {
-    GroupLoads<T, NX, NY> r;
-    const int idx = g + lk;
-    const bool valid = idx < ke;
-    const int2 ent = load_at<int2>(a.list, (uint32_t)(valid ? idx : ke - 1) * 8u);
-    const uint32_t j = (uint32_t)ent.x;
-    const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
-    const uint32_t rec = j * rbytes;
-    r.u = load_at<T>(a.uhat, j * (uint32_t)sizeof(C2<T>) + upart);
-    // tap d = (p - start) mod nf of a point p covers it iff d < w (w <= nf);
-    // with signed starts d = p - start, and a negative d fails the unsigned test
-    int dz = zb - ez;
-    if (!NOWRAP && dz < 0) dz += a.nf2;
-    const bool inz = valid && (uint32_t)dz < (uint32_t)a.w2;
-    r.z = load_at<T>(a.wts, rec + (inz ? (uint32_t)((2 * W + dz) * sizeof(T)) : zslot));
-#pragma unroll
-    for (int b = 0; b < NX; ++b) {
-      int dx = xs[b] - ex;
-      if (!NOWRAP && dx < 0) dx += a.nf0;
-      const bool in = valid && (uint32_t)dx < (uint32_t)a.w0;
-      r.px[b] = load_at<T>(a.wts, rec + (in ? (uint32_t)(dx * sizeof(T)) : zslot));
-    }
-#pragma unroll
-    for (int b = 0; b < NY; ++b) {
-      int dy = ys[b] - ey;
-      if (!NOWRAP && dy < 0) dy += a.nf1;
-      const bool in = valid && (uint32_t)dy < (uint32_t)a.w1;
-      r.py[b] = load_at<T>(a.wts, rec + (in ? (uint32_t)((W + dy) * sizeof(T)) : zslot));
-    }
-    return r;
-  };
-
-  auto mma_group = [&](const GroupLoads<T, NX, NY>& c) {
-    const T qv = c.z * c.u;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const T pv = c.px[NX == 4 ? b : 0] * c.py[NY == 4 ? b : 0];
-      acc[b] = Mfma<T>::mma(pv, qv, acc[b]);
-    }
-  };
-  if (kb < ke) {
-    auto clampg = [&](int g) { return g < ke ? g : kb + ((ke - 1 - kb) & ~3); };
-    GroupLoads<T, NX, NY> cur = fetch(kb);
-    if constexpr (sizeof(T) == 4) {
-      GroupLoads<T, NX, NY> nx1 = fetch(clampg(kb + 4));
-      for (int g = kb; g < ke; g += 4) {
-        const GroupLoads<T, NX, NY> nx2 = fetch(clampg(g + 8));
-        mma_group(cur);
-        cur = nx1;
-        nx1 = nx2;
+  constexpr int kChunk = 16 / sizeof(T);
+  const int nchunk = a.rstride / kChunk;
+  const uint32_t rbytes = (uint32_t)(a.rstride * sizeof(T));
+  for (int g = kb; g < ke; g += 16) {
+    // stage entries g .. g + 15 (lanes past the end copy entry ke - 1, whose
+    // kernel values the groups below then never use)
+    {
+      const int e16 = g + li;
+      const int2 ent = load_at<int2>(a.list, (uint32_t)(e16 < ke ? e16 : ke - 1) * 8u);
+      const uint32_t rec = (uint32_t)ent.x * rbytes;
+      __builtin_amdgcn_wave_barrier();  // the previous batch's reads are done
+      for (int c = lk; c < nchunk; c += 4)
+        *reinterpret_cast<uint4*>(recs + li * a.lstride + c * kChunk) = load_at<uint4>(a.wts, rec + (uint32_t)c * 16u);
+      if (lk == 0) {
+        // an entry past the end contributes nothing: its weighted value is zero
+        const C2<T> u = load_at<C2<T>>(a.uhat, (uint32_t)ent.x * (uint32_t)sizeof(C2<T>));
+        *reinterpret_cast<C2<T>*>(uh + 2 * li) = e16 < ke ? u : C2<T>{T(0), T(0)};
+        ents[li] = ent;
       }
-    } else {
-      for (int g = kb; g < ke; g += 4) {
-        const GroupLoads<T, NX, NY> nx1 = fetch(clampg(g + 4));
-        mma_group(cur);
-        cur = nx1;
-      }
+      __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int gq = 0; gq < 4; ++gq) {
+      const int e = 4 * gq + lk;
+      const int2 ent = ents[e];
+      const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
+      const T* rr = recs + e * a.lstride;
+      // tap d = (p - start) mod nf of a point p covers it iff d < w (w <= nf);
+      // with signed starts d = p - start, and a negative d is a large unsigned
+      // value: min(d, W) points every tap off the footprint at the zero after
+      // its axis's values (points off the grid have d < 0)
+      auto tap = [&](int d, int axis_nf, int axis) {
+        if (!NOWRAP && d < 0) d += axis_nf;
+        return rr[axis * (W + 1) + (int)min((uint32_t)d, (uint32_t)W)];
+      };
+      const T qv = tap(zb - ez, a.nf2, 2) * uh[2 * e + upart];
+      T px[NX], py[NY];
+#pragma unroll
+      for (int b = 0; b < NX; ++b) px[b] = tap(xs[b] - ex, a.nf0, 0);
+#pragma unroll
+      for (int b = 0; b < NY; ++b) py[b] = tap(ys[b] - ey, a.nf1, 1);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[b] = Mfma<T>::mma(px[NX == 4 ? b : 0] * py[NY == 4 ? b : 0], qv, acc[b]);
     }
   }
 
   // fixed-order sum of the active wavefronts' partial tiles: w0 alone,
-  // w0 + w1, or (w0 + w2) + (w1 + w3)
+  // w0 + w1, or (w0 + w2) + (w1 + w3); the staging area is reused
+  __syncthreads();
+  T* red0 = reinterpret_cast<T*>(smem_raw);
+  T* red1 = red0 + 4 * 4 * 64;
   const int base = lane;  // element (b, r) at base + 64 * (4 b + r)
   if (wave >= 2 && nw == kWaves) {
+    T* red = wave == 2 ? red0 : red1;
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[wave - 2][base + 64 * (4 * b + r)] = acc[b][r];
+      for (int r = 0; r < 4; ++r) red[base + 64 * (4 * b + r)] = acc[b][r];
   }
   __syncthreads();
   if (wave < 2 && nw == kWaves) {
+    const T* red = wave == 0 ? red0 : red1;
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[b][r] += red[wave][base + 64 * (4 * b + r)];
+      for (int r = 0; r < 4; ++r) acc[b][r] += red[base + 64 * (4 * b + r)];
   }
   __syncthreads();
   if (wave == 1 && nw >= 2) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[0][base + 64 * (4 * b + r)] = acc[b][r];
+      for (int r = 0; r < 4; ++r) red0[base + 64 * (4 * b + r)] = acc[b][r];
   }
   __syncthreads();
   if (wave == 0 && nw >= 2) {
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[b][r] += red[0][base + 64 * (4 * b + r)];
+      for (int r = 0; r < 4; ++r) acc[b][r] += red0[base + 64 * (4 * b + r)];
   }
   if (wave != 0) return;
   // column li holds the real part of tile z = li (li < 8) or the imaginary
@@ -332,6 +331,26 @@ __global__ void k_energy_finalize(const double* parts, int n, double scale, cons
 
 }  // namespace
 
+// Values between the LDS copies of two node records in the gather: the record
+// length plus whole 16-byte steps until four consecutive copies (the four
+// entries of a group, read together) start at least eight values apart in the
+// 4-byte banks.
+template <typename T>
+int gather_lds_stride(int rstride) {
+  const int step = 16 / (int)sizeof(T);
+  for (int s = rstride; s < rstride + 16 * step; s += step) {
+    bool ok = true;
+    for (int i = 0; i < 4 && ok; ++i)
+      for (int k = 0; k < i && ok; ++k) {
+        const int span = (int)sizeof(T) / 4;
+        const int bi = (i * s * (int)sizeof(T) / 4) % 64, bk = (k * s * (int)sizeof(T) / 4) % 64;
+        ok = !(bi < bk + 8 * span && bk < bi + 8 * span);
+      }
+    if (ok) return s;
+  }
+  return rstride;
+}
+
 template <typename T>
 hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   SpreadArgs<T> a{};
@@ -344,6 +363,7 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   a.nt1 = pl.gnt[1];
   a.width = pl.width;
   a.rstride = record_stride(pl.width);
+  a.lstride = gather_lds_stride<T>(a.rstride);
   a.nt2 = pl.gnt[2];
   a.list = pl.d_list;
   a.items = pl.d_items;
@@ -355,16 +375,17 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   unsigned blocks = (unsigned)pl.nitems;
   if (blocks == 0) return hipSuccess;  // no node touches the grid: G stays zero
   stage_mark(pl, ST_SPREAD, 0, s);
+  const size_t smem = std::max((size_t)kWaves * GatherLds<T>::wave_values(a.lstride), (size_t)2 * 4 * 4 * 64) * sizeof(T);
   if (pl.GT[0] == 8 && pl.GT[1] == 8) {
     if (pl.gather_nowrap)
-      hipLaunchKernelGGL((k_spread_gather<T, 8, true>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_spread_gather<T, 8, true>), dim3(blocks), dim3(256), smem, s, a);
     else
-      hipLaunchKernelGGL((k_spread_gather<T, 8, false>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_spread_gather<T, 8, false>), dim3(blocks), dim3(256), smem, s, a);
   } else if (pl.GT[0] == 1 && pl.GT[1] == 64) {
     if (pl.gather_nowrap)
-      hipLaunchKernelGGL((k_spread_gather<T, 64, true>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_spread_gather<T, 64, true>), dim3(blocks), dim3(256), smem, s, a);
     else
-      hipLaunchKernelGGL((k_spread_gather<T, 64, false>), dim3(blocks), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_spread_gather<T, 64, false>), dim3(blocks), dim3(256), smem, s, a);
   } else {
     return hipErrorInvalidValue;
   }
