@@ -162,6 +162,15 @@ struct Plan {
   // index d_nstart / d_npos (node j's entries are d_npos[d_nstart[j] ..
   // d_nstart[j + 1])).
   bool tile_interp = false;
+
+  // Hermitian half of the oversampled spectrum (Algorithm 1: rho and u are
+  // real).  The forward FFT keeps only the lines q2 = 0 .. nf2/2 of axis 2
+  // (h2 of them, rows of hs2 >= h2 elements: F is [nf0][nf1][hs2]); the
+  // interpolation reads F(q) for q2 > nf2/2 as conj F(-q); the inverse's
+  // first pass forms (G(q) + conj G(-q)) / 2 on those lines and its last
+  // completes each line by symmetry.
+  bool r2c = false;
+  int h2 = 0, hs2 = 0;
   int* d_nstart = nullptr;     // Mh + 1 offsets into d_npos
   int* d_npos = nullptr;       // nlist list positions, node-major
   void* d_ipart = nullptr;     // nlist complex T: per list entry, the tile's share of the node's value

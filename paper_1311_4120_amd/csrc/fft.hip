@@ -207,6 +207,14 @@ struct PassArgs {
   int split;          // Z passes of Algorithm 2: forward imag = rho H; inverse u += imag
   double* mparts;     // forward Z: per-block sums of rho (the node at k = 0), nullable
   const double* shift;  // inverse Z: constant added to u (the node at k = 0), nullable
+  // Hermitian half along the last axis (real input, Algorithm 1): the forward
+  // Z pass stores only outputs 0 .. nout - 1 = L/2 (half_out); the inverse Z
+  // pass loads those nin = L/2 + 1 values and completes the line by
+  // v(L - p) = conj v(p) (half_in); the inverse's first pass averages each
+  // element with the conjugate of its mirror, v(q) = (g(q) + conj g(-q)) / 2,
+  // the mirror of line (outer, inner) and element e being
+  // (-outer mod sym_no, -inner mod sym_ni, -e mod L) (hsym)
+  int half_out, half_in, hsym, sym_no, sym_ni;
   // the paired passes of Algorithm 2 (k_fft_pair_pass): lines are
   // (a, b) of an A x B set, element stride es_in / es_out; P lines and their
   // mirrors per block; nb1 blocks for the rows 0 < a < A/2 (cb per row), then cs
@@ -314,7 +322,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
   }
 
   // zero the padding region of every line when the input is padded
-  if (a.nin < L) {
+  if (a.nin < L && !a.half_in) {
     const int N = a.nin;
     const int nz = L - N;  // fine positions [N - N/2, L - N/2) stay zero
     for (int idx = threadIdx.x; idx < LB * nz; idx += NT) {
@@ -361,10 +369,17 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
         const T r = ((const T*)a.in)[base];
         buf[i] = C2<T>{lok ? r : T(0), T(0)};
       } else {
-        const C2<T> v = ((const C2<T>*)a.in)[base];
+        C2<T> v = ((const C2<T>*)a.in)[base];
+        if (a.hsym) {
+          const int li = ln - lo * (int)a.ic;
+          const int mo = lo ? a.sym_no - lo : 0, mi = li ? a.sym_ni - li : 0, me = e ? L - e : 0;
+          const C2<T> m =
+              ((const C2<T>*)a.in)[(int64_t)mo * a.in_os + (int64_t)mi * a.in_is + (int64_t)me * a.in_es];
+          v = C2<T>{T(0.5) * (v.x + m.x), T(0.5) * (v.y - m.y)};
+        }
         buf[i] = lok ? v : C2<T>{T(0), T(0)};
       }
-      const int pos = (a.nin < L) ? fine_pos(e, a.nin, L) : e;
+      const int pos = (a.nin < L && !a.half_in) ? fine_pos(e, a.nin, L) : e;
       dst[i] = ok ? l * ldl + pos : -1;
       le[i] = (l << 16) | e;
     }
@@ -384,6 +399,17 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
     }
   }
   __syncthreads();
+  if (a.half_in) {
+    // the rest of each line from the Hermitian symmetry of its spectrum
+    const int nfill = L - a.nin;
+    for (int idx = threadIdx.x; idx < LB * nfill; idx += NT) {
+      const int e = (int)a.dLB.div(idx), l = idx - e * LB;
+      const int p = a.nin + e;
+      const C2<T> v = lds[l * ldl + (L - p)];
+      lds[l * ldl + p] = C2<T>{v.x, -v.y};
+    }
+    __syncthreads();
+  }
 
   // FFT stages
   auto transform = [&](T sign) {
@@ -460,7 +486,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
         l = (int)a.dnout.div(idx);
         e = idx - l * a.nout;
       }
-      const int pos = (a.nout < L) ? fine_pos(e, a.nout, L) : e;
+      const int pos = (a.nout < L && !a.half_out) ? fine_pos(e, a.nout, L) : e;
       buf[i] = lds[l * ldl + pos];
     }
     T rho_v[KIND == PASS_INV_Z ? MAXV : 1];
@@ -1017,20 +1043,24 @@ hipError_t forward_passes(const Plan& pl, const T* rho, hipStream_t s, bool last
   const int64_t n0 = pl.n[0], n1 = pl.n[1], n2 = pl.n[2];
   const int64_t f0 = pl.nf[0], f1 = pl.nf[1], f2 = pl.nf[2];
   const bool has_x = f0 > 1;
+  // lines along axis 2 that the later passes keep (the Hermitian half
+  // 0 .. f2/2 for a real input; all f2 otherwise) and their row stride
+  const int64_t c2 = pl.r2c ? pl.h2 : f2, r2 = pl.r2c ? pl.hs2 : f2;
   // G belongs to the spreading: the intermediates use F and W
   void* A1 = has_x ? pl.d_F : pl.d_W;
   void* A2 = has_x ? pl.d_W : pl.d_F;
   hipError_t e;
-  {  // Z: rho -> A1 [n0][n1][f2]
+  {  // Z: rho -> A1 [n0][n1][r2]
     PassArgs<T> a = base_args<T>(pl, 2, T(-1));
     a.nlines = n0 * n1;
     a.nin = (int)n2;
-    a.nout = (int)f2;
+    a.nout = (int)c2;
+    a.half_out = pl.r2c ? 1 : 0;
     a.ic = 1;
     a.in_os = n2;
     a.in_is = 0;
     a.in_es = 1;
-    a.out_os = f2;
+    a.out_os = r2;
     a.out_is = 0;
     a.out_es = 1;
     a.lines_fastest = 0;
@@ -1044,35 +1074,35 @@ hipError_t forward_passes(const Plan& pl, const T* rho, hipStream_t s, bool last
     a.mparts = (pl.c0 != 0.0) ? pl.d_mparts : nullptr;
     if ((e = run_pass<T, PASS_FWD_Z>(pl, ST_FWD_Z, a, s)) != hipSuccess) return e;
   }
-  if (has_x || last) {  // Y: A1 -> A2 [n0][f1][f2]
+  if (has_x || last) {  // Y: A1 -> A2 [n0][f1][r2]
     PassArgs<T> a = base_args<T>(pl, 1, T(-1));
-    a.nlines = n0 * f2;
+    a.nlines = n0 * c2;
     a.nin = (int)n1;
     a.nout = (int)f1;
-    a.ic = f2;
-    a.in_os = n1 * f2;
+    a.ic = c2;
+    a.in_os = n1 * r2;
     a.in_is = 1;
-    a.in_es = f2;
-    a.out_os = f1 * f2;
+    a.in_es = r2;
+    a.out_os = f1 * r2;
     a.out_is = 1;
-    a.out_es = f2;
+    a.out_es = r2;
     a.lines_fastest = 1;
     a.in = A1;
     a.out = A2;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_FWD_Y, a, s)) != hipSuccess) return e;
   }
-  if (has_x && last) {  // X: A2 -> F [f0][f1][f2]
+  if (has_x && last) {  // X: A2 -> F [f0][f1][r2]
     PassArgs<T> a = base_args<T>(pl, 0, T(-1));
-    a.nlines = f1 * f2;
+    a.nlines = f1 * c2;
     a.nin = (int)n0;
     a.nout = (int)f0;
-    a.ic = f1 * f2;
-    a.in_os = 0;
+    a.ic = c2;
+    a.in_os = r2;
     a.in_is = 1;
-    a.in_es = f1 * f2;
-    a.out_os = 0;
+    a.in_es = f1 * r2;
+    a.out_os = r2;
     a.out_is = 1;
-    a.out_es = f1 * f2;
+    a.out_es = f1 * r2;
     a.lines_fastest = 1;
     a.in = A2;
     a.out = pl.d_F;
@@ -1163,20 +1193,27 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
   void* src = pl.d_G;
   void* B2 = has_x ? pl.d_F : src;  // (2D: the input grid itself)
   void* B1 = pl.d_W;
+  // a real output needs only the Hermitian part of the spectrum,
+  // (G(q) + conj G(-q)) / 2, at the lines 0 .. f2/2 of axis 2: the first pass
+  // forms it from G and G's mirror (rows of r2), the last completes each line
+  const int64_t c2 = pl.r2c ? pl.h2 : f2, r2 = pl.r2c ? pl.hs2 : f2;
   hipError_t e;
-  if (has_x) {  // X: src -> B2 [n0][f1][f2]
+  if (has_x) {  // X: src -> B2 [n0][f1][r2]
     PassArgs<T> a = base_args<T>(pl, 0, T(1));
-    a.nlines = f1 * f2;
+    a.nlines = f1 * c2;
     a.nin = (int)f0;
     a.nout = (int)n0;
-    a.ic = f1 * f2;
-    a.in_os = 0;
+    a.ic = c2;
+    a.in_os = f2;
     a.in_is = 1;
     a.in_es = f1 * f2;
-    a.out_os = 0;
+    a.out_os = r2;
     a.out_is = 1;
-    a.out_es = f1 * f2;
+    a.out_es = f1 * r2;
     a.lines_fastest = 1;
+    a.hsym = pl.r2c ? 1 : 0;
+    a.sym_no = (int)f1;
+    a.sym_ni = (int)f2;
     a.in = src;
     a.out = B2;
     if (pl.split) {
@@ -1192,19 +1229,23 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     PassArgs<T> b = split_pair_args<T>(pl, 1);
     b.out = B1;
     if ((e = run_pair_pass<T, PAIR_FUSED>(pl, ST_INV_Y, b, s)) != hipSuccess) return e;
-  } else {  // Y: B2 -> B1 [n0][n1][f2]
+  } else {  // Y: B2 -> B1 [n0][n1][r2]; in 2D the first pass, reading G [1][f1][f2]
     PassArgs<T> a = base_args<T>(pl, 1, T(1));
-    a.nlines = n0 * f2;
+    const int64_t rin = has_x ? r2 : f2;
+    a.nlines = n0 * c2;
     a.nin = (int)f1;
     a.nout = (int)n1;
-    a.ic = f2;
-    a.in_os = f1 * f2;
+    a.ic = c2;
+    a.in_os = f1 * rin;
     a.in_is = 1;
-    a.in_es = f2;
-    a.out_os = n1 * f2;
+    a.in_es = rin;
+    a.out_os = n1 * r2;
     a.out_is = 1;
-    a.out_es = f2;
+    a.out_es = r2;
     a.lines_fastest = 1;
+    a.hsym = (pl.r2c && !has_x) ? 1 : 0;
+    a.sym_no = 1;
+    a.sym_ni = (int)f2;
     a.in = B2;
     a.out = B1;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_Y, a, s)) != hipSuccess) return e;
@@ -1212,10 +1253,11 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
   {  // Z: B1 -> u [n0][n1][n2], real part, deconvolution, energy partials
     PassArgs<T> a = base_args<T>(pl, 2, T(1));
     a.nlines = n0 * n1;
-    a.nin = (int)f2;
+    a.nin = (int)c2;
+    a.half_in = pl.r2c ? 1 : 0;
     a.nout = (int)n2;
     a.ic = 1;
-    a.in_os = f2;
+    a.in_os = r2;
     a.in_is = 0;
     a.in_es = 1;
     a.out_os = n2;

@@ -41,7 +41,9 @@ struct InterpArgs {
   const int4* hdr;
   const double* coef;
   const int* perm;
-  const C2<T>* F;
+  const C2<T>* F;     // rows of hs2 along axis 2
+  int hs2;
+  int r2c;            // F holds q2 = 0 .. nf2/2 only: F(q) = conj F(-q) beyond
   int mode;
   C2<T>* uhat;
   const T* wts;
@@ -123,6 +125,8 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     const bool act = r0 < rpp;
     const int i2 = act ? threadIdx.x - r0 * E2 : 0;
     const int g2 = (int)a.dnf2.mod((uint32_t)(oz + i2));
+    const bool mirror = a.r2c && 2 * g2 > a.nf2;  // the conjugate mirror of the stored half
+    const int m2 = mirror ? a.nf2 - g2 : g2;
     const int d0 = rpp / a.E1, d1 = rpp - d0 * a.E1;
     int i0 = r0 / a.E1, i1 = r0 - (r0 / a.E1) * a.E1;
     const int nrow = a.E0 * a.E1;
@@ -134,11 +138,15 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
         const int r = rb + k * rpp;
         const bool ok = r < nrow;
         // the region may be wider than the grid on small grids: reduce modulo nf
-        const int g0 = ok ? (int)a.dnf0.mod((uint32_t)(ox + i0)) : 0;
-        const int g1 = ok ? (int)a.dnf1.mod((uint32_t)(oy + i1)) : 0;
-        const C2<T> v = a.F[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2];
+        int g0 = ok ? (int)a.dnf0.mod((uint32_t)(ox + i0)) : 0;
+        int g1 = ok ? (int)a.dnf1.mod((uint32_t)(oy + i1)) : 0;
+        if (mirror) {
+          g0 = g0 ? a.nf0 - g0 : 0;
+          g1 = g1 ? a.nf1 - g1 : 0;
+        }
+        const C2<T> v = a.F[((int64_t)g0 * a.nf1 + g1) * a.hs2 + m2];
         vr[k] = v.x;
-        vi[k] = v.y;
+        vi[k] = mirror ? -v.y : v.y;
         dst[k] = ok ? i0 * a.pstride + i1 * E2 + i2 : -1;
         i0 += d0;
         i1 += d1;
@@ -330,7 +338,9 @@ struct TileArgs {
   int lstride;        // values between the LDS copies of two records (>= rstride; see the launcher)
   const int2* list;
   const WorkItem* items;
-  const T* F;         // oversampled grid, interleaved (re, im)
+  const T* F;         // oversampled grid, interleaved (re, im), rows of hs2 along axis 2
+  int hs2;            // row stride of F along axis 2
+  int r2c;            // F holds q2 = 0 .. nf2/2 only: F(q) = conj F(-q) beyond
   const T* wts;
   C2<T>* ipart;
 };
@@ -367,9 +377,17 @@ __global__ void __launch_bounds__(256) k_interp_tile(TileArgs<T> a) {
     const int z = j16 & 7, part = j16 >> 3;
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      const int gx = o0 + (t >> 1), gy = o1 + ((t & 1) << 2) + k4, gz = o2 + z;
+      int gx = o0 + (t >> 1), gy = o1 + ((t & 1) << 2) + k4, gz = o2 + z;
       const bool in = gx < a.nf0 && gy < a.nf1 && gz < a.nf2;
-      B[t] = in ? a.F[2 * (((int64_t)gx * a.nf1 + gy) * a.nf2 + gz) + part] : T(0);
+      // the Hermitian half: the other half is the conjugate mirror image
+      const bool mirror = a.r2c && 2 * gz > a.nf2;
+      if (mirror) {
+        gx = gx ? a.nf0 - gx : 0;
+        gy = gy ? a.nf1 - gy : 0;
+        gz = a.nf2 - gz;
+      }
+      const T v = in ? a.F[2 * (((int64_t)gx * a.nf1 + gy) * a.hs2 + gz) + part] : T(0);
+      B[t] = (mirror && part) ? -v : v;
     }
   }
   // the tile z and part of the lane's result registers
@@ -574,6 +592,8 @@ hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipSt
   a.items = pl.d_items;
   // Algorithm 2: the type-2 spectrum was separated into G's touched tiles
   a.F = (const T*)(pl.split ? pl.d_G : pl.d_F);
+  a.hs2 = pl.split ? pl.nf[2] : pl.hs2;
+  a.r2c = pl.r2c ? 1 : 0;
   a.wts = (const T*)pl.nodes.wts;
   a.ipart = (C2<T>*)pl.d_ipart;
   stage_mark(pl, ST_INTERP, 0, s);
@@ -658,6 +678,8 @@ hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t
   a.perm = pl.nodes.perm;
   // Algorithm 2: the type-2 spectrum was separated into G's touched tiles
   a.F = (const C2<T>*)(pl.split ? pl.d_G : pl.d_F);
+  a.hs2 = pl.split ? pl.nf[2] : pl.hs2;
+  a.r2c = pl.r2c ? 1 : 0;
   a.mode = mode;
   a.uhat = (C2<T>*)pl.nodes.uhat;
   a.wts = (const T*)pl.nodes.wts;

@@ -494,6 +494,12 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     hmax = std::max(hmax, pl.h[i]);
   }
   pl.K = (p->kmax > 0) ? p->kmax : M_PI / hmax;
+  // Algorithm 1 on a real density keeps the Hermitian half of the spectrum
+  // (Algorithm 2 packs a second real transform into the imaginary part)
+  pl.split = (p->flags & JGB_FLAG_SPLIT) != 0;
+  pl.r2c = !pl.split;
+  pl.h2 = pl.nf[2] / 2 + 1;
+  pl.hs2 = pl.r2c ? (pl.h2 + 7) / 8 * 8 : pl.nf[2];
   {
     // the second dipole orientation: m = n unless given
     double mm = 0;
