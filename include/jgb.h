@@ -111,6 +111,16 @@ typedef enum { JGB_THETA_GL = 0, JGB_COSTHETA_GL = 1 } jgb_theta_rule;
  * evaluated directly to eps (relative L2 of u, relative E).  See
  * jgb_params.window and jgb_params.kmax for the scales. */
 #define JGB_FLAG_SPLIT 2u
+/* Interpolate by tiles on the matrix cores (3D only, else UNSUPPORTED): the
+ * type-2 back end runs as the transpose of the spreading's tile products --
+ * for each output tile of the spreading and 16 of its listed nodes at a time,
+ * 16x16x4 products of the tile's grid values with the nodes' kernel values --
+ * and each node's shares of its tiles are summed in a fixed order.  Without
+ * this flag the interpolation stages each sub-bin's neighbourhood in LDS; with
+ * JGB_FLAG_AUTOTUNE alone the plan times both and keeps the faster.  Results
+ * agree to rounding.  Costs one complex value and one index per list entry of
+ * device memory. */
+#define JGB_FLAG_INTERP_TILES 4u
 
 typedef struct jgb_plan_s* jgb_plan_t;
 
@@ -165,7 +175,8 @@ typedef struct {
   double beta;             /* exponential-of-semicircle kernel shape parameter */
   double kmax;             /* K actually used */
   int64_t workspace_bytes; /* device memory owned by the plan */
-  int32_t interp_chunk;    /* nodes per interpolation block at most */
+  int32_t interp_chunk;    /* nodes per interpolation block at most; 0: the autotuner chose the
+                              interpolation by tiles on the matrix cores */
   int32_t spread_chunk;    /* list entries per spreading block at most */
   uint32_t flags;          /* the plan's JGB_FLAG_* */
   double window[2];        /* JGB_FLAG_SPLIT: the window scales used (a, 0) or (R0, R1); else 0 */

@@ -26,6 +26,7 @@ STAGE_NAMES = ["fwd_fft_z", "fwd_fft_y", "fwd_fft_x", "interp", "spread", "sprea
 FP64, MIXED = 0, 1
 FLAG_AUTOTUNE = 1
 FLAG_SPLIT = 2
+FLAG_INTERP_TILES = 4
 THETA_GL, COSTHETA_GL = 0, 1
 
 

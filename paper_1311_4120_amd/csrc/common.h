@@ -161,7 +161,8 @@ struct Plan {
   // kernel sums each node's partials in a fixed order through the node-major
   // index d_nstart / d_npos (node j's entries are d_npos[d_nstart[j] ..
   // d_nstart[j + 1])).
-  bool tile_interp = false;
+  bool tile_ok = false;        // the tables below are built (autotuned 3D plans)
+  bool tile_interp = false;    // and the interpolation uses them
 
   // Hermitian half of the oversampled spectrum (Algorithm 1: rho and u are
   // real).  The forward FFT keeps only the lines q2 = 0 .. nf2/2 of axis 2
@@ -295,6 +296,8 @@ hipError_t launch_fft_periodic_kinetic(const Plan& pl, void* const tw[3], void* 
 jgb_status potential_pipeline(Plan& pl, const void* rho, void* u, double* energy, hipStream_t st);
 int fft_inverse_z_blocks(const Plan& pl);
 int interp_blocks(const Plan& pl);
+// energy partials the interpolation by tiles writes (0 without its tables)
+int tile_interp_blocks(const Plan& pl);
 hipError_t interp_prepare(const Plan& pl);
 // out = scale (sum of the n parts + *extra); extra may be null
 hipError_t launch_energy_finalize(const double* parts, int n, double scale, const double* extra, double* out,

@@ -568,11 +568,13 @@ int reduce_lanes(const Plan& pl) {
   return mean >= 10.0 ? 8 : (mean >= 4.0 ? 4 : 1);
 }
 
-int interp_blocks(const Plan& pl) {
-  if (!pl.tile_interp) return pl.niitems;
+int tile_interp_blocks(const Plan& pl) {
+  if (!pl.tile_ok) return 0;
   const int64_t per = 256 / reduce_lanes(pl);
   return (int)((pl.Mh + per - 1) / per);
 }
+
+int interp_blocks(const Plan& pl) { return pl.tile_interp ? tile_interp_blocks(pl) : pl.niitems; }
 
 template <typename T>
 hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipStream_t s) {

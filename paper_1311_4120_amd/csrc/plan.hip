@@ -19,6 +19,8 @@ namespace {
 // candidate work-item sizes; the first of each is the smallest and sizes the buffers
 constexpr int kInterpChunks[] = {256, 512, 1024, 2048};
 constexpr int kSpreadChunks[] = {1024, 2048, 4096, 8192};
+// the autotuner's record of the interpolation by tiles in place of a chunk size
+constexpr int kTileInterp = -1;
 constexpr size_t kInterpLdsMax = 144 * 1024;  // of 160 KB per CU, beside the kernel's static LDS
 
 bool is_235(int64_t n) {
@@ -275,6 +277,7 @@ bool cache_lookup(const std::string& path, const std::string& key, int& ic, int&
   if (sscanf(text.c_str() + i2, "\"spread_chunk\": %d", &sc) != 1) return false;
   bool ok_i = false, ok_s = false;
   for (int c : kInterpChunks) ok_i |= (c == ic);
+  ok_i |= ic == kTileInterp;
   for (int c : kSpreadChunks) ok_s |= (c == sc);
   return ok_i && ok_s;
 }
@@ -333,8 +336,10 @@ Status autotune(Plan& pl) {
   const char* path = getenv("JGB_AUTOTUNE_CACHE");
   const std::string key = tune_key(pl);
   int ic = 0, sc = 0;
-  if (path && cache_lookup(path, key, ic, sc)) {
-    TRY(apply_interp_chunk(pl, ic));
+  const bool forced = (pl.p.flags & JGB_FLAG_INTERP_TILES) != 0;
+  if (path && cache_lookup(path, key, ic, sc) && (ic != kTileInterp || pl.tile_ok)) {
+    pl.tile_interp = forced || ic == kTileInterp;
+    if (!pl.tile_interp) TRY(apply_interp_chunk(pl, ic));
     TRY(apply_spread_chunk(pl, sc));
     return Status::ok();
   }
@@ -352,6 +357,18 @@ Status autotune(Plan& pl) {
     }
   }
   TRY(apply_interp_chunk(pl, ic));
+  if (pl.tile_ok && !(pl.p.flags & JGB_FLAG_INTERP_TILES)) {
+    // the interpolation by tiles on the matrix cores, against the best chunk
+    pl.tile_interp = true;
+    double ms;
+    TRY(pl.fp64 ? time_stage<double>(pl, true, ms) : time_stage<float>(pl, true, ms));
+    if (ms < best_i) {
+      best_i = ms;
+      ic = kTileInterp;
+    } else {
+      pl.tile_interp = false;
+    }
+  }
   double ms0;
   TRY(pl.fp64 ? time_stage<double>(pl, true, ms0) : time_stage<float>(pl, true, ms0));  // node values for spreading
   for (int c : kSpreadChunks) {
@@ -415,7 +432,10 @@ Status validate(const jgb_params* p) {
   double kn = M_PI / hmax;
   if (!(std::isfinite(p->kmax) && p->kmax >= 0)) return fail(JGB_ERR_INVALID_ARG, "kmax must be finite and >= 0");
   if (p->kmax > kn * (1 + 1e-12)) return fail(JGB_ERR_INVALID_ARG, "kmax must not exceed pi / max_j h_j");
-  if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT)) return fail(JGB_ERR_INVALID_ARG, "unknown flags");
+  if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT | JGB_FLAG_INTERP_TILES))
+    return fail(JGB_ERR_INVALID_ARG, "unknown flags");
+  if ((p->flags & JGB_FLAG_INTERP_TILES) && p->dim != 3)
+    return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_INTERP_TILES needs dim == 3");
   for (int i = 0; i < 2; ++i)
     if (!std::isfinite(p->window[i])) return fail(JGB_ERR_INVALID_ARG, "window must be finite");
   if (!(p->flags & JGB_FLAG_SPLIT)) {
@@ -716,9 +736,13 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   std::vector<int2> list(nlist + 1, make_int2(0, 0));  // one spare entry
   // node-major index of the list for the tile interpolation: node j's entries
   // are generated together below, in the order of its tiles
-  pl.tile_interp = pl.dim == 3 && pl.GT[0] == 8 && pl.GT[1] == 8 && pl.GT[2] == 8;
+  // (built only for autotuned plans: the tuner times it against the staged
+  // interpolation and keeps the faster)
+  pl.tile_ok = pl.dim == 3 && pl.GT[0] == 8 && pl.GT[1] == 8 && pl.GT[2] == 8 &&
+               (p->flags & (JGB_FLAG_AUTOTUNE | JGB_FLAG_INTERP_TILES));
+  pl.tile_interp = pl.tile_ok && (p->flags & JGB_FLAG_INTERP_TILES);
   std::vector<int> nstart, npos;
-  if (pl.tile_interp) {
+  if (pl.tile_ok) {
     nstart.assign(Mh + 1, 0);
     npos.reserve(nlist);
   }
@@ -726,7 +750,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
     int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
     for (int64_t j = 0; j < Mh; ++j) {
-      if (pl.tile_interp) nstart[j] = (int)npos.size();
+      if (pl.tile_ok) nstart[j] = (int)npos.size();
       int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
       for (int a0 = 0; a0 < nx; ++a0)
         for (int a1 = 0; a1 < ny; ++a1)
@@ -737,13 +761,13 @@ Status build_plan(Plan& pl, const jgb_params* p) {
             const int ez = start_code(2, hdr[j].z - tz[a2] * pl.GT[2]);
             if (ex < 0 || ex > 1023 || ey < 0 || ey > 1023 || ez < 0 || ez > 1023)
               return fail(JGB_ERR_UNSUPPORTED, "gather list start out of range");
-            if (pl.tile_interp) npos.push_back((int)fill[tile]);
+            if (pl.tile_ok) npos.push_back((int)fill[tile]);
             list[fill[tile]++] = make_int2((int)j, ex | (ey << 10) | (ez << 20));
           }
     }
-    if (pl.tile_interp) nstart[Mh] = (int)npos.size();
+    if (pl.tile_ok) nstart[Mh] = (int)npos.size();
   }
-  if (pl.tile_interp) {
+  if (pl.tile_ok) {
     TRY(dev_alloc(pl, &pl.d_nstart, sizeof(int) * (Mh + 1)));
     TRY(upload(pl, pl.d_nstart, nstart.data(), sizeof(int) * (Mh + 1)));
     TRY(dev_alloc(pl, &pl.d_npos, sizeof(int) * std::max<int64_t>(nlist, 1)));
@@ -865,7 +889,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     TRY(dev_alloc(pl, &pl.d_mparts, pl.ws_bytes[Plan::WS_MPARTS]));
     TRY(dev_alloc(pl, &pl.d_origin, pl.ws_bytes[Plan::WS_ORIGIN]));
   }
-  pl.neparts = std::max(fft_inverse_z_blocks(pl), std::max(pl.iitems_cap, interp_blocks(pl)) + pl.nsym_blocks);
+  pl.neparts = std::max(fft_inverse_z_blocks(pl), std::max(pl.iitems_cap, tile_interp_blocks(pl)) + pl.nsym_blocks);
   pl.neparts = std::max(pl.neparts, 1);
   pl.ws_bytes[Plan::WS_EPARTS] = sizeof(double) * pl.neparts;
   TRY(dev_alloc(pl, &pl.d_eparts, pl.ws_bytes[Plan::WS_EPARTS]));

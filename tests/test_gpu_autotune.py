@@ -23,11 +23,12 @@ def test_autotune_and_cache(prec, tmp_path, monkeypatch):
     tuned = make_plan(p, autotune=True)
     ic, sc = tuned.info["interp_chunk"], tuned.info["spread_chunk"]
     say("   chose interp %d spread %d" % (ic, sc))
-    assert ic in (256, 512, 1024, 2048) and sc in (1024, 2048, 4096, 8192)
+    # 0: the interpolation by tiles on the matrix cores was faster
+    assert ic in (0, 256, 512, 1024, 2048) and sc in (1024, 2048, 4096, 8192)
     data = json.loads(cache.read_text())
     assert len(data) == 1
     entry = next(iter(data.values()))
-    assert entry["interp_chunk"] == ic and entry["spread_chunk"] == sc
+    assert entry["interp_chunk"] == (ic if ic else -1) and entry["spread_chunk"] == sc
     again = make_plan(p, autotune=True)
     assert (again.info["interp_chunk"], again.info["spread_chunk"]) == (ic, sc)
     plain = make_plan(p)

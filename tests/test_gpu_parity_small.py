@@ -48,15 +48,20 @@ def test_nodes_match_oracle(name):
     plan.close()
 
 
-@pytest.mark.parametrize("name", list(CASES))
+# (name, interpolation by tiles on the matrix cores): every case with the
+# staged interpolation, the 3D cases also by tiles
+VARIANTS = [(n, False) for n in CASES] + [(n, True) for n in CASES if CASES[n].dim == 3]
+
+
+@pytest.mark.parametrize("name,tiles", VARIANTS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_transform_matches_oracle(name, prec):
+def test_transform_matches_oracle(name, tiles, prec):
     p = CASES[name]
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("transform", name, prec)
+    say("transform", name, prec, "tiles" if tiles else "staged")
     rho = _rho(p)
     dt = torch.float64 if prec == "fp64" else torch.float32
-    plan = make_plan(p, eps=eps, precision=prec)
+    plan = make_plan(p, eps=eps, precision=prec, interp_tiles=tiles)
     got = plan.transform(torch.tensor(rho, dtype=dt, device="cuda")).cpu().numpy()
     ko, Wo = oracle.fourier_nodes(p)
     rho_in = rho if prec == "fp64" else rho.astype(np.float32).astype(np.float64)
@@ -67,15 +72,15 @@ def test_transform_matches_oracle(name, prec):
     plan.close()
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name,tiles", VARIANTS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_potential_and_energy_match_oracle(name, prec):
+def test_potential_and_energy_match_oracle(name, tiles, prec):
     p = CASES[name]
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("potential", name, prec)
+    say("potential", name, prec, "tiles" if tiles else "staged")
     rho = _rho(p)
     dt = torch.float64 if prec == "fp64" else torch.float32
-    plan = make_plan(p, eps=eps, precision=prec)
+    plan = make_plan(p, eps=eps, precision=prec, interp_tiles=tiles)
     rt = torch.tensor(rho, dtype=dt, device="cuda")
     u, E = plan.potential(rt)
     Ef = plan.energy(rt)

@@ -71,18 +71,23 @@ def _oracle(name):
     return _REF[name]
 
 
-def _plan(p, window, eps, prec):
-    return make_plan(p, eps=eps, precision=prec, split=True, window=window or (0.0, 0.0))
+def _plan(p, window, eps, prec, tiles=False):
+    return make_plan(p, eps=eps, precision=prec, split=True, window=window or (0.0, 0.0), interp_tiles=tiles)
+
+
+# every case with the staged interpolation; the 3D ones also by tiles on the matrix cores
+VARIANTS = [(n, False) for n in CASES] + [(n, True) for n in CASES if CASES[n][0].dim == 3]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", list(CASES))
-def test_split_matches_oracle(name, prec):
+@pytest.mark.parametrize("name,tiles", VARIANTS)
+def test_split_matches_oracle(name, tiles, prec):
     p, window = CASES[name]
     rho, par, u_ref, E_ref = _oracle(name)
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("split", name, prec, "grid", p.n, "nodes", (p.n_r, p.n_theta, p.n_phi), "window", par)
-    plan = _plan(p, window, eps, prec)
+    say("split", name, prec, "grid", p.n, "nodes", (p.n_r, p.n_theta, p.n_phi), "window", par,
+        "tiles" if tiles else "staged")
+    plan = _plan(p, window, eps, prec, tiles)
     K2 = p.kmax if p.kmax > 0 else split.default_cutoff(p.n, p.box, par)
     assert plan.info["kmax"] == pytest.approx(K2, rel=1e-14)
     want = (par["a"], 0.0) if p.dim == 3 else (par["R0"], par["R1"])

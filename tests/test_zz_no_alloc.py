@@ -32,14 +32,15 @@ def _noalloc(plan, rho, u, E):
                                           ctypes.c_void_p(E.data_ptr()))
 
 
+@pytest.mark.parametrize("tiles", [False, True])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_noalloc_equals_potential(prec):
+def test_noalloc_equals_potential(prec, tiles):
     from paper_1311_4120_amd import _lib
     dt = torch.float64 if prec == "fp64" else torch.float32
     for n in (48, 24):   # the second call is smaller: the array holds the first call's values
         p, rho = _problem(n, prec)
-        say("noalloc", prec, n)
-        plan = make_plan(p)
+        say("noalloc", prec, n, "tiles" if tiles else "staged")
+        plan = make_plan(p, interp_tiles=tiles)
         rt = torch.tensor(rho, dtype=dt, device="cuda")
         u_ref, E_ref = plan.potential(rt)
         u = torch.full_like(rt, float("nan"))
