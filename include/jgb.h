@@ -320,6 +320,12 @@ jgb_status jgb_batch_bind(jgb_batch_t batch, const void* const* rho, void* const
  * nothing is bound. */
 jgb_status jgb_batch_run(jgb_batch_t batch);
 
+/* Kernel launches one jgb_batch_run replays (after jgb_batch_bind): one per
+ * pipeline site over all members when the members' pipelines merge (every
+ * member by Algorithm 1), else the members' own launches on the batch's
+ * streams.  *launches must not be NULL. */
+jgb_status jgb_batch_launches(jgb_batch_t batch, int* launches);
+
 /* Member plan i (owned by the batch: do not destroy it). */
 jgb_status jgb_batch_plan(jgb_batch_t batch, int i, jgb_plan_t* plan);
 

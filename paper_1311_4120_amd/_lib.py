@@ -123,6 +123,7 @@ def _load():
         "jgb_batch_create": (st, [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)]),
         "jgb_batch_bind": (st, [P, ctypes.POINTER(P), ctypes.POINTER(P), P]),
         "jgb_batch_run": (st, [P]),
+        "jgb_batch_launches": (st, [P, ctypes.POINTER(ctypes.c_int)]),
         "jgb_batch_plan": (st, [P, ctypes.c_int, ctypes.POINTER(P)]),
         "jgb_batch_destroy": (st, [P]),
         "jgb_timing_end": (st, [P, P, P]),

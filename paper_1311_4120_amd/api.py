@@ -298,6 +298,12 @@ class Batch:
         check(lib.jgb_batch_run(self._h))
         return self.u, self.energies
 
+    def launches(self):
+        """Kernel launches one run() replays (after bind)."""
+        n = ctypes.c_int()
+        check(lib.jgb_batch_launches(self._h, ctypes.byref(n)))
+        return n.value
+
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:

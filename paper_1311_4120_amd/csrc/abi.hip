@@ -23,6 +23,11 @@ thread_local std::string g_last_error;
 }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+std::vector<LaunchRecord>*& launch_record() {
+  thread_local std::vector<LaunchRecord>* rec = nullptr;
+  return rec;
+}
 const char* get_error() { return g_last_error.c_str(); }
 
 }  // namespace jgb
@@ -40,6 +45,8 @@ struct jgb_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int device = 0;
+  void* d_tables = nullptr;               // argument tables of the batched launches
+  int nlaunch = 0;                        // launches in the graph (0: per-member branches)
 };
 
 namespace {
@@ -360,8 +367,116 @@ jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* cc) {
 static void release_graph(jgb_batch_s* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_tables) (void)hipFree(b->d_tables);
   b->exec = nullptr;
   b->graph = nullptr;
+  b->d_tables = nullptr;
+  b->nlaunch = 0;
+}
+
+// One launch per pipeline site over all members: every member's pipeline is
+// recorded (nothing is issued), the records are merged site by site -- a site
+// being a kernel and its occurrence in the member's pipeline, in pipeline
+// order -- and each site becomes one launch over the members that have it,
+// its blocks the members' blocks in turn.  Returns JGB_ERR_UNSUPPORTED (and
+// captures nothing) when the members' pipelines do not merge.
+static jgb_status bind_batched(jgb_batch_s* b, const void* const* rho, void* const* u, double* energies) {
+  const int nm = (int)b->plans.size();
+  std::vector<std::vector<jgb::LaunchRecord>> recs(nm);
+  for (int i = 0; i < nm; ++i) {
+    Plan& pl = b->plans[i]->pl;
+    jgb::launch_record() = &recs[i];
+    double* E = energies ? energies + i : nullptr;
+    jgb_status st = pl.fp64 ? run_potential<double>(pl, rho[i], u[i], E, b->stream)
+                            : run_potential<float>(pl, rho[i], u[i], E, b->stream);
+    jgb::launch_record() = nullptr;
+    if (st != JGB_OK) return st;
+  }
+  struct Site {
+    jgb::BatchLaunch f;
+    int occ;
+    std::vector<std::pair<int, int>> members;  // (member, record)
+  };
+  std::vector<Site> sites;
+  for (int i = 0; i < nm; ++i) {
+    std::vector<std::pair<jgb::BatchLaunch, int>> seen;
+    int prev = -1;
+    for (int r = 0; r < (int)recs[i].size(); ++r) {
+      const jgb::BatchLaunch f = recs[i][r].launch;
+      int occ = 0;
+      for (auto& q : seen)
+        if (q.first == f) occ = ++q.second;
+      if (occ == 0) seen.push_back({f, 0});
+      int pos = -1;
+      for (int k = 0; k < (int)sites.size(); ++k)
+        if (sites[k].f == f && sites[k].occ == occ) pos = k;
+      if (pos < 0) {
+        pos = prev + 1;
+        sites.insert(sites.begin() + pos, Site{f, occ, {}});
+      } else if (pos <= prev) {
+        return report(JGB_ERR_UNSUPPORTED, "batch members' pipelines do not merge");
+      }
+      sites[pos].members.push_back({i, r});
+      prev = pos;
+    }
+  }
+  // argument tables and block offsets, 256-byte aligned, in one allocation
+  std::vector<unsigned char> host;
+  std::vector<size_t> toff(sites.size()), boff(sites.size());
+  std::vector<unsigned> blocks(sites.size()), threads(sites.size());
+  std::vector<size_t> smem(sites.size());
+  auto align = [&]() { host.resize((host.size() + 255) / 256 * 256, 0); };
+  for (size_t k = 0; k < sites.size(); ++k) {
+    align();
+    toff[k] = host.size();
+    unsigned nb = 0;
+    threads[k] = 0;
+    smem[k] = 0;
+    std::vector<int> bs;
+    for (auto& mr : sites[k].members) {
+      const jgb::LaunchRecord& r = recs[mr.first][mr.second];
+      host.insert(host.end(), r.args.begin(), r.args.end());
+      if (threads[k] && threads[k] != r.threads) return report(JGB_ERR_UNSUPPORTED, "batched launch block sizes differ");
+      threads[k] = r.threads;
+      smem[k] = std::max(smem[k], r.smem);
+      bs.push_back((int)nb);
+      nb += r.blocks;
+    }
+    bs.push_back((int)nb);
+    blocks[k] = nb;
+    align();
+    boff[k] = host.size();
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(bs.data());
+    host.insert(host.end(), p, p + bs.size() * sizeof(int));
+  }
+  hipError_t e = hipMalloc(&b->d_tables, std::max<size_t>(host.size(), 16));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b->d_tables = nullptr;
+    return report(JGB_ERR_OUT_OF_MEMORY, "batch tables: hipMalloc failed");
+  }
+  e = hipMemcpy(b->d_tables, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return from_hip(e, "batch tables upload");
+  hipStream_t origin = b->branches[0];
+  e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return from_hip(e, "begin capture");
+  hipError_t ce = hipSuccess;
+  const unsigned char* base = static_cast<const unsigned char*>(b->d_tables);
+  for (size_t k = 0; k < sites.size() && ce == hipSuccess; ++k)
+    ce = sites[k].f(base + toff[k], reinterpret_cast<const int*>(base + boff[k]), (int)sites[k].members.size(),
+                    blocks[k], threads[k], smem[k], origin);
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(origin, &g);
+  if (ce != hipSuccess || ee != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return from_hip(ce != hipSuccess ? ce : ee, "capture");
+  }
+  b->graph = g;
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return from_hip(e, "graph instantiate");
+  b->nlaunch = (int)sites.size();
+  return JGB_OK;
 }
 
 static void release_batch(jgb_batch_s* b) {
@@ -443,6 +558,19 @@ jgb_status jgb_batch_bind(jgb_batch_t b, const void* const* rho, void* const* u,
   for (size_t k = 0; k < b->branches.size() && e == hipSuccess; ++k) e = hipStreamSynchronize(b->branches[k]);
   if (e != hipSuccess) return from_hip(e, "batch bind");
   release_graph(b);
+  // one launch per site over all members, unless a member runs Algorithm 2
+  // (its paired passes index blocks by the whole grid)
+  bool merged = true;
+  for (int i = 0; i < count; ++i) merged &= !b->plans[i]->pl.split;
+  if (merged) {
+    jgb_status st = bind_batched(b, rho, u, energies);
+    if (st != JGB_ERR_UNSUPPORTED) {
+      if (st != JGB_OK) release_graph(b);
+      return st;
+    }
+    release_graph(b);
+    jgb::set_error("");
+  }
   // longest-processing-time assignment of members to branches by grid volume
   const int nbr = (int)b->branches.size();
   std::vector<int> order(count);
@@ -508,6 +636,16 @@ jgb_status jgb_batch_run(jgb_batch_t b) {
   if (e == hipSuccess) e = hipEventRecord(b->ev_out, origin);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out, 0);
   return from_hip(e, "graph launch");
+}
+
+jgb_status jgb_batch_launches(jgb_batch_t b, int* launches) {
+  if (!b || !launches) return report(JGB_ERR_INVALID_ARG, "batch and launches must not be NULL");
+  if (!b->exec) return report(JGB_ERR_INVALID_ARG, "batch has no bound buffers (call jgb_batch_bind)");
+  size_t n = 0;
+  hipError_t e = hipGraphGetNodes(b->graph, nullptr, &n);
+  if (e != hipSuccess) return from_hip(e, "graph nodes");
+  *launches = b->nlaunch > 0 ? b->nlaunch : (int)n;
+  return JGB_OK;
 }
 
 jgb_status jgb_batch_plan(jgb_batch_t b, int i, jgb_plan_t* plan) {

@@ -20,6 +20,9 @@ namespace jgb {
 
 // Largest spreading width supported (taps per axis).
 constexpr int kMaxWidth = 16;
+// Largest staged interpolation region, bytes of LDS (of 160 KB per CU, beside
+// the kernel's static LDS).
+constexpr size_t kInterpLdsCap = 144 * 1024;
 // Largest FFT line length (oversampled grid points on one axis).
 constexpr int kMaxLine = 1024;
 // Output tile of the type-1 gather kernel: TX x TY lanes, TZ points per lane.
@@ -231,6 +234,67 @@ __host__ __device__ inline T es_kernel(T x, T two_over_w, T beta) {
   T q = T(1) - z * z;
   if (q <= T(0)) return T(0);
   return exp(beta * (sqrt(q) - T(1)));
+}
+
+// ----------------------------------------------------------------- batches
+//
+// A batch (jgb_batch_*) evaluates many plans with one launch per pipeline
+// site over all of its members.  While a launch record is open on the calling
+// thread (launch_record()), the launchers append each kernel launch -- its
+// argument block, grid, block and LDS size, and the function that launches
+// the kernel's batched form -- instead of issuing it.  The batch then merges
+// its members' records site by site and issues, for each site, one launch
+// whose blocks are the members' blocks in turn: block b belongs to the member
+// m with bstart[m] <= b < bstart[m + 1] and runs as that member's block
+// b - bstart[m], with the member's argument block from a device table.
+
+typedef hipError_t (*BatchLaunch)(const void* table, const int* bstart, int nmembers, unsigned blocks,
+                                  unsigned threads, size_t smem, hipStream_t s);
+struct LaunchRecord {
+  BatchLaunch launch;
+  std::vector<unsigned char> args;  // the kernel's argument block
+  unsigned blocks = 0, threads = 0;
+  size_t smem = 0;
+};
+// the calling thread's open record (null: launches are issued)
+std::vector<LaunchRecord>*& launch_record();
+
+// the member of a batched launch that block b belongs to
+__device__ __forceinline__ int batch_member(const int* bstart, int nm, int b) {
+  int lo = 0, hi = nm - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bstart[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename A, void (*KB)(const A*, const int*, int)>
+hipError_t batch_launch(const void* table, const int* bstart, int nm, unsigned blocks, unsigned threads, size_t smem,
+                        hipStream_t s) {
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(KB, dim3(blocks), dim3(threads), smem, s, static_cast<const A*>(table), bstart, nm);
+  return hipGetLastError();
+}
+
+// Launch kernel K (argument block a) or, with a record open, record it with
+// its batched form KB.
+template <typename A, void (*K)(A), void (*KB)(const A*, const int*, int)>
+hipError_t launch(const A& a, unsigned blocks, unsigned threads, size_t smem, hipStream_t s) {
+  if (std::vector<LaunchRecord>* rec = launch_record()) {
+    LaunchRecord r;
+    r.launch = &batch_launch<A, KB>;
+    r.args.assign(reinterpret_cast<const unsigned char*>(&a), reinterpret_cast<const unsigned char*>(&a) + sizeof(A));
+    r.blocks = blocks;
+    r.threads = threads;
+    r.smem = smem;
+    rec->push_back(std::move(r));
+    return hipSuccess;
+  }
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(K, dim3(blocks), dim3(threads), smem, s, a);
+  return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- launchers

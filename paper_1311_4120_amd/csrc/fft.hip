@@ -294,14 +294,14 @@ __device__ inline void stage(C2<T>* lds, int ldl, int L, int LB, int Ns, const F
 // the complex passes run along a strided axis with consecutive threads on
 // consecutive lines, the Z passes along the contiguous axis.
 template <typename T, int KIND, int MAXV, int NT>
-__global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
+__device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int blk) {
   constexpr bool LINES_FASTEST = (KIND == PASS_COMPLEX || KIND == PASS_KINETIC);
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
   const int L = a.L;
   const int ldl = L + 1;
   const int LB = a.LB;
-  const int line0 = blockIdx.x * LB;
+  const int line0 = blk * LB;
   // Z passes: deconvolution factors of the block's lines and of the elements,
   // staged after the lines
   double* fline = reinterpret_cast<double*>(smem_raw + (size_t)LB * ldl * sizeof(C2<T>));
@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
       if (threadIdx.x == 0) {
         double s = 0.0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += msum[i];
-        a.mparts[blockIdx.x] = s;
+        a.mparts[blk] = s;
       }
     }
   }
@@ -559,10 +559,20 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
       if (threadIdx.x == 0) {
         double s = 0.0;
         for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += wsum[i];
-        a.eparts[blockIdx.x] = s;
+        a.eparts[blk] = s;
       }
     }
   }
+}
+
+template <typename T, int KIND, int MAXV, int NT>
+__global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
+  fft_pass_body<T, KIND, MAXV, NT>(a, blockIdx.x);
+}
+template <typename T, int KIND, int MAXV, int NT>
+__global__ void __launch_bounds__(NT) k_fft_pass_b(const PassArgs<T>* tab, const int* bstart, int nm) {
+  const int m = batch_member(bstart, nm, blockIdx.x);
+  fft_pass_body<T, KIND, MAXV, NT>(tab[m], blockIdx.x - bstart[m]);
 }
 
 // Algorithm 2's paired passes along the last forward / first inverse axis.  A
@@ -953,9 +963,10 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   constexpr int NT = pass_threads<T, KIND>();
   constexpr int MAXV = pass_elems<T, KIND>();
   stage_mark(pl, stage, 0, s);
-  hipLaunchKernelGGL((k_fft_pass<T, KIND, MAXV, NT>), dim3(blocks), dim3(NT), smem, s, a);
+  const hipError_t e =
+      launch<PassArgs<T>, k_fft_pass<T, KIND, MAXV, NT>, k_fft_pass_b<T, KIND, MAXV, NT>>(a, blocks, NT, smem, s);
   stage_mark(pl, stage, 1, s);
-  return hipGetLastError();
+  return e;
 }
 
 // The paired passes of Algorithm 2 along the internal axis `axis` (0 in 3D:
@@ -1409,7 +1420,18 @@ template hipError_t launch_fft_periodic_kinetic<float>(const Plan&, void* const[
 
 // d_origin = {c0 H sum rho, c0 (H sum rho)^2} from the first forward pass's
 // per-block sums (one block, fixed order).
-__global__ void __launch_bounds__(256) k_origin(const double* parts, int n, double H, double c0, double* out) {
+struct OriginArgs {
+  const double* parts;
+  int n;
+  double H, c0;
+  double* out;
+};
+
+__device__ __forceinline__ void origin_body(const OriginArgs& a) {
+  const double* parts = a.parts;
+  const int n = a.n;
+  const double H = a.H, c0 = a.c0;
+  double* out = a.out;
   __shared__ double s[256];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) acc += parts[i];
@@ -1426,10 +1448,14 @@ __global__ void __launch_bounds__(256) k_origin(const double* parts, int n, doub
   }
 }
 
+__global__ void __launch_bounds__(256) k_origin(OriginArgs a) { origin_body(a); }
+__global__ void __launch_bounds__(256) k_origin_b(const OriginArgs* tab, const int* bstart, int nm) {
+  origin_body(tab[batch_member(bstart, nm, blockIdx.x)]);
+}
+
 hipError_t launch_origin(const Plan& pl, hipStream_t s) {
-  hipLaunchKernelGGL(k_origin, dim3(1), dim3(256), 0, s, pl.d_mparts, fft_inverse_z_blocks(pl), pl.H, pl.c0,
-                     pl.d_origin);
-  return hipGetLastError();
+  const OriginArgs a{pl.d_mparts, fft_inverse_z_blocks(pl), pl.H, pl.c0, pl.d_origin};
+  return launch<OriginArgs, k_origin, k_origin_b>(a, 1, 256, 0, s);
 }
 
 int fft_inverse_z_blocks(const Plan& pl) {

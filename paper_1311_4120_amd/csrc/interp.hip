@@ -92,7 +92,7 @@ __device__ __forceinline__ T half_totals(T v) {
 
 // D3: three spreading axes; a 2D problem has one tap on axis 0.
 template <typename T, int W, bool D3>
-__global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
+__device__ __forceinline__ void interp_body(const InterpArgs<T>& a, const int blk) {
   constexpr int E2 = W + 16;  // staged row length (the plan guarantees a.E2 == E2)
   extern __shared__ unsigned char smem_raw[];
   C2<T>* tile = reinterpret_cast<C2<T>*>(smem_raw);
@@ -100,9 +100,9 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   __shared__ double ws[kInterpWaves];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const Plan::InterpItem item = a.items[blockIdx.x];
+  const Plan::InterpItem item = a.items[blk];
   if (item.sub < 0) {  // idle slot of the dispatch order
-    if (a.mode != INTERP_TRANSFORM && a.eparts && threadIdx.x == 0) a.eparts[blockIdx.x] = 0.0;
+    if (a.mode != INTERP_TRANSFORM && a.eparts && threadIdx.x == 0) a.eparts[blk] = 0.0;
     return;
   }
 
@@ -284,9 +284,19 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
     if (threadIdx.x == 0) {
       double s = 0.0;
       for (int i = 0; i < kInterpWaves; ++i) s += ws[i];
-      a.eparts[blockIdx.x] = s;
+      a.eparts[blk] = s;
     }
   }
+}
+
+template <typename T, int W, bool D3>
+__global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
+  interp_body<T, W, D3>(a, blockIdx.x);
+}
+template <typename T, int W, bool D3>
+__global__ void __launch_bounds__(kInterpThreads) k_interp_b(const InterpArgs<T>* tab, const int* bstart, int nm) {
+  const int m = batch_member(bstart, nm, blockIdx.x);
+  interp_body<T, W, D3>(tab[m], blockIdx.x - bstart[m]);
 }
 
 // ------------------------------------------------------------------ by tiles
@@ -353,14 +363,14 @@ __device__ __forceinline__ V tload(const void* base, uint32_t byte_off) {
 constexpr int kTileWaves = 4;
 
 template <typename T, bool NOWRAP>
-__global__ void __launch_bounds__(256) k_interp_tile(TileArgs<T> a) {
+__device__ __forceinline__ void interp_tile_body(const TileArgs<T>& a, const int blk) {
   typedef typename TileMfma<T>::acc_t acc_t;
   extern __shared__ unsigned char smem_raw[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // the wave's copies of its group's 16 node records
   T* recs = reinterpret_cast<T*>(smem_raw) + (size_t)wave * 16 * a.lstride;
-  const WorkItem item = a.items[blockIdx.x];
+  const WorkItem item = a.items[blk];
   if (item.tile < 0) return;  // idle slot of the dispatch order
   const int tile = item.tile;
   const int t2 = tile % a.nt2;
@@ -458,6 +468,16 @@ __global__ void __launch_bounds__(256) k_interp_tile(TileArgs<T> a) {
   }
 }
 
+template <typename T, bool NOWRAP>
+__global__ void __launch_bounds__(256) k_interp_tile(TileArgs<T> a) {
+  interp_tile_body<T, NOWRAP>(a, blockIdx.x);
+}
+template <typename T, bool NOWRAP>
+__global__ void __launch_bounds__(256) k_interp_tile_b(const TileArgs<T>* tab, const int* bstart, int nm) {
+  const int m = batch_member(bstart, nm, blockIdx.x);
+  interp_tile_body<T, NOWRAP>(tab[m], blockIdx.x - bstart[m]);
+}
+
 template <typename T>
 struct ReduceArgs {
   int Mh;
@@ -479,9 +499,9 @@ struct ReduceArgs {
 // ... (all of them in flight at once), then a fixed-order tree sum over the
 // LPN lanes (LPN = 1, 4 or 8).
 template <typename T, int LPN>
-__global__ void __launch_bounds__(256) k_interp_reduce(ReduceArgs<T> a) {
+__device__ __forceinline__ void interp_reduce_body(const ReduceArgs<T>& a, const int blk) {
   __shared__ double ws[4];
-  const int j = blockIdx.x * (256 / LPN) + (int)(threadIdx.x / LPN);
+  const int j = blk * (256 / LPN) + (int)(threadIdx.x / LPN);
   const int li = threadIdx.x % LPN;
   double sr = 0.0, si = 0.0;
   if (j < a.Mh) {
@@ -518,25 +538,36 @@ __global__ void __launch_bounds__(256) k_interp_reduce(ReduceArgs<T> a) {
   for (int off = 32; off >= 1; off >>= 1) eacc += __shfl_down(eacc, off, 64);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = eacc;
   __syncthreads();
-  if (threadIdx.x == 0) a.eparts[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+  if (threadIdx.x == 0) a.eparts[blk] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+template <typename T, int LPN>
+__global__ void __launch_bounds__(256) k_interp_reduce(ReduceArgs<T> a) {
+  interp_reduce_body<T, LPN>(a, blockIdx.x);
+}
+template <typename T, int LPN>
+__global__ void __launch_bounds__(256) k_interp_reduce_b(const ReduceArgs<T>* tab, const int* bstart, int nm) {
+  const int m = batch_member(bstart, nm, blockIdx.x);
+  interp_reduce_body<T, LPN>(tab[m], blockIdx.x - bstart[m]);
 }
 
 template <typename T, int W>
 hipError_t launch_w(const InterpArgs<T>& a, bool d3, unsigned blocks, size_t smem, hipStream_t s) {
-  if (d3)
-    hipLaunchKernelGGL((k_interp<T, W, true>), dim3(blocks), dim3(kInterpThreads), smem, s, a);
-  else
-    hipLaunchKernelGGL((k_interp<T, W, false>), dim3(blocks), dim3(kInterpThreads), smem, s, a);
-  return hipGetLastError();
+  if (d3) return launch<InterpArgs<T>, k_interp<T, W, true>, k_interp_b<T, W, true>>(a, blocks, kInterpThreads, smem, s);
+  return launch<InterpArgs<T>, k_interp<T, W, false>, k_interp_b<T, W, false>>(a, blocks, kInterpThreads, smem, s);
 }
 
+// The largest staged region any plan may use (the attribute is per kernel, so
+// it is set to the cap rather than to one plan's size).
 template <typename T, int W>
 hipError_t allow_lds(size_t smem) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_interp<T, W, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)smem);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_interp<T, W, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)smem);
+  const void* ks[4] = {(const void*)k_interp<T, W, true>, (const void*)k_interp<T, W, false>,
+                       (const void*)k_interp_b<T, W, true>, (const void*)k_interp_b<T, W, false>};
+  for (const void* k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
@@ -601,11 +632,11 @@ hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipSt
   stage_mark(pl, ST_INTERP, 0, s);
   if (pl.nitems > 0) {
     const size_t smem = (size_t)kTileWaves * 16 * a.lstride * sizeof(T);
-    if (pl.gather_nowrap)
-      hipLaunchKernelGGL((k_interp_tile<T, true>), dim3((unsigned)pl.nitems), dim3(256), smem, s, a);
-    else
-      hipLaunchKernelGGL((k_interp_tile<T, false>), dim3((unsigned)pl.nitems), dim3(256), smem, s, a);
-    hipError_t e = hipGetLastError();
+    const hipError_t e =
+        pl.gather_nowrap
+            ? launch<TileArgs<T>, k_interp_tile<T, true>, k_interp_tile_b<T, true>>(a, (unsigned)pl.nitems, 256, smem, s)
+            : launch<TileArgs<T>, k_interp_tile<T, false>, k_interp_tile_b<T, false>>(a, (unsigned)pl.nitems, 256, smem,
+                                                                                      s);
     if (e != hipSuccess) return e;
   }
   ReduceArgs<T> r{};
@@ -620,17 +651,18 @@ hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipSt
   r.out = (C2<T>*)out;
   r.eparts = pl.d_eparts;
   const unsigned rb = (unsigned)interp_blocks(pl);
+  hipError_t e = hipSuccess;
   if (rb > 0) {
     const int lpn = reduce_lanes(pl);
     if (lpn == 8)
-      hipLaunchKernelGGL((k_interp_reduce<T, 8>), dim3(rb), dim3(256), 0, s, r);
+      e = launch<ReduceArgs<T>, k_interp_reduce<T, 8>, k_interp_reduce_b<T, 8>>(r, rb, 256, 0, s);
     else if (lpn == 4)
-      hipLaunchKernelGGL((k_interp_reduce<T, 4>), dim3(rb), dim3(256), 0, s, r);
+      e = launch<ReduceArgs<T>, k_interp_reduce<T, 4>, k_interp_reduce_b<T, 4>>(r, rb, 256, 0, s);
     else
-      hipLaunchKernelGGL((k_interp_reduce<T, 1>), dim3(rb), dim3(256), 0, s, r);
+      e = launch<ReduceArgs<T>, k_interp_reduce<T, 1>, k_interp_reduce_b<T, 1>>(r, rb, 256, 0, s);
   }
   stage_mark(pl, ST_INTERP, 1, s);
-  return hipGetLastError();
+  return e;
 }
 
 // Let the plan's interpolation kernel use its staged-region size of LDS
@@ -639,7 +671,7 @@ hipError_t interp_prepare(const Plan& pl) {
   switch (pl.width) {
 #define JGB_W(W) \
   case W:        \
-    return pl.fp64 ? allow_lds<double, W>(pl.interp_lds) : allow_lds<float, W>(pl.interp_lds);
+    return pl.fp64 ? allow_lds<double, W>(kInterpLdsCap) : allow_lds<float, W>(kInterpLdsCap);
     JGB_W(2) JGB_W(3) JGB_W(4) JGB_W(5) JGB_W(6) JGB_W(7) JGB_W(8) JGB_W(9) JGB_W(10) JGB_W(11) JGB_W(12)
     JGB_W(13) JGB_W(14) JGB_W(15) JGB_W(16)
 #undef JGB_W

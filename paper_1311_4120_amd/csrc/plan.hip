@@ -21,7 +21,7 @@ constexpr int kInterpChunks[] = {256, 512, 1024, 2048};
 constexpr int kSpreadChunks[] = {1024, 2048, 4096, 8192};
 // the autotuner's record of the interpolation by tiles in place of a chunk size
 constexpr int kTileInterp = -1;
-constexpr size_t kInterpLdsMax = 144 * 1024;  // of 160 KB per CU, beside the kernel's static LDS
+constexpr size_t kInterpLdsMax = kInterpLdsCap;
 
 bool is_235(int64_t n) {
   if (n < 1) return false;

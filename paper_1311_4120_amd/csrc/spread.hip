@@ -129,7 +129,7 @@ struct GatherLds {
 };
 
 template <typename T, int T1, bool NOWRAP>
-__global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
+__device__ __forceinline__ void gather_body(const SpreadArgs<T>& a, const int blk) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int T0 = 64 / T1;
   constexpr int NX = (T1 == 8) ? 4 : 1;   // distinct x over the row blocks
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const WorkItem item = a.items[blockIdx.x];
+  const WorkItem item = a.items[blk];
   if (item.tile < 0) return;  // idle slot of the dispatch order
   const int tile = item.tile;
   const int t2 = tile % a.nt2;
@@ -288,16 +288,37 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
     }
 }
 
+template <typename T, int T1, bool NOWRAP>
+__global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
+  gather_body<T, T1, NOWRAP>(a, blockIdx.x);
+}
+template <typename T, int T1, bool NOWRAP>
+__global__ void __launch_bounds__(256) k_spread_gather_b(const SpreadArgs<T>* tab, const int* bstart, int nm) {
+  const int m = batch_member(bstart, nm, blockIdx.x);
+  gather_body<T, T1, NOWRAP>(tab[m], blockIdx.x - bstart[m]);
+}
+
 // Sum the partial tiles of each split tile in slot order and store the tile.
 template <typename T>
-__global__ void __launch_bounds__(256) k_spread_reduce(const int* multi, int nmulti, int nf0, int nf1, int nf2,
-                                                       int T0, int T1, int nt1, int nt2, const C2<T>* partials,
-                                                       C2<T>* G) {
+struct SpreadReduceArgs {
+  const int* multi;
+  int nmulti, nf0, nf1, nf2, T0, T1, nt1, nt2;
+  const C2<T>* partials;
+  C2<T>* G;
+};
+
+template <typename T>
+__device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs<T>& a, const int blk) {
+  const int* multi = a.multi;
+  const int nmulti = a.nmulti, nf0 = a.nf0, nf1 = a.nf1, nf2 = a.nf2, T1 = a.T1, nt1 = a.nt1, nt2 = a.nt2;
+  const int T0 = a.T0;
+  const C2<T>* partials = a.partials;
+  C2<T>* G = a.G;
   // two blocks per split tile, one tile point per thread; the slots are
   // summed in slot order, their loads issued several at a time
-  const int m = blockIdx.x >> 1;
+  const int m = blk >> 1;
   if (m >= nmulti) return;
-  const int idx = (blockIdx.x & 1) * 256 + threadIdx.x;  // < 64 kGatherZ
+  const int idx = (blk & 1) * 256 + threadIdx.x;  // < 64 kGatherZ
   const int tile = multi[3 * m], first = multi[3 * m + 1], count = multi[3 * m + 2];
   const int t2 = tile % nt2;
   const int t1 = (tile / nt2) % nt1;
@@ -316,7 +337,28 @@ __global__ void __launch_bounds__(256) k_spread_reduce(const int* multi, int nmu
   G[((int64_t)g0 * nf1 + g1) * nf2 + g2] = C2<T>{sr, si};
 }
 
-__global__ void k_energy_finalize(const double* parts, int n, double scale, const double* extra, double* out) {
+template <typename T>
+__global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs<T> a) { spread_reduce_body<T>(a, blockIdx.x); }
+template <typename T>
+__global__ void __launch_bounds__(256) k_spread_reduce_b(const SpreadReduceArgs<T>* tab, const int* bstart, int nm) {
+  const int m = batch_member(bstart, nm, blockIdx.x);
+  spread_reduce_body<T>(tab[m], blockIdx.x - bstart[m]);
+}
+
+struct FinalizeArgs {
+  const double* parts;
+  int n;
+  double scale;
+  const double* extra;
+  double* out;
+};
+
+__device__ __forceinline__ void finalize_body(const FinalizeArgs& a) {
+  const double* parts = a.parts;
+  const int n = a.n;
+  const double scale = a.scale;
+  const double* extra = a.extra;
+  double* out = a.out;
   __shared__ double s[256];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc += parts[i];
@@ -327,6 +369,11 @@ __global__ void k_energy_finalize(const double* parts, int n, double scale, cons
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = scale * (s[0] + (extra ? *extra : 0.0));
+}
+
+__global__ void __launch_bounds__(256) k_energy_finalize(FinalizeArgs a) { finalize_body(a); }
+__global__ void __launch_bounds__(256) k_energy_finalize_b(const FinalizeArgs* tab, const int* bstart, int nm) {
+  finalize_body(tab[batch_member(bstart, nm, blockIdx.x)]);
 }
 
 }  // namespace
@@ -376,34 +423,36 @@ hipError_t launch_spread(const Plan& pl, hipStream_t s) {
   if (blocks == 0) return hipSuccess;  // no node touches the grid: G stays zero
   stage_mark(pl, ST_SPREAD, 0, s);
   const size_t smem = std::max((size_t)kWaves * GatherLds<T>::wave_values(a.lstride), (size_t)2 * 4 * 4 * 64) * sizeof(T);
+  hipError_t e;
+  typedef SpreadArgs<T> A;
   if (pl.GT[0] == 8 && pl.GT[1] == 8) {
     if (pl.gather_nowrap)
-      hipLaunchKernelGGL((k_spread_gather<T, 8, true>), dim3(blocks), dim3(256), smem, s, a);
+      e = launch<A, k_spread_gather<T, 8, true>, k_spread_gather_b<T, 8, true>>(a, blocks, 256, smem, s);
     else
-      hipLaunchKernelGGL((k_spread_gather<T, 8, false>), dim3(blocks), dim3(256), smem, s, a);
+      e = launch<A, k_spread_gather<T, 8, false>, k_spread_gather_b<T, 8, false>>(a, blocks, 256, smem, s);
   } else if (pl.GT[0] == 1 && pl.GT[1] == 64) {
     if (pl.gather_nowrap)
-      hipLaunchKernelGGL((k_spread_gather<T, 64, true>), dim3(blocks), dim3(256), smem, s, a);
+      e = launch<A, k_spread_gather<T, 64, true>, k_spread_gather_b<T, 64, true>>(a, blocks, 256, smem, s);
     else
-      hipLaunchKernelGGL((k_spread_gather<T, 64, false>), dim3(blocks), dim3(256), smem, s, a);
+      e = launch<A, k_spread_gather<T, 64, false>, k_spread_gather_b<T, 64, false>>(a, blocks, 256, smem, s);
   } else {
     return hipErrorInvalidValue;
   }
   stage_mark(pl, ST_SPREAD, 1, s);
-  hipError_t e = hipGetLastError();
   if (e != hipSuccess || pl.nmulti == 0) return e;
   stage_mark(pl, ST_SPREAD_REDUCE, 0, s);
   static_assert(64 * kGatherZ == 2 * 256, "two 256-thread blocks per tile");
-  hipLaunchKernelGGL(k_spread_reduce<T>, dim3(2 * pl.nmulti), dim3(256), 0, s, pl.d_multi, pl.nmulti, pl.nf[0], pl.nf[1],
-                     pl.nf[2], pl.GT[0], pl.GT[1], pl.gnt[1], pl.gnt[2], (const C2<T>*)pl.d_partials, (C2<T>*)pl.d_G);
+  const SpreadReduceArgs<T> r{pl.d_multi, pl.nmulti, pl.nf[0], pl.nf[1], pl.nf[2], pl.GT[0], pl.GT[1], pl.gnt[1],
+                              pl.gnt[2], (const C2<T>*)pl.d_partials, (C2<T>*)pl.d_G};
+  e = launch<SpreadReduceArgs<T>, k_spread_reduce<T>, k_spread_reduce_b<T>>(r, 2 * pl.nmulti, 256, 0, s);
   stage_mark(pl, ST_SPREAD_REDUCE, 1, s);
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_energy_finalize(const double* parts, int n, double scale, const double* extra, double* out,
                                   hipStream_t s) {
-  hipLaunchKernelGGL(k_energy_finalize, dim3(1), dim3(256), 0, s, parts, n, scale, extra, out);
-  return hipGetLastError();
+  const FinalizeArgs a{parts, n, scale, extra, out};
+  return launch<FinalizeArgs, k_energy_finalize, k_energy_finalize_b>(a, 1, 256, 0, s);
 }
 
 template hipError_t launch_spread<double>(const Plan&, hipStream_t);

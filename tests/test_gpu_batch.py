@@ -46,6 +46,9 @@ def test_batch_equals_eager_and_oracle():
     b = jgb.Batch([kw for _, kw, _ in mem], nstreams=3)
     rhos = [torch.tensor(r, dtype=_dt(kw), device="cuda") for _, kw, r in mem]
     u, E = b.bind(rhos)
+    # every member by Algorithm 1: one launch per pipeline site over all members
+    say("   %d launches per run" % b.launches())
+    assert b.launches() <= 24
     b.run()
     torch.cuda.synchronize()
     for i, (p, kw, r) in enumerate(mem):
@@ -97,6 +100,8 @@ def test_batched_coulomb_workload():
     for p, mix in members:
         rhos.append(torch.tensor(mix.evaluate(p.n, p.box), dtype=torch.float32, device="cuda"))
     u, E = b.bind(rhos)
+    say("   %d launches per run" % b.launches())
+    assert b.launches() <= 16
     b.run()
     torch.cuda.synchronize()
     say("   run ok; checking members against their eager results and the closed forms")
