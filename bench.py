@@ -141,7 +141,7 @@ def roofline(stage, ms, by, fl, prec):
     return out
 
 
-def run_gpu(prec, steps, warmup, nodes="pattern"):
+def run_gpu(prec, steps, warmup, nodes="pattern", eps=None):
     import torch
 
     import paper_1311_4120_amd as jgb
@@ -150,6 +150,8 @@ def run_gpu(prec, steps, warmup, nodes="pattern"):
     p, rho = wl.dipole3d_128(wl.FP64 if prec == "fp64" else wl.MIXED, nodes=nodes)
     dt = torch.float64 if prec == "fp64" else torch.float32
     t0 = time.time()
+    if eps is not None:
+        p.eps = eps
     plan = jgb.Plan(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), eps=p.eps, precision=prec,
                     lam=p.lam, axis=p.axis, theta_rule="theta" if p.theta_rule == wl.THETA_GL else "costheta",
                     autotune=True, split=(nodes == "split"))
@@ -193,9 +195,11 @@ def run_gpu(prec, steps, warmup, nodes="pattern"):
             "tuned": {"interp_chunk": info["interp_chunk"], "spread_chunk": info["spread_chunk"]}}
 
 
-def run_batched(steps, warmup):
+def run_batched(steps, warmup, nstreams=1):
     """64 seeded Gaussian-mixture densities, N in {64, 96, 128, 160}, mixed
-    precision, evaluated by one HIP graph launch per step."""
+    precision, evaluated by one HIP graph launch per step: with one stream the
+    graph holds one kernel launch per pipeline site over all members; with
+    more, every member's own pipeline on nstreams concurrent branches."""
     import torch
 
     import paper_1311_4120_amd as jgb
@@ -207,11 +211,12 @@ def run_batched(steps, warmup):
     # members of one grid size share a tuning: cache it for the run
     os.environ.setdefault("JGB_AUTOTUNE_CACHE", os.path.join("/tmp", "jgb_autotune_bench_%d.json" % os.getpid()))
     t0 = time.time()
-    b = jgb.Batch(kws, nstreams=4)
+    b = jgb.Batch(kws, nstreams=nstreams)
     rhos = [torch.tensor(mix.evaluate(p.n, p.box), dtype=torch.float32, device="cuda") for p, mix in members]
     b.bind(rhos)
     torch.cuda.synchronize()
     plan_s = time.time() - t0
+    launches = b.launches()
     for _ in range(warmup):
         b.run()
     torch.cuda.synchronize()
@@ -226,7 +231,11 @@ def run_batched(steps, warmup):
     return {"workload": "batched_coulomb", "members": len(members), "grid_points": npts, "nodes": nodes,
             "ms_per_launch": 1e3 * wall / steps, "evals_per_s": len(members) * steps / wall,
             "grid_points_per_s": npts * steps / wall, "launches": steps, "plan_and_capture_s": plan_s,
-            "precision": "mixed", "eps": 1e-5, "graph": "one hipGraph launch per step over 4 branches"}
+            "precision": "mixed", "eps": 1e-5, "nstreams": nstreams, "kernel_launches_per_step": launches,
+            "ns_per_point": 1e6 * wall / steps / npts,
+            "graph": ("one hipGraph launch per step: one kernel launch per pipeline site over all members"
+                      if nstreams == 1 else
+                      "one hipGraph launch per step: the members' pipelines on %d branches" % nstreams)}
 
 
 def run_resolved(steps, warmup):
@@ -400,7 +409,17 @@ def cpu_baseline(sample_nodes=32768):
         oracle.evaluate(pp, rr)
         ts = time.perf_counter() - ts
         small[name] = {"s_per_eval": ts, "evals_per_s": 1.0 / ts}
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": 1.0 / full, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": cpu_model, "host_cpus_available": len(os.sched_getaffinity(0)),
             "sample": "type-2 sum at %d of %d nodes (every %d-th) + type-1 sum from them to all 128^3 points, "
                       "%.1f s, extrapolated x%.1f to one full evaluation (%.0f s); O(N M) direct sums"
                       % (len(idx), len(k), stride, t, len(k) / len(idx), full),
@@ -510,9 +529,20 @@ def main():
                         "width": m["info"]["width"], "energy": m["energy"],
                         "speedup_vs_fp64": r["ms_per_step"] / m["ms_per_step"],
                         "stages_ms": {k: v for k, v in m["stages_ms"].items() if v > 0}}
+    if "mixed" in res and head == "fp64":
+        # both precisions at the same stated accuracy: float64 at eps = 1e-5
+        print("[bench] fp64 at eps 1e-5 (the mixed path's accuracy)", file=sys.stderr, flush=True)
+        f5 = run_gpu("fp64", args.steps, args.warmup, eps=1e-5)
+        m = res["mixed"]
+        out["equal_accuracy_1e-5"] = {
+            "eps": 1e-5, "fp64": {"value": 1e3 / f5["ms_per_step"], "ms_per_step": f5["ms_per_step"],
+                                  "width": f5["info"]["width"]},
+            "mixed": {"value": 1e3 / m["ms_per_step"], "ms_per_step": m["ms_per_step"], "width": m["info"]["width"]},
+            "mixed_speedup": f5["ms_per_step"] / m["ms_per_step"]}
     if not args.no_batched and args.only is None:
         print("[bench] batched_coulomb: 64 densities, one graph launch per step", file=sys.stderr, flush=True)
         out["batched"] = run_batched(max(3, args.steps // 10), 2)
+        out["batched_streams"] = run_batched(max(3, args.steps // 10), 2, nstreams=4)
         print("[bench] dipole3d_128 with accuracy-matched node sets", file=sys.stderr, flush=True)
         out["resolved"] = run_resolved(max(3, args.steps // 5), 2)
         print("[bench] dipole3d_128 by Algorithm 2", file=sys.stderr, flush=True)

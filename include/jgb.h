@@ -293,11 +293,17 @@ jgb_status jgb_timing_end(jgb_plan_t plan, double* stage_ms, int* calls);
  * Many independent densities evaluated together, as in the repeated
  * evaluations of a time-splitting or ground-state solver (Section 1: u is
  * needed on the grid many times for different rho).  A batch owns one plan
- * per member; binding device buffers captures every member's full pipeline
- * (forward FFT, interpolation, spreading, inverse FFT, energy) into one HIP
- * graph whose independent members run on up to nstreams concurrent branches
- * (longest members first, each to the least loaded branch).  Each evaluation
- * of the whole batch is then one graph launch. */
+ * per member; binding device buffers captures the whole batch into one HIP
+ * graph, and each evaluation of the batch is one graph launch:
+ *   nstreams == 1: one kernel launch per pipeline site (forward FFT passes,
+ *     interpolation, spreading, inverse FFT passes, energy) over all members,
+ *     its blocks the members' blocks in turn, each block taking its member's
+ *     arguments from a table (members by Algorithm 2 fall back to the next
+ *     form);
+ *   nstreams > 1: every member's own pipeline, the members spread over
+ *     nstreams concurrent branches (longest first, each to the least loaded
+ *     branch), so that different members' kernels overlap.
+ * Each member's results are bitwise those of its own plan either way. */
 typedef struct jgb_batch_s* jgb_batch_t;
 
 /* Create the member plans (as jgb_plan each; all params must name

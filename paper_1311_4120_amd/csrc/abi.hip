@@ -374,12 +374,20 @@ static void release_graph(jgb_batch_s* b) {
   b->nlaunch = 0;
 }
 
-// One launch per pipeline site over all members: every member's pipeline is
-// recorded (nothing is issued), the records are merged site by site -- a site
-// being a kernel and its occurrence in the member's pipeline, in pipeline
-// order -- and each site becomes one launch over the members that have it,
-// its blocks the members' blocks in turn.  Returns JGB_ERR_UNSUPPORTED (and
-// captures nothing) when the members' pipelines do not merge.
+// Member work for balancing batch branches: grid volume and tap work.
+static double member_work(const Plan& pl) {
+  return (double)pl.nf[0] * pl.nf[1] * pl.nf[2] + 8.0 * (double)pl.Mh * pl.width;
+}
+
+// One launch per pipeline site over all members of a group: every member's
+// pipeline is recorded (nothing is issued), the records are merged site by
+// site -- a site being a kernel and its occurrence in the member's pipeline,
+// in pipeline order -- and each site becomes one launch over the group's
+// members that have it, its blocks the members' blocks in turn.  With several
+// branches the members are dealt to them (longest work first onto the least
+// loaded branch), one chain of merged launches per branch.  Returns
+// JGB_ERR_UNSUPPORTED (and captures nothing) when the members' pipelines do
+// not merge.
 static jgb_status bind_batched(jgb_batch_s* b, const void* const* rho, void* const* u, double* energies) {
   const int nm = (int)b->plans.size();
   std::vector<std::vector<jgb::LaunchRecord>> recs(nm);
@@ -392,62 +400,85 @@ static jgb_status bind_batched(jgb_batch_s* b, const void* const* rho, void* con
     jgb::launch_record() = nullptr;
     if (st != JGB_OK) return st;
   }
+  // groups, one per branch
+  const int nbr = std::min((int)b->branches.size(), nm);
+  std::vector<std::vector<int>> groups(nbr);
+  {
+    std::vector<int> order(nm);
+    for (int i = 0; i < nm; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return member_work(b->plans[x]->pl) > member_work(b->plans[y]->pl);
+    });
+    std::vector<double> load(nbr, 0.0);
+    for (int i : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[k] += member_work(b->plans[i]->pl);
+      groups[k].push_back(i);
+    }
+    for (auto& g : groups) std::sort(g.begin(), g.end());
+  }
   struct Site {
     jgb::BatchLaunch f;
     int occ;
     std::vector<std::pair<int, int>> members;  // (member, record)
+    size_t toff = 0, boff = 0;
+    unsigned blocks = 0, threads = 0;
+    size_t smem = 0;
   };
-  std::vector<Site> sites;
-  for (int i = 0; i < nm; ++i) {
-    std::vector<std::pair<jgb::BatchLaunch, int>> seen;
-    int prev = -1;
-    for (int r = 0; r < (int)recs[i].size(); ++r) {
-      const jgb::BatchLaunch f = recs[i][r].launch;
-      int occ = 0;
-      for (auto& q : seen)
-        if (q.first == f) occ = ++q.second;
-      if (occ == 0) seen.push_back({f, 0});
-      int pos = -1;
-      for (int k = 0; k < (int)sites.size(); ++k)
-        if (sites[k].f == f && sites[k].occ == occ) pos = k;
-      if (pos < 0) {
-        pos = prev + 1;
-        sites.insert(sites.begin() + pos, Site{f, occ, {}});
-      } else if (pos <= prev) {
-        return report(JGB_ERR_UNSUPPORTED, "batch members' pipelines do not merge");
-      }
-      sites[pos].members.push_back({i, r});
-      prev = pos;
-    }
-  }
-  // argument tables and block offsets, 256-byte aligned, in one allocation
+  std::vector<std::vector<Site>> chains(nbr);
   std::vector<unsigned char> host;
-  std::vector<size_t> toff(sites.size()), boff(sites.size());
-  std::vector<unsigned> blocks(sites.size()), threads(sites.size());
-  std::vector<size_t> smem(sites.size());
   auto align = [&]() { host.resize((host.size() + 255) / 256 * 256, 0); };
-  for (size_t k = 0; k < sites.size(); ++k) {
-    align();
-    toff[k] = host.size();
-    unsigned nb = 0;
-    threads[k] = 0;
-    smem[k] = 0;
-    std::vector<int> bs;
-    for (auto& mr : sites[k].members) {
-      const jgb::LaunchRecord& r = recs[mr.first][mr.second];
-      host.insert(host.end(), r.args.begin(), r.args.end());
-      if (threads[k] && threads[k] != r.threads) return report(JGB_ERR_UNSUPPORTED, "batched launch block sizes differ");
-      threads[k] = r.threads;
-      smem[k] = std::max(smem[k], r.smem);
-      bs.push_back((int)nb);
-      nb += r.blocks;
+  for (int g = 0; g < nbr; ++g) {
+    std::vector<Site>& sites = chains[g];
+    for (int i : groups[g]) {
+      std::vector<std::pair<jgb::BatchLaunch, int>> seen;
+      int prev = -1;
+      for (int r = 0; r < (int)recs[i].size(); ++r) {
+        const jgb::BatchLaunch f = recs[i][r].launch;
+        int occ = 0;
+        for (auto& q : seen)
+          if (q.first == f) occ = ++q.second;
+        if (occ == 0) seen.push_back({f, 0});
+        int pos = -1;
+        for (int k = 0; k < (int)sites.size(); ++k)
+          if (sites[k].f == f && sites[k].occ == occ) pos = k;
+        if (pos < 0) {
+          pos = prev + 1;
+          sites.insert(sites.begin() + pos, Site{f, occ, {}});
+        } else if (pos <= prev) {
+          return report(JGB_ERR_UNSUPPORTED, "batch members' pipelines do not merge");
+        }
+        sites[pos].members.push_back({i, r});
+        prev = pos;
+      }
     }
-    bs.push_back((int)nb);
-    blocks[k] = nb;
-    align();
-    boff[k] = host.size();
-    const unsigned char* p = reinterpret_cast<const unsigned char*>(bs.data());
-    host.insert(host.end(), p, p + bs.size() * sizeof(int));
+    // argument tables and block offsets, 256-byte aligned, in one allocation:
+    // the members' first blocks (multiples of eight: each member keeps its
+    // blocks' places on the eight XCDs), then their block counts
+    for (Site& st : sites) {
+      align();
+      st.toff = host.size();
+      std::vector<int> bs, cnt;
+      unsigned nb = 0;
+      for (auto& mr : st.members) {
+        const jgb::LaunchRecord& r = recs[mr.first][mr.second];
+        host.insert(host.end(), r.args.begin(), r.args.end());
+        if (st.threads && st.threads != r.threads)
+          return report(JGB_ERR_UNSUPPORTED, "batched launch block sizes differ");
+        st.threads = r.threads;
+        st.smem = std::max(st.smem, r.smem);
+        bs.push_back((int)nb);
+        cnt.push_back((int)r.blocks);
+        nb += (r.blocks + 7) / 8 * 8;
+      }
+      bs.push_back((int)nb);
+      bs.insert(bs.end(), cnt.begin(), cnt.end());
+      st.blocks = nb;
+      align();
+      st.boff = host.size();
+      const unsigned char* p = reinterpret_cast<const unsigned char*>(bs.data());
+      host.insert(host.end(), p, p + bs.size() * sizeof(int));
+    }
   }
   hipError_t e = hipMalloc(&b->d_tables, std::max<size_t>(host.size(), 16));
   if (e != hipSuccess) {
@@ -460,22 +491,32 @@ static jgb_status bind_batched(jgb_batch_s* b, const void* const* rho, void* con
   hipStream_t origin = b->branches[0];
   e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return from_hip(e, "begin capture");
-  hipError_t ce = hipSuccess;
+  hipError_t ce = hipEventRecord(b->events[0], origin);
+  for (int k = 1; k < nbr && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branches[k], b->events[0], 0);
   const unsigned char* base = static_cast<const unsigned char*>(b->d_tables);
-  for (size_t k = 0; k < sites.size() && ce == hipSuccess; ++k)
-    ce = sites[k].f(base + toff[k], reinterpret_cast<const int*>(base + boff[k]), (int)sites[k].members.size(),
-                    blocks[k], threads[k], smem[k], origin);
-  hipGraph_t g = nullptr;
-  hipError_t ee = hipStreamEndCapture(origin, &g);
+  int nlaunch = 0;
+  for (int g = 0; g < nbr && ce == hipSuccess; ++g)
+    for (const Site& st : chains[g]) {
+      if (ce != hipSuccess) break;
+      ce = st.f(base + st.toff, reinterpret_cast<const int*>(base + st.boff), (int)st.members.size(), st.blocks,
+                st.threads, st.smem, b->branches[g]);
+      ++nlaunch;
+    }
+  for (int k = 1; k < nbr && ce == hipSuccess; ++k) {
+    ce = hipEventRecord(b->events[k], b->branches[k]);
+    if (ce == hipSuccess) ce = hipStreamWaitEvent(origin, b->events[k], 0);
+  }
+  hipGraph_t gr = nullptr;
+  hipError_t ee = hipStreamEndCapture(origin, &gr);
   if (ce != hipSuccess || ee != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
+    if (gr) (void)hipGraphDestroy(gr);
     (void)hipGetLastError();
     return from_hip(ce != hipSuccess ? ce : ee, "capture");
   }
-  b->graph = g;
-  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  b->graph = gr;
+  e = hipGraphInstantiate(&b->exec, gr, nullptr, nullptr, 0);
   if (e != hipSuccess) return from_hip(e, "graph instantiate");
-  b->nlaunch = (int)sites.size();
+  b->nlaunch = nlaunch;
   return JGB_OK;
 }
 
@@ -539,6 +580,7 @@ jgb_status jgb_batch_create(const jgb_params* params, int count, int nstreams, j
   b->events.pop_back();
   b->ev_out = b->events.back();
   b->events.pop_back();
+
   *out = b;
   return JGB_OK;
 }
@@ -558,9 +600,10 @@ jgb_status jgb_batch_bind(jgb_batch_t b, const void* const* rho, void* const* u,
   for (size_t k = 0; k < b->branches.size() && e == hipSuccess; ++k) e = hipStreamSynchronize(b->branches[k]);
   if (e != hipSuccess) return from_hip(e, "batch bind");
   release_graph(b);
-  // one launch per site over all members, unless a member runs Algorithm 2
-  // (its paired passes index blocks by the whole grid)
-  bool merged = true;
+  // With one stream: one launch per pipeline site over all members, unless a
+  // member runs Algorithm 2 (its paired passes index blocks by the whole
+  // grid).  With more: the members' own pipelines, spread over the streams.
+  bool merged = b->branches.size() == 1;
   for (int i = 0; i < count; ++i) merged &= !b->plans[i]->pl.split;
   if (merged) {
     jgb_status st = bind_batched(b, rho, u, energies);
@@ -575,10 +618,7 @@ jgb_status jgb_batch_bind(jgb_batch_t b, const void* const* rho, void* const* u,
   const int nbr = (int)b->branches.size();
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
-  auto work = [&](int i) {
-    const Plan& pl = b->plans[i]->pl;
-    return (double)pl.nf[0] * pl.nf[1] * pl.nf[2] + 8.0 * (double)pl.Mh * pl.width;
-  };
+  auto work = [&](int i) { return member_work(b->plans[i]->pl); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
   std::vector<double> load(nbr, 0.0);
   std::vector<std::vector<int>> members(nbr);

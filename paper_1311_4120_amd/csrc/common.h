@@ -246,7 +246,8 @@ __host__ __device__ inline T es_kernel(T x, T two_over_w, T beta) {
 // its members' records site by site and issues, for each site, one launch
 // whose blocks are the members' blocks in turn: block b belongs to the member
 // m with bstart[m] <= b < bstart[m + 1] and runs as that member's block
-// b - bstart[m], with the member's argument block from a device table.
+// b - bstart[m] (see batch_block), with the member's argument block from a
+// device table.
 
 typedef hipError_t (*BatchLaunch)(const void* table, const int* bstart, int nmembers, unsigned blocks,
                                   unsigned threads, size_t smem, hipStream_t s);
@@ -259,15 +260,21 @@ struct LaunchRecord {
 // the calling thread's open record (null: launches are issued)
 std::vector<LaunchRecord>*& launch_record();
 
-// the member of a batched launch that block b belongs to
-__device__ __forceinline__ int batch_member(const int* bstart, int nm, int b) {
+// The member m of a batched launch that block b belongs to, and b's block
+// within the member, or -1 for a padding block.  bstart holds the members'
+// first blocks (nm + 1 offsets, each a multiple of eight, so that every
+// member's blocks keep their place in the dispatch order across the eight
+// XCDs) and then the members' block counts.
+__device__ __forceinline__ int batch_block(const int* bstart, int nm, int b, int& m) {
   int lo = 0, hi = nm - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (bstart[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
-  return lo;
+  m = lo;
+  const int blk = b - bstart[lo];
+  return blk < bstart[nm + 1 + lo] ? blk : -1;
 }
 
 template <typename A, void (*KB)(const A*, const int*, int)>

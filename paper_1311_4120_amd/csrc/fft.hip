@@ -570,9 +570,11 @@ __global__ void __launch_bounds__(NT) k_fft_pass(PassArgs<T> a) {
   fft_pass_body<T, KIND, MAXV, NT>(a, blockIdx.x);
 }
 template <typename T, int KIND, int MAXV, int NT>
-__global__ void __launch_bounds__(NT) k_fft_pass_b(const PassArgs<T>* tab, const int* bstart, int nm) {
-  const int m = batch_member(bstart, nm, blockIdx.x);
-  fft_pass_body<T, KIND, MAXV, NT>(tab[m], blockIdx.x - bstart[m]);
+__global__ void __launch_bounds__(NT) k_fft_pass_b(const PassArgs<T>* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  const int blk = batch_block(bstart, nm, blockIdx.x, m);
+  if (blk < 0) return;
+  fft_pass_body<T, KIND, MAXV, NT>(tab[m], blk);
 }
 
 // Algorithm 2's paired passes along the last forward / first inverse axis.  A
@@ -1449,8 +1451,10 @@ __device__ __forceinline__ void origin_body(const OriginArgs& a) {
 }
 
 __global__ void __launch_bounds__(256) k_origin(OriginArgs a) { origin_body(a); }
-__global__ void __launch_bounds__(256) k_origin_b(const OriginArgs* tab, const int* bstart, int nm) {
-  origin_body(tab[batch_member(bstart, nm, blockIdx.x)]);
+__global__ void __launch_bounds__(256) k_origin_b(const OriginArgs* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  if (batch_block(bstart, nm, blockIdx.x, m) < 0) return;
+  origin_body(tab[m]);
 }
 
 hipError_t launch_origin(const Plan& pl, hipStream_t s) {

@@ -294,9 +294,11 @@ __global__ void __launch_bounds__(kInterpThreads) k_interp(InterpArgs<T> a) {
   interp_body<T, W, D3>(a, blockIdx.x);
 }
 template <typename T, int W, bool D3>
-__global__ void __launch_bounds__(kInterpThreads) k_interp_b(const InterpArgs<T>* tab, const int* bstart, int nm) {
-  const int m = batch_member(bstart, nm, blockIdx.x);
-  interp_body<T, W, D3>(tab[m], blockIdx.x - bstart[m]);
+__global__ void __launch_bounds__(kInterpThreads) k_interp_b(const InterpArgs<T>* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  const int blk = batch_block(bstart, nm, blockIdx.x, m);
+  if (blk < 0) return;
+  interp_body<T, W, D3>(tab[m], blk);
 }
 
 // ------------------------------------------------------------------ by tiles
@@ -473,9 +475,11 @@ __global__ void __launch_bounds__(256) k_interp_tile(TileArgs<T> a) {
   interp_tile_body<T, NOWRAP>(a, blockIdx.x);
 }
 template <typename T, bool NOWRAP>
-__global__ void __launch_bounds__(256) k_interp_tile_b(const TileArgs<T>* tab, const int* bstart, int nm) {
-  const int m = batch_member(bstart, nm, blockIdx.x);
-  interp_tile_body<T, NOWRAP>(tab[m], blockIdx.x - bstart[m]);
+__global__ void __launch_bounds__(256) k_interp_tile_b(const TileArgs<T>* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  const int blk = batch_block(bstart, nm, blockIdx.x, m);
+  if (blk < 0) return;
+  interp_tile_body<T, NOWRAP>(tab[m], blk);
 }
 
 template <typename T>
@@ -546,9 +550,11 @@ __global__ void __launch_bounds__(256) k_interp_reduce(ReduceArgs<T> a) {
   interp_reduce_body<T, LPN>(a, blockIdx.x);
 }
 template <typename T, int LPN>
-__global__ void __launch_bounds__(256) k_interp_reduce_b(const ReduceArgs<T>* tab, const int* bstart, int nm) {
-  const int m = batch_member(bstart, nm, blockIdx.x);
-  interp_reduce_body<T, LPN>(tab[m], blockIdx.x - bstart[m]);
+__global__ void __launch_bounds__(256) k_interp_reduce_b(const ReduceArgs<T>* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  const int blk = batch_block(bstart, nm, blockIdx.x, m);
+  if (blk < 0) return;
+  interp_reduce_body<T, LPN>(tab[m], blk);
 }
 
 template <typename T, int W>

@@ -84,10 +84,22 @@ std::vector<double> kernel_ft(int w, double beta, const std::vector<double>& xi)
   return out;
 }
 
+// Failure injection for tests of the out-of-memory path: with the environment
+// variable JGB_FAULT=alloc:K, the K-th device allocation of every plan fails
+// as if the device were out of memory (K >= 1).
+int injected_alloc_failure() {
+  const char* f = getenv("JGB_FAULT");
+  if (!f || strncmp(f, "alloc:", 6) != 0) return 0;
+  return atoi(f + 6);
+}
+
 template <typename Tp>
 Status dev_alloc(Plan& pl, Tp** ptr, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
+  const int fault = injected_alloc_failure();
+  if (fault > 0 && (int)pl.allocations.size() + 1 == fault)
+    return fail(JGB_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed (injected)");
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -895,6 +907,17 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   TRY(dev_alloc(pl, &pl.d_eparts, pl.ws_bytes[Plan::WS_EPARTS]));
   TRY_HIP(interp_prepare(pl), "interpolation LDS limit");
   if (p->flags & JGB_FLAG_AUTOTUNE) TRY(autotune(pl));
+  // JGB_LOG=1: one line per plan on stderr with the shape the plan chose
+  if (const char* lg = getenv("JGB_LOG")) {
+    if (lg[0] && lg[0] != '0')
+      fprintf(stderr,
+              "jgb plan: dim %d n %dx%dx%d nf %dx%dx%d nodes %lld (half %lld) width %d %s %s%s interp %s chunk %d "
+              "spread chunk %d tiles %d items %d list entries %lld workspace %.1f MB\n",
+              pl.dim, pl.n[0], pl.n[1], pl.n[2], pl.nf[0], pl.nf[1], pl.nf[2], (long long)pl.M, (long long)pl.Mh,
+              pl.width, pl.fp64 ? "fp64" : "mixed", pl.split ? "algorithm 2" : "algorithm 1",
+              pl.r2c ? " (half spectrum)" : "", pl.tile_interp ? "by tiles" : "staged", pl.interp_chunk,
+              pl.spread_chunk, pl.ngtiles, pl.nitems, (long long)pl.nlist, pl.workspace_bytes / 1e6);
+  }
   TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");
   TRY_HIP(hipGetLastError(), "plan kernels");
   return Status::ok();

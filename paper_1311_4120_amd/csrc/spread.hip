@@ -293,9 +293,11 @@ __global__ void __launch_bounds__(256) k_spread_gather(SpreadArgs<T> a) {
   gather_body<T, T1, NOWRAP>(a, blockIdx.x);
 }
 template <typename T, int T1, bool NOWRAP>
-__global__ void __launch_bounds__(256) k_spread_gather_b(const SpreadArgs<T>* tab, const int* bstart, int nm) {
-  const int m = batch_member(bstart, nm, blockIdx.x);
-  gather_body<T, T1, NOWRAP>(tab[m], blockIdx.x - bstart[m]);
+__global__ void __launch_bounds__(256) k_spread_gather_b(const SpreadArgs<T>* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  const int blk = batch_block(bstart, nm, blockIdx.x, m);
+  if (blk < 0) return;
+  gather_body<T, T1, NOWRAP>(tab[m], blk);
 }
 
 // Sum the partial tiles of each split tile in slot order and store the tile.
@@ -340,9 +342,11 @@ __device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs<T>& a,
 template <typename T>
 __global__ void __launch_bounds__(256) k_spread_reduce(SpreadReduceArgs<T> a) { spread_reduce_body<T>(a, blockIdx.x); }
 template <typename T>
-__global__ void __launch_bounds__(256) k_spread_reduce_b(const SpreadReduceArgs<T>* tab, const int* bstart, int nm) {
-  const int m = batch_member(bstart, nm, blockIdx.x);
-  spread_reduce_body<T>(tab[m], blockIdx.x - bstart[m]);
+__global__ void __launch_bounds__(256) k_spread_reduce_b(const SpreadReduceArgs<T>* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  const int blk = batch_block(bstart, nm, blockIdx.x, m);
+  if (blk < 0) return;
+  spread_reduce_body<T>(tab[m], blk);
 }
 
 struct FinalizeArgs {
@@ -372,8 +376,10 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs& a) {
 }
 
 __global__ void __launch_bounds__(256) k_energy_finalize(FinalizeArgs a) { finalize_body(a); }
-__global__ void __launch_bounds__(256) k_energy_finalize_b(const FinalizeArgs* tab, const int* bstart, int nm) {
-  finalize_body(tab[batch_member(bstart, nm, blockIdx.x)]);
+__global__ void __launch_bounds__(256) k_energy_finalize_b(const FinalizeArgs* __restrict__ tab, const int* __restrict__ bstart, int nm) {
+  int m;
+  if (batch_block(bstart, nm, blockIdx.x, m) < 0) return;
+  finalize_body(tab[m]);
 }
 
 }  // namespace
