@@ -33,11 +33,15 @@ LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12
 METRIC = "potential evals/s + ns/grid-pt at 128³: FP64 ε=1e-10 vs mixed FP32 ε=1e-5"
 
 
-def stage_work(info, prec, energy=True):
+def stage_work(info, prec, energy=True, half=True):
     """Algorithmic HBM bytes and flops of one launch of each stage.
 
-    FFT passes: input + output of the pass.  Tap kernels: one pass over the
-    oversampled grid (interpolation reads F, spreading writes G) and 5 flops
+    FFT passes: input + output of the pass.  For a real density (Algorithm 1)
+    the spectrum is kept on the Hermitian half h = f/2 + 1 of the lines along
+    the last axis (half=True): every pass but the inverse's first moves h/f of
+    the full-complex bytes, and that first pass reads all of G (each line and
+    its mirror).  Tap kernels: one pass over the oversampled grid
+    (interpolation reads the stored spectrum, spreading writes G) and 5 flops
     per tap (complex x real multiply-add + the weight product) over the w^3
     taps of every node the launch processes (the half set; the other half is
     its mirror image)."""
@@ -45,19 +49,20 @@ def stage_work(info, prec, energy=True):
     nf = info["nf"]
     N = n[0]
     f = nf[0]
+    h = f // 2 + 1 if half else f
     rb = 8 if prec == "fp64" else 4
     cb = 2 * rb
     w = info["width"]
     Mh = info["n_half"]
     N3, F3 = N ** 3, f ** 3
     by = {
-        "fwd_fft_z": N3 * rb + N * N * f * cb,
-        "fwd_fft_y": N * N * f * cb + N * f * f * cb,
-        "fwd_fft_x": N * f * f * cb + F3 * cb,
-        "inv_fft_x": F3 * cb + N * f * f * cb,
-        "inv_fft_y": N * f * f * cb + N * N * f * cb,
-        "inv_fft_z": N * N * f * cb + N3 * rb + (N3 * rb if energy else 0),
-        "interp": F3 * cb,
+        "fwd_fft_z": N3 * rb + N * N * h * cb,
+        "fwd_fft_y": N * N * h * cb + N * f * h * cb,
+        "fwd_fft_x": N * f * h * cb + f * f * h * cb,
+        "inv_fft_x": F3 * cb + N * f * h * cb,
+        "inv_fft_y": N * f * h * cb + N * N * h * cb,
+        "inv_fft_z": N * N * h * cb + N3 * rb + (N3 * rb if energy else 0),
+        "interp": f * f * h * cb,
         "spread": F3 * cb,
     }
     fl = {"interp": 5.0 * Mh * w ** 3, "spread": 5.0 * Mh * w ** 3}
@@ -494,6 +499,8 @@ def main():
                     d["bound"], d["frac"] = "lds", t_lds / (v * 1e-3)
         stages[k] = d
     total_bytes = sum(by.values())
+    # the full-complex model of the scope (no Hermitian halving), for comparison
+    full_bytes = sum(stage_work(r["info"], head, half=False)[0].values())
     out = {
         "metric": METRIC,
         "value": 1e3 / r["ms_per_step"],
@@ -518,6 +525,8 @@ def main():
         "autotuned": r["tuned"],
         "model_hbm_bytes_per_step": total_bytes,
         "model_hbm_frac": total_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "model_hbm_bytes_full_complex": full_bytes,
+        "model_hbm_frac_full_complex": full_bytes / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "stages": stages,
         "roofline": roof,
     }

@@ -203,8 +203,11 @@ __device__ __forceinline__ void gather_body(const SpreadArgs<T>& a, const int bl
       }
       __builtin_amdgcn_wave_barrier();
     }
+    // the groups of four that hold entries (the count is uniform over the wave)
+    const int ngq = min(4, (ke - g + 3) >> 2);
 #pragma unroll
     for (int gq = 0; gq < 4; ++gq) {
+      if (gq >= ngq) break;
       const int e = 4 * gq + lk;
       const int2 ent = ents[e];
       const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;

@@ -26,19 +26,28 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_work_model_bytes_and_flops():
-    by, fl = bench.stage_work(INFO64, "fp64")
     N, f, cb, rb = 128, 256, 16, 8
-    # forward X: the N-line input plane set in, the whole oversampled grid out
-    assert by["fwd_fft_x"] == N * f * f * cb + f ** 3 * cb
-    # last inverse pass: the N^2 f input lines, u out and rho in for the energy
-    assert by["inv_fft_z"] == N * N * f * cb + 2 * N ** 3 * rb
-    assert by["interp"] == by["spread"] == f ** 3 * cb
+    h = f // 2 + 1
+    full, _ = bench.stage_work(INFO64, "fp64", half=False)
+    # full complex: forward X takes the N-line plane set in, the whole
+    # oversampled grid out; the last inverse pass reads the N^2 f input lines
+    # and writes u, reading rho for the energy
+    assert full["fwd_fft_x"] == N * f * f * cb + f ** 3 * cb
+    assert full["inv_fft_z"] == N * N * f * cb + 2 * N ** 3 * rb
+    assert full["interp"] == full["spread"] == f ** 3 * cb
+    # about 56 N c_b + 2 N r_b with N the oversampled grid size over 8, 1.91 GB
+    assert 1.85e9 < sum(full.values()) < 1.95e9
+    by, fl = bench.stage_work(INFO64, "fp64")
+    # Hermitian half: the last axis keeps h = f/2 + 1 of its f lines, except in
+    # what spreading writes and the first inverse pass reads
+    assert by["fwd_fft_x"] == N * f * h * cb + f * f * h * cb
+    assert by["interp"] == f * f * h * cb and by["spread"] == f ** 3 * cb
+    assert by["inv_fft_x"] == f ** 3 * cb + N * f * h * cb
+    assert by["inv_fft_z"] == N * N * h * cb + 2 * N ** 3 * rb
     assert fl["interp"] == 5.0 * 524288 * 12 ** 3
-    # the whole path's HBM bytes: about 56 N c_b + 2 N r_b with N the oversampled
-    # grid size over 8, 1.91 GB at FP64 128^3
-    assert 1.85e9 < sum(by.values()) < 1.95e9
+    assert 1.2e9 < sum(by.values()) < 1.3e9
     by32, _ = bench.stage_work(INFO32, "mixed")
-    assert by32["interp"] == f ** 3 * 8
+    assert by32["interp"] == f * f * h * 8
 
 
 def test_roofline_picks_the_longer_bound():
@@ -50,9 +59,9 @@ def test_roofline_picks_the_longer_bound():
     assert r["frac"] == pytest.approx(r["achieved"] / 78.6)
     assert bench.roofline("spread", 0.44, by, fl, "fp64")["bound"] == "mfma"
     by32, fl32 = bench.stage_work(INFO32, "mixed")
-    r32 = bench.roofline("interp", 0.14, by32, fl32, "mixed")
+    r32 = bench.roofline("interp", 0.07, by32, fl32, "mixed")
     assert r32["bound"] == "hbm" and r32["unit"] == "GB/s"
-    assert r32["frac"] == pytest.approx(by32["interp"] / 0.14e-3 / 1e9 / 8000.0)
+    assert r32["frac"] == pytest.approx(by32["interp"] / 0.07e-3 / 1e9 / 8000.0)
     # LDS reads of the interpolation: one grid value per tap
     assert bench.lds_bytes(INFO64, "fp64") == 524288 * 12 ** 3 * 16
 
