@@ -121,6 +121,17 @@ typedef enum { JGB_THETA_GL = 0, JGB_COSTHETA_GL = 1 } jgb_theta_rule;
  * agree to rounding.  Costs one complex value and one index per list entry of
  * device memory. */
 #define JGB_FLAG_INTERP_TILES 4u
+/* Spread by rings (3D only, else UNSUPPORTED; also UNSUPPORTED when an
+ * oversampled side is shorter than its tile plus the width less one: 16 + w - 1
+ * on a0 and a2, 8 + w - 1 on a1).  The node set is the product r_a x theta_b
+ * x phi_l (Section 3.1), and the a2 coordinate r_a cos(theta_b) of a node does
+ * not depend on its azimuth: the type-1 front end first sums each ring's
+ * nodes over the two other axes on the matrix cores, then spreads each such
+ * ring sum along a2 once.  Without this flag the spreading sums every node
+ * over all three axes; with JGB_FLAG_AUTOTUNE alone the plan times both and
+ * keeps the faster.  Results agree to rounding.  Costs two index tables of
+ * about one entry per node and touched tile of device memory. */
+#define JGB_FLAG_SPREAD_RINGS 8u
 
 typedef struct jgb_plan_s* jgb_plan_t;
 
@@ -177,7 +188,9 @@ typedef struct {
   int64_t workspace_bytes; /* device memory owned by the plan */
   int32_t interp_chunk;    /* nodes per interpolation block at most; 0: the autotuner chose the
                               interpolation by tiles on the matrix cores */
-  int32_t spread_chunk;    /* list entries per spreading block at most */
+  int32_t spread_chunk;    /* list entries per spreading block at most; negative: the spreading
+                              by rings (JGB_FLAG_SPREAD_RINGS, or the autotuner's choice) with
+                              -spread_chunk node entries per block at most */
   uint32_t flags;          /* the plan's JGB_FLAG_* */
   double window[2];        /* JGB_FLAG_SPLIT: the window scales used (a, 0) or (R0, R1); else 0 */
   double origin_coef;      /* c_0 of the node at k = 0 (JGB_POISSON_2D; 0 for the others) */

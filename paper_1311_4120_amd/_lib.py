@@ -27,6 +27,7 @@ FP64, MIXED = 0, 1
 FLAG_AUTOTUNE = 1
 FLAG_SPLIT = 2
 FLAG_INTERP_TILES = 4
+FLAG_SPREAD_RINGS = 8
 THETA_GL, COSTHETA_GL = 0, 1
 
 

@@ -21,7 +21,8 @@ def _ptr(t):
 
 
 def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                 autotune=False, split=False, window=(0.0, 0.0), axis2=None, alpha=0.0, interp_tiles=False):
+                 autotune=False, split=False, window=(0.0, 0.0), axis2=None, alpha=0.0, interp_tiles=False,
+                 spread_rings=False):
     dim = len(n)
     kern = _KERNELS.get(kernel, kernel)
     rule = _RULES.get(theta_rule, theta_rule)
@@ -49,7 +50,7 @@ def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, k
     p.device = dev
     p.stream = ctypes.c_void_p(st.cuda_stream)
     p.flags = ((_lib.FLAG_AUTOTUNE if autotune else 0) | (_lib.FLAG_SPLIT if split else 0)
-               | (_lib.FLAG_INTERP_TILES if interp_tiles else 0))
+               | (_lib.FLAG_INTERP_TILES if interp_tiles else 0) | (_lib.FLAG_SPREAD_RINGS if spread_rings else 0))
     for i in range(2):
         p.window[i] = float(window[i]) if i < len(window) else 0.0
     for i in range(3):
@@ -72,6 +73,9 @@ class Plan:
                the nodes); then kmax is I2's cut-off and window the scales
                (3D: (a, 0); 2D: (R0, R1); zeros: the defaults)
     interp_tiles: interpolate by tiles on the matrix cores (3D)
+    spread_rings: spread ring by ring, each ring's nodes summed over the first
+               two axes on the matrix cores and the ring sums spread along
+               the last (3D)
     """
 
     def __init__(self, n: Sequence[int], box: Sequence[float], kernel, nodes: Sequence[int],
@@ -79,9 +83,10 @@ class Plan:
                  axis: Sequence[float] = (0.0, 0.0, 1.0), theta_rule="theta", kmax: float = 0.0,
                  device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, autotune: bool = False,
                  split: bool = False, window: Sequence[float] = (0.0, 0.0),
-                 axis2: Optional[Sequence[float]] = None, alpha: float = 0.0, interp_tiles: bool = False):
+                 axis2: Optional[Sequence[float]] = None, alpha: float = 0.0, interp_tiles: bool = False,
+                 spread_rings: bool = False):
         p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                                  autotune, split, window, axis2, alpha, interp_tiles)
+                                  autotune, split, window, axis2, alpha, interp_tiles, spread_rings)
         self._init_from(p, dev, st, box)
         h = ctypes.c_void_p()
         check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))

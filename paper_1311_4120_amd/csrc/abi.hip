@@ -794,7 +794,7 @@ jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info) {
   info->origin_coef = pl.c0;
   info->workspace_bytes = (int64_t)pl.workspace_bytes;
   info->interp_chunk = pl.tile_interp ? 0 : pl.interp_chunk;
-  info->spread_chunk = pl.spread_chunk;
+  info->spread_chunk = pl.ring_spread ? -pl.ring_chunk : pl.spread_chunk;
   return JGB_OK;
 }
 

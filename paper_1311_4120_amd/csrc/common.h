@@ -32,6 +32,17 @@ constexpr int kGatherZ = 8;
 // Offset added to the signed tile-relative footprint starts of the gather lists
 // (when the plan's grid needs no wrap-around, Plan::gather_nowrap).
 constexpr int kGatherBias = 512;
+// Output tile of the ring-factored gather (3D): a0 x a1 x a2 points.
+constexpr int kRingTile0 = 16;
+constexpr int kRingTile1 = 8;
+constexpr int kRingTile2 = 16;
+// Bits of a ring node entry's code beside its a0 and a1 start codes (10 bits
+// each): the entry is its ring's last in the tile, and then the a2 start code.
+constexpr int kRingEndBit = 20;
+constexpr int kRingZBit = 21;
+// Spare entries at the end of the ring node list (read by the prefetch of the
+// batch after the last).
+constexpr int kRingSpare = 32;
 // Per-node kernel values, tabulated at plan time: for each internal axis a,
 // the w values of its taps at [a (w + 1), a (w + 1) + w) of the node's record
 // followed by a zero (a unit axis has the single value 1 at tap 0 and zeros
@@ -74,6 +85,15 @@ struct WorkItem {
   int vbegin;  // range of the node list d_list handled by this item
   int vend;
   int slot;    // -1: write the tile to the grid; >= 0: write partial slot
+};
+
+// A work item of the spreading by rings: a tile (slot -1) or one of its
+// partial tiles (slot >= 0), and the node-entry ranges [e[w], e[w + 1]) of
+// the block's four wavefronts, each holding whole rings.
+struct RingItem {
+  int tile;
+  int slot;
+  int e[5];
 };
 
 enum Stage {
@@ -166,6 +186,31 @@ struct Plan {
   // d_nstart[j + 1])).
   bool tile_ok = false;        // the tables below are built (autotuned 3D plans)
   bool tile_interp = false;    // and the interpolation uses them
+
+  // Spreading by rings (3D): the nodes of one ring (r_a, theta_b) share their
+  // a2 footprint, so each tile of kRingTile0 x kRingTile1 x kRingTile2 points
+  // lists, ring by ring, the ring's nodes that touch the tile (d_rnodes: node
+  // and code = a0 start | a1 start << 10, each ring padded to whole groups of
+  // four with entries whose a0 values all vanish; the ring's last entry also
+  // carries kRingEndBit and its a2 start at kRingZBit; kRingSpare spare
+  // entries at the end).  Work items run over ranges of a tile's entries that
+  // hold whole rings; split tiles write partial tiles (d_partials) that
+  // d_rmulti sums.  The host keeps per tile its ring ranges (h_rcount into
+  // h_rcost, each ring's entry count, h_rfirst its first entry).
+  bool ring_ok = false;        // the ring tables are built
+  bool ring_spread = false;    // and the spreading uses them
+  int rnt[3] = {1, 1, 1};      // ring tiles per axis
+  int nrtiles = 0;
+  int2* d_rnodes = nullptr;
+  int64_t nrings_ent = 0, nrnodes = 0;
+  std::vector<int64_t> h_rcount;  // host: ring offsets per ring tile
+  std::vector<int> h_rcost;       // host: per ring of a tile, its node entries
+  std::vector<int> h_rfirst;      // host: per ring of a tile, its first node entry
+  RingItem* d_ritems = nullptr;
+  int nritems = 0, nrslots = 0, nrmulti = 0;
+  int* d_rmulti = nullptr;
+  int ritems_cap = 0, rmulti_cap = 0, rslots_cap = 0;
+  int ring_chunk = 8192;       // node entries per ring work item at most (tunable)
 
   // Hermitian half of the oversampled spectrum (Algorithm 1: rho and u are
   // real).  The forward FFT keeps only the lines q2 = 0 .. nf2/2 of axis 2
@@ -342,6 +387,8 @@ template <typename T>
 hipError_t launch_interp(const Plan& pl, InterpMode mode, void* out, hipStream_t s);
 template <typename T>
 hipError_t launch_spread(const Plan& pl, hipStream_t s);
+template <typename T>
+hipError_t launch_ring_spread(const Plan& pl, hipStream_t s);
 template <typename T>
 hipError_t launch_density(const Plan& pl, const void* psi, void* rho, hipStream_t s);
 template <typename T>

@@ -21,6 +21,10 @@ constexpr int kInterpChunks[] = {256, 512, 1024, 2048};
 constexpr int kSpreadChunks[] = {1024, 2048, 4096, 8192};
 // the autotuner's record of the interpolation by tiles in place of a chunk size
 constexpr int kTileInterp = -1;
+// node entries per work item of the ring-factored spreading (a ring entry
+// counts as kRingEntryCost node entries)
+constexpr int kRingChunks[] = {2048, 4096, 8192, 16384};
+constexpr int kRingEntryCost = 8;
 constexpr size_t kInterpLdsMax = kInterpLdsCap;
 
 bool is_235(int64_t n) {
@@ -230,6 +234,194 @@ void spread_items(const Plan& pl, int chunk, std::vector<WorkItem>& items, std::
                          WorkItem{-1, 0, 0, -1}, key);
 }
 
+// Work items of the spreading by rings: one per ring tile, tiles whose rings
+// cost more than chunk split at ring boundaries into items that write
+// partial tiles (cost: node entries plus kRingEntryCost per ring); each item's
+// rings are shared out among the block's four wavefronts in contiguous runs
+// of about equal cost.
+void ring_items(const Plan& pl, int chunk, std::vector<RingItem>& items, std::vector<int>& multi, int& nslots) {
+  items.clear();
+  multi.clear();
+  nslots = 0;
+  const std::vector<int64_t>& rc = pl.h_rcount;
+  std::vector<double> cum(pl.h_rcost.size() + 1, 0.0);
+  for (size_t i = 0; i < pl.h_rcost.size(); ++i) cum[i + 1] = cum[i] + pl.h_rcost[i] + kRingEntryCost;
+  auto entry = [&](int64_t r) {  // first node entry of ring r (r may be one past a tile's last)
+    return r < (int64_t)pl.h_rfirst.size() ? pl.h_rfirst[r] : pl.h_rfirst.back() + pl.h_rcost.back();
+  };
+  auto make = [&](int tile, int slot, int64_t s, int64_t t) {
+    RingItem it{tile, slot, {0, 0, 0, 0, 0}};
+    const double total = cum[t] - cum[s];
+    int64_t r = s;
+    it.e[0] = entry(s);
+    for (int w = 1; w < 4; ++w) {
+      while (r < t && cum[r] - cum[s] < w * total / 4) ++r;
+      it.e[w] = (r < t) ? entry(r) : pl.h_rfirst[t - 1] + pl.h_rcost[t - 1];
+    }
+    it.e[4] = pl.h_rfirst[t - 1] + pl.h_rcost[t - 1];
+    items.push_back(it);
+  };
+  for (int tile = 0; tile < pl.nrtiles; ++tile) {
+    const int64_t b = rc[tile], e = rc[tile + 1];
+    if (b == e) continue;  // stays zero (cleared at plan time)
+    if (cum[e] - cum[b] <= chunk) {
+      make(tile, -1, b, e);
+      continue;
+    }
+    const int first = nslots;
+    int64_t s = b;
+    while (s < e) {
+      int64_t t = s + 1;
+      while (t < e && cum[t + 1] - cum[s] <= chunk) ++t;
+      make(tile, nslots++, s, t);
+      s = t;
+    }
+    multi.push_back(tile);
+    multi.push_back(first);
+    multi.push_back(nslots - first);
+  }
+  const int n12 = pl.rnt[1] * pl.rnt[2];
+  auto key = [&](const RingItem& it) {
+    const int t0 = it.tile / n12, r = it.tile - t0 * n12, t1 = r / pl.rnt[2], t2 = r - t1 * pl.rnt[2];
+    return morton3(t0, t1, t2);
+  };
+  items = dispatch_order(items, [&](const RingItem& it) { return (double)(it.e[4] - it.e[0]); },
+                         RingItem{-1, -1, {0, 0, 0, 0, 0}}, key);
+}
+
+Status apply_ring_chunk(Plan& pl, int chunk) {
+  std::vector<RingItem> items;
+  std::vector<int> multi;
+  int nslots = 0;
+  ring_items(pl, chunk, items, multi, nslots);
+  if ((int)items.size() > pl.ritems_cap || (int)multi.size() > pl.rmulti_cap || nslots > pl.rslots_cap)
+    return fail(JGB_ERR_DEVICE, "ring items exceed capacity");
+  TRY(upload(pl, pl.d_ritems, items.data(), sizeof(RingItem) * items.size()));
+  if (!multi.empty()) TRY(upload(pl, pl.d_rmulti, multi.data(), sizeof(int) * multi.size()));
+  pl.nritems = (int)items.size();
+  pl.nrslots = nslots;
+  pl.nrmulti = (int)multi.size() / 3;
+  pl.ring_chunk = chunk;
+  return Status::ok();
+}
+
+// Node entries of the spreading by rings (Plan::d_rnodes) from the
+// bin-sorted nodes' natural half indices (perm) and footprint starts (hdr):
+// per ring tile, the rings that touch it in ring order, and per ring its
+// nodes that touch the tile, in sorted order.
+Status build_ring_lists(Plan& pl, const std::vector<int>& perm, const std::vector<int4>& hdr) {
+  const int RT[3] = {kRingTile0, kRingTile1, kRingTile2};
+  for (int a = 0; a < 3; ++a) pl.rnt[a] = (pl.nf[a] + RT[a] - 1) / RT[a];
+  pl.nrtiles = pl.rnt[0] * pl.rnt[1] * pl.rnt[2];
+  const int64_t Mh = pl.Mh;
+  const int nph2 = pl.n_phi / 2;
+  const int nrings = pl.n_r * pl.n_theta;
+  // the sorted nodes ring by ring
+  std::vector<int64_t> rstart(nrings + 1, 0);
+  for (int64_t j = 0; j < Mh; ++j) rstart[perm[j] / nph2 + 1]++;
+  for (int r = 0; r < nrings; ++r) rstart[r + 1] += rstart[r];
+  std::vector<int> byring(Mh);
+  {
+    std::vector<int64_t> fill(rstart.begin(), rstart.end() - 1);
+    for (int64_t j = 0; j < Mh; ++j) byring[fill[perm[j] / nph2]++] = (int)j;
+  }
+  auto touched = [&](int a, int x0, int* out) {
+    const int nf = pl.nf[a], T = RT[a], w = pl.w[a];
+    int n = 0;
+    for (int t = 0; t < w; ++t) {
+      const int tile = ((x0 + t) % nf) / T;
+      bool seen = false;
+      for (int i = 0; i < n; ++i) seen |= (out[i] == tile);
+      if (!seen) out[n++] = tile;
+    }
+    return n;
+  };
+  // a footprint start relative to a tile origin: its representative in
+  // [-(w - 1), T - 1] (nf >= T + w - 1 makes it unique), plus kGatherBias
+  auto code = [&](int a, int rel) {
+    const int nf = pl.nf[a];
+    int e = ((rel % nf) + nf) % nf;
+    if (e > RT[a] - 1) e -= nf;
+    return e + kGatherBias;
+  };
+  std::vector<int64_t> tcnt(pl.nrtiles + 1, 0);
+  int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
+  for (int64_t j = 0; j < Mh; ++j) {
+    const int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
+    for (int a0 = 0; a0 < nx; ++a0)
+      for (int a1 = 0; a1 < ny; ++a1)
+        for (int a2 = 0; a2 < nz; ++a2) tcnt[(tx[a0] * pl.rnt[1] + ty[a1]) * pl.rnt[2] + tz[a2] + 1]++;
+  }
+  for (int t = 0; t < pl.nrtiles; ++t) tcnt[t + 1] += tcnt[t];
+  const int64_t nent = tcnt[pl.nrtiles];
+  // per tile, its entries in ring order: node, ring, a0 | a1 codes
+  std::vector<int> enode(nent), ering(nent), ecode(nent);
+  {
+    std::vector<int64_t> fill(tcnt.begin(), tcnt.end() - 1);
+    for (int r = 0; r < nrings; ++r)
+      for (int64_t q = rstart[r]; q < rstart[r + 1]; ++q) {
+        const int j = byring[q];
+        const int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
+        for (int a0 = 0; a0 < nx; ++a0)
+          for (int a1 = 0; a1 < ny; ++a1)
+            for (int a2 = 0; a2 < nz; ++a2) {
+              const int tile = (tx[a0] * pl.rnt[1] + ty[a1]) * pl.rnt[2] + tz[a2];
+              const int64_t at = fill[tile]++;
+              enode[at] = j;
+              ering[at] = r;
+              ecode[at] = code(0, hdr[j].x - tx[a0] * RT[0]) | (code(1, hdr[j].y - ty[a1] * RT[1]) << 10);
+            }
+      }
+  }
+  // node entries, each ring's padded to whole groups of four with entries
+  // whose a0 start code (1023) leaves every a0 tap off the tile; the ring's
+  // last entry (a node of the ring: all share its a2 values) carries the end
+  // flag and the ring's a2 start code
+  const int kPad = 1023 | (1023 << 10);
+  std::vector<int2> rnodes;
+  rnodes.reserve(nent + nent / 4 + kRingSpare);
+  pl.h_rcount.assign(pl.nrtiles + 1, 0);
+  pl.h_rcost.clear();
+  pl.h_rfirst.clear();
+  for (int t = 0; t < pl.nrtiles; ++t) {
+    const int tz0 = t % pl.rnt[2];
+    for (int64_t i = tcnt[t]; i < tcnt[t + 1];) {
+      int64_t e = i;
+      while (e < tcnt[t + 1] && ering[e] == ering[i]) ++e;
+      const int j0 = enode[i];
+      const int64_t nb = (int64_t)rnodes.size();
+      for (int64_t q = i; q < e; ++q) rnodes.push_back(make_int2(enode[q], ecode[q]));
+      while ((rnodes.size() - nb) % 4) rnodes.push_back(make_int2(j0, kPad));
+      rnodes.back().y |= (1 << kRingEndBit) | (code(2, hdr[j0].z - tz0 * RT[2]) << kRingZBit);
+      if ((int64_t)rnodes.size() + kRingSpare >= ((int64_t)1 << 31))
+        return fail(JGB_ERR_UNSUPPORTED, "ring node lists too long");
+      pl.h_rfirst.push_back((int)nb);
+      pl.h_rcost.push_back((int)(rnodes.size() - nb));
+      i = e;
+    }
+    pl.h_rcount[t + 1] = (int64_t)pl.h_rcost.size();
+  }
+  for (int i = 0; i < kRingSpare; ++i) rnodes.push_back(make_int2(0, kPad));  // read by the last prefetch
+  pl.nrings_ent = (int64_t)pl.h_rcost.size();
+  pl.nrnodes = (int64_t)rnodes.size();
+  TRY(dev_alloc(pl, &pl.d_rnodes, sizeof(int2) * rnodes.size()));
+  TRY(upload(pl, pl.d_rnodes, rnodes.data(), sizeof(int2) * rnodes.size()));
+  // item tables large enough for every chunk candidate
+  std::vector<RingItem> items;
+  std::vector<int> multi;
+  int nslots = 0;
+  pl.ritems_cap = pl.rmulti_cap = pl.rslots_cap = 0;
+  for (int c : kRingChunks) {
+    ring_items(pl, c, items, multi, nslots);
+    pl.ritems_cap = std::max(pl.ritems_cap, (int)items.size());
+    pl.rmulti_cap = std::max(pl.rmulti_cap, (int)multi.size());
+    pl.rslots_cap = std::max(pl.rslots_cap, nslots);
+  }
+  TRY(dev_alloc(pl, &pl.d_ritems, sizeof(RingItem) * std::max(pl.ritems_cap, 1)));
+  TRY(dev_alloc(pl, &pl.d_rmulti, sizeof(int) * std::max(pl.rmulti_cap, 1)));
+  return Status::ok();
+}
+
 Status apply_interp_chunk(Plan& pl, int chunk) {
   std::vector<Plan::InterpItem> iit = interp_items(pl, chunk);
   if ((int)iit.size() > pl.iitems_cap) return fail(JGB_ERR_DEVICE, "interpolation items exceed capacity");
@@ -291,6 +483,7 @@ bool cache_lookup(const std::string& path, const std::string& key, int& ic, int&
   for (int c : kInterpChunks) ok_i |= (c == ic);
   ok_i |= ic == kTileInterp;
   for (int c : kSpreadChunks) ok_s |= (c == sc);
+  for (int c : kRingChunks) ok_s |= (-c == sc);  // spreading by rings
   return ok_i && ok_s;
 }
 
@@ -349,10 +542,14 @@ Status autotune(Plan& pl) {
   const std::string key = tune_key(pl);
   int ic = 0, sc = 0;
   const bool forced = (pl.p.flags & JGB_FLAG_INTERP_TILES) != 0;
-  if (path && cache_lookup(path, key, ic, sc) && (ic != kTileInterp || pl.tile_ok)) {
+  const bool forced_rings = (pl.p.flags & JGB_FLAG_SPREAD_RINGS) != 0;
+  if (path && cache_lookup(path, key, ic, sc) && (ic != kTileInterp || pl.tile_ok) && (sc > 0 || pl.ring_ok) &&
+      !(forced_rings && sc > 0)) {
     pl.tile_interp = forced || ic == kTileInterp;
     if (!pl.tile_interp) TRY(apply_interp_chunk(pl, ic));
-    TRY(apply_spread_chunk(pl, sc));
+    pl.ring_spread = sc < 0;
+    if (sc > 0) TRY(apply_spread_chunk(pl, sc));
+    else TRY(apply_ring_chunk(pl, -sc));
     return Status::ok();
   }
   // ordinary values on the grid: time on an all-zero oversampled grid
@@ -383,16 +580,41 @@ Status autotune(Plan& pl) {
   }
   double ms0;
   TRY(pl.fp64 ? time_stage<double>(pl, true, ms0) : time_stage<float>(pl, true, ms0));  // node values for spreading
-  for (int c : kSpreadChunks) {
-    TRY(apply_spread_chunk(pl, c));
-    double ms;
-    TRY(pl.fp64 ? time_stage<double>(pl, false, ms) : time_stage<float>(pl, false, ms));
-    if (ms < best_s) {
-      best_s = ms;
-      sc = c;
+  pl.ring_spread = false;
+  if (!forced_rings) {
+    for (int c : kSpreadChunks) {
+      TRY(apply_spread_chunk(pl, c));
+      double ms;
+      TRY(pl.fp64 ? time_stage<double>(pl, false, ms) : time_stage<float>(pl, false, ms));
+      if (ms < best_s) {
+        best_s = ms;
+        sc = c;
+      }
+    }
+    TRY(apply_spread_chunk(pl, sc));
+  }
+  if (pl.ring_ok) {
+    // the spreading by rings, each chunk, against the best of the above
+    pl.ring_spread = true;
+    int rc = 0;
+    double best_r = 1e30;
+    for (int c : kRingChunks) {
+      TRY(apply_ring_chunk(pl, c));
+      double ms;
+      TRY(pl.fp64 ? time_stage<double>(pl, false, ms) : time_stage<float>(pl, false, ms));
+      if (ms < best_r) {
+        best_r = ms;
+        rc = c;
+      }
+    }
+    TRY(apply_ring_chunk(pl, rc));
+    if (best_r < best_s || forced_rings) {
+      best_s = best_r;
+      sc = -rc;
+    } else {
+      pl.ring_spread = false;
     }
   }
-  TRY(apply_spread_chunk(pl, sc));
   if (path) cache_store(path, key, ic, sc, best_i, best_s);
   return Status::ok();
 }
@@ -444,10 +666,12 @@ Status validate(const jgb_params* p) {
   double kn = M_PI / hmax;
   if (!(std::isfinite(p->kmax) && p->kmax >= 0)) return fail(JGB_ERR_INVALID_ARG, "kmax must be finite and >= 0");
   if (p->kmax > kn * (1 + 1e-12)) return fail(JGB_ERR_INVALID_ARG, "kmax must not exceed pi / max_j h_j");
-  if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT | JGB_FLAG_INTERP_TILES))
+  if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT | JGB_FLAG_INTERP_TILES | JGB_FLAG_SPREAD_RINGS))
     return fail(JGB_ERR_INVALID_ARG, "unknown flags");
   if ((p->flags & JGB_FLAG_INTERP_TILES) && p->dim != 3)
     return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_INTERP_TILES needs dim == 3");
+  if ((p->flags & JGB_FLAG_SPREAD_RINGS) && p->dim != 3)
+    return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_SPREAD_RINGS needs dim == 3");
   for (int i = 0; i < 2; ++i)
     if (!std::isfinite(p->window[i])) return fail(JGB_ERR_INVALID_ARG, "window must be finite");
   if (!(p->flags & JGB_FLAG_SPLIT)) {
@@ -792,6 +1016,17 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   pl.nlist = nlist;
 
   pl.h_tcount = tcount;
+  // the ring tables (3D; built when forced or for the tuner to time)
+  {
+    const bool forced = (p->flags & JGB_FLAG_SPREAD_RINGS) != 0;
+    bool fits = pl.dim == 3;
+    const int RT[3] = {kRingTile0, kRingTile1, kRingTile2};
+    for (int a = 0; a < 3; ++a) fits &= pl.nf[a] >= RT[a] + pl.w[a] - 1;
+    if (forced && !fits)
+      return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_SPREAD_RINGS needs every oversampled side >= tile + width - 1");
+    pl.ring_ok = fits && (p->flags & (JGB_FLAG_AUTOTUNE | JGB_FLAG_SPREAD_RINGS));
+    if (pl.ring_ok) TRY(build_ring_lists(pl, perm, hdr));
+  }
   {
     std::vector<WorkItem> items;
     std::vector<int> multi;
@@ -810,9 +1045,23 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     }
     TRY(dev_alloc(pl, &pl.d_items, sizeof(WorkItem) * std::max(pl.items_cap, 1)));
     TRY(dev_alloc(pl, &pl.d_multi, sizeof(int) * std::max(pl.multi_cap, 1)));
-    pl.ws_bytes[Plan::WS_PARTIALS] = (size_t)std::max(pl.slots_cap, 1) * 64 * kGatherZ * 2 * pl.real_bytes;
+    pl.ws_bytes[Plan::WS_PARTIALS] = std::max((size_t)std::max(pl.slots_cap, 1) * 64 * kGatherZ,
+                                              (size_t)pl.rslots_cap * kRingTile0 * kRingTile1 * kRingTile2) *
+                                     2 * pl.real_bytes;
     TRY(dev_alloc(pl, &pl.d_partials, pl.ws_bytes[Plan::WS_PARTIALS]));
     TRY(apply_spread_chunk(pl, pl.spread_chunk));
+    if (pl.ring_ok) {
+      // the untuned ring chunk: halved while a launch would have fewer than
+      // two work items per CU
+      std::vector<RingItem> ritems;
+      while (pl.ring_chunk > kRingChunks[0]) {
+        ring_items(pl, pl.ring_chunk, ritems, multi, nslots);
+        if ((int)ritems.size() >= fill_items) break;
+        pl.ring_chunk /= 2;
+      }
+      TRY(apply_ring_chunk(pl, pl.ring_chunk));
+      pl.ring_spread = (p->flags & JGB_FLAG_SPREAD_RINGS) != 0;
+    }
   }
 
   // FFT twiddles and deconvolution factors per axis
@@ -916,7 +1165,9 @@ Status build_plan(Plan& pl, const jgb_params* p) {
               pl.dim, pl.n[0], pl.n[1], pl.n[2], pl.nf[0], pl.nf[1], pl.nf[2], (long long)pl.M, (long long)pl.Mh,
               pl.width, pl.fp64 ? "fp64" : "mixed", pl.split ? "algorithm 2" : "algorithm 1",
               pl.r2c ? " (half spectrum)" : "", pl.tile_interp ? "by tiles" : "staged", pl.interp_chunk,
-              pl.spread_chunk, pl.ngtiles, pl.nitems, (long long)pl.nlist, pl.workspace_bytes / 1e6);
+              pl.ring_spread ? -pl.ring_chunk : pl.spread_chunk, pl.ring_spread ? pl.nrtiles : pl.ngtiles,
+              pl.ring_spread ? pl.nritems : pl.nitems, (long long)(pl.ring_spread ? pl.nrnodes : pl.nlist),
+              pl.workspace_bytes / 1e6);
   }
   TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");
   TRY_HIP(hipGetLastError(), "plan kernels");

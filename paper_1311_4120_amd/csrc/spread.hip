@@ -409,6 +409,7 @@ int gather_lds_stride(int rstride) {
 
 template <typename T>
 hipError_t launch_spread(const Plan& pl, hipStream_t s) {
+  if (pl.ring_spread) return launch_ring_spread<T>(pl, s);
   SpreadArgs<T> a{};
   a.nf0 = pl.nf[0];
   a.nf1 = pl.nf[1];

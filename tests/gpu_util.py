@@ -12,6 +12,13 @@ def say(*a):
     sys.stdout.flush()
 
 
+# the plan's tap-kernel forms: the staged interpolation and the gather over
+# all three axes (the defaults), the interpolation by tiles, the spreading by
+# rings, and both
+MODES = {"staged": {}, "tiles": {"interp_tiles": True}, "rings": {"spread_rings": True},
+         "tiles+rings": {"interp_tiles": True, "spread_rings": True}}
+
+
 def make_plan(problem, **kw):
     import paper_1311_4120_amd as jgb
     nodes = (problem.n_r, problem.n_theta, problem.n_phi) if problem.dim == 3 else (problem.n_r, problem.n_phi)

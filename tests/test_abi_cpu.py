@@ -112,8 +112,9 @@ BAD = [
     ("odd n_phi", dict(n_phi=7), 1),
     ("theta rule", dict(theta_rule=5), 1),
     ("kmax too large", dict(kmax=100.0), 1),
-    ("flags", dict(flags=8), 1),
+    ("flags", dict(flags=16), 1),
     ("interp tiles in 2D", dict(flags=4, dim=2, kernel=1), 2),
+    ("spread rings in 2D", dict(flags=8, dim=2, kernel=1), 2),
     ("window without split", dict(window=(1.0, 0.0)), 1),
     ("window nan", dict(flags=2, window=(float("nan"), 0.0)), 1),
     ("3D window[1]", dict(flags=2, window=(1.0, 2.0)), 1),

@@ -23,8 +23,9 @@ def test_autotune_and_cache(prec, tmp_path, monkeypatch):
     tuned = make_plan(p, autotune=True)
     ic, sc = tuned.info["interp_chunk"], tuned.info["spread_chunk"]
     say("   chose interp %d spread %d" % (ic, sc))
-    # 0: the interpolation by tiles on the matrix cores was faster
-    assert ic in (0, 256, 512, 1024, 2048) and sc in (1024, 2048, 4096, 8192)
+    # 0: the interpolation by tiles on the matrix cores was faster; a negative
+    # spread chunk: the spreading by rings was
+    assert ic in (0, 256, 512, 1024, 2048) and sc in (1024, 2048, 4096, 8192, -2048, -4096, -8192, -16384)
     data = json.loads(cache.read_text())
     assert len(data) == 1
     entry = next(iter(data.values()))

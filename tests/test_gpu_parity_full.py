@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import load_sampled, make_plan, rel_l2, sampled_errors, say
+from gpu_util import MODES, load_sampled, make_plan, rel_l2, sampled_errors, say
 
 pytestmark = pytest.mark.gpu
 import torch  # noqa: E402
@@ -77,20 +77,20 @@ def _c3_oracle():
     return _C3
 
 
-@pytest.mark.parametrize("tiles", [False, True])
+@pytest.mark.parametrize("mode", ["staged", "tiles", "rings", "tiles+rings"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_dipole3d_128_headline_sampled(prec, tiles):
+def test_dipole3d_128_headline_sampled(prec, mode):
     """u at 4096 points of a random sub-lattice, the three axis lines through
     (64, 64, 64) and 512 random points; E both ways; the transform at all
-    524 288 half-set nodes; with the staged interpolation and by tiles."""
+    524 288 half-set nodes; with each form of the tap kernels."""
     say("dipole3d_128: oracle at all nodes (separable regrouping) + stored sampled u")
     o = _c3_oracle()
     ref = load_sampled("dipole3d_128")
     assert abs(ref["energy"] / o["E"] - 1) < 1e-13
     p = o["p"]
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("dipole3d_128", prec, "tiles" if tiles else "staged")
-    plan = make_plan(p, eps=eps, precision=prec, interp_tiles=tiles)
+    say("dipole3d_128", prec, mode)
+    plan = make_plan(p, eps=eps, precision=prec, **MODES[mode])
     dt = torch.float64 if prec == "fp64" else torch.float32
     rt = torch.tensor(o["rho"], dtype=dt, device="cuda")
     u, E = plan.potential(rt)
@@ -112,14 +112,14 @@ def test_dipole3d_128_headline_sampled(prec, tiles):
     plan.close()
 
 
-@pytest.mark.parametrize("tiles", [False, True])
+@pytest.mark.parametrize("mode", ["staged", "tiles+rings"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_full_size_properties(prec, tiles):
+def test_full_size_properties(prec, mode):
     """Properties that hold at any size: A symmetric, linear, backward == A, energy identity."""
     p, rho = wl.dipole3d_128()
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("properties dipole3d_128", prec, "tiles" if tiles else "staged")
-    plan = make_plan(p, eps=eps, precision=prec, interp_tiles=tiles)
+    say("properties dipole3d_128", prec, mode)
+    plan = make_plan(p, eps=eps, precision=prec, **MODES[mode])
     dt = torch.float64 if prec == "fp64" else torch.float32
     g = torch.Generator(device="cpu").manual_seed(5)
     r1 = torch.randn(p.n, generator=g, dtype=torch.float64).to(dt).cuda()

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import half_index, make_plan, rel_l2, say
+from gpu_util import MODES, half_index, make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 
@@ -48,20 +48,21 @@ def test_nodes_match_oracle(name):
     plan.close()
 
 
-# (name, interpolation by tiles on the matrix cores): every case with the
-# staged interpolation, the 3D cases also by tiles
-VARIANTS = [(n, False) for n in CASES] + [(n, True) for n in CASES if CASES[n].dim == 3]
+# (name, tap-kernel forms): every case with the staged interpolation and the
+# three-axis gather, the 3D cases also with the interpolation by tiles and
+# with the spreading by rings
+VARIANTS = [(n, "staged") for n in CASES] + [(n, m) for n in CASES if CASES[n].dim == 3 for m in ("tiles", "rings")]
 
 
-@pytest.mark.parametrize("name,tiles", VARIANTS)
+@pytest.mark.parametrize("name,mode", VARIANTS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_transform_matches_oracle(name, tiles, prec):
+def test_transform_matches_oracle(name, mode, prec):
     p = CASES[name]
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("transform", name, prec, "tiles" if tiles else "staged")
+    say("transform", name, prec, mode)
     rho = _rho(p)
     dt = torch.float64 if prec == "fp64" else torch.float32
-    plan = make_plan(p, eps=eps, precision=prec, interp_tiles=tiles)
+    plan = make_plan(p, eps=eps, precision=prec, **MODES[mode])
     got = plan.transform(torch.tensor(rho, dtype=dt, device="cuda")).cpu().numpy()
     ko, Wo = oracle.fourier_nodes(p)
     rho_in = rho if prec == "fp64" else rho.astype(np.float32).astype(np.float64)
@@ -72,15 +73,15 @@ def test_transform_matches_oracle(name, tiles, prec):
     plan.close()
 
 
-@pytest.mark.parametrize("name,tiles", VARIANTS)
+@pytest.mark.parametrize("name,mode", VARIANTS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_potential_and_energy_match_oracle(name, tiles, prec):
+def test_potential_and_energy_match_oracle(name, mode, prec):
     p = CASES[name]
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("potential", name, prec, "tiles" if tiles else "staged")
+    say("potential", name, prec, mode)
     rho = _rho(p)
     dt = torch.float64 if prec == "fp64" else torch.float32
-    plan = make_plan(p, eps=eps, precision=prec, interp_tiles=tiles)
+    plan = make_plan(p, eps=eps, precision=prec, **MODES[mode])
     rt = torch.tensor(rho, dtype=dt, device="cuda")
     u, E = plan.potential(rt)
     Ef = plan.energy(rt)
