@@ -79,7 +79,7 @@ def lds_bytes(info, prec):
 # summary in profiles/ is used only while these files are unchanged.
 STAGE_SOURCES = {
     "interp": ["paper_1311_4120_amd/csrc/interp.hip"],
-    "spread": ["paper_1311_4120_amd/csrc/spread.hip"],
+    "spread": ["paper_1311_4120_amd/csrc/spread.hip", "paper_1311_4120_amd/csrc/ring.hip"],
 }
 TRAFFIC_SOURCES_COMMON = ["paper_1311_4120_amd/csrc/plan.hip", "paper_1311_4120_amd/csrc/common.h",
                           "paper_1311_4120_amd/csrc/nodes.hip"]

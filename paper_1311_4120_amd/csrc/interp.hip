@@ -364,7 +364,8 @@ __device__ __forceinline__ V tload(const void* base, uint32_t byte_off) {
 
 constexpr int kTileWaves = 4;
 
-template <typename T, bool NOWRAP>
+// NF: 16-byte pieces of a record each lane fetches, ceil(record pieces / 4).
+template <typename T, bool NOWRAP, int NF>
 __device__ __forceinline__ void interp_tile_body(const TileArgs<T>& a, const int blk) {
   typedef typename TileMfma<T>::acc_t acc_t;
   extern __shared__ unsigned char smem_raw[];
@@ -418,22 +419,39 @@ __device__ __forceinline__ void interp_tile_body(const TileArgs<T>& a, const int
   const uint32_t rbytes = (uint32_t)(a.rstride * sizeof(T));
   const T* myrec = recs + j16 * a.lstride;
   const int vb = item.vbegin, ve = item.vend;
-  for (int g0 = vb + 16 * wave; g0 < ve; g0 += 16 * kTileWaves) {
+  // node j16's record reaches the wave's LDS through registers, one group
+  // ahead: the four lanes of the node take every fourth 16-byte piece
+  // (coalesced runs instead of one scattered load per kernel value) while the
+  // group before is computed; the list entries come one group further ahead
+  uint4 pre[NF];
+  int g0 = vb + 16 * wave;
+  int2 entc = tload<int2>(a.list, (uint32_t)min(g0 + j16, ve - 1) * 8u);
+#define JGB_TILE_FETCH()                                                                                     \
+  do {                                                                                                       \
+    const uint32_t rec_ = (uint32_t)entc.x * rbytes;                                                         \
+    _Pragma("unroll") for (int m = 0; m < NF; ++m) {                                                         \
+      const int c = k4 + 4 * m;                                                                              \
+      pre[m] = c < nchunk ? tload<uint4>(a.wts, rec_ + (uint32_t)c * 16u) : uint4{0u, 0u, 0u, 0u};           \
+    }                                                                                                        \
+  } while (0)
+  if (g0 < ve) JGB_TILE_FETCH();
+  int2 entn = tload<int2>(a.list, (uint32_t)min(g0 + 16 * kTileWaves + j16, ve - 1) * 8u);
+  for (; g0 < ve; g0 += 16 * kTileWaves) {
     const int idx = g0 + j16;
     const bool valid = idx < ve;
-    const int2 ent = tload<int2>(a.list, (uint32_t)(valid ? idx : ve - 1) * 8u);
+    const int2 ent = entc;
     const int ex = ent.y & 1023, ey = (ent.y >> 10) & 1023, ez = (ent.y >> 20) & 1023;
-    // copy node j16's record into the wave's LDS: the four lanes of the node
-    // take every fourth 16-byte piece (coalesced runs instead of one scattered
-    // load per kernel value)
-    {
-      const uint32_t rec = (uint32_t)ent.x * rbytes;
-      __builtin_amdgcn_wave_barrier();  // the previous group's reads are done
-      for (int c = k4; c < nchunk; c += 4) {
-        const uint4 v = tload<uint4>(a.wts, rec + (uint32_t)c * 16u);
-        *reinterpret_cast<uint4*>(recs + j16 * a.lstride + c * kChunk) = v;
-      }
-      __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_wave_barrier();  // the previous group's reads are done
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const int c = k4 + 4 * m;
+      if (c < nchunk) *reinterpret_cast<uint4*>(recs + j16 * a.lstride + c * kChunk) = pre[m];
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (g0 + 16 * kTileWaves < ve) {
+      entc = entn;
+      JGB_TILE_FETCH();
+      entn = tload<int2>(a.list, (uint32_t)min(g0 + 32 * kTileWaves + j16, ve - 1) * 8u);
     }
     // node j16's kernel values at the tile's 8 x, the lane's 2 y and the z of
     // its result registers; taps outside the footprint read the zero after
@@ -468,18 +486,35 @@ __device__ __forceinline__ void interp_tile_body(const TileArgs<T>& a, const int
     im += __shfl_xor(im, 32, 64);
     if (k4 == 0 && valid) a.ipart[idx] = C2<T>{re, im};
   }
+#undef JGB_TILE_FETCH
 }
 
-template <typename T, bool NOWRAP>
+template <typename T, bool NOWRAP, int NF>
 __global__ void __launch_bounds__(256) k_interp_tile(TileArgs<T> a) {
-  interp_tile_body<T, NOWRAP>(a, blockIdx.x);
+  interp_tile_body<T, NOWRAP, NF>(a, blockIdx.x);
 }
-template <typename T, bool NOWRAP>
+template <typename T, bool NOWRAP, int NF>
 __global__ void __launch_bounds__(256) k_interp_tile_b(const TileArgs<T>* __restrict__ tab, const int* __restrict__ bstart, int nm) {
   int m;
   const int blk = batch_block(bstart, nm, blockIdx.x, m);
   if (blk < 0) return;
-  interp_tile_body<T, NOWRAP>(tab[m], blk);
+  interp_tile_body<T, NOWRAP, NF>(tab[m], blk);
+}
+
+template <typename T, bool NOWRAP>
+hipError_t launch_tile_kernel(const TileArgs<T>& a, unsigned blocks, size_t smem, hipStream_t s) {
+  const int nf = (a.rstride * (int)sizeof(T) / 16 + 3) / 4;
+  typedef TileArgs<T> A;
+  switch (nf) {
+    case 1:
+    case 2: return launch<A, k_interp_tile<T, NOWRAP, 2>, k_interp_tile_b<T, NOWRAP, 2>>(a, blocks, 256, smem, s);
+    case 3: return launch<A, k_interp_tile<T, NOWRAP, 3>, k_interp_tile_b<T, NOWRAP, 3>>(a, blocks, 256, smem, s);
+    case 4: return launch<A, k_interp_tile<T, NOWRAP, 4>, k_interp_tile_b<T, NOWRAP, 4>>(a, blocks, 256, smem, s);
+    case 5: return launch<A, k_interp_tile<T, NOWRAP, 5>, k_interp_tile_b<T, NOWRAP, 5>>(a, blocks, 256, smem, s);
+    case 6: return launch<A, k_interp_tile<T, NOWRAP, 6>, k_interp_tile_b<T, NOWRAP, 6>>(a, blocks, 256, smem, s);
+    case 7: return launch<A, k_interp_tile<T, NOWRAP, 7>, k_interp_tile_b<T, NOWRAP, 7>>(a, blocks, 256, smem, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
@@ -638,11 +673,8 @@ hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipSt
   stage_mark(pl, ST_INTERP, 0, s);
   if (pl.nitems > 0) {
     const size_t smem = (size_t)kTileWaves * 16 * a.lstride * sizeof(T);
-    const hipError_t e =
-        pl.gather_nowrap
-            ? launch<TileArgs<T>, k_interp_tile<T, true>, k_interp_tile_b<T, true>>(a, (unsigned)pl.nitems, 256, smem, s)
-            : launch<TileArgs<T>, k_interp_tile<T, false>, k_interp_tile_b<T, false>>(a, (unsigned)pl.nitems, 256, smem,
-                                                                                      s);
+    const hipError_t e = pl.gather_nowrap ? launch_tile_kernel<T, true>(a, (unsigned)pl.nitems, smem, s)
+                                          : launch_tile_kernel<T, false>(a, (unsigned)pl.nitems, smem, s);
     if (e != hipSuccess) return e;
   }
   ReduceArgs<T> r{};

@@ -17,7 +17,7 @@ import pytest
 import oracle
 import workloads as wl
 from oracle import split
-from gpu_util import half_index, make_plan, rel_l2, say
+from gpu_util import MODES, half_index, make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 import torch  # noqa: E402
@@ -71,23 +71,31 @@ def _oracle(name):
     return _REF[name]
 
 
-def _plan(p, window, eps, prec, tiles=False):
-    return make_plan(p, eps=eps, precision=prec, split=True, window=window or (0.0, 0.0), interp_tiles=tiles)
+def _plan(p, window, eps, prec, mode="staged"):
+    return make_plan(p, eps=eps, precision=prec, split=True, window=window or (0.0, 0.0), **MODES[mode])
 
 
-# every case with the staged interpolation; the 3D ones also by tiles on the matrix cores
-VARIANTS = [(n, False) for n in CASES] + [(n, True) for n in CASES if CASES[n][0].dim == 3]
+def _rings_fit(p):
+    # the spreading by rings needs every oversampled side >= its tile (16, 8,
+    # 16) + w - 1, w = 12 at eps = 1e-10
+    return p.dim == 3 and 2 * p.n[0] >= 27 and 2 * p.n[1] >= 19 and 2 * p.n[2] >= 27
+
+
+# every case with the staged interpolation and the three-axis gather; the 3D
+# ones also with the interpolation by tiles, and with the spreading by rings
+# where their grids allow it
+VARIANTS = ([(n, "staged") for n in CASES] + [(n, "tiles") for n in CASES if CASES[n][0].dim == 3]
+            + [(n, "rings") for n in CASES if _rings_fit(CASES[n][0])])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("name,tiles", VARIANTS)
-def test_split_matches_oracle(name, tiles, prec):
+@pytest.mark.parametrize("name,mode", VARIANTS)
+def test_split_matches_oracle(name, mode, prec):
     p, window = CASES[name]
     rho, par, u_ref, E_ref = _oracle(name)
     eps = 1e-10 if prec == "fp64" else 1e-5
-    say("split", name, prec, "grid", p.n, "nodes", (p.n_r, p.n_theta, p.n_phi), "window", par,
-        "tiles" if tiles else "staged")
-    plan = _plan(p, window, eps, prec, tiles)
+    say("split", name, prec, "grid", p.n, "nodes", (p.n_r, p.n_theta, p.n_phi), "window", par, mode)
+    plan = _plan(p, window, eps, prec, mode)
     K2 = p.kmax if p.kmax > 0 else split.default_cutoff(p.n, p.box, par)
     assert plan.info["kmax"] == pytest.approx(K2, rel=1e-14)
     want = (par["a"], 0.0) if p.dim == 3 else (par["R0"], par["R1"])

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from gpu_util import make_plan, rel_l2, say
+from gpu_util import MODES, make_plan, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 import torch  # noqa: E402
@@ -32,15 +32,15 @@ def _noalloc(plan, rho, u, E):
                                           ctypes.c_void_p(E.data_ptr()))
 
 
-@pytest.mark.parametrize("tiles", [False, True])
+@pytest.mark.parametrize("mode", ["staged", "tiles+rings"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_noalloc_equals_potential(prec, tiles):
+def test_noalloc_equals_potential(prec, mode):
     from paper_1311_4120_amd import _lib
     dt = torch.float64 if prec == "fp64" else torch.float32
     for n in (48, 24):   # the second call is smaller: the array holds the first call's values
         p, rho = _problem(n, prec)
-        say("noalloc", prec, n, "tiles" if tiles else "staged")
-        plan = make_plan(p, interp_tiles=tiles)
+        say("noalloc", prec, n, mode)
+        plan = make_plan(p, **MODES[mode])
         rt = torch.tensor(rho, dtype=dt, device="cuda")
         u_ref, E_ref = plan.potential(rt)
         u = torch.full_like(rt, float("nan"))
