@@ -94,10 +94,21 @@ def sources_sha1(stage):
     return h.hexdigest()
 
 
-def measured_traffic(stage, prec):
+def kernel_form(stage, tuned):
+    """The form of the stage's kernel the plan chose: the interpolation by
+    tiles or staged, the spreading by rings or the three-axis gather."""
+    if stage == "interp":
+        return "tiles" if tuned["interp_chunk"] == 0 else "staged"
+    if stage == "spread":
+        return "rings" if tuned["spread_chunk"] < 0 else "gather"
+    return None
+
+
+def measured_traffic(stage, prec, form=None):
     """HBM bytes per launch of the stage's kernel from the committed PMC
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or
-    None when there is none or the kernel sources changed since."""
+    None when there is none, the kernel sources changed since, or the summary
+    measured another form of the kernel than `form`."""
     if stage not in STAGE_SOURCES:
         return None
     path = os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md" % (stage, prec))
@@ -106,10 +117,12 @@ def measured_traffic(stage, prec):
     vals = {}
     with open(path) as f:
         for line in f:
-            for key in ("traffic_bytes_per_launch:", "sources_sha1:"):
+            for key in ("traffic_bytes_per_launch:", "sources_sha1:", "kernel_form:"):
                 if line.strip().startswith(key):
                     vals[key] = line.split(":", 1)[1].strip()
     if vals.get("sources_sha1:") != sources_sha1(stage) or "traffic_bytes_per_launch:" not in vals:
+        return None
+    if form is not None and vals.get("kernel_form:") != form:
         return None
     return int(vals["traffic_bytes_per_launch:"])
 
@@ -479,7 +492,8 @@ def main():
     st = r["stages_ms"]
     dom = max((k for k in st if st[k] > 0), key=lambda k: st[k])
     roof = roofline(dom, st[dom], by, fl, head)
-    roof["traffic"] = measured_traffic(dom, head)
+    roof["form"] = kernel_form(dom, r["tuned"])
+    roof["traffic"] = measured_traffic(dom, head, roof["form"])
     stages = {}
     for k, v in st.items():
         if v <= 0:
@@ -493,7 +507,7 @@ def main():
             # (interpolation) LDS reads
             rf = roofline(k, v, by, fl, head)
             d["bound"], d["frac"] = rf["bound"], rf["frac"]
-            if k == "interp":
+            if k == "interp" and kernel_form(k, r["tuned"]) == "staged":
                 t_lds = lds_bytes(r["info"], head) / (LDS_PEAK_TBS * 1e12)
                 if t_lds / (v * 1e-3) > d["frac"]:
                     d["bound"], d["frac"] = "lds", t_lds / (v * 1e-3)

@@ -295,10 +295,12 @@ jgb_status jgb_nodes(jgb_plan_t plan, double* k, double* w, double* c);
  *  10 JGB_FLAG_SPLIT: separation of the two real transforms on the tiles
  *     the interpolation reads
  *  11 JGB_FLAG_SPLIT: I1's symbol (or its energy sum) over the regular grid
+ *  12 interpolation by tiles: sum of each node's tile shares, weight x symbol
+ *     and Fourier-side energy terms (stage 3 is then the tile products alone)
  * (2D problems run no pass on a third axis: stages 2 and 6 stay 0.)
  * Errors: INVALID_ARG (NULL plan, max_calls < 1 or > 100000, NULL outputs),
  * OUT_OF_MEMORY (event creation), DEVICE. */
-#define JGB_NUM_STAGES 12
+#define JGB_NUM_STAGES 13
 jgb_status jgb_timing_begin(jgb_plan_t plan, int max_calls);
 jgb_status jgb_timing_end(jgb_plan_t plan, double* stage_ms, int* calls);
 

@@ -20,9 +20,9 @@ STATUS_NAMES = {0: "JGB_OK", 1: "JGB_ERR_INVALID_ARG", 2: "JGB_ERR_UNSUPPORTED",
                 3: "JGB_ERR_OUT_OF_MEMORY", 4: "JGB_ERR_DEVICE"}
 
 COULOMB_3D, COULOMB_2D, DIPOLE_3D, DIPOLE_2D, POISSON_2D = 0, 1, 2, 3, 4
-NUM_STAGES = 12
+NUM_STAGES = 13
 STAGE_NAMES = ["fwd_fft_z", "fwd_fft_y", "fwd_fft_x", "interp", "spread", "spread_reduce",
-               "inv_fft_x", "inv_fft_y", "inv_fft_z", "energy", "split_unmix", "split_symbol"]
+               "inv_fft_x", "inv_fft_y", "inv_fft_z", "energy", "split_unmix", "split_symbol", "interp_reduce"]
 FP64, MIXED = 0, 1
 FLAG_AUTOTUNE = 1
 FLAG_SPLIT = 2

@@ -98,7 +98,7 @@ struct RingItem {
 
 enum Stage {
   ST_FWD_Z = 0, ST_FWD_Y, ST_FWD_X, ST_INTERP, ST_SPREAD, ST_SPREAD_REDUCE,
-  ST_INV_X, ST_INV_Y, ST_INV_Z, ST_ENERGY, ST_SPLIT_UNMIX, ST_SPLIT_SYMBOL, ST_COUNT
+  ST_INV_X, ST_INV_Y, ST_INV_Z, ST_ENERGY, ST_SPLIT_UNMIX, ST_SPLIT_SYMBOL, ST_INTERP_REDUCE, ST_COUNT
 };
 
 // Event ring for per-stage timing (see jgb_timing_begin).

@@ -677,6 +677,8 @@ hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipSt
                                           : launch_tile_kernel<T, false>(a, (unsigned)pl.nitems, smem, s);
     if (e != hipSuccess) return e;
   }
+  stage_mark(pl, ST_INTERP, 1, s);
+  stage_mark(pl, ST_INTERP_REDUCE, 0, s);
   ReduceArgs<T> r{};
   r.Mh = (int)pl.Mh;
   r.nstart = pl.d_nstart;
@@ -699,7 +701,7 @@ hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipSt
     else
       e = launch<ReduceArgs<T>, k_interp_reduce<T, 1>, k_interp_reduce_b<T, 1>>(r, rb, 256, 0, s);
   }
-  stage_mark(pl, ST_INTERP, 1, s);
+  stage_mark(pl, ST_INTERP_REDUCE, 1, s);
   return e;
 }
 

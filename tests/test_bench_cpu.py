@@ -70,21 +70,28 @@ def _recorded(stage, prec):
     vals = {}
     with open(os.path.join(ROOT, "profiles", "%s_%s_hbm_traffic.md" % (stage, prec))) as f:
         for line in f:
-            for key in ("traffic_bytes_per_launch:", "sources_sha1:"):
+            for key in ("traffic_bytes_per_launch:", "sources_sha1:", "kernel_form:"):
                 if line.strip().startswith(key):
                     vals[key] = line.split(":", 1)[1].strip()
-    return int(vals["traffic_bytes_per_launch:"]), vals["sources_sha1:"]
+    return int(vals["traffic_bytes_per_launch:"]), vals["sources_sha1:"], vals["kernel_form:"]
 
 
 def test_measured_traffic_follows_the_sources(monkeypatch):
     """The summary's bytes are used while the kernels' sources hash to the value
-    recorded with them, and dropped (null) once they differ."""
+    recorded with them and the plan runs the form of the kernel measured, and
+    dropped (null) otherwise."""
+    other = {"tiles": "staged", "staged": "tiles", "rings": "gather", "gather": "rings"}
     for stage in ("interp", "spread"):
         for prec in ("fp64", "mixed"):
-            want, sha = _recorded(stage, prec)
-            assert want > 0
+            want, sha, form = _recorded(stage, prec)
+            assert want > 0 and form in other
             monkeypatch.setattr(bench, "sources_sha1", lambda st, sha=sha: sha)
             assert bench.measured_traffic(stage, prec) == want
+            assert bench.measured_traffic(stage, prec, form) == want
+            assert bench.measured_traffic(stage, prec, other[form]) is None
             monkeypatch.setattr(bench, "sources_sha1", lambda st: "0" * 40)
             assert bench.measured_traffic(stage, prec) is None
     assert bench.measured_traffic("fwd_fft_x", "fp64") is None
+    assert bench.kernel_form("interp", {"interp_chunk": 0, "spread_chunk": -4096}) == "tiles"
+    assert bench.kernel_form("spread", {"interp_chunk": 0, "spread_chunk": -4096}) == "rings"
+    assert bench.kernel_form("spread", {"interp_chunk": 512, "spread_chunk": 4096}) == "gather"
