@@ -82,7 +82,7 @@ STAGE_SOURCES = {
     "spread": ["paper_1311_4120_amd/csrc/spread.hip", "paper_1311_4120_amd/csrc/ring.hip"],
 }
 TRAFFIC_SOURCES_COMMON = ["paper_1311_4120_amd/csrc/plan.hip", "paper_1311_4120_amd/csrc/common.h",
-                          "paper_1311_4120_amd/csrc/nodes.hip"]
+                          "paper_1311_4120_amd/csrc/nodes.hip", "paper_1311_4120_amd/csrc/lists.h"]
 
 
 def sources_sha1(stage):

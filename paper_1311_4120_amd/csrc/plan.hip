@@ -11,6 +11,7 @@
 #include <string>
 
 #include "common.h"
+#include "lists.h"
 
 namespace jgb {
 
@@ -309,103 +310,26 @@ Status apply_ring_chunk(Plan& pl, int chunk) {
 // bin-sorted nodes' natural half indices (perm) and footprint starts (hdr):
 // per ring tile, the rings that touch it in ring order, and per ring its
 // nodes that touch the tile, in sorted order.
-Status build_ring_lists(Plan& pl, const std::vector<int>& perm, const std::vector<int4>& hdr) {
+Status build_ring_lists(Plan& pl, const std::vector<int>& perm, const std::vector<lists::Start>& hdr) {
   const int RT[3] = {kRingTile0, kRingTile1, kRingTile2};
-  for (int a = 0; a < 3; ++a) pl.rnt[a] = (pl.nf[a] + RT[a] - 1) / RT[a];
+  lists::Geometry g{};
+  for (int a = 0; a < 3; ++a) {
+    pl.rnt[a] = (pl.nf[a] + RT[a] - 1) / RT[a];
+    g.nf[a] = pl.nf[a];
+    g.T[a] = RT[a];
+    g.nt[a] = pl.rnt[a];
+    g.w[a] = pl.w[a];
+  }
   pl.nrtiles = pl.rnt[0] * pl.rnt[1] * pl.rnt[2];
-  const int64_t Mh = pl.Mh;
-  const int nph2 = pl.n_phi / 2;
-  const int nrings = pl.n_r * pl.n_theta;
-  // the sorted nodes ring by ring
-  std::vector<int64_t> rstart(nrings + 1, 0);
-  for (int64_t j = 0; j < Mh; ++j) rstart[perm[j] / nph2 + 1]++;
-  for (int r = 0; r < nrings; ++r) rstart[r + 1] += rstart[r];
-  std::vector<int> byring(Mh);
-  {
-    std::vector<int64_t> fill(rstart.begin(), rstart.end() - 1);
-    for (int64_t j = 0; j < Mh; ++j) byring[fill[perm[j] / nph2]++] = (int)j;
-  }
-  auto touched = [&](int a, int x0, int* out) {
-    const int nf = pl.nf[a], T = RT[a], w = pl.w[a];
-    int n = 0;
-    for (int t = 0; t < w; ++t) {
-      const int tile = ((x0 + t) % nf) / T;
-      bool seen = false;
-      for (int i = 0; i < n; ++i) seen |= (out[i] == tile);
-      if (!seen) out[n++] = tile;
-    }
-    return n;
-  };
-  // a footprint start relative to a tile origin: its representative in
-  // [-(w - 1), T - 1] (nf >= T + w - 1 makes it unique), plus kGatherBias
-  auto code = [&](int a, int rel) {
-    const int nf = pl.nf[a];
-    int e = ((rel % nf) + nf) % nf;
-    if (e > RT[a] - 1) e -= nf;
-    return e + kGatherBias;
-  };
-  std::vector<int64_t> tcnt(pl.nrtiles + 1, 0);
-  int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
-  for (int64_t j = 0; j < Mh; ++j) {
-    const int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
-    for (int a0 = 0; a0 < nx; ++a0)
-      for (int a1 = 0; a1 < ny; ++a1)
-        for (int a2 = 0; a2 < nz; ++a2) tcnt[(tx[a0] * pl.rnt[1] + ty[a1]) * pl.rnt[2] + tz[a2] + 1]++;
-  }
-  for (int t = 0; t < pl.nrtiles; ++t) tcnt[t + 1] += tcnt[t];
-  const int64_t nent = tcnt[pl.nrtiles];
-  // per tile, its entries in ring order: node, ring, a0 | a1 codes
-  std::vector<int> enode(nent), ering(nent), ecode(nent);
-  {
-    std::vector<int64_t> fill(tcnt.begin(), tcnt.end() - 1);
-    for (int r = 0; r < nrings; ++r)
-      for (int64_t q = rstart[r]; q < rstart[r + 1]; ++q) {
-        const int j = byring[q];
-        const int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
-        for (int a0 = 0; a0 < nx; ++a0)
-          for (int a1 = 0; a1 < ny; ++a1)
-            for (int a2 = 0; a2 < nz; ++a2) {
-              const int tile = (tx[a0] * pl.rnt[1] + ty[a1]) * pl.rnt[2] + tz[a2];
-              const int64_t at = fill[tile]++;
-              enode[at] = j;
-              ering[at] = r;
-              ecode[at] = code(0, hdr[j].x - tx[a0] * RT[0]) | (code(1, hdr[j].y - ty[a1] * RT[1]) << 10);
-            }
-      }
-  }
-  // node entries, each ring's padded to whole groups of four with entries
-  // whose a0 start code (1023) leaves every a0 tap off the tile; the ring's
-  // last entry (a node of the ring: all share its a2 values) carries the end
-  // flag and the ring's a2 start code
-  const int kPad = 1023 | (1023 << 10);
-  std::vector<int2> rnodes;
-  rnodes.reserve(nent + nent / 4 + kRingSpare);
-  pl.h_rcount.assign(pl.nrtiles + 1, 0);
-  pl.h_rcost.clear();
-  pl.h_rfirst.clear();
-  for (int t = 0; t < pl.nrtiles; ++t) {
-    const int tz0 = t % pl.rnt[2];
-    for (int64_t i = tcnt[t]; i < tcnt[t + 1];) {
-      int64_t e = i;
-      while (e < tcnt[t + 1] && ering[e] == ering[i]) ++e;
-      const int j0 = enode[i];
-      const int64_t nb = (int64_t)rnodes.size();
-      for (int64_t q = i; q < e; ++q) rnodes.push_back(make_int2(enode[q], ecode[q]));
-      while ((rnodes.size() - nb) % 4) rnodes.push_back(make_int2(j0, kPad));
-      rnodes.back().y |= (1 << kRingEndBit) | (code(2, hdr[j0].z - tz0 * RT[2]) << kRingZBit);
-      if ((int64_t)rnodes.size() + kRingSpare >= ((int64_t)1 << 31))
-        return fail(JGB_ERR_UNSUPPORTED, "ring node lists too long");
-      pl.h_rfirst.push_back((int)nb);
-      pl.h_rcost.push_back((int)(rnodes.size() - nb));
-      i = e;
-    }
-    pl.h_rcount[t + 1] = (int64_t)pl.h_rcost.size();
-  }
-  for (int i = 0; i < kRingSpare; ++i) rnodes.push_back(make_int2(0, kPad));  // read by the last prefetch
+  std::vector<lists::Entry> rnodes;
+  const std::string err = lists::ring_lists(g, kGatherBias, pl.n_phi / 2, pl.n_r * pl.n_theta, perm, hdr, kRingEndBit,
+                                            kRingZBit, kRingSpare, rnodes, pl.h_rcount, pl.h_rcost, pl.h_rfirst);
+  if (!err.empty()) return fail(JGB_ERR_UNSUPPORTED, err);
   pl.nrings_ent = (int64_t)pl.h_rcost.size();
   pl.nrnodes = (int64_t)rnodes.size();
-  TRY(dev_alloc(pl, &pl.d_rnodes, sizeof(int2) * rnodes.size()));
-  TRY(upload(pl, pl.d_rnodes, rnodes.data(), sizeof(int2) * rnodes.size()));
+  static_assert(sizeof(lists::Entry) == sizeof(int2), "list entries are int2 on the device");
+  TRY(dev_alloc(pl, &pl.d_rnodes, sizeof(lists::Entry) * rnodes.size()));
+  TRY(upload(pl, pl.d_rnodes, rnodes.data(), sizeof(lists::Entry) * rnodes.size()));
   // item tables large enough for every chunk candidate
   std::vector<RingItem> items;
   std::vector<int> multi;
@@ -927,34 +851,10 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   // exact per-tile node lists: node j (bin-sorted order) is listed under every
   // output tile its w^3 footprint touches, so the gather never visits a node
   // that misses its tile
-  std::vector<int4> hdr(Mh);
+  static_assert(sizeof(lists::Start) == sizeof(int4), "node headers are int4 on the device");
+  std::vector<lists::Start> hdr(Mh);
   TRY_HIP(hipMemcpyAsync(hdr.data(), pl.nodes.hdr, sizeof(int4) * Mh, hipMemcpyDeviceToHost, pl.stream), "hdr copy");
   TRY_HIP(hipStreamSynchronize(pl.stream), "hdr sync");
-  auto touched = [&](int a, int x0, int* out) {
-    const int nf = pl.nf[a], T = pl.GT[a], w = pl.w[a];
-    int n = 0;
-    for (int t = 0; t < w; ++t) {
-      int tile = ((x0 + t) % nf) / T;
-      bool seen = false;
-      for (int i = 0; i < n; ++i) seen |= (out[i] == tile);
-      if (!seen) out[n++] = tile;
-    }
-    return n;
-  };
-  std::vector<int64_t> tcount(pl.ngtiles + 1, 0);
-  {
-    int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
-    for (int64_t j = 0; j < Mh; ++j) {
-      int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
-      for (int a0 = 0; a0 < nx; ++a0)
-        for (int a1 = 0; a1 < ny; ++a1)
-          for (int a2 = 0; a2 < nz; ++a2) tcount[(tx[a0] * pl.gnt[1] + ty[a1]) * pl.gnt[2] + tz[a2] + 1]++;
-    }
-  }
-  for (int t = 0; t < pl.ngtiles; ++t) tcount[t + 1] += tcount[t];
-  const int64_t nlist = tcount[pl.ngtiles];
-  // the gather addresses its list by 32-bit byte offsets (8 bytes per entry)
-  if ((nlist + 1) * 8 >= ((int64_t)1 << 32)) return fail(JGB_ERR_UNSUPPORTED, "gather lists too long");
   // entry: node index and its first tap relative to the tile origin on each
   // axis (10 bits each).  When every axis has nf >= T + w - 1 the start of a
   // footprint that touches the tile has exactly one representative in
@@ -962,47 +862,28 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   // reduction modulo nf; otherwise it is stored modulo nf (nf <= 1024).
   pl.gather_nowrap = true;
   for (int a = 0; a < 3; ++a) pl.gather_nowrap &= pl.nf[a] >= pl.GT[a] + pl.w[a] - 1;
-  auto start_code = [&](int a, int rel) {
-    const int nf = pl.nf[a];
-    int e = ((rel % nf) + nf) % nf;
-    if (!pl.gather_nowrap) return e;
-    if (e > pl.GT[a] - 1) e -= nf;
-    return e + kGatherBias;
-  };
-  std::vector<int2> list(nlist + 1, make_int2(0, 0));  // one spare entry
-  // node-major index of the list for the tile interpolation: node j's entries
-  // are generated together below, in the order of its tiles
-  // (built only for autotuned plans: the tuner times it against the staged
-  // interpolation and keeps the faster)
+  // the node-major index of the list, for the tile interpolation (built only
+  // for autotuned plans: the tuner times it against the staged interpolation
+  // and keeps the faster)
   pl.tile_ok = pl.dim == 3 && pl.GT[0] == 8 && pl.GT[1] == 8 && pl.GT[2] == 8 &&
                (p->flags & (JGB_FLAG_AUTOTUNE | JGB_FLAG_INTERP_TILES));
   pl.tile_interp = pl.tile_ok && (p->flags & JGB_FLAG_INTERP_TILES);
+  std::vector<int64_t> tcount;
+  std::vector<lists::Entry> list;
   std::vector<int> nstart, npos;
-  if (pl.tile_ok) {
-    nstart.assign(Mh + 1, 0);
-    npos.reserve(nlist);
-  }
   {
-    std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
-    int tx[kMaxWidth], ty[kMaxWidth], tz[kMaxWidth];
-    for (int64_t j = 0; j < Mh; ++j) {
-      if (pl.tile_ok) nstart[j] = (int)npos.size();
-      int nx = touched(0, hdr[j].x, tx), ny = touched(1, hdr[j].y, ty), nz = touched(2, hdr[j].z, tz);
-      for (int a0 = 0; a0 < nx; ++a0)
-        for (int a1 = 0; a1 < ny; ++a1)
-          for (int a2 = 0; a2 < nz; ++a2) {
-            const int tile = (tx[a0] * pl.gnt[1] + ty[a1]) * pl.gnt[2] + tz[a2];
-            const int ex = start_code(0, hdr[j].x - tx[a0] * pl.GT[0]);
-            const int ey = start_code(1, hdr[j].y - ty[a1] * pl.GT[1]);
-            const int ez = start_code(2, hdr[j].z - tz[a2] * pl.GT[2]);
-            if (ex < 0 || ex > 1023 || ey < 0 || ey > 1023 || ez < 0 || ez > 1023)
-              return fail(JGB_ERR_UNSUPPORTED, "gather list start out of range");
-            if (pl.tile_ok) npos.push_back((int)fill[tile]);
-            list[fill[tile]++] = make_int2((int)j, ex | (ey << 10) | (ez << 20));
-          }
+    lists::Geometry g{};
+    for (int a = 0; a < 3; ++a) {
+      g.nf[a] = pl.nf[a];
+      g.T[a] = pl.GT[a];
+      g.nt[a] = pl.gnt[a];
+      g.w[a] = pl.w[a];
     }
-    if (pl.tile_ok) nstart[Mh] = (int)npos.size();
+    const std::string err =
+        lists::gather_lists(g, pl.gather_nowrap, kGatherBias, hdr, tcount, list, pl.tile_ok, nstart, npos);
+    if (!err.empty()) return fail(JGB_ERR_UNSUPPORTED, err);
   }
+  const int64_t nlist = tcount[pl.ngtiles];
   if (pl.tile_ok) {
     TRY(dev_alloc(pl, &pl.d_nstart, sizeof(int) * (Mh + 1)));
     TRY(upload(pl, pl.d_nstart, nstart.data(), sizeof(int) * (Mh + 1)));
@@ -1011,8 +892,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     pl.ws_bytes[Plan::WS_IPART] = (size_t)std::max<int64_t>(nlist, 1) * 2 * pl.real_bytes;
     TRY(dev_alloc(pl, &pl.d_ipart, pl.ws_bytes[Plan::WS_IPART]));
   }
-  TRY(dev_alloc(pl, &pl.d_list, sizeof(int2) * list.size()));
-  TRY(upload(pl, pl.d_list, list.data(), sizeof(int2) * list.size()));
+  TRY(dev_alloc(pl, &pl.d_list, sizeof(lists::Entry) * list.size()));
+  TRY(upload(pl, pl.d_list, list.data(), sizeof(lists::Entry) * list.size()));
   pl.nlist = nlist;
 
   pl.h_tcount = tcount;

@@ -1,0 +1,235 @@
+// CPU harness for the host list construction (paper_1311_4120_amd/csrc/lists.h),
+// built with the address and undefined-behaviour sanitizers by
+// tests/test_list_sanitizers.py.  It builds the gather and ring lists for
+// product node sets r_a x theta_b x phi_l on oversampled grids up to 1024 points
+// per axis (N = 512, where the 10-bit start codes are tightest) and checks every
+// entry against a brute-force enumeration of the (node, tile) pairs whose
+// footprints meet.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lists.h"
+
+using namespace jgb::lists;
+
+static int failures = 0;
+#define CHECK(cond, ...)                         \
+  do {                                           \
+    if (!(cond)) {                               \
+      if (failures++ < 20) {                     \
+        fprintf(stderr, "FAIL %s:%d: ", __FILE__, __LINE__); \
+        fprintf(stderr, __VA_ARGS__);            \
+        fprintf(stderr, "\n");                   \
+      }                                          \
+    }                                            \
+  } while (0)
+
+struct Case {
+  const char* name;
+  int dim;          // 3, or 2 (a0 a unit axis)
+  int nf[3];
+  int w;
+  int n_r, n_theta, n_phi;
+  int T[3];         // tile extent
+  bool ring;        // also build the ring lists (3D)
+};
+
+static int mod(int a, int n) { return ((a % n) + n) % n; }
+
+// first taps of the half node set (l < n_phi / 2), natural order
+static std::vector<Start> node_starts(const Case& c, std::vector<int>& natural) {
+  std::vector<Start> h;
+  const double kmax = 0.999;  // fraction of the alias-free radius nf / 2 cells
+  for (int a = 0; a < c.n_r; ++a)
+    for (int b = 0; b < (c.dim == 3 ? c.n_theta : 1); ++b)
+      for (int l = 0; l < c.n_phi / 2; ++l) {
+        const double r = kmax * (a + 0.5) / c.n_r;
+        const double th = M_PI * (b + 0.5) / c.n_theta;
+        const double ph = 2 * M_PI * l / c.n_phi;
+        double k[3];
+        if (c.dim == 3) {
+          k[0] = r * std::sin(th) * std::cos(ph);
+          k[1] = r * std::sin(th) * std::sin(ph);
+          k[2] = r * std::cos(th);
+        } else {
+          k[0] = 0.0;
+          k[1] = r * std::cos(ph);
+          k[2] = r * std::sin(ph);
+        }
+        Start s{0, 0, 0, 0};
+        int* out[3] = {&s.x, &s.y, &s.z};
+        for (int ax = 0; ax < 3; ++ax) {
+          const int w = (c.nf[ax] == 1) ? 1 : c.w;
+          const double pos = k[ax] * c.nf[ax] / 2;  // fine-grid position in cells
+          *out[ax] = mod((int)std::ceil(pos - 0.5 * w), c.nf[ax]);
+        }
+        natural.push_back((int)h.size());
+        h.push_back(s);
+      }
+  return h;
+}
+
+static bool touches(int start, int nf, int w, int tile, int T) {
+  for (int t = 0; t < w; ++t)
+    if (((start + t) % nf) / T == tile) return true;
+  return false;
+}
+
+// relative start of node start s against a tile origin o, as a code decodes it
+static int decoded(int code, bool nowrap, int bias) { return nowrap ? code - bias : code; }
+
+static void run(const Case& c, bool nowrap_gather) {
+  std::vector<int> natural;
+  std::vector<Start> hdr = node_starts(c, natural);
+  const int64_t Mh = (int64_t)hdr.size();
+  Geometry g{};
+  for (int a = 0; a < 3; ++a) {
+    g.nf[a] = c.nf[a];
+    g.T[a] = c.T[a];
+    g.nt[a] = (c.nf[a] + c.T[a] - 1) / c.T[a];
+    g.w[a] = (c.nf[a] == 1) ? 1 : c.w;
+  }
+  const int bias = 512;
+  bool nowrap = nowrap_gather;
+  for (int a = 0; a < 3; ++a) nowrap &= g.nf[a] >= g.T[a] + g.w[a] - 1;
+  // a permutation of the nodes, as the plan's bin sort produces one
+  std::vector<int> perm(Mh);
+  for (int64_t j = 0; j < Mh; ++j) perm[j] = (int)((j * 7919 + 13) % Mh);
+  std::set<int> seen(perm.begin(), perm.end());
+  if ((int64_t)seen.size() != Mh) {  // 7919 shares a factor with Mh: use the identity
+    for (int64_t j = 0; j < Mh; ++j) perm[j] = (int)j;
+  }
+  std::vector<Start> sorted(Mh);
+  for (int64_t j = 0; j < Mh; ++j) sorted[j] = hdr[perm[j]];
+
+  // brute force: every (node, tile) pair whose footprints meet
+  std::map<int64_t, std::vector<int>> pairs;  // tile -> nodes (sorted index)
+  for (int64_t j = 0; j < Mh; ++j) {
+    int tl[3][kMaxTaps], nt[3];
+    const int st[3] = {sorted[j].x, sorted[j].y, sorted[j].z};
+    for (int a = 0; a < 3; ++a) nt[a] = touched(st[a], g.nf[a], g.T[a], g.w[a], tl[a]);
+    for (int i0 = 0; i0 < nt[0]; ++i0)
+      for (int i1 = 0; i1 < nt[1]; ++i1)
+        for (int i2 = 0; i2 < nt[2]; ++i2) {
+          const int64_t t = ((int64_t)tl[0][i0] * g.nt[1] + tl[1][i1]) * g.nt[2] + tl[2][i2];
+          pairs[t].push_back((int)j);
+        }
+  }
+
+  // gather lists
+  std::vector<int64_t> tcount;
+  std::vector<Entry> list;
+  std::vector<int> nstart, npos;
+  std::string err = gather_lists(g, nowrap, bias, sorted, tcount, list, true, nstart, npos);
+  CHECK(err.empty(), "%s: gather_lists: %s", c.name, err.c_str());
+  if (!err.empty()) return;
+  const int64_t ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
+  int64_t total = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int t0 = (int)(t / ((int64_t)g.nt[1] * g.nt[2])), t1 = (int)((t / g.nt[2]) % g.nt[1]), t2 = (int)(t % g.nt[2]);
+    const int org[3] = {t0 * g.T[0], t1 * g.T[1], t2 * g.T[2]};
+    const std::vector<int>& want = pairs.count(t) ? pairs[t] : std::vector<int>();
+    CHECK((int64_t)want.size() == tcount[t + 1] - tcount[t], "%s: tile %lld lists %lld nodes, %zu touch it", c.name,
+          (long long)t, (long long)(tcount[t + 1] - tcount[t]), want.size());
+    for (int64_t e = tcount[t]; e < tcount[t + 1]; ++e) {
+      const Entry en = list[e];
+      CHECK(en.node >= 0 && en.node < Mh, "%s: node index", c.name);
+      if (en.node < 0 || en.node >= Mh) continue;
+      const int codes[3] = {en.code & 1023, (en.code >> 10) & 1023, (en.code >> 20) & 1023};
+      const int st[3] = {sorted[en.node].x, sorted[en.node].y, sorted[en.node].z};
+      for (int a = 0; a < 3; ++a) {
+        const int rel = decoded(codes[a], nowrap, bias);
+        CHECK(mod(rel - (st[a] - org[a]), g.nf[a]) == 0, "%s: axis %d start code %d of node %d in tile %lld", c.name,
+              a, codes[a], en.node, (long long)t);
+        if (nowrap) CHECK(rel >= -(g.w[a] - 1) && rel <= g.T[a] - 1, "%s: nowrap code range", c.name);
+        CHECK(touches(st[a], g.nf[a], g.w[a], org[a] / g.T[a], g.T[a]), "%s: listed node misses the tile", c.name);
+      }
+      if (e > tcount[t]) CHECK(list[e - 1].node < en.node, "%s: entries of a tile in node order", c.name);
+    }
+    total += tcount[t + 1] - tcount[t];
+  }
+  CHECK((int64_t)list.size() == total + 1, "%s: one spare entry", c.name);
+  // node-major index
+  CHECK((int64_t)nstart.size() == Mh + 1 && nstart[Mh] == (int)npos.size() && (int64_t)npos.size() == total,
+        "%s: node-major index sizes", c.name);
+  for (int64_t j = 0; j < Mh; ++j)
+    for (int q = nstart[j]; q < nstart[j + 1]; ++q)
+      CHECK(npos[q] >= 0 && npos[q] < total && list[npos[q]].node == (int)j, "%s: node-major position", c.name);
+
+  if (!c.ring) return;
+  // ring lists (natural index = (a n_theta + b) nph2 + l)
+  const int nph2 = c.n_phi / 2;
+  std::vector<Entry> rnodes;
+  std::vector<int64_t> rcount;
+  std::vector<int> rcost, rfirst;
+  const int end_bit = 20, z_bit = 21, spare = 32;
+  err = ring_lists(g, bias, nph2, c.n_r * c.n_theta, perm, sorted, end_bit, z_bit, spare, rnodes, rcount, rcost, rfirst);
+  CHECK(err.empty(), "%s: ring_lists: %s", c.name, err.c_str());
+  if (!err.empty()) return;
+  int64_t listed = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int t0 = (int)(t / ((int64_t)g.nt[1] * g.nt[2])), t1 = (int)((t / g.nt[2]) % g.nt[1]), t2 = (int)(t % g.nt[2]);
+    const int org[3] = {t0 * g.T[0], t1 * g.T[1], t2 * g.T[2]};
+    std::multiset<int> want;
+    if (pairs.count(t)) want.insert(pairs[t].begin(), pairs[t].end());
+    std::multiset<int> got;
+    std::set<int> rings_seen;
+    for (int64_t r = rcount[t]; r < rcount[t + 1]; ++r) {
+      CHECK(rcost[r] > 0 && rcost[r] % 4 == 0, "%s: ring padded to groups of four", c.name);
+      const int ring = perm[rnodes[rfirst[r]].node] / nph2;
+      CHECK(!rings_seen.count(ring), "%s: a ring listed twice in a tile", c.name);
+      rings_seen.insert(ring);
+      for (int q = 0; q < rcost[r]; ++q) {
+        const Entry en = rnodes[rfirst[r] + q];
+        const bool last = q == rcost[r] - 1;
+        CHECK(((en.code >> end_bit) & 1) == (last ? 1 : 0), "%s: ring end flag", c.name);
+        CHECK(perm[en.node] / nph2 == ring, "%s: entry of another ring", c.name);
+        const int cx = en.code & 1023, cy = (en.code >> 10) & 1023;
+        if (cx == 1023 && cy == 1023) continue;  // padding
+        got.insert(en.node);
+        const int st[2] = {sorted[en.node].x, sorted[en.node].y};
+        CHECK(mod(cx - bias - (st[0] - org[0]), g.nf[0]) == 0 && mod(cy - bias - (st[1] - org[1]), g.nf[1]) == 0,
+              "%s: ring entry start codes", c.name);
+        if (last) {
+          const int cz = (en.code >> z_bit) & 1023;
+          CHECK(mod(cz - bias - (sorted[en.node].z - org[2]), g.nf[2]) == 0, "%s: ring a2 start code", c.name);
+        }
+      }
+      const Entry lastent = rnodes[rfirst[r] + rcost[r] - 1];
+      const int cz = (lastent.code >> z_bit) & 1023;
+      CHECK(mod(cz - bias - (sorted[lastent.node].z - org[2]), g.nf[2]) == 0, "%s: ring a2 start code", c.name);
+      listed += rcost[r];
+    }
+    CHECK(got == want, "%s: tile %lld: ring lists hold %zu nodes, %zu touch it", c.name, (long long)t, got.size(),
+          want.size());
+  }
+  CHECK((int64_t)rnodes.size() == listed + spare, "%s: spare ring entries", c.name);
+}
+
+int main() {
+  const Case cases[] = {
+      // N = 512: the oversampled side 1024, the largest the 10-bit codes allow
+      {"3d_512_w12", 3, {1024, 1024, 1024}, 12, 24, 16, 32, {8, 8, 8}, false},
+      {"3d_512_w16_rings", 3, {1024, 1024, 1024}, 16, 24, 16, 32, {16, 8, 16}, true},
+      {"3d_ragged_w12_rings", 3, {40, 48, 60}, 12, 10, 8, 12, {16, 8, 16}, true},
+      {"3d_small_wrap_w12", 3, {16, 16, 24}, 12, 6, 4, 8, {8, 8, 8}, false},
+      {"2d_512_w12", 2, {1, 1024, 1024}, 12, 64, 1, 96, {1, 64, 8}, false},
+  };
+  for (const Case& c : cases) {
+    run(c, true);
+    if (c.dim == 3 && !c.ring) run(c, false);  // modulo-nf start codes (what small grids store)
+    fprintf(stderr, "case %s done\n", c.name);
+  }
+  if (failures) {
+    fprintf(stderr, "%d failures\n", failures);
+    return 1;
+  }
+  printf("ok\n");
+  return 0;
+}
