@@ -18,10 +18,17 @@
 // representative in [-(w - 1), T - 1] plus a bias ("nowrap"); otherwise modulo
 // nf.  Either way it must fit in 10 bits: the functions return an error
 // message instead of a list that would not.
+//
+// Both run on `threads` host threads over contiguous ranges of nodes (or
+// rings, or tiles): per-thread counts per tile give every thread its own
+// write positions, so the lists come out identical to a serial build.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace jgb {
@@ -66,42 +73,58 @@ inline int start_code(int rel, int nf, int T, bool nowrap, int bias) {
 
 inline bool code_fits(int c) { return c >= 0 && c <= 1023; }
 
+// f(begin, end, thread) over `threads` contiguous ranges of [0, n).
+template <typename F>
+void parallel_ranges(int64_t n, int threads, F f) {
+  threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, n));
+  if (threads == 1) {
+    f((int64_t)0, n, 0);
+    return;
+  }
+  std::vector<std::thread> pool;
+  pool.reserve(threads);
+  for (int t = 0; t < threads; ++t) pool.emplace_back(f, n * t / threads, n * (t + 1) / threads, t);
+  for (std::thread& th : pool) th.join();
+}
+
+// Threads worth starting: one per 4096 nodes at most, and per-thread counts
+// per tile within 256 MB.
+inline int usable_threads(int threads, int64_t nodes, int64_t ntiles) {
+  const int64_t by_mem = ((int64_t)256 << 20) / std::max<int64_t>(1, ntiles * (int64_t)sizeof(int64_t));
+  return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)threads, nodes / 4096 + 1, by_mem}));
+}
+
+// Turns per-thread counts per tile (cnt[t][tile]) into per-thread write
+// positions (in place) and tile offsets (offs, ntiles + 1).
+inline void count_offsets(std::vector<std::vector<int64_t>>& cnt, int64_t ntiles, std::vector<int64_t>& offs) {
+  offs.assign(ntiles + 1, 0);
+  int64_t run = 0;
+  for (int64_t tile = 0; tile < ntiles; ++tile) {
+    offs[tile] = run;
+    for (std::vector<int64_t>& c : cnt) {
+      const int64_t k = c[tile];
+      c[tile] = run;
+      run += k;
+    }
+  }
+  offs[ntiles] = run;
+}
+
 // The three-axis gather's lists (see above): tcount gets ntiles + 1 offsets
 // into list; list gets the entries tile by tile, nodes in their order, then
 // one spare entry.  With node_major, nstart (Mh + 1 offsets) and npos (list
 // positions) index each node's entries in the order of its tiles.
 inline std::string gather_lists(const Geometry& g, bool nowrap, int bias, const std::vector<Start>& hdr,
                                 std::vector<int64_t>& tcount, std::vector<Entry>& list, bool node_major,
-                                std::vector<int>& nstart, std::vector<int>& npos) {
+                                std::vector<int>& nstart, std::vector<int>& npos, int threads = 1) {
   for (int a = 0; a < 3; ++a)
     if (g.w[a] < 1 || g.w[a] > kMaxTaps || g.w[a] > g.nf[a]) return "width out of range";
   const int64_t Mh = (int64_t)hdr.size();
   const int64_t ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
-  tcount.assign(ntiles + 1, 0);
-  int tx[kMaxTaps], ty[kMaxTaps], tz[kMaxTaps];
-  for (int64_t j = 0; j < Mh; ++j) {
-    const int nx = touched(hdr[j].x, g.nf[0], g.T[0], g.w[0], tx);
-    const int ny = touched(hdr[j].y, g.nf[1], g.T[1], g.w[1], ty);
-    const int nz = touched(hdr[j].z, g.nf[2], g.T[2], g.w[2], tz);
-    for (int a0 = 0; a0 < nx; ++a0)
-      for (int a1 = 0; a1 < ny; ++a1)
-        for (int a2 = 0; a2 < nz; ++a2) tcount[((int64_t)tx[a0] * g.nt[1] + ty[a1]) * g.nt[2] + tz[a2] + 1]++;
-  }
-  for (int64_t t = 0; t < ntiles; ++t) tcount[t + 1] += tcount[t];
-  const int64_t nlist = tcount[ntiles];
-  // the kernels address the list by 32-bit byte offsets (8 bytes per entry)
-  // and the node-major index by 32-bit positions
-  if ((nlist + 1) * 8 >= ((int64_t)1 << 32)) return "gather lists too long";
-  list.assign(nlist + 1, Entry{0, 0});
-  nstart.clear();
-  npos.clear();
-  if (node_major) {
-    nstart.assign(Mh + 1, 0);
-    npos.reserve(nlist);
-  }
-  std::vector<int64_t> fill(tcount.begin(), tcount.end() - 1);
-  for (int64_t j = 0; j < Mh; ++j) {
-    if (node_major) nstart[j] = (int)npos.size();
+  threads = usable_threads(threads, Mh, ntiles);
+  // visit(j, f): f(tile, code) for node j's tiles in tap order
+  auto visit = [&](int64_t j, auto&& f) {
+    int tx[kMaxTaps], ty[kMaxTaps], tz[kMaxTaps];
     const int nx = touched(hdr[j].x, g.nf[0], g.T[0], g.w[0], tx);
     const int ny = touched(hdr[j].y, g.nf[1], g.T[1], g.w[1], ty);
     const int nz = touched(hdr[j].z, g.nf[2], g.T[2], g.w[2], tz);
@@ -112,12 +135,45 @@ inline std::string gather_lists(const Geometry& g, bool nowrap, int bias, const 
           const int ex = start_code(hdr[j].x - tx[a0] * g.T[0], g.nf[0], g.T[0], nowrap, bias);
           const int ey = start_code(hdr[j].y - ty[a1] * g.T[1], g.nf[1], g.T[1], nowrap, bias);
           const int ez = start_code(hdr[j].z - tz[a2] * g.T[2], g.nf[2], g.T[2], nowrap, bias);
-          if (!code_fits(ex) || !code_fits(ey) || !code_fits(ez)) return "gather list start out of range";
-          if (node_major) npos.push_back((int)fill[tile]);
-          list[fill[tile]++] = Entry{(int)j, ex | (ey << 10) | (ez << 20)};
+          f(tile, ex, ey, ez);
         }
+  };
+  std::vector<std::vector<int64_t>> cnt(threads, std::vector<int64_t>(ntiles, 0));
+  std::vector<int64_t> per_node(node_major ? Mh + 1 : 0, 0);
+  std::atomic<bool> bad{false};
+  parallel_ranges(Mh, threads, [&](int64_t b, int64_t e, int t) {
+    std::vector<int64_t>& c = cnt[t];
+    for (int64_t j = b; j < e; ++j)
+      visit(j, [&](int64_t tile, int ex, int ey, int ez) {
+        c[tile]++;
+        if (node_major) per_node[j + 1]++;
+        if (!code_fits(ex) || !code_fits(ey) || !code_fits(ez)) bad = true;
+      });
+  });
+  if (bad) return "gather list start out of range";
+  count_offsets(cnt, ntiles, tcount);
+  const int64_t nlist = tcount[ntiles];
+  // the kernels address the list by 32-bit byte offsets (8 bytes per entry)
+  // and the node-major index by 32-bit positions
+  if ((nlist + 1) * 8 >= ((int64_t)1 << 32)) return "gather lists too long";
+  list.assign(nlist + 1, Entry{0, 0});
+  nstart.clear();
+  npos.clear();
+  if (node_major) {
+    nstart.assign(Mh + 1, 0);
+    for (int64_t j = 0; j < Mh; ++j) nstart[j + 1] = nstart[j] + (int)per_node[j + 1];
+    npos.assign(nlist, 0);
   }
-  if (node_major) nstart[Mh] = (int)npos.size();
+  parallel_ranges(Mh, threads, [&](int64_t b, int64_t e, int t) {
+    std::vector<int64_t>& at = cnt[t];
+    for (int64_t j = b; j < e; ++j) {
+      int k = 0;
+      visit(j, [&](int64_t tile, int ex, int ey, int ez) {
+        if (node_major) npos[nstart[j] + k++] = (int)at[tile];
+        list[at[tile]++] = Entry{(int)j, ex | (ey << 10) | (ez << 20)};
+      });
+    }
+  });
   return "";
 }
 
@@ -131,13 +187,14 @@ inline std::string gather_lists(const Geometry& g, bool nowrap, int bias, const 
 inline std::string ring_lists(const Geometry& g, int bias, int nph2, int nrings, const std::vector<int>& perm,
                               const std::vector<Start>& hdr, int end_bit, int z_bit, int spare,
                               std::vector<Entry>& rnodes, std::vector<int64_t>& rcount, std::vector<int>& rcost,
-                              std::vector<int>& rfirst) {
+                              std::vector<int>& rfirst, int threads = 1) {
   for (int a = 0; a < 3; ++a)
     if (g.nf[a] < g.T[a] + g.w[a] - 1 || g.w[a] < 1 || g.w[a] > kMaxTaps) return "grid too small for ring tiles";
   const int64_t Mh = (int64_t)hdr.size();
   if ((int64_t)perm.size() != Mh || nph2 < 1 || nrings < 1 || (int64_t)nrings * nph2 != Mh)
     return "node set is not a product of rings";
   const int64_t ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
+  threads = usable_threads(threads, Mh, ntiles);
   // the nodes ring by ring
   std::vector<int64_t> rstart(nrings + 1, 0);
   for (int64_t j = 0; j < Mh; ++j) {
@@ -150,68 +207,94 @@ inline std::string ring_lists(const Geometry& g, int bias, int nph2, int nrings,
     std::vector<int64_t> fill(rstart.begin(), rstart.end() - 1);
     for (int64_t j = 0; j < Mh; ++j) byring[fill[perm[j] / nph2]++] = (int)j;
   }
-  std::vector<int64_t> tcnt(ntiles + 1, 0);
-  int tx[kMaxTaps], ty[kMaxTaps], tz[kMaxTaps];
-  for (int64_t j = 0; j < Mh; ++j) {
+  auto visit = [&](int j, auto&& f) {
+    int tx[kMaxTaps], ty[kMaxTaps], tz[kMaxTaps];
     const int nx = touched(hdr[j].x, g.nf[0], g.T[0], g.w[0], tx);
     const int ny = touched(hdr[j].y, g.nf[1], g.T[1], g.w[1], ty);
     const int nz = touched(hdr[j].z, g.nf[2], g.T[2], g.w[2], tz);
     for (int a0 = 0; a0 < nx; ++a0)
       for (int a1 = 0; a1 < ny; ++a1)
-        for (int a2 = 0; a2 < nz; ++a2) tcnt[((int64_t)tx[a0] * g.nt[1] + ty[a1]) * g.nt[2] + tz[a2] + 1]++;
-  }
-  for (int64_t t = 0; t < ntiles; ++t) tcnt[t + 1] += tcnt[t];
+        for (int a2 = 0; a2 < nz; ++a2) {
+          const int64_t tile = ((int64_t)tx[a0] * g.nt[1] + ty[a1]) * g.nt[2] + tz[a2];
+          const int ex = start_code(hdr[j].x - tx[a0] * g.T[0], g.nf[0], g.T[0], true, bias);
+          const int ey = start_code(hdr[j].y - ty[a1] * g.T[1], g.nf[1], g.T[1], true, bias);
+          f(tile, ex, ey);
+        }
+  };
+  // per tile, its entries in ring order (threads over contiguous rings)
+  std::vector<std::vector<int64_t>> cnt(threads, std::vector<int64_t>(ntiles, 0));
+  std::atomic<bool> bad{false};
+  parallel_ranges(nrings, threads, [&](int64_t rb, int64_t re, int t) {
+    std::vector<int64_t>& c = cnt[t];
+    for (int64_t q = rstart[rb]; q < rstart[re]; ++q)
+      visit(byring[q], [&](int64_t tile, int ex, int ey) {
+        c[tile]++;
+        if (!code_fits(ex) || !code_fits(ey)) bad = true;
+      });
+  });
+  if (bad) return "ring list start out of range";
+  std::vector<int64_t> tcnt;
+  count_offsets(cnt, ntiles, tcnt);
   const int64_t nent = tcnt[ntiles];
-  // per tile, its entries in ring order
   std::vector<int> enode(nent), ering(nent), ecode(nent);
-  {
-    std::vector<int64_t> fill(tcnt.begin(), tcnt.end() - 1);
-    for (int r = 0; r < nrings; ++r)
+  parallel_ranges(nrings, threads, [&](int64_t rb, int64_t re, int t) {
+    std::vector<int64_t>& at = cnt[t];
+    for (int64_t r = rb; r < re; ++r)
       for (int64_t q = rstart[r]; q < rstart[r + 1]; ++q) {
         const int j = byring[q];
-        const int nx = touched(hdr[j].x, g.nf[0], g.T[0], g.w[0], tx);
-        const int ny = touched(hdr[j].y, g.nf[1], g.T[1], g.w[1], ty);
-        const int nz = touched(hdr[j].z, g.nf[2], g.T[2], g.w[2], tz);
-        for (int a0 = 0; a0 < nx; ++a0)
-          for (int a1 = 0; a1 < ny; ++a1)
-            for (int a2 = 0; a2 < nz; ++a2) {
-              const int64_t tile = ((int64_t)tx[a0] * g.nt[1] + ty[a1]) * g.nt[2] + tz[a2];
-              const int ex = start_code(hdr[j].x - tx[a0] * g.T[0], g.nf[0], g.T[0], true, bias);
-              const int ey = start_code(hdr[j].y - ty[a1] * g.T[1], g.nf[1], g.T[1], true, bias);
-              if (!code_fits(ex) || !code_fits(ey)) return "ring list start out of range";
-              const int64_t at = fill[tile]++;
-              enode[at] = j;
-              ering[at] = r;
-              ecode[at] = ex | (ey << 10);
-            }
+        visit(j, [&](int64_t tile, int ex, int ey) {
+          const int64_t k = at[tile]++;
+          enode[k] = j;
+          ering[k] = (int)r;
+          ecode[k] = ex | (ey << 10);
+        });
       }
-  }
+  });
+  // each tile's rings, padded to whole groups of four: sizes first (threads
+  // over contiguous tiles), then the entries at their offsets
   const int kPad = 1023 | (1023 << 10);
-  rnodes.clear();
-  rnodes.reserve(nent + nent / 4 + spare);
-  rcount.assign(ntiles + 1, 0);
-  rcost.clear();
-  rfirst.clear();
+  std::vector<int64_t> tsize(ntiles + 1, 0), tring(ntiles + 1, 0);
+  parallel_ranges(ntiles, threads, [&](int64_t b, int64_t e, int) {
+    for (int64_t t = b; t < e; ++t)
+      for (int64_t i = tcnt[t]; i < tcnt[t + 1];) {
+        int64_t k = i;
+        while (k < tcnt[t + 1] && ering[k] == ering[i]) ++k;
+        tsize[t + 1] += (k - i + 3) / 4 * 4;
+        tring[t + 1]++;
+        i = k;
+      }
+  });
   for (int64_t t = 0; t < ntiles; ++t) {
-    const int tz0 = (int)(t % g.nt[2]);
-    for (int64_t i = tcnt[t]; i < tcnt[t + 1];) {
-      int64_t e = i;
-      while (e < tcnt[t + 1] && ering[e] == ering[i]) ++e;
-      const int j0 = enode[i];
-      const int64_t nb = (int64_t)rnodes.size();
-      for (int64_t q = i; q < e; ++q) rnodes.push_back(Entry{enode[q], ecode[q]});
-      while ((rnodes.size() - nb) % 4) rnodes.push_back(Entry{j0, kPad});
-      const int ez = start_code(hdr[j0].z - tz0 * g.T[2], g.nf[2], g.T[2], true, bias);
-      if (!code_fits(ez)) return "ring list start out of range";
-      rnodes.back().code |= (1 << end_bit) | (ez << z_bit);
-      if ((int64_t)rnodes.size() + spare >= ((int64_t)1 << 31)) return "ring node lists too long";
-      rfirst.push_back((int)nb);
-      rcost.push_back((int)(rnodes.size() - nb));
-      i = e;
-    }
-    rcount[t + 1] = (int64_t)rcost.size();
+    tsize[t + 1] += tsize[t];
+    tring[t + 1] += tring[t];
   }
-  for (int i = 0; i < spare; ++i) rnodes.push_back(Entry{0, kPad});  // read by the last prefetch
+  if (tsize[ntiles] + spare >= ((int64_t)1 << 31)) return "ring node lists too long";
+  rnodes.assign(tsize[ntiles] + spare, Entry{0, kPad});  // the spare entries are read by the last prefetch
+  rcost.assign(tring[ntiles], 0);
+  rfirst.assign(tring[ntiles], 0);
+  rcount = tring;
+  parallel_ranges(ntiles, threads, [&](int64_t b, int64_t e, int) {
+    for (int64_t t = b; t < e; ++t) {
+      const int tz0 = (int)(t % g.nt[2]);
+      int64_t at = tsize[t], ring = tring[t];
+      for (int64_t i = tcnt[t]; i < tcnt[t + 1];) {
+        int64_t k = i;
+        while (k < tcnt[t + 1] && ering[k] == ering[i]) ++k;
+        const int j0 = enode[i];
+        const int64_t nb = at;
+        for (int64_t q = i; q < k; ++q) rnodes[at++] = Entry{enode[q], ecode[q]};
+        while ((at - nb) % 4) rnodes[at++] = Entry{j0, kPad};
+        const int ez = start_code(hdr[j0].z - tz0 * g.T[2], g.nf[2], g.T[2], true, bias);
+        if (!code_fits(ez)) bad = true;
+        rnodes[at - 1].code |= (1 << end_bit) | ((ez & 1023) << z_bit);
+        rfirst[ring] = (int)nb;
+        rcost[ring] = (int)(at - nb);
+        ++ring;
+        i = k;
+      }
+    }
+  });
+  if (bad) return "ring list start out of range";
   return "";
 }
 

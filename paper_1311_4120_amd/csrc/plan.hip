@@ -3,12 +3,14 @@
 // workspace.  Everything here runs once per plan; the compute calls only read
 // what the plan holds.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <cstdio>
 #include <cstdlib>
 #include <limits>
 #include <string>
+#include <thread>
 
 #include "common.h"
 #include "lists.h"
@@ -306,6 +308,12 @@ Status apply_ring_chunk(Plan& pl, int chunk) {
   return Status::ok();
 }
 
+// Host threads for the list construction: the hardware's, at most 16.
+int host_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::min(16u, std::max(1u, hw));
+}
+
 // Node entries of the spreading by rings (Plan::d_rnodes) from the
 // bin-sorted nodes' natural half indices (perm) and footprint starts (hdr):
 // per ring tile, the rings that touch it in ring order, and per ring its
@@ -323,7 +331,8 @@ Status build_ring_lists(Plan& pl, const std::vector<int>& perm, const std::vecto
   pl.nrtiles = pl.rnt[0] * pl.rnt[1] * pl.rnt[2];
   std::vector<lists::Entry> rnodes;
   const std::string err = lists::ring_lists(g, kGatherBias, pl.n_phi / 2, pl.n_r * pl.n_theta, perm, hdr, kRingEndBit,
-                                            kRingZBit, kRingSpare, rnodes, pl.h_rcount, pl.h_rcost, pl.h_rfirst);
+                                            kRingZBit, kRingSpare, rnodes, pl.h_rcount, pl.h_rcost, pl.h_rfirst,
+                                            host_threads());
   if (!err.empty()) return fail(JGB_ERR_UNSUPPORTED, err);
   pl.nrings_ent = (int64_t)pl.h_rcost.size();
   pl.nrnodes = (int64_t)rnodes.size();
@@ -638,6 +647,12 @@ void accuracy_parameters(double eps, int& w, double& beta) {
 }
 
 Status build_plan(Plan& pl, const jgb_params* p) {
+  // wall time of the plan's phases, for JGB_LOG
+  const auto t_start = std::chrono::steady_clock::now();
+  double t_phase[5] = {0, 0, 0, 0, 0};  // nodes and sort, gather lists, ring lists, tables and grids, tuning
+  auto since = [](std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
   pl.p = *p;
   pl.device = p->device;
   pl.stream = (hipStream_t)p->stream;
@@ -848,6 +863,9 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   TRY(dev_alloc(pl, &pl.d_bin_start, sizeof(int) * (pl.ntiles + 1)));
   TRY(upload(pl, pl.d_bin_start, bin_start.data(), sizeof(int) * (pl.ntiles + 1)));
 
+  TRY_HIP(hipStreamSynchronize(pl.stream), "node setup sync");
+  t_phase[0] = since(t_start);
+  const auto t_lists = std::chrono::steady_clock::now();
   // exact per-tile node lists: node j (bin-sorted order) is listed under every
   // output tile its w^3 footprint touches, so the gather never visits a node
   // that misses its tile
@@ -880,7 +898,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
       g.w[a] = pl.w[a];
     }
     const std::string err =
-        lists::gather_lists(g, pl.gather_nowrap, kGatherBias, hdr, tcount, list, pl.tile_ok, nstart, npos);
+        lists::gather_lists(g, pl.gather_nowrap, kGatherBias, hdr, tcount, list, pl.tile_ok, nstart, npos, host_threads());
     if (!err.empty()) return fail(JGB_ERR_UNSUPPORTED, err);
   }
   const int64_t nlist = tcount[pl.ngtiles];
@@ -897,6 +915,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   pl.nlist = nlist;
 
   pl.h_tcount = tcount;
+  t_phase[1] = since(t_lists);
+  const auto t_rings = std::chrono::steady_clock::now();
   // the ring tables (3D; built when forced or for the tuner to time)
   {
     const bool forced = (p->flags & JGB_FLAG_SPREAD_RINGS) != 0;
@@ -945,6 +965,8 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     }
   }
 
+  t_phase[2] = since(t_rings);
+  const auto t_tables = std::chrono::steady_clock::now();
   // FFT twiddles and deconvolution factors per axis
   for (int a = 0; a < 3; ++a) {
     const int L = pl.nf[a];
@@ -1036,19 +1058,24 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   pl.ws_bytes[Plan::WS_EPARTS] = sizeof(double) * pl.neparts;
   TRY(dev_alloc(pl, &pl.d_eparts, pl.ws_bytes[Plan::WS_EPARTS]));
   TRY_HIP(interp_prepare(pl), "interpolation LDS limit");
+  TRY_HIP(hipStreamSynchronize(pl.stream), "tables sync");
+  t_phase[3] = since(t_tables);
+  const auto t_tune = std::chrono::steady_clock::now();
   if (p->flags & JGB_FLAG_AUTOTUNE) TRY(autotune(pl));
+  t_phase[4] = since(t_tune);
   // JGB_LOG=1: one line per plan on stderr with the shape the plan chose
   if (const char* lg = getenv("JGB_LOG")) {
     if (lg[0] && lg[0] != '0')
       fprintf(stderr,
               "jgb plan: dim %d n %dx%dx%d nf %dx%dx%d nodes %lld (half %lld) width %d %s %s%s interp %s chunk %d "
-              "spread chunk %d tiles %d items %d list entries %lld workspace %.1f MB\n",
+              "spread chunk %d tiles %d items %d list entries %lld workspace %.1f MB; seconds: nodes %.3f lists %.3f "
+              "rings %.3f tables %.3f tuning %.3f\n",
               pl.dim, pl.n[0], pl.n[1], pl.n[2], pl.nf[0], pl.nf[1], pl.nf[2], (long long)pl.M, (long long)pl.Mh,
               pl.width, pl.fp64 ? "fp64" : "mixed", pl.split ? "algorithm 2" : "algorithm 1",
               pl.r2c ? " (half spectrum)" : "", pl.tile_interp ? "by tiles" : "staged", pl.interp_chunk,
               pl.ring_spread ? -pl.ring_chunk : pl.spread_chunk, pl.ring_spread ? pl.nrtiles : pl.ngtiles,
               pl.ring_spread ? pl.nritems : pl.nitems, (long long)(pl.ring_spread ? pl.nrnodes : pl.nlist),
-              pl.workspace_bytes / 1e6);
+              pl.workspace_bytes / 1e6, t_phase[0], t_phase[1], t_phase[2], t_phase[3], t_phase[4]);
   }
   TRY_HIP(hipStreamSynchronize(pl.stream), "plan sync");
   TRY_HIP(hipGetLastError(), "plan kernels");

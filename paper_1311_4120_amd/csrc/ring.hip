@@ -365,20 +365,23 @@ __global__ void __launch_bounds__(256) k_ring_reduce_b(const RingReduceArgs<T>* 
 }  // namespace
 
 // Values between the LDS copies of two staged records: the staged length plus
-// whole 16-byte steps until the four records a product reads together start
-// at least eight 4-byte banks apart.
+// whole 16-byte steps until (a) the 16 records a batch writes, one 16-byte
+// piece each per instruction, fall on disjoint groups of four 4-byte banks,
+// and (b) the four records a product reads together start at least eight
+// banks apart.
 template <typename T>
 int ring_lds_stride(int width) {
   const int step = 16 / (int)sizeof(T);
   const int base = (3 * (width + 1) + step - 1) / step * step;  // a whole record (the a2 values of a ring's end)
+  auto bank = [](int i, int s) { return (i * s * (int)sizeof(T) / 4) % 64; };
   for (int s = base; s < base + 16 * step; s += step) {
     bool ok = true;
+    for (int i = 0; i < 16 && ok; ++i)
+      for (int k = 0; k < i && ok; ++k) ok = !(bank(i, s) < bank(k, s) + 4 && bank(k, s) < bank(i, s) + 4);
+    const int span = (int)sizeof(T) / 4;
     for (int i = 0; i < 4 && ok; ++i)
-      for (int k = 0; k < i && ok; ++k) {
-        const int span = (int)sizeof(T) / 4;
-        const int bi = (i * s * (int)sizeof(T) / 4) % 64, bk = (k * s * (int)sizeof(T) / 4) % 64;
-        ok = !(bi < bk + 8 * span && bk < bi + 8 * span);
-      }
+      for (int k = 0; k < i && ok; ++k)
+        ok = !(bank(i, s) < bank(k, s) + 8 * span && bank(k, s) < bank(i, s) + 8 * span);
     if (ok) return s;
   }
   return base;

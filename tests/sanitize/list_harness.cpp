@@ -126,9 +126,19 @@ static void run(const Case& c, bool nowrap_gather) {
   std::vector<int64_t> tcount;
   std::vector<Entry> list;
   std::vector<int> nstart, npos;
-  std::string err = gather_lists(g, nowrap, bias, sorted, tcount, list, true, nstart, npos);
+  std::string err = gather_lists(g, nowrap, bias, sorted, tcount, list, true, nstart, npos, 8);
   CHECK(err.empty(), "%s: gather_lists: %s", c.name, err.c_str());
   if (!err.empty()) return;
+  {
+    // the threaded build equals the serial one
+    std::vector<int64_t> tc1;
+    std::vector<Entry> l1;
+    std::vector<int> ns1, np1;
+    CHECK(gather_lists(g, nowrap, bias, sorted, tc1, l1, true, ns1, np1, 1).empty(), "%s: serial build", c.name);
+    bool same = tc1 == tcount && ns1 == nstart && np1 == npos && l1.size() == list.size();
+    for (size_t i = 0; same && i < l1.size(); ++i) same = l1[i].node == list[i].node && l1[i].code == list[i].code;
+    CHECK(same, "%s: threaded gather lists differ from the serial build", c.name);
+  }
   const int64_t ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
   int64_t total = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
@@ -169,9 +179,21 @@ static void run(const Case& c, bool nowrap_gather) {
   std::vector<int64_t> rcount;
   std::vector<int> rcost, rfirst;
   const int end_bit = 20, z_bit = 21, spare = 32;
-  err = ring_lists(g, bias, nph2, c.n_r * c.n_theta, perm, sorted, end_bit, z_bit, spare, rnodes, rcount, rcost, rfirst);
+  err = ring_lists(g, bias, nph2, c.n_r * c.n_theta, perm, sorted, end_bit, z_bit, spare, rnodes, rcount, rcost, rfirst,
+                   8);
   CHECK(err.empty(), "%s: ring_lists: %s", c.name, err.c_str());
   if (!err.empty()) return;
+  {
+    std::vector<Entry> r1;
+    std::vector<int64_t> rc1;
+    std::vector<int> cost1, first1;
+    CHECK(ring_lists(g, bias, nph2, c.n_r * c.n_theta, perm, sorted, end_bit, z_bit, spare, r1, rc1, cost1, first1, 1)
+              .empty(),
+          "%s: serial ring build", c.name);
+    bool same = rc1 == rcount && cost1 == rcost && first1 == rfirst && r1.size() == rnodes.size();
+    for (size_t i = 0; same && i < r1.size(); ++i) same = r1[i].node == rnodes[i].node && r1[i].code == rnodes[i].code;
+    CHECK(same, "%s: threaded ring lists differ from the serial build", c.name);
+  }
   int64_t listed = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
     const int t0 = (int)(t / ((int64_t)g.nt[1] * g.nt[2])), t1 = (int)((t / g.nt[2]) % g.nt[1]), t2 = (int)(t % g.nt[2]);

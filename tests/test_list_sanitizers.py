@@ -2,7 +2,8 @@
 CPU with the address and undefined-behaviour sanitizers and run on node sets up
 to N = 512 (1024 oversampled points per axis, where the 10-bit start codes are
 tightest), every list entry checked against a brute-force enumeration of the
-(node, tile) pairs whose footprints meet (tests/sanitize/list_harness.cpp)."""
+(node, tile) pairs whose footprints meet, and the threaded build against the
+serial one (tests/sanitize/list_harness.cpp)."""
 import os
 import shutil
 import subprocess
@@ -17,7 +18,7 @@ def test_list_construction_under_sanitizers(tmp_path):
     if cxx is None:
         pytest.fail("g++ is needed to build the sanitizer harness")
     exe = str(tmp_path / "list_harness")
-    cmd = [cxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+    cmd = [cxx, "-std=c++17", "-O1", "-g", "-pthread", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=all", "-I", os.path.join(ROOT, "paper_1311_4120_amd", "csrc"),
            os.path.join(ROOT, "tests", "sanitize", "list_harness.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
