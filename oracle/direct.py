@@ -232,7 +232,7 @@ def evaluate(problem, rho):
     k, W = fourier_nodes(problem)
     u, rh, c, im = potential(rho, problem.box, problem.kernel, k, W, problem.axis, problem.axis2, problem.alpha)
     K = problem.kmax if problem.kmax > 0 else default_kmax(problem.n, problem.box)
-    c0 = origin_coefficient(problem.kernel, K, problem.n_r)
+    c0 = origin_coefficient(problem.kernel, K, problem.n_r, getattr(problem, "radial", 0), problem.eps)
     r0 = _cell_volume(rho.shape, problem.box) * float(np.sum(rho))
     u = u + c0 * r0
     return Result(u=u,

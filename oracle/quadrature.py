@@ -30,8 +30,13 @@ def gauss_legendre(n: int):
     return s.astype(np.float64), w.astype(np.float64)
 
 
-def radial_rule(K: float, n_r: int):
-    """r_a = K (1 + s_a)/2, w_a = K omega_a / 2 on [0, K]."""
+def radial_rule(K: float, n_r: int, radial: int = 0, eps: float = 1e-10):
+    """r_a = K (1 + s_a)/2, w_a = K omega_a / 2 on [0, K]: Gauss-Legendre
+    (radial = 0), or the generalized Gaussian rule of ggq.py for band-limited
+    integrands (radial = 1) at accuracy eps."""
+    if radial == 1:
+        from .ggq import radial_rule_ggq
+        return radial_rule_ggq(K, n_r, eps)
     s, w = gauss_legendre(n_r)
     return 0.5 * K * (1.0 + s), 0.5 * K * w
 
@@ -53,9 +58,9 @@ def phi_rule(n_phi: int):
     return 2.0 * np.pi * l / n_phi, np.full(int(n_phi), 2.0 * np.pi / n_phi)
 
 
-def spherical_nodes(K, n_r, n_theta, n_phi, rule=THETA_GL):
+def spherical_nodes(K, n_r, n_theta, n_phi, rule=THETA_GL, radial=0, eps=1e-10):
     """k_j = r (sin th cos ph, sin th sin ph, cos th), W_j = w_r w_th w_ph.  Shapes (M,3), (M,)."""
-    r, wr = radial_rule(K, n_r)
+    r, wr = radial_rule(K, n_r, radial, eps)
     ct, st, wt = theta_rule(n_theta, rule)
     ph, wp = phi_rule(n_phi)
     R = r[:, None, None]
@@ -67,9 +72,9 @@ def spherical_nodes(K, n_r, n_theta, n_phi, rule=THETA_GL):
     return k, W.ravel()
 
 
-def polar_nodes(K, n_r, n_phi):
+def polar_nodes(K, n_r, n_phi, radial=0, eps=1e-10):
     """k_j = r (cos ph, sin ph), W_j = w_r w_ph.  Shapes (M,2), (M,)."""
-    r, wr = radial_rule(K, n_r)
+    r, wr = radial_rule(K, n_r, radial, eps)
     ph, wp = phi_rule(n_phi)
     k1 = r[:, None] * np.cos(ph)[None, :]
     k2 = r[:, None] * np.sin(ph)[None, :]
@@ -86,6 +91,7 @@ def default_kmax(n, box):
 def fourier_nodes(problem):
     """Nodes and weights of a workloads.Problem."""
     K = problem.kmax if problem.kmax > 0 else default_kmax(problem.n, problem.box)
+    radial = getattr(problem, "radial", 0)
     if problem.dim == 3:
-        return spherical_nodes(K, problem.n_r, problem.n_theta, problem.n_phi, problem.theta_rule)
-    return polar_nodes(K, problem.n_r, problem.n_phi)
+        return spherical_nodes(K, problem.n_r, problem.n_theta, problem.n_phi, problem.theta_rule, radial, problem.eps)
+    return polar_nodes(K, problem.n_r, problem.n_phi, radial, problem.eps)

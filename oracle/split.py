@@ -178,7 +178,7 @@ def energy_split_fourier(problem, rho, par=None, rh=None):
     if rh is None:
         rh = rho_hat(rho, problem.box, k)
     r0 = _cell_volume(rho.shape, problem.box) * float(np.sum(rho))
-    e2 = float(np.sum(c * np.abs(rh) ** 2)) + origin_coefficient(problem.kernel, problem.kmax, problem.n_r) * r0 * r0
+    e2 = float(np.sum(c * np.abs(rh) ** 2)) + origin_coefficient(problem.kernel, problem.kmax, problem.n_r, getattr(problem, "radial", 0), problem.eps) * r0 * r0
     e1 = i1_energy(rho, problem.box, problem.kernel, par, problem.axis, axis2=problem.axis2, alpha=problem.alpha)
     return 0.5 * problem.lam * (e1 + e2)
 
@@ -196,7 +196,7 @@ def potential_split(problem, rho, par=None):
     c = i2_coefficients(problem.kernel, k, W, par, problem.axis, problem.axis2, problem.alpha)
     i2 = sum_to_grid(c * rho_hat(rho, problem.box, k), k, rho.shape, problem.box).real
     # the node at k = 0 of the 2D Poisson kernel belongs to I2 (p(0) = 1)
-    i2 = i2 + origin_coefficient(problem.kernel, problem.kmax, problem.n_r) * _cell_volume(rho.shape, problem.box) * float(np.sum(rho))
+    i2 = i2 + origin_coefficient(problem.kernel, problem.kmax, problem.n_r, getattr(problem, "radial", 0), problem.eps) * _cell_volume(rho.shape, problem.box) * float(np.sum(rho))
     u = i1 + i2
     E = 0.5 * problem.lam * _cell_volume(rho.shape, problem.box) * float(np.sum(rho * u))
     return u, i1, i2, E

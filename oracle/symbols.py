@@ -55,7 +55,7 @@ def coefficients(kernel, k, W, axis=None, axis2=None, alpha=0.0):
     return W * symbol(kernel, k, axis, axis2, alpha) / (2.0 * np.pi) ** d
 
 
-def origin_coefficient(kernel, K, n_r):
+def origin_coefficient(kernel, K, n_r, radial=0, eps=1e-10):
     """The coefficient c_0 of the node k = 0 (zero for every kernel but the 2D Poisson one).
 
     For U = -(1/2pi) log|x| the radial integrand g(r)/r, g(r) = int rho^ e^{ik.x} dphi,
@@ -68,9 +68,10 @@ def origin_coefficient(kernel, K, n_r):
         sum_a (w_a / r_a) g(r_a) + g(0) (log K - sum_a w_a / r_a),
     exact when g is a polynomial of degree <= 2 n_r (then (g - g(0))/r has
     degree <= 2 n_r - 1).  So c_0 = (log K - sum_a w_a/r_a + gamma - log 2) / (2pi),
+    with (r_a, w_a) the radial rule in use (radial, eps: see quadrature.radial_rule),
     and the node adds c_0 rho^(0) = c_0 H sum rho to u everywhere."""
     if kernel != POISSON_2D:
         return 0.0
     from .quadrature import radial_rule
-    r, w = radial_rule(K, n_r)
+    r, w = radial_rule(K, n_r, radial, eps)
     return (np.log(K) - float(np.sum(w / r)) + EULER_GAMMA - np.log(2.0)) / (2.0 * np.pi)

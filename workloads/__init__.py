@@ -174,6 +174,9 @@ def random_wave_packets(rng, p=6, lo=-6.0, hi=6.0):
 
 # ---------------------------------------------------------------- configs
 
+RADIAL_GL, RADIAL_GGQ = 0, 1   # Gauss-Legendre, generalized Gaussian (band-limited)
+
+
 @dataclass
 class Problem:
     """One evaluation of u = U*rho: grid, box, kernel and Fourier node counts."""
@@ -193,6 +196,7 @@ class Problem:
     eps: float = 1e-10
     precision: int = FP64
     kmax: float = 0.0   # 0 -> pi / max_j h_j
+    radial: int = 0     # radial rule: RADIAL_GL or RADIAL_GGQ
 
     @property
     def npoints(self):
