@@ -132,6 +132,17 @@ typedef enum { JGB_THETA_GL = 0, JGB_COSTHETA_GL = 1 } jgb_theta_rule;
  * keeps the faster.  Results agree to rounding.  Costs two index tables of
  * about one entry per node and touched tile of device memory. */
 #define JGB_FLAG_SPREAD_RINGS 8u
+/* Radial nodes by a generalized Gaussian rule for band-limited integrands
+ * (Section 3.3's last remark; Conclusions) instead of Gauss-Legendre: along a
+ * ray the radial integrand rho^(r e) e^{i r e.x} is band-limited by the box's
+ * diameter, and the rule of Xiao, Rokhlin and Yarvin (nodes at the roots of a
+ * prolate spheroidal wave function psi_{n_r}^c, weights exact on psi_0 ..
+ * psi_{n_r - 1}) integrates such functions with fewer nodes.  The bandwidth is
+ * c = (pi/2)(n_r - 2 - 1.8 log10(10/eps) - 0.06 n_r) on [-1, 1] (jgb_info.
+ * radial_c; Gauss-Legendre when c < 1).  Any kernel; for JGB_POISSON_2D the
+ * node at k = 0 takes the rule's own weights.  UNSUPPORTED if the rule cannot
+ * be built (n_r > 2048). */
+#define JGB_FLAG_RADIAL_GGQ 16u
 
 typedef struct jgb_plan_s* jgb_plan_t;
 
@@ -194,6 +205,7 @@ typedef struct {
   uint32_t flags;          /* the plan's JGB_FLAG_* */
   double window[2];        /* JGB_FLAG_SPLIT: the window scales used (a, 0) or (R0, R1); else 0 */
   double origin_coef;      /* c_0 of the node at k = 0 (JGB_POISSON_2D; 0 for the others) */
+  double radial_c;         /* JGB_FLAG_RADIAL_GGQ: the radial rule's bandwidth c (0: Gauss-Legendre) */
 } jgb_info;
 
 /* Build a plan: validates the parameters, generates the Fourier nodes and

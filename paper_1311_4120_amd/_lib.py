@@ -28,6 +28,7 @@ FLAG_AUTOTUNE = 1
 FLAG_SPLIT = 2
 FLAG_INTERP_TILES = 4
 FLAG_SPREAD_RINGS = 8
+FLAG_RADIAL_GGQ = 16
 THETA_GL, COSTHETA_GL = 0, 1
 
 
@@ -73,6 +74,7 @@ class Info(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("window", ctypes.c_double * 2),
         ("origin_coef", ctypes.c_double),
+        ("radial_c", ctypes.c_double),
     ]
 
 

@@ -22,7 +22,7 @@ def _ptr(t):
 
 def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
                  autotune=False, split=False, window=(0.0, 0.0), axis2=None, alpha=0.0, interp_tiles=False,
-                 spread_rings=False):
+                 spread_rings=False, radial_ggq=False):
     dim = len(n)
     kern = _KERNELS.get(kernel, kernel)
     rule = _RULES.get(theta_rule, theta_rule)
@@ -50,7 +50,8 @@ def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, k
     p.device = dev
     p.stream = ctypes.c_void_p(st.cuda_stream)
     p.flags = ((_lib.FLAG_AUTOTUNE if autotune else 0) | (_lib.FLAG_SPLIT if split else 0)
-               | (_lib.FLAG_INTERP_TILES if interp_tiles else 0) | (_lib.FLAG_SPREAD_RINGS if spread_rings else 0))
+               | (_lib.FLAG_INTERP_TILES if interp_tiles else 0) | (_lib.FLAG_SPREAD_RINGS if spread_rings else 0)
+               | (_lib.FLAG_RADIAL_GGQ if radial_ggq else 0))
     for i in range(2):
         p.window[i] = float(window[i]) if i < len(window) else 0.0
     for i in range(3):
@@ -76,6 +77,8 @@ class Plan:
     spread_rings: spread ring by ring, each ring's nodes summed over the first
                two axes on the matrix cores and the ring sums spread along
                the last (3D)
+    radial_ggq: radial nodes by the generalized Gaussian rule for band-limited
+               integrands (prolate spheroidal) instead of Gauss-Legendre
     """
 
     def __init__(self, n: Sequence[int], box: Sequence[float], kernel, nodes: Sequence[int],
@@ -84,9 +87,9 @@ class Plan:
                  device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, autotune: bool = False,
                  split: bool = False, window: Sequence[float] = (0.0, 0.0),
                  axis2: Optional[Sequence[float]] = None, alpha: float = 0.0, interp_tiles: bool = False,
-                 spread_rings: bool = False):
+                 spread_rings: bool = False, radial_ggq: bool = False):
         p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                                  autotune, split, window, axis2, alpha, interp_tiles, spread_rings)
+                                  autotune, split, window, axis2, alpha, interp_tiles, spread_rings, radial_ggq)
         self._init_from(p, dev, st, box)
         h = ctypes.c_void_p()
         check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))

@@ -792,6 +792,7 @@ jgb_status jgb_plan_info(jgb_plan_t plan, jgb_info* info) {
   info->window[0] = pl.split ? pl.win[0] : 0.0;
   info->window[1] = pl.split ? pl.win[1] : 0.0;
   info->origin_coef = pl.c0;
+  info->radial_c = pl.radial_c;
   info->workspace_bytes = (int64_t)pl.workspace_bytes;
   info->interp_chunk = pl.tile_interp ? 0 : pl.interp_chunk;
   info->spread_chunk = pl.ring_spread ? -pl.ring_chunk : pl.spread_chunk;

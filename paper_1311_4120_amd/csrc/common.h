@@ -126,6 +126,7 @@ struct Plan {
   double box[3] = {1, 1, 1};
   double H = 1.0;          // cell volume prod h_j over physical axes
   double K = 0.0;          // radius of the Fourier ball
+  double radial_c = 0.0;   // bandwidth of the generalized Gaussian radial rule (0: Gauss-Legendre)
   double axis2[3] = {0, 0, 0};  // second dipole orientation m (= the dipole axis n unless given)
   int width = 0;
   double beta = 0.0;

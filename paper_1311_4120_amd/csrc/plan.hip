@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include "lists.h"
+#include "radial.h"
 
 namespace jgb {
 
@@ -599,8 +600,11 @@ Status validate(const jgb_params* p) {
   double kn = M_PI / hmax;
   if (!(std::isfinite(p->kmax) && p->kmax >= 0)) return fail(JGB_ERR_INVALID_ARG, "kmax must be finite and >= 0");
   if (p->kmax > kn * (1 + 1e-12)) return fail(JGB_ERR_INVALID_ARG, "kmax must not exceed pi / max_j h_j");
-  if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT | JGB_FLAG_INTERP_TILES | JGB_FLAG_SPREAD_RINGS))
+  if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT | JGB_FLAG_INTERP_TILES | JGB_FLAG_SPREAD_RINGS |
+                   JGB_FLAG_RADIAL_GGQ))
     return fail(JGB_ERR_INVALID_ARG, "unknown flags");
+  if ((p->flags & JGB_FLAG_RADIAL_GGQ) && p->n_r > 2048)
+    return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_RADIAL_GGQ needs n_r <= 2048");
   if ((p->flags & JGB_FLAG_INTERP_TILES) && p->dim != 3)
     return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_INTERP_TILES needs dim == 3");
   if ((p->flags & JGB_FLAG_SPREAD_RINGS) && p->dim != 3)
@@ -799,7 +803,17 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   // 1D rules on the device
   TRY(dev_alloc(pl, &pl.d_gl_r, 2 * sizeof(double) * pl.n_r));
   TRY(dev_alloc(pl, &pl.d_gl_t, 2 * sizeof(double) * pl.n_theta));
-  TRY_HIP(launch_gl_roots(pl.n_r, pl.d_gl_r, pl.stream), "gl roots");
+  pl.radial_c = (p->flags & JGB_FLAG_RADIAL_GGQ) ? radial::bandwidth(pl.n_r, p->eps) : 0.0;
+  if (pl.radial_c > 0.0) {
+    // the generalized Gaussian rule on [-1, 1], built on the host
+    std::vector<double> x, w;
+    const std::string err = radial::prolate_rule(pl.radial_c, pl.n_r, x, w);
+    if (!err.empty()) return fail(JGB_ERR_UNSUPPORTED, "radial rule: " + err);
+    x.insert(x.end(), w.begin(), w.end());
+    TRY(upload(pl, pl.d_gl_r, x.data(), sizeof(double) * 2 * pl.n_r));
+  } else {
+    TRY_HIP(launch_gl_roots(pl.n_r, pl.d_gl_r, pl.stream), "gl roots");
+  }
   TRY_HIP(launch_gl_roots(pl.n_theta, pl.d_gl_t, pl.stream), "gl roots");
   if (p->kernel == JGB_POISSON_2D) {
     // the node at k = 0 of the finite-part radial rule: with r_a = K (1 + s_a)/2

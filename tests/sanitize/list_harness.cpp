@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "lists.h"
+#include "radial.h"
 
 using namespace jgb::lists;
 
@@ -234,7 +235,18 @@ static void run(const Case& c, bool nowrap_gather) {
   CHECK((int64_t)rnodes.size() == listed + spare, "%s: spare ring entries", c.name);
 }
 
-int main() {
+int main(int argc, char** argv) {
+  if (argc == 4 && std::string(argv[1]) == "radial") {
+    // the plan's generalized Gaussian radial rule of bandwidth c with n nodes
+    std::vector<double> x, w;
+    const std::string err = jgb::radial::prolate_rule(atof(argv[2]), atoi(argv[3]), x, w);
+    if (!err.empty()) {
+      fprintf(stderr, "%s\n", err.c_str());
+      return 1;
+    }
+    for (size_t i = 0; i < x.size(); ++i) printf("%.17g %.17g\n", x[i], w[i]);
+    return 0;
+  }
   const Case cases[] = {
       // N = 512: the oversampled side 1024, the largest the 10-bit codes allow
       {"3d_512_w12", 3, {1024, 1024, 1024}, 12, 24, 16, 32, {8, 8, 8}, false},

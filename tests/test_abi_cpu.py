@@ -112,7 +112,8 @@ BAD = [
     ("odd n_phi", dict(n_phi=7), 1),
     ("theta rule", dict(theta_rule=5), 1),
     ("kmax too large", dict(kmax=100.0), 1),
-    ("flags", dict(flags=16), 1),
+    ("flags", dict(flags=32), 1),
+    ("radial rule too large", dict(flags=16, n_r=4096), 2),
     ("interp tiles in 2D", dict(flags=4, dim=2, kernel=1), 2),
     ("spread rings in 2D", dict(flags=8, dim=2, kernel=1), 2),
     ("window without split", dict(window=(1.0, 0.0)), 1),

@@ -1,19 +1,23 @@
-"""The host list construction (csrc/lists.h, which the plan calls) built for the
-CPU with the address and undefined-behaviour sanitizers and run on node sets up
-to N = 512 (1024 oversampled points per axis, where the 10-bit start codes are
-tightest), every list entry checked against a brute-force enumeration of the
-(node, tile) pairs whose footprints meet, and the threaded build against the
-serial one (tests/sanitize/list_harness.cpp)."""
+"""The host list construction (csrc/lists.h) and radial rule (csrc/radial.h),
+which the plan calls, built for the CPU with the address and
+undefined-behaviour sanitizers (tests/sanitize/list_harness.cpp):
+
+  * the lists on node sets up to N = 512 (1024 oversampled points per axis,
+    where the 10-bit start codes are tightest), every entry checked against a
+    brute-force enumeration of the (node, tile) pairs whose footprints meet,
+    and the threaded build against the serial one;
+  * the generalized Gaussian radial rule against the oracle's."""
 import os
 import shutil
 import subprocess
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_list_construction_under_sanitizers(tmp_path):
+def _build(tmp_path):
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.fail("g++ is needed to build the sanitizer harness")
@@ -23,10 +27,33 @@ def test_list_construction_under_sanitizers(tmp_path):
            os.path.join(ROOT, "tests", "sanitize", "list_harness.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-4000:]
+    return exe
+
+
+def _env():
     # verify_asan_link_order=0: the runtime need not come first among the
     # libraries the environment loads
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0",
-               UBSAN_OPTIONS="print_stacktrace=1")
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    return dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1:verify_asan_link_order=0",
+                UBSAN_OPTIONS="print_stacktrace=1")
+
+
+def test_list_construction_under_sanitizers(tmp_path):
+    exe = _build(tmp_path)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=_env())
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert r.stdout.strip() == "ok"
+
+
+@pytest.mark.parametrize("c,n", [(30.7247761521, 44), (3.5, 24), (116.6, 96)])
+def test_host_radial_rule_matches_the_oracle(tmp_path, c, n):
+    """The plan's generalized Gaussian radial rule (Sturm bisection and inverse
+    iteration for the prolate functions, bisection for their roots) against the
+    oracle's (scipy's tridiagonal eigensolver and root finder)."""
+    from oracle.ggq import prolate_rule
+    exe = _build(tmp_path)
+    r = subprocess.run([exe, "radial", repr(c), str(n)], capture_output=True, text=True, timeout=300, env=_env())
+    assert r.returncode == 0, r.stderr[-2000:]
+    got = np.array([[float(v) for v in line.split()] for line in r.stdout.strip().splitlines()])
+    x, w = prolate_rule(c, n)
+    assert got.shape == (n, 2)
+    assert np.max(np.abs(got[:, 0] - x)) < 1e-13 and np.max(np.abs(got[:, 1] - w)) < 1e-13
