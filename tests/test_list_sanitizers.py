@@ -17,6 +17,11 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    return _build(tmp_path_factory.mktemp("sanitize"))
+
+
 def _build(tmp_path):
     cxx = shutil.which("g++")
     if cxx is None:
@@ -37,20 +42,20 @@ def _env():
                 UBSAN_OPTIONS="print_stacktrace=1")
 
 
-def test_list_construction_under_sanitizers(tmp_path):
-    exe = _build(tmp_path)
+def test_list_construction_under_sanitizers(harness):
+    exe = harness
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=_env())
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert r.stdout.strip() == "ok"
 
 
 @pytest.mark.parametrize("c,n", [(30.7247761521, 44), (3.5, 24), (116.6, 96)])
-def test_host_radial_rule_matches_the_oracle(tmp_path, c, n):
+def test_host_radial_rule_matches_the_oracle(harness, c, n):
     """The plan's generalized Gaussian radial rule (Sturm bisection and inverse
     iteration for the prolate functions, bisection for their roots) against the
     oracle's (scipy's tridiagonal eigensolver and root finder)."""
     from oracle.ggq import prolate_rule
-    exe = _build(tmp_path)
+    exe = harness
     r = subprocess.run([exe, "radial", repr(c), str(n)], capture_output=True, text=True, timeout=300, env=_env())
     assert r.returncode == 0, r.stderr[-2000:]
     got = np.array([[float(v) for v in line.split()] for line in r.stdout.strip().splitlines()])
