@@ -22,13 +22,19 @@ namespace {
 
 // candidate work-item sizes; the first of each is the smallest and sizes the buffers
 constexpr int kInterpChunks[] = {256, 512, 1024, 2048};
-constexpr int kSpreadChunks[] = {1024, 2048, 4096, 8192};
+constexpr int kSpreadChunks[] = {256, 512, 1024, 2048, 4096, 8192};
 // the autotuner's record of the interpolation by tiles in place of a chunk size
 constexpr int kTileInterp = -1;
 // node entries per work item of the ring-factored spreading (a ring entry
 // counts as kRingEntryCost node entries)
-constexpr int kRingChunks[] = {2048, 4096, 8192, 16384};
+constexpr int kRingChunks[] = {512, 1024, 2048, 4096, 8192, 16384};
 constexpr int kRingEntryCost = 8;
+// The chunks below 1024 (2048 by rings) are tried only for small node sets
+// (such as Algorithm 2's I2), where a few long items would leave most CUs
+// idle; for large sets their partial tiles would not pay.
+constexpr int64_t kSmallNodeSet = 65536;
+int min_spread_chunk(int64_t Mh) { return Mh <= kSmallNodeSet ? 256 : 1024; }
+int min_ring_chunk(int64_t Mh) { return Mh <= kSmallNodeSet ? 512 : 2048; }
 constexpr size_t kInterpLdsMax = kInterpLdsCap;
 
 bool is_235(int64_t n) {
@@ -346,6 +352,7 @@ Status build_ring_lists(Plan& pl, const std::vector<int>& perm, const std::vecto
   int nslots = 0;
   pl.ritems_cap = pl.rmulti_cap = pl.rslots_cap = 0;
   for (int c : kRingChunks) {
+    if (c < min_ring_chunk(pl.Mh)) continue;
     ring_items(pl, c, items, multi, nslots);
     pl.ritems_cap = std::max(pl.ritems_cap, (int)items.size());
     pl.rmulti_cap = std::max(pl.rmulti_cap, (int)multi.size());
@@ -517,6 +524,7 @@ Status autotune(Plan& pl) {
   pl.ring_spread = false;
   if (!forced_rings) {
     for (int c : kSpreadChunks) {
+      if (c < min_spread_chunk(pl.Mh)) continue;
       TRY(apply_spread_chunk(pl, c));
       double ms;
       TRY(pl.fp64 ? time_stage<double>(pl, false, ms) : time_stage<float>(pl, false, ms));
@@ -533,6 +541,7 @@ Status autotune(Plan& pl) {
     int rc = 0;
     double best_r = 1e30;
     for (int c : kRingChunks) {
+      if (c < min_ring_chunk(pl.Mh)) continue;
       TRY(apply_ring_chunk(pl, c));
       double ms;
       TRY(pl.fp64 ? time_stage<double>(pl, false, ms) : time_stage<float>(pl, false, ms));
@@ -948,12 +957,13 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     int nslots = 0;
     pl.items_cap = pl.multi_cap = pl.slots_cap = 0;
     for (int c : kSpreadChunks) {
+      if (c < min_spread_chunk(pl.Mh)) continue;
       spread_items(pl, c, items, multi, nslots);
       pl.items_cap = std::max(pl.items_cap, (int)items.size());
       pl.multi_cap = std::max(pl.multi_cap, (int)multi.size());
       pl.slots_cap = std::max(pl.slots_cap, nslots);
     }
-    while (pl.spread_chunk > kSpreadChunks[0]) {
+    while (pl.spread_chunk > min_spread_chunk(pl.Mh)) {
       spread_items(pl, pl.spread_chunk, items, multi, nslots);
       if ((int)items.size() >= fill_items) break;
       pl.spread_chunk /= 2;
@@ -969,7 +979,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
       // the untuned ring chunk: halved while a launch would have fewer than
       // two work items per CU
       std::vector<RingItem> ritems;
-      while (pl.ring_chunk > kRingChunks[0]) {
+      while (pl.ring_chunk > min_ring_chunk(pl.Mh)) {
         ring_items(pl, pl.ring_chunk, ritems, multi, nslots);
         if ((int)ritems.size() >= fill_items) break;
         pl.ring_chunk /= 2;

@@ -25,7 +25,7 @@ def test_autotune_and_cache(prec, tmp_path, monkeypatch):
     say("   chose interp %d spread %d" % (ic, sc))
     # 0: the interpolation by tiles on the matrix cores was faster; a negative
     # spread chunk: the spreading by rings was
-    assert ic in (0, 256, 512, 1024, 2048) and sc in (1024, 2048, 4096, 8192, -2048, -4096, -8192, -16384)
+    assert ic in (0, 256, 512, 1024, 2048) and sc in (256, 512, 1024, 2048, 4096, 8192, -512, -1024, -2048, -4096, -8192, -16384)
     data = json.loads(cache.read_text())
     assert len(data) == 1
     entry = next(iter(data.values()))
