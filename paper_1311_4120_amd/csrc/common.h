@@ -221,6 +221,10 @@ struct Plan {
   // completes each line by symmetry.
   bool r2c = false;
   int h2 = 0, hs2 = 0;
+  // per line of G along the inverse's first axis (lines q1 nf2 + q2 in 3D,
+  // q2 in 2D): the circular range {first, span} the spreading can write;
+  // the first inverse pass reads zero outside it (Algorithm 1)
+  int2* d_gext = nullptr;
   int* d_nstart = nullptr;     // Mh + 1 offsets into d_npos
   int* d_npos = nullptr;       // nlist list positions, node-major
   void* d_ipart = nullptr;     // nlist complex T: per list entry, the tile's share of the node's value

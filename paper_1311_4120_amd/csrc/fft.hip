@@ -172,7 +172,9 @@ __device__ inline void dft(C2<T>* v, T s) {
 // KINETIC: the GPE driver's kinetic step along one strided axis: the forward
 // transform, the multiplier exp(-i h |k|^2 / 2) / N (imaginary time:
 // exp(-h |k|^2 / 2) / N), and the inverse transform, in LDS.
-enum PassKind { PASS_FWD_Z = 0, PASS_COMPLEX = 1, PASS_INV_Z = 2, PASS_COMPLEX_Z = 3, PASS_KINETIC = 4 };
+// HSYM: the inverse's first pass on a real output, a strided complex pass
+// whose input is the Hermitian part of the spreading grid.
+enum PassKind { PASS_FWD_Z = 0, PASS_COMPLEX = 1, PASS_INV_Z = 2, PASS_COMPLEX_Z = 3, PASS_KINETIC = 4, PASS_HSYM = 5 };
 template <int KIND>
 constexpr bool has_factors() { return KIND == PASS_FWD_Z || KIND == PASS_INV_Z; }
 
@@ -210,11 +212,15 @@ struct PassArgs {
   // Hermitian half along the last axis (real input, Algorithm 1): the forward
   // Z pass stores only outputs 0 .. nout - 1 = L/2 (half_out); the inverse Z
   // pass loads those nin = L/2 + 1 values and completes the line by
-  // v(L - p) = conj v(p) (half_in); the inverse's first pass averages each
-  // element with the conjugate of its mirror, v(q) = (g(q) + conj g(-q)) / 2,
-  // the mirror of line (outer, inner) and element e being
-  // (-outer mod sym_no, -inner mod sym_ni, -e mod L) (hsym)
-  int half_out, half_in, hsym, sym_no, sym_ni;
+  // v(L - p) = conj v(p) (half_in); the inverse's first pass (PASS_HSYM)
+  // averages each element with the conjugate of its mirror,
+  // v(q) = (g(q) + conj g(-q)) / 2, the mirror of line (outer, inner) and
+  // element e being (-outer mod sym_no, -inner mod sym_ni, -e mod L)
+  int half_out, half_in, sym_no, sym_ni;
+  // PASS_HSYM: per input line (outer sym_ni + inner), the circular range
+  // {first, span} of elements the spreading can have written; the pass takes
+  // the other elements as zero without loading them
+  const int2* lext;
   // the paired passes of Algorithm 2 (k_fft_pair_pass): lines are
   // (a, b) of an A x B set, element stride es_in / es_out; P lines and their
   // mirrors per block; nb1 blocks for the rows 0 < a < A/2 (cb per row), then cs
@@ -295,7 +301,7 @@ __device__ inline void stage(C2<T>* lds, int ldl, int L, int LB, int Ns, const F
 // consecutive lines, the Z passes along the contiguous axis.
 template <typename T, int KIND, int MAXV, int NT>
 __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int blk) {
-  constexpr bool LINES_FASTEST = (KIND == PASS_COMPLEX || KIND == PASS_KINETIC);
+  constexpr bool LINES_FASTEST = (KIND == PASS_COMPLEX || KIND == PASS_KINETIC || KIND == PASS_HSYM);
   extern __shared__ unsigned char smem_raw[];
   C2<T>* lds = reinterpret_cast<C2<T>*>(smem_raw);
   const int L = a.L;
@@ -333,18 +339,42 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
   if constexpr (has_factors<KIND>()) __syncthreads();  // factors staged
 
   double macc = 0.0;  // forward Z: the block's sum of rho
-  // load
+  // load: every load is issued before any loaded value is used, so that they
+  // are in flight together; masked elements load from a valid index instead
+  // of branching around the load, and their values are dropped afterwards
   {
     const int total_in = LB * a.nin;
+    constexpr bool HSYM = KIND == PASS_HSYM;
     C2<T> buf[MAXV];
+    T rbuf[KIND == PASS_FWD_Z ? MAXV : 1];
+    C2<T> mir[HSYM ? MAXV : 1];
     int dst[MAXV];
     int le[MAXV];  // Z pass: line (high bits) and element (low 16 bits)
+    unsigned keep = 0, keepm = 0;  // bit i: element i's value (its mirror's) is used
+    // HSYM: LB divides NT, so all of a thread's elements lie on one line, whose
+    // mirror line and reaches are read once, before the element loads
+    int hl = 0, hlo = 0, hli = 0, hmo = 0, hmi = 0;
+    bool hlok = false;
+    int2 xp{0, -1}, xm{0, -1};
+    if constexpr (HSYM) {
+      hl = threadIdx.x - (int)a.dLB.div(threadIdx.x) * LB;
+      const int line = line0 + hl;
+      hlok = line < a.nlines;
+      const int ln = hlok ? line : 0;
+      hlo = (int)a.dic.div(ln);
+      hli = ln - hlo * (int)a.ic;
+      hmo = hlo ? a.sym_no - hlo : 0;
+      hmi = hli ? a.sym_ni - hli : 0;
+      xp = a.lext[(int64_t)hlo * a.sym_ni + hli];
+      xm = a.lext[(int64_t)hmo * a.sym_ni + hmi];
+    }
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       // slots past the block's inputs (padded passes load N of L) issue nothing;
-      // the test is uniform across the block
-      if (i * NT >= total_in) {
-        buf[i] = C2<T>{T(0), T(0)};
+      // the test is uniform across the block.  HSYM takes no such branch (its
+      // line reaches must stay visibly loaded across the slots): its empty
+      // slots are masked lanes
+      if (!HSYM && i * NT >= total_in) {
         dst[i] = -1;
         le[i] = 0;
         continue;
@@ -360,24 +390,36 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
         l = (int)a.dnin.div(idx);
         e = idx - l * a.nin;
       }
+      if constexpr (HSYM) {
+        // elements beyond their line's reach are zero: not fetched
+        const bool lok = ok && hlok;
+        const int me = e ? L - e : 0;
+        int dp = e - xp.x, dm = me - xm.x;
+        dp += dp < 0 ? L : 0;
+        dm += dm < 0 ? L : 0;
+        const bool in_p = lok && dp <= xp.y, in_m = lok && dm <= xm.y;
+        const int64_t base = (int64_t)hlo * a.in_os + (int64_t)hli * a.in_is + (int64_t)e * a.in_es;
+        const int64_t mbase = (int64_t)hmo * a.in_os + (int64_t)hmi * a.in_is + (int64_t)me * a.in_es;
+        buf[i] = ((const C2<T>*)a.in)[in_p ? base : 0];
+        mir[i] = ((const C2<T>*)a.in)[in_m ? mbase : 0];
+        keep |= (unsigned)in_p << i;
+        keepm |= (unsigned)in_m << i;
+        dst[i] = ok ? hl * ldl + e : -1;
+        le[i] = 0;
+        continue;
+      }
       const int line = line0 + l;
       const bool lok = ok && line < a.nlines;
       const int ln = lok ? line : 0;
       const int lo = (int)a.dic.div(ln);
-      const int64_t base = (int64_t)lo * a.in_os + (int64_t)(ln - lo * (int)a.ic) * a.in_is + (int64_t)e * a.in_es;
+      const int li = ln - lo * (int)a.ic;
+      const int64_t base = (int64_t)lo * a.in_os + (int64_t)li * a.in_is + (int64_t)e * a.in_es;
       if constexpr (KIND == PASS_FWD_Z) {
-        const T r = ((const T*)a.in)[base];
-        buf[i] = C2<T>{lok ? r : T(0), T(0)};
+        rbuf[i] = ((const T*)a.in)[base];
+        keep |= (unsigned)lok << i;
       } else {
-        C2<T> v = ((const C2<T>*)a.in)[base];
-        if (a.hsym) {
-          const int li = ln - lo * (int)a.ic;
-          const int mo = lo ? a.sym_no - lo : 0, mi = li ? a.sym_ni - li : 0, me = e ? L - e : 0;
-          const C2<T> m =
-              ((const C2<T>*)a.in)[(int64_t)mo * a.in_os + (int64_t)mi * a.in_is + (int64_t)me * a.in_es];
-          v = C2<T>{T(0.5) * (v.x + m.x), T(0.5) * (v.y - m.y)};
-        }
-        buf[i] = lok ? v : C2<T>{T(0), T(0)};
+        buf[i] = ((const C2<T>*)a.in)[base];
+        keep |= (unsigned)lok << i;
       }
       const int pos = (a.nin < L && !a.half_in) ? fine_pos(e, a.nin, L) : e;
       dst[i] = ok ? l * ldl + pos : -1;
@@ -386,13 +428,22 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       if (dst[i] >= 0) {
-        C2<T> v = buf[i];
+        const bool use = (keep >> i) & 1u;
+        C2<T> v;
         if constexpr (KIND == PASS_FWD_Z) {
           // deconvolution and cell volume, applied in float64
+          const T r = use ? rbuf[i] : T(0);
           const double d = fline[le[i] >> 16] * felem[le[i] & 0xffff];
-          macc += (double)v.x;
-          if (a.split) v.y = (T)((double)v.x * a.scale);
-          v.x = (T)((double)v.x * d);
+          macc += (double)r;
+          v.y = a.split ? (T)((double)r * a.scale) : T(0);
+          v.x = (T)((double)r * d);
+        } else if constexpr (HSYM) {
+          const bool usem = (keepm >> i) & 1u;
+          const T px = use ? buf[i].x : T(0), py = use ? buf[i].y : T(0);
+          const T mx = usem ? mir[i].x : T(0), my = usem ? mir[i].y : T(0);
+          v = C2<T>{T(0.5) * (px + mx), T(0.5) * (py - my)};
+        } else {
+          v = use ? buf[i] : C2<T>{T(0), T(0)};
         }
         lds[dst[i]] = v;
       }
@@ -907,14 +958,15 @@ void factor(int L, int* rad, int& nrad, bool radix16 = false) {
 constexpr int PASS_PAIR = 9;
 template <typename T, int KIND = PASS_PAIR>
 constexpr int pass_threads() {
-  if (KIND == PASS_COMPLEX || KIND == PASS_KINETIC) return sizeof(T) == 8 ? 256 : 512;
+  if (KIND == PASS_COMPLEX || KIND == PASS_KINETIC || KIND == PASS_HSYM) return sizeof(T) == 8 ? 256 : 512;
   if (KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 256;
   if (KIND == PASS_PAIR) return 256;
   return 512;
 }
 template <typename T, int KIND = PASS_PAIR>
 constexpr int pass_elems() {
-  if (KIND == PASS_COMPLEX || KIND == PASS_KINETIC || KIND == PASS_FWD_Z || KIND == PASS_INV_Z) return 8;
+  if (KIND == PASS_COMPLEX || KIND == PASS_KINETIC || KIND == PASS_HSYM || KIND == PASS_FWD_Z || KIND == PASS_INV_Z)
+    return 8;
   return sizeof(T) == 8 ? 8 : 16;
 }
 template <typename T, int KIND>
@@ -938,6 +990,8 @@ int lines_per_block(int L) {
   int lb = cap / L;
   if (lb > maxlb) lb = maxlb;
   if (lb < 1) lb = 1;
+  if (KIND == PASS_HSYM)  // a power of two, dividing the block's threads
+    while (lb & (lb - 1)) lb &= lb - 1;
   return lb;
 }
 
@@ -954,6 +1008,8 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
     }
   }
   if (a.nlines >= (1 << 30) || (int64_t)a.LB * a.L >= (1 << 30)) return hipErrorInvalidValue;
+  // whole lines, with reaches; a thread's elements on one line
+  if (KIND == PASS_HSYM && (a.nin != a.L || !a.lext || pass_threads<T, KIND>() % a.LB != 0)) return hipErrorInvalidValue;
   a.dLB = FastDiv((uint32_t)a.LB);
   a.dnin = FastDiv((uint32_t)a.nin);
   a.dnout = FastDiv((uint32_t)a.nout);
@@ -1224,9 +1280,9 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.out_is = 1;
     a.out_es = f1 * r2;
     a.lines_fastest = 1;
-    a.hsym = pl.r2c ? 1 : 0;
     a.sym_no = (int)f1;
     a.sym_ni = (int)f2;
+    a.lext = pl.d_gext;
     a.in = src;
     a.out = B2;
     if (pl.split) {
@@ -1234,7 +1290,7 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
       b.out = B2;
       e = run_pair_pass<T, PAIR_FUSED>(pl, ST_INV_X, b, s);
     } else {
-      e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_X, a, s);
+      e = run_pass<T, PASS_HSYM>(pl, ST_INV_X, a, s);  // r2c: Algorithm 1
     }
     if (e != hipSuccess) return e;
   }
@@ -1256,12 +1312,14 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.out_is = 1;
     a.out_es = r2;
     a.lines_fastest = 1;
-    a.hsym = (pl.r2c && !has_x) ? 1 : 0;
     a.sym_no = 1;
     a.sym_ni = (int)f2;
+    a.lext = pl.d_gext;
     a.in = B2;
     a.out = B1;
-    if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_INV_Y, a, s)) != hipSuccess) return e;
+    // in 2D the first pass (Algorithm 1, real output), else a plain strided pass
+    e = has_x ? run_pass<T, PASS_COMPLEX>(pl, ST_INV_Y, a, s) : run_pass<T, PASS_HSYM>(pl, ST_INV_Y, a, s);
+    if (e != hipSuccess) return e;
   }
   {  // Z: B1 -> u [n0][n1][n2], real part, deconvolution, energy partials
     PassArgs<T> a = base_args<T>(pl, 2, T(1));

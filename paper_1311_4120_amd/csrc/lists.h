@@ -12,6 +12,9 @@
 //     their a2 footprint), the ring's nodes that touch the tile, each ring
 //     padded to whole groups of four, its last entry flagged and carrying the
 //     ring's a2 start.
+//   line_extents: for every line of the spreading grid along the inverse
+//     transform's first axis, the range of positions the nodes' footprints
+//     can reach (the grid is zero elsewhere).
 //
 // Starts are the nodes' first taps wrapped into [0, nf).  A tile-relative
 // start is stored, when every axis has nf >= T + w - 1, as its one
@@ -295,6 +298,66 @@ inline std::string ring_lists(const Geometry& g, int bias, int nph2, int nrings,
     }
   });
   if (bad) return "ring list start out of range";
+  return "";
+}
+
+struct Extent {  // the layout of an int2 line extent
+  int first, span;
+};
+
+// The spreading writes kernel values only inside the nodes' footprints, so a
+// line of the spreading grid along axis ax (0, or 1 when axis 0 is a unit
+// axis) is zero outside the footprints that cross it.  Per line (index
+// q_a nf[2] + q2 over the two other axes a, 2), ext gets the circular range
+// {first, span} of positions first .. first + span (mod nf[ax]) that holds
+// every footprint crossing the line: span -1 for a line none crosses, span
+// nf[ax] - 1 for the whole line.  Each footprint is taken at its start's
+// representative in (-nf/2, nf/2], and the range is the hull of those in
+// unwrapped positions.
+inline std::string line_extents(const Geometry& g, int ax, const std::vector<Start>& hdr, std::vector<Extent>& ext,
+                                int threads = 1) {
+  if (ax != 0 && ax != 1) return "line axis must be 0 or 1";
+  for (int a = 0; a < 3; ++a)
+    if (g.w[a] < 1 || g.w[a] > kMaxTaps || g.w[a] > g.nf[a]) return "width out of range";
+  const int oa = ax == 0 ? 1 : 0;  // the other axis besides 2
+  const int nf = g.nf[ax], w = g.w[ax];
+  const int64_t nlines = (int64_t)g.nf[oa] * g.nf[2];
+  const int64_t Mh = (int64_t)hdr.size();
+  threads = usable_threads(threads, Mh, 2 * nlines);
+  // per thread: the lowest and highest unwrapped position per line
+  std::vector<std::vector<int>> lo(threads), hi(threads);
+  parallel_ranges(Mh, threads, [&](int64_t j0, int64_t j1, int t) {
+    std::vector<int>& L = lo[t];
+    std::vector<int>& H = hi[t];
+    L.assign(nlines, INT32_MAX);
+    H.assign(nlines, INT32_MIN);
+    for (int64_t j = j0; j < j1; ++j) {
+      const int st[3] = {hdr[j].x, hdr[j].y, hdr[j].z};
+      const int s = 2 * st[ax] > nf ? st[ax] - nf : st[ax];
+      for (int da = 0; da < g.w[oa]; ++da) {
+        const int qa = (st[oa] + da) % g.nf[oa];
+        for (int d2 = 0; d2 < g.w[2]; ++d2) {
+          const int64_t line = (int64_t)qa * g.nf[2] + (st[2] + d2) % g.nf[2];
+          L[line] = std::min(L[line], s);
+          H[line] = std::max(H[line], s + w - 1);
+        }
+      }
+    }
+  });
+  ext.assign(nlines, Extent{0, -1});
+  for (int64_t line = 0; line < nlines; ++line) {
+    int l = INT32_MAX, h = INT32_MIN;
+    for (int t = 0; t < threads; ++t) {
+      if (lo[t].empty()) continue;
+      l = std::min(l, lo[t][line]);
+      h = std::max(h, hi[t][line]);
+    }
+    if (l > h) continue;
+    if (h - l >= nf - 1)
+      ext[line] = Extent{0, nf - 1};
+    else
+      ext[line] = Extent{((l % nf) + nf) % nf, h - l};
+  }
   return "";
 }
 

@@ -938,6 +938,23 @@ Status build_plan(Plan& pl, const jgb_params* p) {
   pl.nlist = nlist;
 
   pl.h_tcount = tcount;
+  if (pl.r2c) {
+    // the spreading grid's reach per line of the inverse's first pass (axis
+    // 0 in 3D, axis 1 in 2D): that pass reads zero beyond it
+    lists::Geometry g{};
+    for (int a = 0; a < 3; ++a) {
+      g.nf[a] = pl.nf[a];
+      g.T[a] = 1;
+      g.nt[a] = pl.nf[a];
+      g.w[a] = pl.w[a];
+    }
+    std::vector<lists::Extent> ext;
+    const std::string err = lists::line_extents(g, pl.nf[0] > 1 ? 0 : 1, hdr, ext, host_threads());
+    if (!err.empty()) return fail(JGB_ERR_UNSUPPORTED, err);
+    static_assert(sizeof(lists::Extent) == sizeof(int2), "line extents are int2 on the device");
+    TRY(dev_alloc(pl, &pl.d_gext, sizeof(int2) * ext.size()));
+    TRY(upload(pl, pl.d_gext, ext.data(), sizeof(int2) * ext.size()));
+  }
   t_phase[1] = since(t_lists);
   const auto t_rings = std::chrono::steady_clock::now();
   // the ring tables (3D; built when forced or for the tuner to time)

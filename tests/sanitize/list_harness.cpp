@@ -123,6 +123,53 @@ static void run(const Case& c, bool nowrap_gather) {
         }
   }
 
+  // line extents along the inverse transform's first axis: every footprint
+  // cell lies in its line's range, lines no footprint crosses are empty, and
+  // the threaded build equals the serial one
+  {
+    const int ax = c.dim == 3 ? 0 : 1, oa = ax == 0 ? 1 : 0;
+    std::vector<Extent> ext, ext1;
+    std::string e8 = line_extents(g, ax, sorted, ext, 8);
+    CHECK(e8.empty(), "%s: line_extents: %s", c.name, e8.c_str());
+    CHECK(line_extents(g, ax, sorted, ext1, 1).empty(), "%s: serial line extents", c.name);
+    const int64_t nlines = (int64_t)g.nf[oa] * g.nf[2];
+    CHECK((int64_t)ext.size() == nlines && ext1.size() == ext.size(), "%s: line extent count", c.name);
+    bool same = ext.size() == ext1.size();
+    for (size_t i = 0; same && i < ext.size(); ++i) same = ext[i].first == ext1[i].first && ext[i].span == ext1[i].span;
+    CHECK(same, "%s: threaded line extents differ from the serial build", c.name);
+    std::vector<char> crossed(nlines, 0);
+    int64_t outside = 0;
+    for (int64_t j = 0; j < Mh; ++j) {
+      const int st[3] = {sorted[j].x, sorted[j].y, sorted[j].z};
+      for (int da = 0; da < g.w[oa]; ++da)
+        for (int d2 = 0; d2 < g.w[2]; ++d2) {
+          const int64_t line = (int64_t)((st[oa] + da) % g.nf[oa]) * g.nf[2] + (st[2] + d2) % g.nf[2];
+          crossed[line] = 1;
+          const Extent e = ext[line];
+          for (int dx = 0; dx < g.w[ax]; ++dx) {
+            const int q = (st[ax] + dx) % g.nf[ax];
+            if (e.span < 0 || mod(q - e.first, g.nf[ax]) > e.span) ++outside;
+          }
+        }
+    }
+    CHECK(outside == 0, "%s: %lld footprint cells outside their line's extent", c.name, (long long)outside);
+    int64_t covered = 0;
+    for (int64_t line = 0; line < nlines; ++line) {
+      const Extent e = ext[line];
+      if (!crossed[line]) {
+        CHECK(e.span == -1, "%s: line %lld has an extent but no footprint crosses it", c.name, (long long)line);
+        continue;
+      }
+      CHECK(e.first >= 0 && e.first < g.nf[ax] && e.span >= 0 && e.span < g.nf[ax], "%s: extent range", c.name);
+      covered += e.span + 1;
+    }
+    // the half node set of a ball fills about 30% of the large grids: the
+    // extents must not degenerate to whole lines there
+    if (g.nf[ax] >= 512)
+      CHECK(covered < (int64_t)(0.45 * nlines * g.nf[ax]), "%s: extents cover %.2f of the grid", c.name,
+            (double)covered / ((double)nlines * g.nf[ax]));
+  }
+
   // gather lists
   std::vector<int64_t> tcount;
   std::vector<Entry> list;
