@@ -242,6 +242,15 @@ struct PassArgs {
   int kin_imag;
 };
 
+// Byte offset of a pass block's twiddle table in LDS: after LB padded lines
+// and, for the Z passes, LB + L deconvolution factors; 16-byte aligned.
+template <typename T>
+__host__ __device__ inline size_t pass_twiddle_offset(int LB, int L, bool factors) {
+  size_t off = (size_t)LB * (L + 1) * sizeof(C2<T>);
+  if (factors) off += sizeof(double) * (LB + L);
+  return (off + 15) & ~(size_t)15;
+}
+
 // Position on the fine grid of physical index i of a line of N: (i - N/2) mod L.
 __device__ inline int fine_pos(int i, int N, int L) {
   int m = i - N / 2;
@@ -312,8 +321,15 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
   // staged after the lines
   double* fline = reinterpret_cast<double*>(smem_raw + (size_t)LB * ldl * sizeof(C2<T>));
   double* felem = fline + LB;
+  // the strided passes stage the line's twiddles after the lines (16-byte
+  // aligned) and their radix stages read them from LDS; the Z passes, whose
+  // blocks are smaller and more numerous per CU, read them from global memory
+  constexpr bool TW_LDS = LINES_FASTEST;
+  C2<T>* const twl = reinterpret_cast<C2<T>*>(smem_raw + pass_twiddle_offset<T>(LB, L, has_factors<KIND>()));
+  const C2<T>* const ltw = TW_LDS ? twl : a.tw;
 
-  if constexpr (has_factors<KIND>()) {
+  // staged while the element loads are in flight (below)
+  auto stage_factors = [&]() {
     const int ne = (KIND == PASS_FWD_Z) ? a.nin : a.nout;
     for (int t = threadIdx.x; t < LB + ne; t += NT) {
       if (t < LB) {
@@ -325,7 +341,7 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
         felem[t - LB] = a.dec2[t - LB];
       }
     }
-  }
+  };
 
   // zero the padding region of every line when the input is padded
   if (a.nin < L && !a.half_in) {
@@ -336,7 +352,6 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
       lds[l * ldl + (N - N / 2) + e] = C2<T>{T(0), T(0)};
     }
   }
-  if constexpr (has_factors<KIND>()) __syncthreads();  // factors staged
 
   double macc = 0.0;  // forward Z: the block's sum of rho
   // load: every load is issued before any loaded value is used, so that they
@@ -425,6 +440,12 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
       dst[i] = ok ? l * ldl + pos : -1;
       le[i] = (l << 16) | e;
     }
+    // the twiddles or the deconvolution factors, copied while the element
+    // loads are in flight
+    if constexpr (TW_LDS)
+      for (int t = threadIdx.x; t < L; t += NT) twl[t] = a.tw[t];
+    if constexpr (has_factors<KIND>()) stage_factors();
+    if constexpr (KIND == PASS_FWD_Z) __syncthreads();  // factors staged: the LDS writes below apply them
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       if (dst[i] >= 0) {
@@ -470,11 +491,11 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
       const FastDiv& dNs = a.dNs[st];
       const int tws = a.tws[st];
       switch (R) {
-        case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
-        case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
-        case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
-        case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
-        default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, a.tw, sign); break;
+        case 8: stage<T, 8, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, ltw, sign); break;
+        case 5: stage<T, 5, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, ltw, sign); break;
+        case 4: stage<T, 4, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, ltw, sign); break;
+        case 3: stage<T, 3, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, ltw, sign); break;
+        default: stage<T, 2, MAXV>(lds, ldl, L, LB, Ns, a.dLB, dNs, tws, ltw, sign); break;
       }
       Ns *= R;
     }
@@ -1016,8 +1037,9 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   a.dic = FastDiv((uint32_t)a.ic);
   a.dn1 = FastDiv((uint32_t)(a.n1 > 0 ? a.n1 : 1));
   unsigned blocks = (unsigned)((a.nlines + a.LB - 1) / a.LB);
-  size_t smem = (size_t)a.LB * (a.L + 1) * sizeof(C2<T>);
-  if (has_factors<KIND>()) smem += sizeof(double) * (a.LB + a.L);  // deconvolution factors
+  // lines, deconvolution factors (Z passes), twiddles (strided passes)
+  constexpr bool TW_LDS = KIND == PASS_COMPLEX || KIND == PASS_KINETIC || KIND == PASS_HSYM;
+  const size_t smem = pass_twiddle_offset<T>(a.LB, a.L, has_factors<KIND>()) + (TW_LDS ? (size_t)a.L * sizeof(C2<T>) : 0);
   constexpr int NT = pass_threads<T, KIND>();
   constexpr int MAXV = pass_elems<T, KIND>();
   stage_mark(pl, stage, 0, s);
