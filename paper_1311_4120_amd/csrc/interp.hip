@@ -534,21 +534,37 @@ struct ReduceArgs {
 // Sum each node's tile shares in the order of its list entries (fixed), then
 // the epilogue of the interpolation: c_j rho^_j, or the transform itself, and
 // the Fourier-side energy partials.
-// LPN lanes per node: lane i of a node's LPN loads its entries i, i + LPN,
-// ... (all of them in flight at once), then a fixed-order tree sum over the
-// LPN lanes (LPN = 1, 4 or 8).
+// LPN lanes per node: lane i of a node's LPN sums its entries i, i + LPN,
+// ... in that order, then a fixed-order tree sum over the LPN lanes
+// (LPN = 1, 4 or 8).  A lane's entries are taken KU at a time: their list
+// positions are loaded together, then their shares, then summed.  KU covers
+// a lane's usual count (LPN 4 is chosen for 4 to 10 entries per node).
 template <typename T, int LPN>
 __device__ __forceinline__ void interp_reduce_body(const ReduceArgs<T>& a, const int blk) {
   __shared__ double ws[4];
+  constexpr int KU = LPN == 4 ? 2 : 4;
   const int j = blk * (256 / LPN) + (int)(threadIdx.x / LPN);
   const int li = threadIdx.x % LPN;
   double sr = 0.0, si = 0.0;
   if (j < a.Mh) {
     const int b = a.nstart[j], e = a.nstart[j + 1];
-    for (int q = b + li; q < e; q += LPN) {
-      const C2<T> v = a.ipart[a.npos[q]];
-      sr += (double)v.x;
-      si += (double)v.y;
+    for (int q0 = b + li; q0 < e; q0 += KU * LPN) {
+      int pos[KU];
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        const int q = q0 + k * LPN;
+        pos[k] = a.npos[q < e ? q : q0];  // q0 < e: a valid entry stands in
+      }
+      C2<T> v[KU];
+#pragma unroll
+      for (int k = 0; k < KU; ++k) v[k] = a.ipart[pos[k]];
+#pragma unroll
+      for (int k = 0; k < KU; ++k) {
+        if (q0 + k * LPN < e) {
+          sr += (double)v[k].x;
+          si += (double)v[k].y;
+        }
+      }
     }
   }
   if (LPN >= 4) {
