@@ -39,8 +39,10 @@ def stage_work(info, prec, energy=True, half=True):
     FFT passes: input + output of the pass.  For a real density (Algorithm 1)
     the spectrum is kept on the Hermitian half h = f/2 + 1 of the lines along
     the last axis (half=True): every pass but the inverse's first moves h/f of
-    the full-complex bytes, and that first pass reads all of G (each line and
-    its mirror).  Tap kernels: one pass over the oversampled grid
+    the full-complex bytes, and that first pass is counted as reading all of G
+    (each line and its mirror; the kernel itself loads only the part of each
+    line that node footprints reach, so its rate against this count overstates
+    the HBM rate it achieves).  Tap kernels: one pass over the oversampled grid
     (interpolation reads the stored spectrum, spreading writes G) and 5 flops
     per tap (complex x real multiply-add + the weight product) over the w^3
     taps of every node the launch processes (the half set; the other half is
@@ -250,7 +252,7 @@ def run_batched(steps, warmup, nstreams=1):
             "ms_per_launch": 1e3 * wall / steps, "evals_per_s": len(members) * steps / wall,
             "grid_points_per_s": npts * steps / wall, "launches": steps, "plan_and_capture_s": plan_s,
             "precision": "mixed", "eps": 1e-5, "nstreams": nstreams, "kernel_launches_per_step": launches,
-            "ns_per_point": 1e6 * wall / steps / npts,
+            "ns_per_point": 1e9 * wall / steps / npts,
             "graph": ("one hipGraph launch per step: one kernel launch per pipeline site over all members"
                       if nstreams == 1 else
                       "one hipGraph launch per step: the members' pipelines on %d branches" % nstreams)}
