@@ -161,7 +161,7 @@ def roofline(stage, ms, by, fl, prec):
     return out
 
 
-def run_gpu(prec, steps, warmup, nodes="pattern", eps=None):
+def run_gpu(prec, steps, warmup, nodes="pattern", eps=None, gaussian=False):
     import torch
 
     import paper_1311_4120_amd as jgb
@@ -174,7 +174,7 @@ def run_gpu(prec, steps, warmup, nodes="pattern", eps=None):
         p.eps = eps
     plan = jgb.Plan(p.n, p.box, "dipole3d", (p.n_r, p.n_theta, p.n_phi), eps=p.eps, precision=prec,
                     lam=p.lam, axis=p.axis, theta_rule="theta" if p.theta_rule == wl.THETA_GL else "costheta",
-                    autotune=True, split=(nodes == "split"))
+                    autotune=True, split=(nodes == "split"), gaussian_kernel=gaussian)
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     rt = torch.tensor(rho, dtype=dt, device="cuda")
@@ -564,6 +564,18 @@ def main():
                                   "width": f5["info"]["width"]},
             "mixed": {"value": 1e3 / m["ms_per_step"], "ms_per_step": m["ms_per_step"], "width": m["info"]["width"]},
             "mixed_speedup": f5["ms_per_step"] / m["ms_per_step"]}
+        # the paper's Gaussian spreading kernel (12 points per axis, about six
+        # digits) against the exponential of a semicircle at the same eps
+        print("[bench] the paper's Gaussian kernel at eps 1e-6", file=sys.stderr, flush=True)
+        ga = {}
+        for prec in ("fp64", "mixed"):
+            e6 = 1e-6 if prec == "fp64" else 1e-5
+            g = run_gpu(prec, args.steps, args.warmup, eps=e6, gaussian=True)
+            es = run_gpu(prec, args.steps, args.warmup, eps=e6)
+            ga[prec] = {"eps": e6, "gaussian": {"ms_per_step": g["ms_per_step"], "width": g["info"]["width"]},
+                        "semicircle": {"ms_per_step": es["ms_per_step"], "width": es["info"]["width"]},
+                        "gaussian_cost": g["ms_per_step"] / es["ms_per_step"]}
+        out["gaussian_kernel"] = ga
     if not args.no_batched and args.only is None:
         print("[bench] batched_coulomb: 64 densities, one graph launch per step", file=sys.stderr, flush=True)
         out["batched"] = run_batched(max(3, args.steps // 10), 2)

@@ -143,6 +143,15 @@ typedef enum { JGB_THETA_GL = 0, JGB_COSTHETA_GL = 1 } jgb_theta_rule;
  * node at k = 0 takes the rule's own weights.  UNSUPPORTED if the rule cannot
  * be built (n_r > 2048). */
 #define JGB_FLAG_RADIAL_GGQ 16u
+/* The paper's own spreading kernel (Section 2, the heat kernel g_tau and the
+ * deconvolution sqrt(pi/tau) e^{k^2 tau}) instead of the exponential of a
+ * semicircle: with the oversampled grid of 2N points per axis and
+ * tau = 6/N^2, a Gaussian over the nearest 12 points, exp(-pi^2 d^2 / 24) at
+ * a distance of d fine cells, for about six digits.  The paper's 24-point,
+ * twelve-digit setting exceeds the 16-tap node records: with this flag eps
+ * below 1e-6 is UNSUPPORTED.  Both algorithms; jgb_info.width reports 12 and
+ * jgb_info.beta 0. */
+#define JGB_FLAG_GAUSSIAN_KERNEL 32u
 
 typedef struct jgb_plan_s* jgb_plan_t;
 
@@ -194,7 +203,7 @@ typedef struct {
   int64_t n_nodes;         /* M = n_r n_theta n_phi (3D) or n_r n_phi (2D) */
   int64_t n_half;          /* nodes processed on the device: M / 2 (k and -k paired) */
   int32_t width;           /* spreading kernel width in fine-grid cells per axis */
-  double beta;             /* exponential-of-semicircle kernel shape parameter */
+  double beta;             /* exponential-of-semicircle kernel shape parameter (0: the Gaussian) */
   double kmax;             /* K actually used */
   int64_t workspace_bytes; /* device memory owned by the plan */
   int32_t interp_chunk;    /* nodes per interpolation block at most; 0: the autotuner chose the

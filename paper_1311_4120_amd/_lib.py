@@ -24,11 +24,13 @@ NUM_STAGES = 13
 STAGE_NAMES = ["fwd_fft_z", "fwd_fft_y", "fwd_fft_x", "interp", "spread", "spread_reduce",
                "inv_fft_x", "inv_fft_y", "inv_fft_z", "energy", "split_unmix", "split_symbol", "interp_reduce"]
 FP64, MIXED = 0, 1
+FLAG_NONE = 0
 FLAG_AUTOTUNE = 1
 FLAG_SPLIT = 2
 FLAG_INTERP_TILES = 4
 FLAG_SPREAD_RINGS = 8
 FLAG_RADIAL_GGQ = 16
+FLAG_GAUSSIAN_KERNEL = 32
 THETA_GL, COSTHETA_GL = 0, 1
 
 

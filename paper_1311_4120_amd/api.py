@@ -20,9 +20,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# the plan flags a Batch member or a GPE driver may set by keyword
+_FLAG_KWARGS = ("interp_tiles", "spread_rings", "radial_ggq", "gaussian_kernel")
+
+
 def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
                  autotune=False, split=False, window=(0.0, 0.0), axis2=None, alpha=0.0, interp_tiles=False,
-                 spread_rings=False, radial_ggq=False):
+                 spread_rings=False, radial_ggq=False, gaussian_kernel=False):
     dim = len(n)
     kern = _KERNELS.get(kernel, kernel)
     rule = _RULES.get(theta_rule, theta_rule)
@@ -51,7 +55,7 @@ def _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, k
     p.stream = ctypes.c_void_p(st.cuda_stream)
     p.flags = ((_lib.FLAG_AUTOTUNE if autotune else 0) | (_lib.FLAG_SPLIT if split else 0)
                | (_lib.FLAG_INTERP_TILES if interp_tiles else 0) | (_lib.FLAG_SPREAD_RINGS if spread_rings else 0)
-               | (_lib.FLAG_RADIAL_GGQ if radial_ggq else 0))
+               | (_lib.FLAG_RADIAL_GGQ if radial_ggq else 0) | (_lib.FLAG_GAUSSIAN_KERNEL if gaussian_kernel else 0))
     for i in range(2):
         p.window[i] = float(window[i]) if i < len(window) else 0.0
     for i in range(3):
@@ -79,6 +83,9 @@ class Plan:
                the last (3D)
     radial_ggq: radial nodes by the generalized Gaussian rule for band-limited
                integrands (prolate spheroidal) instead of Gauss-Legendre
+    gaussian_kernel: spread and interpolate with the paper's Gaussian (12
+               points per axis, about six digits; eps >= 1e-6) instead of the
+               exponential of a semicircle
     """
 
     def __init__(self, n: Sequence[int], box: Sequence[float], kernel, nodes: Sequence[int],
@@ -87,9 +94,10 @@ class Plan:
                  device: Optional[int] = None, stream: Optional[torch.cuda.Stream] = None, autotune: bool = False,
                  split: bool = False, window: Sequence[float] = (0.0, 0.0),
                  axis2: Optional[Sequence[float]] = None, alpha: float = 0.0, interp_tiles: bool = False,
-                 spread_rings: bool = False, radial_ggq: bool = False):
+                 spread_rings: bool = False, radial_ggq: bool = False, gaussian_kernel: bool = False):
         p, dev, st = _make_params(n, box, kernel, nodes, eps, precision, lam, axis, theta_rule, kmax, device, stream,
-                                  autotune, split, window, axis2, alpha, interp_tiles, spread_rings, radial_ggq)
+                                  autotune, split, window, axis2, alpha, interp_tiles, spread_rings, radial_ggq,
+                                  gaussian_kernel)
         self._init_from(p, dev, st, box)
         h = ctypes.c_void_p()
         check(lib.jgb_plan(ctypes.byref(p), ctypes.byref(h)))
@@ -274,7 +282,8 @@ class Batch:
             kw.update(m)
             p, _, _ = _make_params(kw["n"], kw["box"], kw["kernel"], kw["nodes"], kw["eps"], kw["precision"],
                                    kw["lam"], kw["axis"], kw["theta_rule"], kw["kmax"], dev, st, kw["autotune"],
-                                   kw["split"], kw["window"], kw["axis2"], kw["alpha"])
+                                   kw["split"], kw["window"], kw["axis2"], kw["alpha"],
+                                   **{f: bool(kw.get(f, False)) for f in _FLAG_KWARGS})
             arr[i] = p
             boxes.append(kw["box"])
         h = ctypes.c_void_p()
@@ -342,7 +351,8 @@ class GPE:
         kw.update(plan_kw)
         p, dev, st = _make_params(n, box, kernel, nodes, kw["eps"], kw["precision"], kw["lam"], kw["axis"],
                                   kw["theta_rule"], kw["kmax"], device, stream, kw["autotune"], kw["split"],
-                                  kw["window"], kw["axis2"], kw["alpha"])
+                                  kw["window"], kw["axis2"], kw["alpha"],
+                                  **{f: bool(kw.get(f, False)) for f in _FLAG_KWARGS})
         g = _lib.GpeParams()
         g.struct_size = ctypes.sizeof(_lib.GpeParams)
         g.potential = p

@@ -286,6 +286,14 @@ __host__ __device__ inline T es_kernel(T x, T two_over_w, T beta) {
   return exp(beta * (sqrt(q) - T(1)));
 }
 
+// The paper's spreading kernel (Section 2): the heat kernel with tau = 6/N^2
+// on the grid of 2N points per axis, exp(-pi^2 x^2 / 24) at a distance of x
+// fine cells, over the nearest 12 points.
+template <typename T>
+__host__ __device__ inline T gauss_kernel(T x) {
+  return exp(T(-M_PI * M_PI / 24.0) * x * x);
+}
+
 // ----------------------------------------------------------------- batches
 //
 // A batch (jgb_batch_*) evaluates many plans with one launch per pipeline

@@ -268,7 +268,11 @@ __global__ void k_node_setup(NodeParams q, int64_t Mh, const int* perm, int4* hd
     const int w = q.w[ax];
     const T f = (T)frac[ax], tw = (T)(2.0 / w), beta = (T)q.beta;
     T* out = rec + ax * (q.width + 1);
-    for (int t = 0; t < q.width; ++t) out[t] = (t >= w) ? T(0) : (w == 1 ? T(1) : es_kernel<T>(T(t) - f, tw, beta));
+    for (int t = 0; t < q.width; ++t)
+      out[t] = (t >= w)  ? T(0)
+               : w == 1  ? T(1)
+               : q.beta == 0.0 ? gauss_kernel<T>(T(t) - f)
+                               : es_kernel<T>(T(t) - f, tw, beta);
   }
 }
 

@@ -80,8 +80,15 @@ void host_gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) 
 }
 
 // Fourier transform of the spreading kernel, phi^(xi) = int phi(x) cos(xi x) dx
-// over |x| <= w/2, by Gauss-Legendre quadrature in float64.
+// over |x| <= w/2, by Gauss-Legendre quadrature in float64; for the paper's
+// Gaussian exp(-pi^2 x^2 / 24) (beta = 0) its closed form over the whole line,
+// sqrt(24 / pi) exp(-6 xi^2 / pi^2), the deconvolution of Section 2.
 std::vector<double> kernel_ft(int w, double beta, const std::vector<double>& xi) {
+  if (beta == 0.0) {
+    std::vector<double> out(xi.size());
+    for (size_t k = 0; k < xi.size(); ++k) out[k] = std::sqrt(24.0 / M_PI) * std::exp(-6.0 * xi[k] * xi[k] / (M_PI * M_PI));
+    return out;
+  }
   std::vector<double> z, om;
   int nq = std::max(200, 8 * w + 40);
   host_gauss_legendre(nq, z, om);
@@ -401,8 +408,9 @@ Status apply_spread_chunk(Plan& pl, int chunk) {
 std::string tune_key(const Plan& pl) {
   char buf[256];
   double kh = pl.K * std::max(pl.h[0] * (pl.n[0] > 1), std::max(pl.h[1], pl.h[2])) / M_PI;
-  snprintf(buf, sizeof(buf), "gfx950 d%d n%dx%dx%d nodes%dx%dx%d rule%d kh%.6f w%d %s", pl.dim, pl.n[0], pl.n[1],
-           pl.n[2], pl.n_r, pl.n_theta, pl.n_phi, pl.p.theta_rule, kh, pl.width, pl.fp64 ? "fp64" : "mixed");
+  snprintf(buf, sizeof(buf), "gfx950 d%d n%dx%dx%d nodes%dx%dx%d rule%d kh%.6f w%d%s %s", pl.dim, pl.n[0], pl.n[1],
+           pl.n[2], pl.n_r, pl.n_theta, pl.n_phi, pl.p.theta_rule, kh, pl.width, pl.beta == 0.0 ? " gauss" : "",
+           pl.fp64 ? "fp64" : "mixed");
   return buf;
 }
 
@@ -564,7 +572,7 @@ Status autotune(Plan& pl) {
 
 }  // namespace
 
-void accuracy_parameters(double eps, int& w, double& beta);
+void accuracy_parameters(double eps, bool gaussian, int& w, double& beta);
 
 Status validate(const jgb_params* p) {
   if (!p) return fail(JGB_ERR_INVALID_ARG, "params is NULL");
@@ -610,10 +618,12 @@ Status validate(const jgb_params* p) {
   if (!(std::isfinite(p->kmax) && p->kmax >= 0)) return fail(JGB_ERR_INVALID_ARG, "kmax must be finite and >= 0");
   if (p->kmax > kn * (1 + 1e-12)) return fail(JGB_ERR_INVALID_ARG, "kmax must not exceed pi / max_j h_j");
   if (p->flags & ~(JGB_FLAG_AUTOTUNE | JGB_FLAG_SPLIT | JGB_FLAG_INTERP_TILES | JGB_FLAG_SPREAD_RINGS |
-                   JGB_FLAG_RADIAL_GGQ))
+                   JGB_FLAG_RADIAL_GGQ | JGB_FLAG_GAUSSIAN_KERNEL))
     return fail(JGB_ERR_INVALID_ARG, "unknown flags");
   if ((p->flags & JGB_FLAG_RADIAL_GGQ) && p->n_r > 2048)
     return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_RADIAL_GGQ needs n_r <= 2048");
+  if ((p->flags & JGB_FLAG_GAUSSIAN_KERNEL) && p->eps < 1e-6)
+    return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_GAUSSIAN_KERNEL gives about six digits: eps >= 1e-6");
   if ((p->flags & JGB_FLAG_INTERP_TILES) && p->dim != 3)
     return fail(JGB_ERR_UNSUPPORTED, "JGB_FLAG_INTERP_TILES needs dim == 3");
   if ((p->flags & JGB_FLAG_SPREAD_RINGS) && p->dim != 3)
@@ -637,7 +647,7 @@ Status validate(const jgb_params* p) {
     // and weighted values of the half node set) by 32-bit byte offsets
     int w;
     double beta;
-    accuracy_parameters(p->eps, w, beta);
+    accuracy_parameters(p->eps, (p->flags & JGB_FLAG_GAUSSIAN_KERNEL) != 0, w, beta);
     const uint64_t rb = p->precision == JGB_FP64 ? 8 : 4, Mh = (uint64_t)(M / 2);
     if (Mh * (uint64_t)record_stride(w) * rb >= (1ull << 32) || Mh * 2 * rb >= (1ull << 32))
       return fail(JGB_ERR_UNSUPPORTED, "node tables of 4 GiB or more (too many nodes for this eps and precision)");
@@ -652,8 +662,15 @@ Status validate(const jgb_params* p) {
 }
 
 // Spreading width and shape for a requested accuracy at oversampling 2: the
-// kernel's aliasing error falls by about a decade per extra tap.
-void accuracy_parameters(double eps, int& w, double& beta) {
+// kernel's aliasing error falls by about a decade per extra tap.  The paper's
+// Gaussian (Section 2, about six digits) always spreads to 12 points; beta 0
+// marks it.
+void accuracy_parameters(double eps, bool gaussian, int& w, double& beta) {
+  if (gaussian) {
+    w = 12;
+    beta = 0.0;
+    return;
+  }
   w = (int)std::ceil(std::log10(10.0 / eps)) + 1;
   w = std::max(2, std::min(kMaxWidth, w));
   beta = 2.30 * w;
@@ -734,7 +751,7 @@ Status build_plan(Plan& pl, const jgb_params* p) {
       if (p->kmax <= 0) pl.K = std::min(M_PI / hmax, pl.win[1]);
     }
   }
-  accuracy_parameters(p->eps, pl.width, pl.beta);
+  accuracy_parameters(p->eps, (p->flags & JGB_FLAG_GAUSSIAN_KERNEL) != 0, pl.width, pl.beta);
   for (int i = 0; i < 3; ++i) pl.w[i] = (pl.n[i] == 1) ? 1 : pl.width;
   pl.n_r = p->n_r;
   pl.n_theta = (pl.dim == 3) ? p->n_theta : 1;

@@ -112,7 +112,8 @@ BAD = [
     ("odd n_phi", dict(n_phi=7), 1),
     ("theta rule", dict(theta_rule=5), 1),
     ("kmax too large", dict(kmax=100.0), 1),
-    ("flags", dict(flags=32), 1),
+    ("flags", dict(flags=64), 1),
+    ("gaussian kernel below six digits", dict(flags=32, eps=1e-8), 2),
     ("radial rule too large", dict(flags=16, n_r=4096), 2),
     ("interp tiles in 2D", dict(flags=4, dim=2, kernel=1), 2),
     ("spread rings in 2D", dict(flags=8, dim=2, kernel=1), 2),
@@ -270,3 +271,12 @@ def test_noalloc_scratch_size_matches_header():
     L = _lib()
     m = re.search(r"#define JGB_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", open(HEADER).read())
     assert m and int(m.group(1)) << int(m.group(2)) == L.NOALLOC_SCRATCH_BYTES
+
+
+def test_flag_constants_match_the_header():
+    """Every JGB_FLAG_* of include/jgb.h has the same value in the binding."""
+    import paper_1311_4120_amd._lib as L
+    flags = re.findall(r"#define JGB_FLAG_(\w+) (\d+)u", open(HEADER).read())
+    assert len(flags) >= 7
+    for name, val in flags:
+        assert getattr(L, "FLAG_" + name) == int(val), name
