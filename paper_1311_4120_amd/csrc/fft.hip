@@ -188,7 +188,6 @@ struct PassArgs {
   int64_t ic;       // lines per outer group; line l = (outer, inner) = (l / ic, l % ic)
   int64_t in_os, in_is, in_es;
   int64_t out_os, out_is, out_es;
-  int lines_fastest;  // global access order: 1 -> consecutive threads on consecutive lines
   T sign;
   int nrad;
   int rad[12];
@@ -386,9 +385,10 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
       // slots past the block's inputs (padded passes load N of L) issue nothing;
-      // the test is uniform across the block.  HSYM takes no such branch (its
-      // line reaches must stay visibly loaded across the slots): its empty
-      // slots are masked lanes
+      // the test is uniform across the block.  HSYM takes no such branch:
+      // past one, the compiler no longer knows that the line's reaches have
+      // arrived and waits for every load in flight before using them; its
+      // empty slots are masked lanes instead
       if (!HSYM && i * NT >= total_in) {
         dst[i] = -1;
         le[i] = 0;
@@ -1154,7 +1154,6 @@ hipError_t forward_passes(const Plan& pl, const T* rho, hipStream_t s, bool last
     a.out_os = r2;
     a.out_is = 0;
     a.out_es = 1;
-    a.lines_fastest = 0;
     a.in = rho;
     a.out = A1;
     a.dec0 = pl.d_deconv[0];
@@ -1177,7 +1176,6 @@ hipError_t forward_passes(const Plan& pl, const T* rho, hipStream_t s, bool last
     a.out_os = f1 * r2;
     a.out_is = 1;
     a.out_es = r2;
-    a.lines_fastest = 1;
     a.in = A1;
     a.out = A2;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_FWD_Y, a, s)) != hipSuccess) return e;
@@ -1194,7 +1192,6 @@ hipError_t forward_passes(const Plan& pl, const T* rho, hipStream_t s, bool last
     a.out_os = r2;
     a.out_is = 1;
     a.out_es = f1 * r2;
-    a.lines_fastest = 1;
     a.in = A2;
     a.out = pl.d_F;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_FWD_X, a, s)) != hipSuccess) return e;
@@ -1301,7 +1298,6 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.out_os = r2;
     a.out_is = 1;
     a.out_es = f1 * r2;
-    a.lines_fastest = 1;
     a.sym_no = (int)f1;
     a.sym_ni = (int)f2;
     a.lext = pl.d_gext;
@@ -1333,7 +1329,6 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.out_os = n1 * r2;
     a.out_is = 1;
     a.out_es = r2;
-    a.lines_fastest = 1;
     a.sym_no = 1;
     a.sym_ni = (int)f2;
     a.lext = pl.d_gext;
@@ -1356,7 +1351,6 @@ hipError_t launch_fft_inverse(const Plan& pl, T* u, const T* rho_for_energy, hip
     a.out_os = n2;
     a.out_is = 0;
     a.out_es = 1;
-    a.lines_fastest = 0;
     a.in = B1;
     a.out = u;
     a.dec0 = pl.d_deconv[0];
@@ -1406,7 +1400,6 @@ hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, in
     a.in_os = a.out_os = n1 * n2;
     a.in_is = a.out_is = 1;
     a.in_es = a.out_es = n2;
-    a.lines_fastest = 1;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, -1, a, s)) != hipSuccess) return e;
   }
   if (n0 > 1) {  // axis 0: lines [n1 n2]
@@ -1416,7 +1409,6 @@ hipError_t launch_fft_periodic(const Plan& pl, void* const tw[3], void* data, in
     a.in_os = a.out_os = 0;
     a.in_is = a.out_is = 1;
     a.in_es = a.out_es = n1 * n2;
-    a.lines_fastest = 1;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, -1, a, s)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1468,7 +1460,6 @@ hipError_t launch_fft_periodic_kinetic(const Plan& pl, void* const tw[3], void* 
     a.in_os = a.out_os = n1 * n2;
     a.in_is = a.out_is = 1;
     a.in_es = a.out_es = n2;
-    a.lines_fastest = 1;
     a.kax = 1;
     return kinetic ? run_pass<T, PASS_KINETIC>(pl, -1, a, s) : run_pass<T, PASS_COMPLEX>(pl, -1, a, s);
   };
@@ -1479,7 +1470,6 @@ hipError_t launch_fft_periodic_kinetic(const Plan& pl, void* const tw[3], void* 
     a.in_os = a.out_os = 0;
     a.in_is = a.out_is = 1;
     a.in_es = a.out_es = n1 * n2;
-    a.lines_fastest = 1;
     a.kax = 0;
     return run_pass<T, PASS_KINETIC>(pl, -1, a, s);
   };
