@@ -469,8 +469,14 @@ __device__ __forceinline__ void interp_tile_body(const TileArgs<T>& a, const int
 #pragma unroll
     for (int r = 0; r < 4; ++r) pz[r] = tap(zr[r] + bias - ez, a.nf2, 2);
     acc_t acc = acc_t{T(0), T(0), T(0), T(0)};
+    // product t covers the tile points (x = t/2, y = 4 (t mod 2) + 0..3); it
+    // is skipped when none of the 16 nodes' footprints reaches them (it would
+    // add exact zeros)
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc = TileMfma<T>::mma(B[t], px[t >> 1] * py[t & 1], acc);
+    for (int t = 0; t < 16; ++t) {
+      const T pa = px[t >> 1] * py[t & 1];
+      if (__ballot(pa != T(0))) acc = TileMfma<T>::mma(B[t], pa, acc);
+    }
     T re = T(0), im = T(0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
