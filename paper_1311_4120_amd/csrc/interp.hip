@@ -542,13 +542,14 @@ struct ReduceArgs {
 // the Fourier-side energy partials.
 // LPN lanes per node: lane i of a node's LPN sums its entries i, i + LPN,
 // ... in that order, then a fixed-order tree sum over the LPN lanes
-// (LPN = 1, 4 or 8).  A lane's entries are taken KU at a time: their list
-// positions are loaded together, then their shares, then summed.  KU covers
-// a lane's usual count (LPN 4 is chosen for 4 to 10 entries per node).
+// (LPN = 1 or 4).  A lane's entries are taken four at a time: their list
+// positions are loaded together, then their shares, then summed; the kernel
+// waits on that chain of dependent loads, so each lane covers a node's
+// usual count in one or two such batches.
 template <typename T, int LPN>
 __device__ __forceinline__ void interp_reduce_body(const ReduceArgs<T>& a, const int blk) {
   __shared__ double ws[4];
-  constexpr int KU = LPN == 4 ? 2 : 4;
+  constexpr int KU = 4;
   const int j = blk * (256 / LPN) + (int)(threadIdx.x / LPN);
   const int li = threadIdx.x % LPN;
   double sr = 0.0, si = 0.0;
@@ -573,15 +574,11 @@ __device__ __forceinline__ void interp_reduce_body(const ReduceArgs<T>& a, const
       }
     }
   }
-  if (LPN >= 4) {
+  if (LPN == 4) {
     sr += dpp<0xB1, 0xf>(sr);   // quad_perm [1,0,3,2]
     si += dpp<0xB1, 0xf>(si);
     sr += dpp<0x4E, 0xf>(sr);   // quad_perm [2,3,0,1]
     si += dpp<0x4E, 0xf>(si);
-  }
-  if (LPN == 8) {
-    sr += dpp<0x141, 0xf>(sr);  // row_half_mirror: the other quad of the 8
-    si += dpp<0x141, 0xf>(si);
   }
   double eacc = 0.0;
   if (j < a.Mh && li == 0) {
@@ -655,11 +652,13 @@ int tile_lds_stride(int rstride) {
   return rstride;
 }
 
-// lanes per node of the reduction: about the mean number of list entries
-// per node, a power of two up to 8
+// lanes per node of the reduction: four from ten list entries per node on
+// average (FP64 at 1e-10: about 13), one below (FP32 at 1e-5: about 5); the
+// measured optimum at both, since more lanes mean more waves, each waiting on
+// the same chain
 int reduce_lanes(const Plan& pl) {
   const double mean = pl.Mh > 0 ? (double)pl.nlist / (double)pl.Mh : 0.0;
-  return mean >= 10.0 ? 8 : (mean >= 4.0 ? 4 : 1);
+  return mean >= 10.0 ? 4 : 1;
 }
 
 int tile_interp_blocks(const Plan& pl) {
@@ -716,9 +715,7 @@ hipError_t launch_interp_tiles(const Plan& pl, InterpMode mode, void* out, hipSt
   hipError_t e = hipSuccess;
   if (rb > 0) {
     const int lpn = reduce_lanes(pl);
-    if (lpn == 8)
-      e = launch<ReduceArgs<T>, k_interp_reduce<T, 8>, k_interp_reduce_b<T, 8>>(r, rb, 256, 0, s);
-    else if (lpn == 4)
+    if (lpn == 4)
       e = launch<ReduceArgs<T>, k_interp_reduce<T, 4>, k_interp_reduce_b<T, 4>>(r, rb, 256, 0, s);
     else
       e = launch<ReduceArgs<T>, k_interp_reduce<T, 1>, k_interp_reduce_b<T, 1>>(r, rb, 256, 0, s);
