@@ -225,6 +225,12 @@ struct Plan {
   // q2 in 2D): the circular range {first, span} the spreading can write;
   // the first inverse pass reads zero outside it (Algorithm 1)
   int2* d_gext = nullptr;
+  // per line of the spectrum F along the forward's last axis (lines q1 c2 +
+  // q2 over the kept q2 < c2, 3D plans with the tile tables): the circular
+  // range {first, span} the interpolation by tiles reads; the forward's last
+  // pass stores nothing outside it when the interpolation runs by tiles and
+  // nothing else reads F (Algorithm 1)
+  int2* d_fext = nullptr;
   int* d_nstart = nullptr;     // Mh + 1 offsets into d_npos
   int* d_npos = nullptr;       // nlist list positions, node-major
   void* d_ipart = nullptr;     // nlist complex T: per list entry, the tile's share of the node's value

@@ -220,6 +220,9 @@ struct PassArgs {
   // {first, span} of elements the spreading can have written; the pass takes
   // the other elements as zero without loading them
   const int2* lext;
+  // PASS_COMPLEX (optional): per output line, the circular range {first,
+  // span} of elements that are read later; the pass stores no others
+  const int2* oext;
   // the paired passes of Algorithm 2 (k_fft_pair_pass): lines are
   // (a, b) of an A x B set, element stride es_in / es_out; P lines and their
   // mirrors per block; nb1 blocks for the rows 0 < a < A/2 (cb per row), then cs
@@ -341,6 +344,16 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
       }
     }
   };
+
+  // the output reach of the thread's line (its elements all lie on one line
+  // here), read now and used by the stores
+  int2 ox{0, L - 1};
+  if constexpr (KIND == PASS_COMPLEX) {
+    if (a.oext) {
+      const int line = line0 + (int)(threadIdx.x - a.dLB.div(threadIdx.x) * LB);
+      ox = a.oext[line < a.nlines ? line : 0];
+    }
+  }
 
   // zero the padding region of every line when the input is padded
   if (a.nin < L && !a.half_in) {
@@ -594,6 +607,11 @@ __device__ __forceinline__ void fft_pass_body(const PassArgs<T>& a, const int bl
       if (line >= a.nlines) continue;
       const int lo = (int)a.dic.div(line);
       const int64_t base = (int64_t)lo * a.out_os + (int64_t)(line - lo * (int)a.ic) * a.out_is + (int64_t)e * a.out_es;
+      if constexpr (KIND == PASS_COMPLEX) {
+        int dp = e - ox.x;
+        dp += dp < 0 ? L : 0;
+        if (dp > ox.y) continue;  // never read: not stored
+      }
       if constexpr (KIND == PASS_INV_Z) {
         double u = (double)buf[i].x * (fline[l] * felem[e]) + ushift;
         if (a.split) u += (double)buf[i].y;
@@ -1020,6 +1038,10 @@ template <typename T, int KIND>
 hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   factor(a.L, a.rad, a.nrad);
   a.LB = lines_per_block<T, KIND>(a.L);
+  // with an output reach per line, a thread's elements must lie on one line:
+  // the lines per block divide the thread count
+  if (KIND == PASS_COMPLEX && a.oext)
+    while (pass_threads<T, KIND>() % a.LB != 0) --a.LB;
   {
     int Ns = 1;
     for (int st = 0; st < a.nrad; ++st) {
@@ -1031,6 +1053,9 @@ hipError_t run_pass(const Plan& pl, int stage, PassArgs<T> a, hipStream_t s) {
   if (a.nlines >= (1 << 30) || (int64_t)a.LB * a.L >= (1 << 30)) return hipErrorInvalidValue;
   // whole lines, with reaches; a thread's elements on one line
   if (KIND == PASS_HSYM && (a.nin != a.L || !a.lext || pass_threads<T, KIND>() % a.LB != 0)) return hipErrorInvalidValue;
+  // an output reach per line, the thread's elements on one whole line
+  if (a.oext && (KIND != PASS_COMPLEX || a.nout != a.L || pass_threads<T, KIND>() % a.LB != 0))
+    return hipErrorInvalidValue;
   a.dLB = FastDiv((uint32_t)a.LB);
   a.dnin = FastDiv((uint32_t)a.nin);
   a.dnout = FastDiv((uint32_t)a.nout);
@@ -1194,6 +1219,10 @@ hipError_t forward_passes(const Plan& pl, const T* rho, hipStream_t s, bool last
     a.out_es = f1 * r2;
     a.in = A2;
     a.out = pl.d_F;
+    // Algorithm 1: the interpolation by tiles reads F only within each
+    // line's reach (Algorithm 2's unmixing and Fourier-side energy read all
+    // of F)
+    a.oext = pl.tile_interp && !pl.split ? pl.d_fext : nullptr;
     if ((e = run_pass<T, PASS_COMPLEX>(pl, ST_FWD_X, a, s)) != hipSuccess) return e;
   }
   return hipSuccess;

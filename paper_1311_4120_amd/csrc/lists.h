@@ -15,6 +15,9 @@
 //   line_extents: for every line of the spreading grid along the inverse
 //     transform's first axis, the range of positions the nodes' footprints
 //     can reach (the grid is zero elsewhere).
+//   tile_read_extents: for every line of the forward transform's spectrum
+//     along its last axis, the range of positions the interpolation by tiles
+//     reads (the rest need not be stored).
 //
 // Starts are the nodes' first taps wrapped into [0, nf).  A tile-relative
 // start is stored, when every axis has nf >= T + w - 1, as its one
@@ -358,6 +361,81 @@ inline std::string line_extents(const Geometry& g, int ax, const std::vector<Sta
     else
       ext[line] = Extent{((l % nf) + nf) % nf, h - l};
   }
+  return "";
+}
+
+// The smallest circular range {first, span} (as in line_extents) that holds
+// every set position of a line's bitmap (nw words over nf positions).
+inline Extent bitmap_hull(const uint64_t* b, int nw, int nf) {
+  // the largest run of unset positions between two set ones, or around the
+  // end of the line, is the part left out
+  int first = -1, prev = -1, gap = -1, gap_end = 0;
+  for (int k = 0; k < nw; ++k)
+    for (uint64_t v = b[k]; v; v &= v - 1) {
+      const int q = k * 64 + __builtin_ctzll(v);
+      if (first < 0)
+        first = q;
+      else if (q - prev - 1 > gap) {
+        gap = q - prev - 1;
+        gap_end = q;
+      }
+      prev = q;
+    }
+  if (first < 0) return Extent{0, -1};
+  if (nf - 1 - prev + first >= gap) return Extent{first, prev - first};
+  return Extent{gap_end, nf - 1 - gap};
+}
+
+// The interpolation by tiles reads the forward transform's spectrum only in
+// the gather tiles that hold list entries: all their points on the grid and,
+// when the spectrum is the Hermitian half (mirror), the conjugate mirror
+// image (-q0, -q1, nf2 - q2) in place of each point with 2 q2 > nf2.  Per line
+// of the spectrum along axis 0 (index q1 c2 + q2 over the lines kept, c2 =
+// nf2 / 2 + 1 with mirror, nf2 without), ext gets the smallest circular range
+// {first, span} (as in line_extents) that holds every position read on it;
+// the transform's last pass need not store the rest.
+inline std::string tile_read_extents(const Geometry& g, const std::vector<int64_t>& tcount, bool mirror,
+                                     std::vector<Extent>& ext, int threads = 1) {
+  const int nf0 = g.nf[0], nf1 = g.nf[1], nf2 = g.nf[2];
+  const int64_t ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
+  if ((int64_t)tcount.size() != ntiles + 1) return "tile offsets do not match the tiles";
+  const int c2 = mirror ? nf2 / 2 + 1 : nf2;
+  const int nw = (nf0 + 63) / 64;
+  const int64_t nlines = (int64_t)nf1 * c2;
+  std::vector<uint64_t> bits((size_t)(nlines * nw), 0);
+  // per tile column (t1, t2): the axis-0 positions of its listed tiles (X) and
+  // their mirror images (Xm), then or-ed into the column's lines
+  std::vector<uint64_t> X(nw), Xm(nw);
+  for (int t1 = 0; t1 < g.nt[1]; ++t1)
+    for (int t2 = 0; t2 < g.nt[2]; ++t2) {
+      std::fill(X.begin(), X.end(), 0);
+      std::fill(Xm.begin(), Xm.end(), 0);
+      bool any = false;
+      for (int t0 = 0; t0 < g.nt[0]; ++t0) {
+        const int64_t tile = ((int64_t)t0 * g.nt[1] + t1) * g.nt[2] + t2;
+        if (tcount[tile + 1] == tcount[tile]) continue;
+        any = true;
+        for (int x = t0 * g.T[0]; x < std::min((t0 + 1) * g.T[0], nf0); ++x) {
+          const int xm = x ? nf0 - x : 0;
+          X[x >> 6] |= 1ull << (x & 63);
+          Xm[xm >> 6] |= 1ull << (xm & 63);
+        }
+      }
+      if (!any) continue;
+      for (int y = t1 * g.T[1]; y < std::min((t1 + 1) * g.T[1], nf1); ++y)
+        for (int z = t2 * g.T[2]; z < std::min((t2 + 1) * g.T[2], nf2); ++z) {
+          const bool m = mirror && 2 * z > nf2;
+          const int64_t line = m ? (int64_t)(y ? nf1 - y : 0) * c2 + (nf2 - z) : (int64_t)y * c2 + z;
+          uint64_t* b = &bits[(size_t)(line * nw)];
+          const std::vector<uint64_t>& src = m ? Xm : X;
+          for (int k = 0; k < nw; ++k) b[k] |= src[k];
+        }
+    }
+  ext.assign(nlines, Extent{0, -1});
+  const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(threads, nlines / 4096 + 1));
+  parallel_ranges(nlines, nth, [&](int64_t l0, int64_t l1, int) {
+    for (int64_t line = l0; line < l1; ++line) ext[line] = bitmap_hull(&bits[(size_t)(line * nw)], nw, nf0);
+  });
   return "";
 }
 

@@ -972,6 +972,23 @@ Status build_plan(Plan& pl, const jgb_params* p) {
     TRY(dev_alloc(pl, &pl.d_gext, sizeof(int2) * ext.size()));
     TRY(upload(pl, pl.d_gext, ext.data(), sizeof(int2) * ext.size()));
   }
+  if (pl.tile_ok) {
+    // the spectrum's reach per line of the forward transform's last pass,
+    // from the tiles the interpolation by tiles reads: that pass stores
+    // nothing beyond it when the interpolation runs by tiles
+    lists::Geometry g{};
+    for (int a = 0; a < 3; ++a) {
+      g.nf[a] = pl.nf[a];
+      g.T[a] = pl.GT[a];
+      g.nt[a] = pl.gnt[a];
+      g.w[a] = pl.w[a];
+    }
+    std::vector<lists::Extent> ext;
+    const std::string err = lists::tile_read_extents(g, tcount, pl.r2c, ext, host_threads());
+    if (!err.empty()) return fail(JGB_ERR_UNSUPPORTED, err);
+    TRY(dev_alloc(pl, &pl.d_fext, sizeof(int2) * ext.size()));
+    TRY(upload(pl, pl.d_fext, ext.data(), sizeof(int2) * ext.size()));
+  }
   t_phase[1] = since(t_lists);
   const auto t_rings = std::chrono::steady_clock::now();
   // the ring tables (3D; built when forced or for the tuner to time)

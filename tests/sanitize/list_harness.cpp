@@ -188,6 +188,54 @@ static void run(const Case& c, bool nowrap_gather) {
     CHECK(same, "%s: threaded gather lists differ from the serial build", c.name);
   }
   const int64_t ntiles = (int64_t)g.nt[0] * g.nt[1] * g.nt[2];
+
+  // the spectrum's reach per line for the interpolation by tiles: every point
+  // it reads (all points of the listed tiles, mirrored past nf2 / 2 for the
+  // Hermitian half) lies in its line's range, both ends of a range are points
+  // it reads, lines it reads nothing of are empty, and the threaded build
+  // equals the serial one
+  if (c.dim == 3 && !c.ring)
+    for (int mirror = 0; mirror < 2; ++mirror) {
+      std::vector<Extent> fx, fx1;
+      CHECK(tile_read_extents(g, tcount, mirror, fx, 8).empty(), "%s: tile_read_extents", c.name);
+      CHECK(tile_read_extents(g, tcount, mirror, fx1, 1).empty(), "%s: serial tile read extents", c.name);
+      bool same = fx.size() == fx1.size();
+      for (size_t i = 0; same && i < fx.size(); ++i) same = fx[i].first == fx1[i].first && fx[i].span == fx1[i].span;
+      CHECK(same, "%s: threaded tile read extents differ from the serial build", c.name);
+      const int nf0 = g.nf[0], nf1 = g.nf[1], nf2 = g.nf[2];
+      const int c2 = mirror ? nf2 / 2 + 1 : nf2;
+      const int64_t nl = (int64_t)nf1 * c2;
+      CHECK((int64_t)fx.size() == nl, "%s: one reach per spectrum line", c.name);
+      if ((int64_t)fx.size() != nl) continue;
+      std::vector<char> any(nl, 0), at_first(nl, 0), at_last(nl, 0);
+      int64_t outside = 0;
+      for (int64_t t = 0; t < ntiles; ++t) {
+        if (tcount[t + 1] == tcount[t]) continue;
+        const int t0 = (int)(t / ((int64_t)g.nt[1] * g.nt[2])), t1 = (int)((t / g.nt[2]) % g.nt[1]),
+                  t2 = (int)(t % g.nt[2]);
+        for (int x = t0 * g.T[0]; x < std::min((t0 + 1) * g.T[0], nf0); ++x)
+          for (int y = t1 * g.T[1]; y < std::min((t1 + 1) * g.T[1], nf1); ++y)
+            for (int z = t2 * g.T[2]; z < std::min((t2 + 1) * g.T[2], nf2); ++z) {
+              const bool m = mirror && 2 * z > nf2;
+              const int qx = m ? mod(-x, nf0) : x, qy = m ? mod(-y, nf1) : y, qz = m ? nf2 - z : z;
+              const int64_t line = (int64_t)qy * c2 + qz;
+              const Extent e = fx[line];
+              any[line] = 1;
+              if (e.span < 0 || mod(qx - e.first, nf0) > e.span) ++outside;
+              if (qx == e.first) at_first[line] = 1;
+              if (qx == mod(e.first + e.span, nf0)) at_last[line] = 1;
+            }
+      }
+      CHECK(outside == 0, "%s: %lld points read outside their line's reach (mirror %d)", c.name, (long long)outside,
+            mirror);
+      int64_t loose = 0, stray = 0;
+      for (int64_t line = 0; line < nl; ++line) {
+        if (!any[line]) stray += fx[line].span != -1;
+        else loose += !(at_first[line] && at_last[line]);
+      }
+      CHECK(stray == 0, "%s: %lld unread lines with a reach", c.name, (long long)stray);
+      CHECK(loose == 0, "%s: %lld reaches not ending at read points", c.name, (long long)loose);
+    }
   int64_t total = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
     const int t0 = (int)(t / ((int64_t)g.nt[1] * g.nt[2])), t1 = (int)((t / g.nt[2]) % g.nt[1]), t2 = (int)(t % g.nt[2]);

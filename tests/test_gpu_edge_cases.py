@@ -108,3 +108,36 @@ def test_zero_density(prec):
     assert plan.energy(z).item() == 0.0
     assert torch.count_nonzero(plan.transform(z)).item() == 0
     plan.close()
+
+
+@pytest.mark.parametrize("n", [(24, 20, 30), (96, 12, 10)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_spectrum_reach_after_a_larger_density(prec, n):
+    """Under the interpolation by tiles the forward transform's last pass stores,
+    per line of the spectrum, only the range that the listed tiles read (their
+    points, or the mirror images past nf2 / 2); the rest keeps what an earlier
+    call left there.  A call after one on a density a million times larger must
+    equal, bit for bit, the same call on a fresh plan: no point outside the
+    stored ranges is read.  The grids span several tiles per axis, with ragged
+    edges; the second one's 192-point lines along the masked pass take fewer
+    lines per block than the unmasked pass would (a divisor of its threads)."""
+    box = tuple(0.375 * v for v in n)
+    p = wl.Problem("r1", 3, n, box, wl.DIPOLE_3D, 12, 10, 16, axis=_axis(33))
+    eps = 1e-10 if prec == "fp64" else 1e-5
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(34)
+    rho_a = torch.tensor(1e6 * rng.standard_normal(p.n), dtype=dt, device="cuda")
+    rho_b = torch.tensor(rng.standard_normal(p.n), dtype=dt, device="cuda")
+    used = make_plan(p, eps=eps, precision=prec, interp_tiles=True)
+    fresh = make_plan(p, eps=eps, precision=prec, interp_tiles=True)
+    try:
+        assert used.info["interp_chunk"] == 0  # the interpolation by tiles
+        used.potential(rho_a)
+        u1, e1 = used.potential(rho_b)
+        u2, e2 = fresh.potential(rho_b)
+        torch.cuda.synchronize()
+        say("reach", prec, "max |u1 - u2| %.3e" % float((u1 - u2).abs().max()))
+        assert torch.equal(u1, u2) and float(e1) == float(e2)
+    finally:
+        used.close()
+        fresh.close()

@@ -6,6 +6,10 @@ undefined-behaviour sanitizers (tests/sanitize/list_harness.cpp):
     where the 10-bit start codes are tightest), every entry checked against a
     brute-force enumeration of the (node, tile) pairs whose footprints meet,
     and the threaded build against the serial one;
+  * the per-line ranges of the spreading grid that footprints reach, and of
+    the spectrum that the interpolation by tiles reads (every point of every
+    listed tile, or its mirror image, inside its line's range; both ends of a
+    range points that are read; unread lines empty);
   * the generalized Gaussian radial rule against the oracle's."""
 import os
 import shutil
