@@ -89,19 +89,26 @@ def test_graph_replays_follow_inputs(nstreams):
     b.close()
 
 
-@pytest.mark.parametrize("nstreams", [1, 4])
-def test_batched_coulomb_workload(nstreams):
+@pytest.mark.parametrize("nstreams,autotune", [(1, False), (4, False), (1, True)])
+def test_batched_coulomb_workload(nstreams, autotune):
     """64 seeded densities, N in {64, 96, 128, 160}, mixed precision, one graph:
     one launch per pipeline site over all members (one stream) or the members'
-    pipelines on four streams."""
+    pipelines on four streams; with autotuned members, the tap-kernel forms the
+    tuner picks per member (the interpolation by tiles among them, whose
+    forward transform stores only each line's read range, here on 128- to
+    320-point lines)."""
     import paper_1311_4120_amd as jgb
     members = wl.batched_coulomb()
     kws, rhos = [], []
     for p, mix in members:
         kws.append(dict(n=p.n, box=p.box, kernel="coulomb3d", nodes=(p.n_r, p.n_theta, p.n_phi), eps=p.eps,
-                        precision="mixed"))
-    say("batched_coulomb: planning 64 members")
+                        precision="mixed", autotune=autotune))
+    say("batched_coulomb: planning 64 members", "(autotuned)" if autotune else "")
     b = jgb.Batch(kws, nstreams=nstreams)
+    if autotune:
+        tiles = sum(pl.info["interp_chunk"] == 0 for pl in b.plans)
+        say("   %d members interpolate by tiles" % tiles)
+        assert tiles > 0
     for p, mix in members:
         rhos.append(torch.tensor(mix.evaluate(p.n, p.box), dtype=torch.float32, device="cuda"))
     u, E = b.bind(rhos)
