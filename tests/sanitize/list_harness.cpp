@@ -342,6 +342,28 @@ int main(int argc, char** argv) {
     for (size_t i = 0; i < x.size(); ++i) printf("%.17g %.17g\n", x[i], w[i]);
     return 0;
   }
+  {
+    // the circular hull of a line's read positions: empty, one point, all,
+    // a range around the end of the line, the largest of two gaps left out
+    // (ties to the gap around the end), across 64-bit words
+    auto hull = [](std::initializer_list<int> set, int nf) {
+      std::vector<uint64_t> b((nf + 63) / 64, 0);
+      for (int q : set) b[q >> 6] |= 1ull << (q & 63);
+      return bitmap_hull(b.data(), (int)b.size(), nf);
+    };
+    auto is = [](Extent e, int first, int span) { return e.first == first && e.span == span; };
+    CHECK(is(hull({}, 100), 0, -1), "hull: empty line");
+    CHECK(is(hull({37}, 100), 37, 0), "hull: one point");
+    std::initializer_list<int> all = {0, 1, 2, 3, 4, 5, 6, 7};
+    CHECK(is(hull(all, 8), 0, 7), "hull: whole line");
+    CHECK(is(hull({0, 1, 2, 97, 98, 99}, 100), 97, 5), "hull: range around the end");
+    CHECK(is(hull({10, 20, 90}, 100), 90, 30), "hull: wrap gap smaller than the inner one");
+    CHECK(is(hull({10, 60, 70}, 100), 60, 50), "hull: inner gap (49) larger than the one around the end (39)");
+    CHECK(is(hull({10, 30, 40}, 100), 10, 30), "hull: gap around the end largest");
+    CHECK(is(hull({0, 50}, 100), 0, 50), "hull: equal gaps keep the first range");
+    CHECK(is(hull({5, 63, 64, 200}, 256), 200, 120), "hull: across words, the 64..200 gap left out");
+    CHECK(is(hull({1, 255}, 256), 255, 2), "hull: two points straddling the end");
+  }
   const Case cases[] = {
       // N = 512: the oversampled side 1024, the largest the 10-bit codes allow
       {"3d_512_w12", 3, {1024, 1024, 1024}, 12, 24, 16, 32, {8, 8, 8}, false},
