@@ -342,12 +342,19 @@ __device__ __forceinline__ void ring_reduce_body(const RingReduceArgs<T>& a, con
   const int g0 = t0 * kRingTile0 + x, g1 = t1 * kRingTile1 + y, g2 = t2 * kRingTile2 + z;
   if (g0 >= a.nf0 || g1 >= a.nf1 || g2 >= a.nf2) return;
   const C2<T>* p = a.partials + (int64_t)first * kRingTilePoints + idx;
+  // the slots in order, their loads issued eight at a time (a slot past the
+  // count loads slot c0 instead, and is dropped): one wait per eight slots
   T sr = T(0), si = T(0);
-#pragma unroll 8
-  for (int c = 0; c < count; ++c) {
-    const C2<T> v = p[(int64_t)c * kRingTilePoints];
-    sr += v.x;
-    si += v.y;
+  for (int c0 = 0; c0 < count; c0 += 8) {
+    C2<T> v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = p[(int64_t)(c0 + k < count ? c0 + k : c0) * kRingTilePoints];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (c0 + k < count) {
+        sr += v[k].x;
+        si += v[k].y;
+      }
   }
   a.G[((int64_t)g0 * a.nf1 + g1) * a.nf2 + g2] = C2<T>{sr, si};
 }

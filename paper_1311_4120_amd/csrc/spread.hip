@@ -332,12 +332,19 @@ __device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs<T>& a,
   const int g0 = t0 * T0 + lane / T1, g1 = t1 * T1 + lane % T1, g2 = t2 * kGatherZ + z;
   if (g0 >= nf0 || g1 >= nf1 || g2 >= nf2) return;
   const C2<T>* p = partials + (int64_t)first * 64 * kGatherZ + idx;
+  // the slots in order, their loads issued eight at a time (a slot past the
+  // count loads slot c0 instead, and is dropped): one wait per eight slots
   T sr = T(0), si = T(0);
-#pragma unroll 8
-  for (int c = 0; c < count; ++c) {
-    const C2<T> v = p[(int64_t)c * 64 * kGatherZ];
-    sr += v.x;
-    si += v.y;
+  for (int c0 = 0; c0 < count; c0 += 8) {
+    C2<T> v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = p[(int64_t)(c0 + k < count ? c0 + k : c0) * 64 * kGatherZ];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (c0 + k < count) {
+        sr += v[k].x;
+        si += v[k].y;
+      }
   }
   G[((int64_t)g0 * nf1 + g1) * nf2 + g2] = C2<T>{sr, si};
 }
